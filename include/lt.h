@@ -1,0 +1,271 @@
+/*
+ * lt.h -- C ABI of the lens transport library (liblt.so), gfx950 / HIP.
+ *
+ * The operations follow the problem statement of "Precomputed Lens Transport
+ * Maps" (arXiv 2605.04017):
+ *   - a lens system maps an input ray (position, direction, intensity,
+ *     wavelength) to one output ray per light-path type (Sec. 3, Eq. 1);
+ *   - a light path is a sequence of transmit/reflect interactions at
+ *     successive surfaces; an input is valid for a path iff the ray reaches
+ *     the output plane (Sec. 3, light-path definition and validity);
+ *   - tracing composes per-surface operators: closest hit, new direction,
+ *     Fresnel factor (Sec. 3, operator S and the composite-operator equation);
+ *   - the precomputed map replaces the trace by a classifier g (valid mask)
+ *     and a regressor f (exit ray and Fresnel throughput); the output is f(x)
+ *     where g(x) = 1 and empty otherwise (Sec. 4.2, "Neural Ray Masking").
+ *
+ * Conventions used by every call:
+ *   - z is the optical axis.  Surfaces are listed object side first; the
+ *     first vertex is at z = 0, vertex k+1 at z_k + thickness_k; the sensor
+ *     plane is at z_N + thickness_N.  radius > 0: centre of curvature on the
+ *     image side; radius = 0: flat.
+ *   - Input rays start on the sensor plane and travel toward the object
+ *     (dz < 0).  Positions in mm, wavelengths in nm.  Directions need not be
+ *     exactly unit length; the library renormalises them.
+ *   - The output plane is z = 0 (the front vertex plane); an exit ray is the
+ *     point where the final ray's line meets that plane, its unit direction
+ *     and its Fresnel throughput (input intensity 1).
+ *   - Rays that do not reach the output plane get mask 0, NaN position and
+ *     direction fields and throughput 0.
+ *
+ * Memory: every ray, output, target and workspace pointer is a DEVICE
+ * pointer owned by the caller.  Struct arguments themselves are host memory
+ * read during the call.  Handles (lt_lens, lt_map) are owned by the library
+ * from create to destroy.
+ *
+ * Streams: calls that take `stream` (a hipStream_t, NULL = default stream)
+ * enqueue work and return without synchronising.  Argument errors are
+ * detected on the host before anything is enqueued.  Calls with n == 0 are
+ * valid and do nothing.
+ *
+ * Errors: every call returns an lt_status; lt_last_error() gives a
+ * thread-local message for the most recent failure on the calling thread.
+ */
+#ifndef LT_H
+#define LT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LT_OK = 0,
+    LT_ERR_ARG = 1,     /* bad pointer, size or option */
+    LT_ERR_LENS = 2,    /* malformed prescription */
+    LT_ERR_PATH = 3,    /* path not defined for this lens */
+    LT_ERR_DTYPE = 4,   /* precision not available for this map */
+    LT_ERR_OOM = 5,     /* device allocation failed */
+    LT_ERR_DEVICE = 6,  /* HIP runtime or launch error */
+    LT_ERR_STATE = 7    /* call out of order (e.g. map used before parameters were set) */
+} lt_status;
+
+/* Short name of a status code (static string). */
+const char *lt_status_str(int status);
+/* Message of the last failing call on this thread (static per thread). */
+const char *lt_last_error(void);
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t lt_version(void);
+
+/* ------------------------------------------------------------------ lens */
+
+#define LT_MAX_SURFACES 24
+#define LT_MAX_GLASSES 24
+
+typedef enum { LT_GLASS_AIR = 0, LT_GLASS_CAUCHY = 1, LT_GLASS_SELLMEIER = 2 } lt_glass_kind;
+
+/* Dispersion law of a medium.  Wavelength l in micrometres.
+ *   AIR:       n = 1 exactly (coef ignored)
+ *   CAUCHY:    n = coef[0] + coef[1]/l^2 + coef[2]/l^4
+ *   SELLMEIER: n^2 = 1 + sum_{i<3} coef[i] l^2 / (l^2 - coef[3+i])
+ * (the wavelength dependence of the index is why the map takes lambda as an
+ * input; Sec. 3 ray state). */
+typedef struct {
+    int32_t kind;
+    int32_t reserved;
+    double coef[6];
+} lt_glass;
+
+/* One surface of a rotationally symmetric system on a common axis
+ * (Sec. 4.1, "Geometric Simplification"): spherical or flat.
+ * glass_after indexes the glass table and names the medium on the image side;
+ * the object side of surface 0 is air.  The aperture stop (is_stop = 1) is a
+ * flat pass/fail iris of radius semi_diameter_mm with the same medium on both
+ * sides; it is crossed, never reflected from. */
+typedef struct {
+    double radius_mm;
+    double thickness_mm;
+    double semi_diameter_mm;
+    int32_t glass_after;
+    int32_t is_stop;
+} lt_surface;
+
+typedef struct lt_lens_s *lt_lens;
+
+/* Validate and store a prescription (host memory, copied).
+ * Errors: LT_ERR_ARG for NULL pointers or counts out of [1, LT_MAX_*];
+ * LT_ERR_LENS if a thickness is negative, a semi-diameter is not positive or
+ * not smaller than |radius| on a curved surface, a stop is curved, there is
+ * more than one stop, a stop changes the medium, a glass index is out of
+ * range, or any index is not real and >= 1 over 380..780 nm.  The lens holds
+ * no device memory; its data travels with each launch. */
+lt_status lt_lens_create(const lt_surface *surfaces, int32_t n_surfaces,
+                         const lt_glass *glasses, int32_t n_glasses, lt_lens *out);
+lt_status lt_lens_destroy(lt_lens lens);
+/* Counts of a stored lens: all surfaces, refracting surfaces (not the stop),
+ * and two-reflection ghost paths = C(n_refracting, 2). */
+lt_status lt_lens_query(lt_lens lens, int32_t *n_surfaces, int32_t *n_refracting,
+                        int32_t *n_ghost_paths);
+
+/* ------------------------------------------------------------------ paths */
+
+/* Light path (Sec. 3, light-path definition; Sec. 4.2 keeps paths with at
+ * most two reflections).
+ *   kind 0: transmit at every refracting surface (the path used for
+ *           backward path tracing, Sec. 3 backward-tracing equation);
+ *   kind 1: two-reflection ghost (j, i), 1-based refracting-surface indices,
+ *           1 <= j < i <= n_refracting.  Seen from the sensor: transmit back
+ *           to surface j, reflect there, travel toward the image to surface
+ *           i, reflect, then transmit toward the object through every
+ *           surface in front of i.  It has n_refracting + 2(i - j)
+ *           interactions. */
+typedef struct {
+    int32_t kind;
+    int32_t j;
+    int32_t i;
+} lt_path;
+
+/* Index of a ghost path in [0, C(N,2)) ordered by (j, i) lexicographically,
+ * and its inverse.  Return -1 / LT_ERR_PATH for an invalid path. */
+int32_t lt_ghost_index(int32_t n_refracting, int32_t j, int32_t i);
+lt_status lt_ghost_path(int32_t n_refracting, int32_t index, lt_path *out);
+
+/* ------------------------------------------------------------------ rays */
+
+/* Sensor-side rays, structure of arrays, n entries each (device, float32). */
+typedef struct {
+    const float *x;
+    const float *y;
+    const float *dx;
+    const float *dy;
+    const float *dz;
+    const float *lambda_nm;
+} lt_rays;
+
+/* Exit rays on the output plane z = 0 (device, n entries each). */
+typedef struct {
+    uint8_t *mask;
+    float *x;
+    float *y;
+    float *dx;
+    float *dy;
+    float *dz;
+    float *throughput;
+} lt_exit;
+
+/* ------------------------------------------------------------ brute force */
+
+/* Sequential trace of n rays along one path (Sec. 3 composite operator):
+ * per interaction the closest hit with t > 0 on the hemisphere of the sphere
+ * that contains the vertex, clear-aperture clipping (closed disk), vector
+ * Snell refraction or mirror reflection, and the unpolarised Fresnel factor;
+ * TIR on a transmit step kills the ray, on a reflect step reflects all of it.
+ * All arithmetic is FP32 instructions: geometry is carried as compensated
+ * float pairs (about 44 significant bits) so exit positions stay within
+ * 1e-5 mm of the exact trace; Fresnel factors are plain FP32.
+ * Errors: LT_ERR_ARG (NULL handle/pointers with n > 0, n < 0),
+ * LT_ERR_PATH, LT_ERR_DEVICE (launch failure). */
+lt_status lt_trace(lt_lens lens, const lt_path *path, const lt_rays *rays,
+                   const lt_exit *out, int64_t n, void *stream);
+
+/* Trace options for lt_trace_ex. */
+#define LT_TRACE_PLAIN_FP32 1u  /* one FP32 rounding per operation; FP64 only for the
+                                   discriminant on surfaces with |radius| > 1000 mm and
+                                   the transmitted cosine near grazing.  Faster, but
+                                   exit-position errors reach a few 1e-5 mm on long
+                                   ghost paths. */
+
+/* lt_trace with options (0 = same as lt_trace).  Unknown flags: LT_ERR_ARG. */
+lt_status lt_trace_ex(lt_lens lens, const lt_path *path, const lt_rays *rays,
+                      const lt_exit *out, int64_t n, uint32_t flags, void *stream);
+
+/* ------------------------------------------------------------------ map */
+
+/* The precomputed lens transport map (Sec. 4.2, "Neural Ray Masking"): for
+ * each of n_heads light paths a classifier logit g and a regressor f (exit
+ * position x, y, direction dx, dy and Fresnel throughput) share one trunk of
+ * `depth` hidden layers of `width` neurons (tanh, Sec. 4.2 "C^1 Continuous
+ * Network"; ReLU available).  The network:
+ *   xhat = (x, y, dx, dy, dz, lambda_nm) - in_shift) * in_scale
+ *   h_1 = act(W_0 xhat + b_0), h_l = act(W_{l-1} h_{l-1} + b_{l-1}), l <= depth
+ *   o = W_depth h_depth + b_depth,   6 outputs per head p at o[6p .. 6p+5]:
+ *   logit = o[6p]; mask = logit > 0;
+ *   (x, y, dx, dy, throughput) = out_shift[p] + out_scale[p] * o[6p+1 .. 6p+5];
+ *   dz = -sqrt(max(0, 1 - dx^2 - dy^2)).
+ * Where mask = 0 the map outputs nothing (the empty set of the paper): the
+ * position/direction fields are NaN and throughput is 0.
+ * Parameters are one FP32 vector: W_0, b_0, W_1, b_1, ..., W_depth, b_depth,
+ * each W row-major (output index first). */
+typedef enum { LT_ACT_TANH = 0, LT_ACT_RELU = 1 } lt_activation;
+typedef enum { LT_F32 = 0, LT_BF16 = 1, LT_FP8 = 2 } lt_dtype;
+
+typedef struct {
+    int32_t in_dim;      /* must be 6 */
+    int32_t width;       /* 32, 64 or 128 */
+    int32_t depth;       /* hidden layers, 1..8 */
+    int32_t n_heads;     /* paths, 1..64 */
+    int32_t activation;  /* lt_activation */
+} lt_map_desc;
+
+typedef struct lt_map_s *lt_map;
+
+/* Per-head outputs, head-major: field[p * n + r] (device). */
+typedef struct {
+    float *logit;
+    uint8_t *mask;
+    float *x;
+    float *y;
+    float *dx;
+    float *dy;
+    float *dz;
+    float *throughput;
+} lt_map_out;
+
+/* Create a map (allocates its device parameter, normalisation, packed-weight
+ * and optimizer buffers on the current device).  Parameters start unset.
+ * Errors: LT_ERR_ARG for an unsupported shape, LT_ERR_OOM. */
+lt_status lt_map_create(const lt_map_desc *desc, lt_map *out);
+lt_status lt_map_destroy(lt_map map);
+/* Number of FP32 parameters. */
+int64_t lt_map_num_params(lt_map map);
+/* Copy count (= lt_map_num_params) FP32 parameters from / to device memory,
+ * stream-ordered.  Setting parameters invalidates the packed BF16/FP8 copies;
+ * they are rebuilt on the stream by the next evaluation.  Getting them before
+ * any were set: LT_ERR_STATE. */
+lt_status lt_map_set_params(lt_map map, const float *params, int64_t count, void *stream);
+lt_status lt_map_get_params(lt_map map, float *params, int64_t count, void *stream);
+/* Input and output normalisation (host arrays): in_shift[6], in_scale[6],
+ * out_shift[5 * n_heads], out_scale[5 * n_heads] (x, y, dx, dy, throughput per
+ * head).  Synchronous copy. */
+lt_status lt_map_set_norm(lt_map map, const float *in_shift, const float *in_scale,
+                          const float *out_shift, const float *out_scale);
+
+/* Evaluate the map for n rays (Sec. 4.2: output f(x) where g(x) = 1).
+ * LT_BF16: BF16 MFMA with FP32 accumulation; input layer and output layer
+ * use split hi+lo BF16 weights (and split inputs) to keep ~16 significant
+ * bits there; hidden activations are rounded to BF16.
+ * LT_FP8: hidden layers in OCP FP8 E4M3 MFMA with power-of-two per-layer
+ * scales (weights scaled so max |W| <= 448, tanh activations by 2^8), FP32
+ * accumulation; input and output layers as in LT_BF16.
+ * LT_F32: FP32 MFMA throughout.
+ * Errors: LT_ERR_ARG, LT_ERR_STATE (parameters never set), LT_ERR_DTYPE,
+ * LT_ERR_DEVICE. */
+lt_status lt_map_eval(lt_map map, int32_t dtype, const lt_rays *rays, const lt_map_out *out,
+                      int64_t n, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LT_H */

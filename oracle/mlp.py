@@ -1,0 +1,304 @@
+"""FP64 reference of the precomputed lens transport map (TEST INFRASTRUCTURE).
+
+The map follows Sec. 4.2 of the paper ("Neural Ray Masking"): per light path
+a classifier g(x) decides whether the input ray is valid and a regressor
+f(x) gives the exit ray and its Fresnel throughput; the model outputs f(x)
+where g(x) = 1 and nothing otherwise.  Hidden layers use tanh for C^1
+smoothness (Sec. 4.2, "C^1 Continuous Network"); a ReLU variant is kept for
+the small doublet workload.  Here the classifier logit and the regression
+outputs of every path are heads of one shared trunk:
+
+    xhat = (input - in_shift) * in_scale                     (6 features)
+    h_0 = xhat;  h_l = phi(W_l h_{l-1} + b_l),  l = 1..depth
+    o = W_out h_depth + b_out                                (6 per head)
+    head p: logit = o[6p], mask = logit > 0,
+            (x, y, dx, dy, I) = out_shift + out_scale * o[6p+1 .. 6p+5],
+            dz = -sqrt(1 - dx^2 - dy^2);  mask = 0 gives NaN fields, I = 0.
+
+Training loss (per head, averaged over heads): binary cross-entropy of the
+logit against the traced validity plus the squared error of the normalised
+regression outputs on valid rays only (the regressor only has to fit the
+valid region, Sec. 4.2):
+
+    L = mean_p [ w_bce/N sum_i BCE(logit_ip, v_ip)
+               + w_l2/(5N) sum_i v_ip sum_d (o_ipd - t_ipd)^2 ]
+
+Adam follows Kingma and Ba (2015) with bias correction.
+
+The quantised forward (`forward_quantized`) rounds exactly where the GPU
+kernels round -- BF16 round-to-nearest-even for weights and activations,
+split hi/lo BF16 for the input layer and the output layer, OCP FP8 E4M3
+(bias 7, max 448, round-to-nearest-even, subnormals) with power-of-two
+per-layer scales for the hidden layers in FP8 mode -- and otherwise computes
+in FP64, so it pins the kernels up to FP32 accumulation order.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, List
+
+import numpy as np
+
+ACT_TANH = 0
+ACT_RELU = 1
+N_OUT = 6  # logit, x, y, dx, dy, throughput
+
+
+@dataclasses.dataclass
+class MapDesc:
+    width: int = 128
+    depth: int = 5          # hidden layers
+    n_heads: int = 1
+    activation: int = ACT_TANH
+
+
+@dataclasses.dataclass
+class MapParams:
+    desc: MapDesc
+    W: List[np.ndarray]       # W[0]: (width, 6), W[1..depth-1]: (width, width), W[depth]: (6H, width)
+    b: List[np.ndarray]
+    in_shift: np.ndarray      # (6,)
+    in_scale: np.ndarray      # (6,)
+    out_shift: np.ndarray     # (H, 5)
+    out_scale: np.ndarray     # (H, 5)
+
+    def flat(self) -> np.ndarray:
+        """Parameter vector in the library's order: W0, b0, W1, b1, ..., Wout, bout
+        (row-major, output index first)."""
+        parts = []
+        for W, b in zip(self.W, self.b):
+            parts.append(W.reshape(-1))
+            parts.append(b.reshape(-1))
+        return np.concatenate(parts)
+
+    def set_flat(self, v: np.ndarray):
+        k = 0
+        for li in range(len(self.W)):
+            n = self.W[li].size
+            self.W[li] = v[k:k + n].reshape(self.W[li].shape).astype(np.float64)
+            k += n
+            n = self.b[li].size
+            self.b[li] = v[k:k + n].astype(np.float64)
+            k += n
+        assert k == v.size
+
+    def copy(self) -> "MapParams":
+        return MapParams(self.desc, [w.copy() for w in self.W], [b.copy() for b in self.b],
+                         self.in_shift.copy(), self.in_scale.copy(), self.out_shift.copy(),
+                         self.out_scale.copy())
+
+
+def layer_shapes(desc: MapDesc):
+    shapes = [(desc.width, 6)]
+    shapes += [(desc.width, desc.width)] * (desc.depth - 1)
+    shapes.append((N_OUT * desc.n_heads, desc.width))
+    return shapes
+
+
+def n_params(desc: MapDesc) -> int:
+    return sum(o * i + o for (o, i) in layer_shapes(desc))
+
+
+def init_params(desc: MapDesc, seed: int) -> MapParams:
+    """Uniform Glorot initialisation, zero biases, identity normalisation."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    W, b = [], []
+    for (o, i) in layer_shapes(desc):
+        lim = math.sqrt(6.0 / (o + i))
+        W.append(rng.uniform(-lim, lim, (o, i)))
+        b.append(np.zeros(o))
+    H = desc.n_heads
+    return MapParams(desc, W, b, np.zeros(6), np.ones(6), np.zeros((H, 5)), np.ones((H, 5)))
+
+
+def features(rays: Dict[str, np.ndarray], p: MapParams) -> np.ndarray:
+    x = np.stack([rays[k].astype(np.float64) for k in ("x", "y", "dx", "dy", "dz", "lambda_nm")], 1)
+    return (x - p.in_shift) * p.in_scale
+
+
+def act(z: np.ndarray, kind: int) -> np.ndarray:
+    return np.tanh(z) if kind == ACT_TANH else np.maximum(z, 0.0)
+
+
+def act_grad_from_output(h: np.ndarray, z: np.ndarray, kind: int) -> np.ndarray:
+    return 1.0 - h * h if kind == ACT_TANH else (z > 0).astype(np.float64)
+
+
+def forward(p: MapParams, xhat: np.ndarray):
+    """FP64 forward.  Returns (o, cache) with o of shape (n, 6H)."""
+    h = xhat
+    hs, zs = [h], []
+    L = len(p.W)
+    for li in range(L):
+        z = h @ p.W[li].T + p.b[li]
+        zs.append(z)
+        if li < L - 1:
+            h = act(z, p.desc.activation)
+            hs.append(h)
+        else:
+            h = z
+    return h, (hs, zs)
+
+
+def decode(o: np.ndarray, p: MapParams) -> Dict[str, np.ndarray]:
+    """Head outputs (arrays of shape (H, n)) from raw network outputs."""
+    n = o.shape[0]
+    H = p.desc.n_heads
+    o = o.reshape(n, H, N_OUT).transpose(1, 0, 2)  # (H, n, 6)
+    logit = o[..., 0]
+    mask = logit > 0
+    reg = p.out_shift[:, None, :] + p.out_scale[:, None, :] * o[..., 1:]
+    x, y, dx, dy, thr = (reg[..., k] for k in range(5))
+    dz = -np.sqrt(np.maximum(0.0, 1.0 - dx * dx - dy * dy))
+    res = {"logit": logit, "mask": mask.astype(np.uint8)}
+    for k, v in (("x", x), ("y", y), ("dx", dx), ("dy", dy), ("dz", dz)):
+        res[k] = np.where(mask, v, np.nan)
+    res["throughput"] = np.where(mask, thr, 0.0)
+    return res
+
+
+# ------------------------------------------------------------ rounding ----
+
+def round_bf16(x: np.ndarray) -> np.ndarray:
+    """Round to bfloat16 (round to nearest, ties to even); returns float64."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    r = ((u + 0x7FFF + lsb) >> 16) << 16
+    out = r.astype(np.uint32).view(np.float32).astype(np.float64)
+    nan = np.isnan(f)
+    out[nan] = np.nan
+    return out
+
+
+def split_bf16(x: np.ndarray):
+    hi = round_bf16(x)
+    lo = round_bf16(np.asarray(x, np.float64) - hi)
+    return hi, lo
+
+
+FP8_MAX = 448.0
+
+
+def round_fp8_e4m3(x: np.ndarray) -> np.ndarray:
+    """OCP FP8 E4M3 (bias 7, 3 mantissa bits, max 448, subnormal step 2^-9),
+    round to nearest even, saturating to +-448.  Returns float64."""
+    x = np.asarray(x, np.float64)
+    a = np.abs(x)
+    e = np.floor(np.log2(np.where(a > 0, a, 1.0)))
+    e = np.maximum(e, -6.0)                 # subnormals share the 2^-6 binade spacing
+    step = np.exp2(e - 3.0)
+    q = a / step
+    r = np.floor(q)
+    frac = q - r
+    up = (frac > 0.5) | ((frac == 0.5) & (np.fmod(r, 2.0) == 1.0))
+    r = r + up
+    v = np.minimum(r * step, FP8_MAX)
+    v = np.where(a > 0, v, 0.0)
+    return np.copysign(v, x)
+
+
+def pow2_scale(amax: float, target: float) -> float:
+    """Largest power of two s with amax * s <= target (1 if amax == 0)."""
+    if amax <= 0:
+        return 1.0
+    return float(2.0 ** math.floor(math.log2(target / amax)))
+
+
+def fp8_layer_scales(p: MapParams):
+    """Per hidden layer (1..depth-1): weight scale and activation scale used in
+    FP8 mode.  Weights are scaled so max|W| maps to 448 or below, tanh
+    activations (|h| <= 1) by 2^8."""
+    ws, hs = [], []
+    for li in range(1, len(p.W) - 1):
+        ws.append(pow2_scale(float(np.abs(p.W[li]).max()), FP8_MAX))
+        hs.append(256.0 if p.desc.activation == ACT_TANH else 1.0)
+    return ws, hs
+
+
+def forward_quantized(p: MapParams, xhat: np.ndarray, mode: str):
+    """Forward pass with the kernels' rounding.  mode: "bf16" or "fp8"."""
+    L = len(p.W)
+    x_hi, x_lo = split_bf16(xhat)
+    W0_hi, W0_lo = split_bf16(p.W[0])
+    z = x_hi @ W0_hi.T + x_lo @ W0_hi.T + x_hi @ W0_lo.T + p.b[0]
+    h = round_bf16(act(z, p.desc.activation))
+    if mode == "fp8":
+        ws, hsc = fp8_layer_scales(p)
+    for li in range(1, L - 1):
+        if mode == "bf16":
+            z = h @ round_bf16(p.W[li]).T + p.b[li]
+        else:
+            sw, sh = ws[li - 1], hsc[li - 1]
+            Wq = round_fp8_e4m3(p.W[li] * sw)
+            hq = round_fp8_e4m3(h * sh)
+            z = (hq @ Wq.T) / (sw * sh) + p.b[li]
+        h = round_bf16(act(z, p.desc.activation))
+    Wo_hi, Wo_lo = split_bf16(p.W[L - 1])
+    o = h @ Wo_hi.T + h @ Wo_lo.T + p.b[L - 1]
+    return o
+
+
+# ------------------------------------------------------------ training ----
+
+def normalise_targets(t: Dict[str, np.ndarray], p: MapParams) -> np.ndarray:
+    """(H, n, 5) normalised regression targets from per-head traced exit rays."""
+    stk = np.stack([t[k] for k in ("x", "y", "dx", "dy", "throughput")], -1)  # (H, n, 5)
+    return (stk - p.out_shift[:, None, :]) / p.out_scale[:, None, :]
+
+
+def loss_and_grad(p: MapParams, xhat: np.ndarray, valid: np.ndarray, tnorm: np.ndarray,
+                  w_bce: float = 1.0, w_l2: float = 1.0):
+    """FP64 loss (total, bce, l2) and gradients (list of (dW, db)).
+
+    valid: (H, n) 0/1; tnorm: (H, n, 5), ignored where valid == 0."""
+    n = xhat.shape[0]
+    H = p.desc.n_heads
+    o, (hs, zs) = forward(p, xhat)
+    oo = o.reshape(n, H, N_OUT).transpose(1, 0, 2)
+    logit = oo[..., 0]
+    v = valid.astype(np.float64)
+    # stable BCE with logits
+    bce = np.maximum(logit, 0) - logit * v + np.log1p(np.exp(-np.abs(logit)))
+    sig = 1.0 / (1.0 + np.exp(-logit))
+    t = np.where(v[..., None] > 0, tnorm, 0.0)
+    diff = (oo[..., 1:] - t) * v[..., None]
+    l_bce = w_bce * bce.sum() / (n * H)
+    l_l2 = w_l2 * (diff * diff).sum() / (5 * n * H)
+    g = np.zeros_like(oo)
+    g[..., 0] = w_bce * (sig - v) / (n * H)
+    g[..., 1:] = w_l2 * 2.0 * diff / (5 * n * H)
+    delta = g.transpose(1, 0, 2).reshape(n, H * N_OUT)
+    grads = [None] * len(p.W)
+    for li in range(len(p.W) - 1, -1, -1):
+        grads[li] = (delta.T @ hs[li], delta.sum(0))
+        if li > 0:
+            delta = (delta @ p.W[li]) * act_grad_from_output(hs[li], zs[li - 1], p.desc.activation)
+    return (l_bce + l_l2, l_bce, l_l2), grads
+
+
+@dataclasses.dataclass
+class AdamState:
+    m: np.ndarray
+    v: np.ndarray
+    step: int = 0
+
+
+def adam_init(p: MapParams) -> AdamState:
+    n = p.flat().size
+    return AdamState(np.zeros(n), np.zeros(n), 0)
+
+
+def grads_flat(grads) -> np.ndarray:
+    return np.concatenate([np.concatenate([dW.reshape(-1), db.reshape(-1)]) for dW, db in grads])
+
+
+def adam_step(p: MapParams, g: np.ndarray, st: AdamState, lr: float, beta1: float = 0.9,
+              beta2: float = 0.999, eps: float = 1e-8):
+    st.step += 1
+    st.m = beta1 * st.m + (1 - beta1) * g
+    st.v = beta2 * st.v + (1 - beta2) * g * g
+    mhat = st.m / (1 - beta1 ** st.step)
+    vhat = st.v / (1 - beta2 ** st.step)
+    p.set_flat(p.flat() - lr * mhat / (np.sqrt(vhat) + eps))

@@ -1,0 +1,282 @@
+"""MI355X-native lens transport maps (arXiv 2605.04017): Python binding.
+
+The functions here carry the names of the C ABI in include/lt.h and only
+marshal arguments: every per-ray step runs in the HIP kernels of liblt.so.
+Device buffers are torch tensors (PyTorch provides memory and streams only).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Dict, Optional, Sequence, Tuple
+
+from . import _native as N
+from ._native import LtError
+
+RAY_FIELDS = ("x", "y", "dx", "dy", "dz", "lambda_nm")
+EXIT_FIELDS = ("mask", "x", "y", "dx", "dy", "dz", "throughput")
+
+LT_TRACE_PLAIN_FP32 = N.LT_TRACE_PLAIN_FP32
+LT_F32, LT_BF16, LT_FP8 = N.LT_F32, N.LT_BF16, N.LT_FP8
+LT_ACT_TANH, LT_ACT_RELU = N.LT_ACT_TANH, N.LT_ACT_RELU
+MAP_FIELDS = ("logit", "mask", "x", "y", "dx", "dy", "dz", "throughput")
+
+__all__ = ["LtError", "Lens", "lt_lens_create", "lt_lens_query", "lt_trace", "lt_trace_ex",
+           "lt_ghost_index", "lt_ghost_path", "empty_exit", "RAY_FIELDS", "EXIT_FIELDS",
+           "LT_TRACE_PLAIN_FP32", "LT_F32", "LT_BF16", "LT_FP8", "LT_ACT_TANH", "LT_ACT_RELU",
+           "Map", "lt_map_create", "lt_map_set_params", "lt_map_get_params", "lt_map_set_norm",
+           "lt_map_eval", "empty_map_out", "MAP_FIELDS"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _dev_ptr(t, dtype, n: int, name: str) -> int:
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: tensor must live on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: tensor must be contiguous")
+    if t.numel() < n:
+        raise ValueError(f"{name}: has {t.numel()} elements, need {n}")
+    return t.data_ptr()
+
+
+class Lens:
+    """Owned lt_lens handle."""
+
+    def __init__(self, handle: int, n_surfaces: int, n_refracting: int, n_ghost: int):
+        self._h = C.c_void_p(handle)
+        self.n_surfaces = n_surfaces
+        self.n_refracting = n_refracting
+        self.n_ghost_paths = n_ghost
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            N.lib().lt_lens_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _surface_rows(surfaces):
+    rows = []
+    for s in surfaces:
+        if hasattr(s, "radius"):
+            rows.append((s.radius, s.thickness, s.semi_diameter, s.glass_after, s.is_stop))
+        else:
+            rows.append(tuple(s))
+    return rows
+
+
+def _glass_rows(glasses):
+    rows = []
+    for g in glasses:
+        if hasattr(g, "kind"):
+            rows.append((g.kind, *g.coef))
+        else:
+            rows.append(tuple(g))
+    return rows
+
+
+def lt_lens_create(surfaces, glasses) -> Lens:
+    """Validate and store a prescription.  ``surfaces``: rows (radius,
+    thickness, semi_diameter, glass_after, is_stop) or objects with those
+    attributes; ``glasses``: rows (kind, c0..c5) or objects with kind/coef."""
+    srows = _surface_rows(surfaces)
+    grows = _glass_rows(glasses)
+    S = (N.lt_surface * max(1, len(srows)))()
+    for k, (r, t, sd, ga, st) in enumerate(srows):
+        S[k].radius_mm, S[k].thickness_mm, S[k].semi_diameter_mm = float(r), float(t), float(sd)
+        S[k].glass_after, S[k].is_stop = int(ga), int(st)
+    G = (N.lt_glass * max(1, len(grows)))()
+    for k, row in enumerate(grows):
+        G[k].kind = int(row[0])
+        for m in range(6):
+            G[k].coef[m] = float(row[1 + m]) if 1 + m < len(row) else 0.0
+    h = C.c_void_p()
+    N.check(N.lib().lt_lens_create(S, len(srows), G, len(grows), C.byref(h)))
+    ns, nr, ng = C.c_int32(), C.c_int32(), C.c_int32()
+    N.check(N.lib().lt_lens_query(h, C.byref(ns), C.byref(nr), C.byref(ng)))
+    return Lens(h.value, ns.value, nr.value, ng.value)
+
+
+def lt_lens_query(lens: Lens) -> Tuple[int, int, int]:
+    ns, nr, ng = C.c_int32(), C.c_int32(), C.c_int32()
+    N.check(N.lib().lt_lens_query(lens.handle, C.byref(ns), C.byref(nr), C.byref(ng)))
+    return ns.value, nr.value, ng.value
+
+
+def lt_ghost_index(n_refracting: int, j: int, i: int) -> int:
+    return int(N.lib().lt_ghost_index(n_refracting, j, i))
+
+
+def lt_ghost_path(n_refracting: int, index: int) -> Tuple[int, int, int]:
+    p = N.lt_path()
+    N.check(N.lib().lt_ghost_path(n_refracting, index, C.byref(p)))
+    return (p.kind, p.j, p.i)
+
+
+def _path(path) -> N.lt_path:
+    if isinstance(path, N.lt_path):
+        return path
+    k, j, i = (tuple(path) + (0, 0, 0))[:3]
+    return N.lt_path(int(k), int(j), int(i))
+
+
+def _rays_struct(rays: Dict, n: int) -> N.lt_rays:
+    torch = _torch()
+    r = N.lt_rays()
+    for k in RAY_FIELDS:
+        setattr(r, k, _dev_ptr(rays[k], torch.float32, n, f"rays[{k}]") if n else None)
+    return r
+
+
+def empty_exit(n: int, device="cuda") -> Dict:
+    torch = _torch()
+    out = {"mask": torch.empty(n, dtype=torch.uint8, device=device)}
+    for k in EXIT_FIELDS[1:]:
+        out[k] = torch.empty(n, dtype=torch.float32, device=device)
+    return out
+
+
+def lt_trace(lens: Lens, path, rays: Dict, out: Optional[Dict] = None, n: Optional[int] = None,
+             stream=None) -> Dict:
+    """Brute-force FP32 trace of ``n`` sensor-side rays along ``path``
+    ((0,0,0) = transmit, (1, j, i) = ghost).  ``rays``: dict of float32 CUDA
+    tensors; ``out``: dict of exit tensors (allocated if None)."""
+    return lt_trace_ex(lens, path, rays, out, n, 0, stream)
+
+
+def lt_trace_ex(lens: Lens, path, rays: Dict, out: Optional[Dict] = None,
+                n: Optional[int] = None, flags: int = 0, stream=None) -> Dict:
+    """lt_trace with option flags (LT_TRACE_PLAIN_FP32 = 1)."""
+    torch = _torch()
+    if n is None:
+        n = int(rays["x"].numel())
+    if out is None:
+        out = empty_exit(n, rays["x"].device)
+    e = N.lt_exit()
+    for k in EXIT_FIELDS:
+        dt = torch.uint8 if k == "mask" else torch.float32
+        setattr(e, k, _dev_ptr(out[k], dt, n, f"out[{k}]") if n else None)
+    p = _path(path)
+    N.check(N.lib().lt_trace_ex(lens.handle, C.byref(p), C.byref(_rays_struct(rays, n)),
+                                C.byref(e), int(n), int(flags),
+                                C.c_void_p(_stream_ptr(stream) if n else 0)))
+    return out
+
+
+# ------------------------------------------------------------------- map --
+
+class Map:
+    """Owned lt_map handle."""
+
+    def __init__(self, handle: int, width: int, depth: int, n_heads: int, activation: int):
+        self._h = C.c_void_p(handle)
+        self.width, self.depth, self.n_heads, self.activation = width, depth, n_heads, activation
+        self.n_params = int(N.lib().lt_map_num_params(self._h))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            N.lib().lt_map_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lt_map_create(width: int = 128, depth: int = 5, n_heads: int = 1,
+                  activation: int = N.LT_ACT_TANH) -> Map:
+    d = N.lt_map_desc(6, int(width), int(depth), int(n_heads), int(activation))
+    h = C.c_void_p()
+    N.check(N.lib().lt_map_create(C.byref(d), C.byref(h)))
+    return Map(h.value, width, depth, n_heads, activation)
+
+
+def lt_map_set_params(m: Map, params, stream=None):
+    """``params``: float32 CUDA tensor with m.n_params entries (FP32 master)."""
+    torch = _torch()
+    ptr = _dev_ptr(params, torch.float32, m.n_params, "params")
+    N.check(N.lib().lt_map_set_params(m.handle, C.c_void_p(ptr), m.n_params,
+                                      C.c_void_p(_stream_ptr(stream))))
+
+
+def lt_map_get_params(m: Map, out=None, stream=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty(m.n_params, dtype=torch.float32, device="cuda")
+    ptr = _dev_ptr(out, torch.float32, m.n_params, "out")
+    N.check(N.lib().lt_map_get_params(m.handle, C.c_void_p(ptr), m.n_params,
+                                      C.c_void_p(_stream_ptr(stream))))
+    return out
+
+
+def lt_map_set_norm(m: Map, in_shift, in_scale, out_shift, out_scale):
+    import numpy as np
+
+    def arr(a, k):
+        a = np.ascontiguousarray(np.asarray(a, dtype=np.float32).reshape(-1))
+        if a.size != k:
+            raise ValueError(f"expected {k} values, got {a.size}")
+        return a
+    P = m.n_heads
+    a = [arr(in_shift, 6), arr(in_scale, 6), arr(out_shift, 5 * P), arr(out_scale, 5 * P)]
+    fp = C.POINTER(C.c_float)
+    N.check(N.lib().lt_map_set_norm(m.handle, *[x.ctypes.data_as(fp) for x in a]))
+
+
+def empty_map_out(n_heads: int, n: int, device="cuda") -> Dict:
+    torch = _torch()
+    out = {}
+    for k in MAP_FIELDS:
+        out[k] = torch.empty((n_heads, n), dtype=torch.uint8 if k == "mask" else torch.float32,
+                             device=device)
+    return out
+
+
+def lt_map_eval(m: Map, dtype: int, rays: Dict, out: Optional[Dict] = None,
+                n: Optional[int] = None, stream=None) -> Dict:
+    """Evaluate the map for ``n`` rays; outputs are (n_heads, n) tensors."""
+    torch = _torch()
+    if n is None:
+        n = int(rays["x"].numel())
+    if out is None:
+        out = empty_map_out(m.n_heads, n, rays["x"].device)
+    o = N.lt_map_out()
+    for k in MAP_FIELDS:
+        dt = torch.uint8 if k == "mask" else torch.float32
+        t = out[k]
+        if n and (t.dim() != 2 or t.shape[0] != m.n_heads or t.shape[1] != n):
+            raise ValueError(f"out[{k}] must have shape ({m.n_heads}, {n})")
+        setattr(o, k, _dev_ptr(t, dt, m.n_heads * n, f"out[{k}]") if n else None)
+    N.check(N.lib().lt_map_eval(m.handle, int(dtype), C.byref(_rays_struct(rays, n)), C.byref(o),
+                                int(n), C.c_void_p(_stream_ptr(stream) if n else 0)))
+    return out

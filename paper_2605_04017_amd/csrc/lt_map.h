@@ -1,0 +1,52 @@
+// Internal declarations of the lens transport map (classifier + regressor
+// network, Sec. 4.2 of the paper) for liblt.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "lt.h"
+#include "lt_internal.h"
+
+namespace lt {
+
+constexpr int kMapOut = 6;        // logit, x, y, dx, dy, throughput
+constexpr int kHeadSlots = 8;     // rows reserved per head in the output layer
+constexpr int kFragBytes = 1024;  // one 16x32 bf16 (or 16x128 fp8 half) MFMA operand fragment
+constexpr int kMaxLds = 160 * 1024;
+
+struct MapLayout {
+    // sizes
+    int32_t H = 0, D = 0, P = 0, act = 0;
+    int64_t n_params = 0;
+    int32_t T = 0;    // M-tiles per hidden layer (H / 16)
+    int32_t C = 0;    // K-chunks of 32 per hidden layer (H / 32)
+    int32_t TO = 0;   // M-tiles of the output layer (ceil(P * 8 / 16))
+    // offsets into the flat FP32 parameter vector
+    int64_t w_off[16], b_off[16];
+    // BF16 fragment image (bytes)
+    int64_t img_w0 = 0, img_hidden = 0, img_out = 0, img_bias = 0, img_bytes = 0;
+    int64_t out_in_lds_bytes = 0;  // image bytes staged in LDS (everything, or all but the output layer)
+    // FP8 image: hidden layers as 16x128 fp8 fragments
+    int64_t img8_hidden = 0, img8_bytes = 0;
+};
+
+struct Map {
+    lt_map_desc desc{};
+    MapLayout lay;
+    float *master = nullptr;      // FP32 parameters (n_params)
+    float *norm = nullptr;        // in_shift[6], in_scale[6], out_shift[5P], out_scale[5P]
+    uint8_t *img_bf16 = nullptr;  // packed BF16 image
+    uint8_t *img_fp8 = nullptr;   // packed FP8 image (hidden layers) + scales
+    float *fp8_scales = nullptr;  // per hidden layer: 1 / (s_w * s_h), s_h
+    float *adam_m = nullptr, *adam_v = nullptr;
+    uint64_t version = 0;         // bumped by every parameter write
+    uint64_t packed_bf16 = ~0ull, packed_fp8 = ~0ull;
+    bool has_params = false;
+};
+
+Map *as_map(lt_map h);
+MapLayout make_layout(const lt_map_desc &d);
+
+}  // namespace lt

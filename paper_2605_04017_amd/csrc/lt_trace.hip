@@ -1,0 +1,81 @@
+// Brute-force sequential lens tracer for gfx950 (Sec. 3, composite operator).
+//
+// One ray per lane.  Rays arrive as structure-of-arrays FP32 streams, so each
+// wavefront reads and writes 64 consecutive floats per field (coalesced).  The
+// path's interaction table (curvatures, apertures, media, z shifts) is the
+// same for every lane of a launch: it travels in the kernel-argument segment
+// and is read with scalar loads, so the per-step loop branches uniformly on
+// the interaction type; lanes whose ray dies leave the loop early and the
+// wave retires once its execution mask is empty.
+#include <hip/hip_runtime.h>
+
+#include "lt_internal.h"
+#include "lt_trace_core.h"
+
+namespace lt {
+
+constexpr int kTraceBlock = 256;
+
+template <bool kFast>
+__global__ __launch_bounds__(kTraceBlock) void trace_kernel(
+    TraceTable T, const float *__restrict__ x, const float *__restrict__ y,
+    const float *__restrict__ dx, const float *__restrict__ dy, const float *__restrict__ dz,
+    const float *__restrict__ lam, uint8_t *__restrict__ mask, float *__restrict__ ox,
+    float *__restrict__ oy, float *__restrict__ odx, float *__restrict__ ody,
+    float *__restrict__ odz, float *__restrict__ othr, int64_t n)
+{
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * kTraceBlock + threadIdx.x;
+    if (r >= n)
+        return;
+    const RayOut o = kFast ? trace_one_fast(T, x[r], y[r], dx[r], dy[r], dz[r], lam[r])
+                           : trace_one_ff(T, x[r], y[r], dx[r], dy[r], dz[r], lam[r]);
+    const float nan = __builtin_nanf("");
+    mask[r] = o.valid ? 1 : 0;
+    ox[r] = o.valid ? o.x : nan;
+    oy[r] = o.valid ? o.y : nan;
+    odx[r] = o.valid ? o.dx : nan;
+    ody[r] = o.valid ? o.dy : nan;
+    odz[r] = o.valid ? o.dz : nan;
+    othr[r] = o.valid ? o.I : 0.0f;
+}
+
+}  // namespace lt
+
+using namespace lt;
+
+extern "C" lt_status lt_trace_ex(lt_lens lens, const lt_path *path, const lt_rays *rays,
+                                 const lt_exit *out, int64_t n, uint32_t flags, void *stream)
+{
+    Lens *L = as_lens(lens);
+    if (!L || !path || !rays || !out)
+        return fail(LT_ERR_ARG, "NULL lens, path, rays or out");
+    if (n < 0)
+        return fail(LT_ERR_ARG, "negative ray count");
+    if (flags & ~static_cast<uint32_t>(LT_TRACE_PLAIN_FP32))
+        return fail(LT_ERR_ARG, "unknown trace flag");
+    TraceTable table;
+    lt_status st = build_trace_table(*L, *path, &table);
+    if (st != LT_OK)
+        return st;
+    if (n == 0)
+        return LT_OK;
+    if (!rays->x || !rays->y || !rays->dx || !rays->dy || !rays->dz || !rays->lambda_nm)
+        return fail(LT_ERR_ARG, "NULL ray field");
+    if (!out->mask || !out->x || !out->y || !out->dx || !out->dy || !out->dz || !out->throughput)
+        return fail(LT_ERR_ARG, "NULL output field");
+    const int64_t blocks = (n + kTraceBlock - 1) / kTraceBlock;
+    if (blocks > 0x7fffffffLL)
+        return fail(LT_ERR_ARG, "too many rays for one launch");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    auto kern = (flags & LT_TRACE_PLAIN_FP32) ? trace_kernel<true> : trace_kernel<false>;
+    hipLaunchKernelGGL(kern, dim3(static_cast<uint32_t>(blocks)), dim3(kTraceBlock), 0, s, table,
+                       rays->x, rays->y, rays->dx, rays->dy, rays->dz, rays->lambda_nm, out->mask,
+                       out->x, out->y, out->dx, out->dy, out->dz, out->throughput, n);
+    return check_hip(hipGetLastError(), "trace_kernel launch");
+}
+
+extern "C" lt_status lt_trace(lt_lens lens, const lt_path *path, const lt_rays *rays,
+                              const lt_exit *out, int64_t n, void *stream)
+{
+    return lt_trace_ex(lens, path, rays, out, n, 0u, stream);
+}

@@ -1,0 +1,373 @@
+// Per-ray sequential trace (Sec. 3: positional operator p, directional
+// operator d and Fresnel factor f, composed along the path).  Written once as
+// __host__ __device__ functions so the arithmetic can be inspected on the CPU;
+// the product runs them only inside the HIP kernels of lt_trace.hip.
+//
+// Two variants:
+//   trace_one_ff   -- the library's tracer.  Geometry (positions, directions,
+//                     normals, refractive indices, cosines) is carried as
+//                     float pairs (lt_ff.h), so the FP32 instruction stream
+//                     keeps about 44 bits; each hit is refined by one Newton
+//                     step on the sphere equation.  Fresnel factors are plain
+//                     FP32.  Sensor-side rays leave a camera lens nearly
+//                     collimated, so exit positions are about EFL-times more
+//                     sensitive to direction errors near the sensor; plain
+//                     FP32 rounding there already costs ~1e-5 mm.
+//   trace_one_fast -- the same operators in plain FP32 (one rounding per
+//                     operation), with FP64 only for the discriminant of
+//                     near-flat surfaces and the transmitted cosine near
+//                     grazing incidence.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "lt_ff.h"
+#include "lt_internal.h"
+
+namespace lt {
+
+struct RayOut {
+    float x, y, dx, dy, dz, I;
+    bool valid;
+};
+
+// ------------------------------------------------------------ dispersion --
+
+// Plain FP32 index of glass g; l2 = lambda^2, il2 = 1/lambda^2 (micrometres).
+__host__ __device__ __forceinline__ float glass_n_f(const GlassF &g, float l2, float il2)
+{
+    if (g.kind == 1)
+        return fmaf(il2, fmaf(il2, g.k[4], g.k[2]), g.k[0]);
+    if (g.kind == 2) {
+        float s = 1.0f;
+        s += g.k[0] * l2 / (l2 - g.k[6]);
+        s += g.k[2] * l2 / (l2 - g.k[8]);
+        s += g.k[4] * l2 / (l2 - g.k[10]);
+        return sqrtf(s);
+    }
+    return 1.0f;
+}
+
+// Double-word index of glass g (Cauchy: A + B/l^2 + C/l^4; Sellmeier:
+// sqrt(1 + sum B_i l^2 / (l^2 - C_i))).
+__host__ __device__ __forceinline__ ff glass_n_ff(const GlassF &g, ff l2, ff il2)
+{
+    if (g.kind == 1) {
+        const ff A{g.k[0], g.k[1]}, B{g.k[2], g.k[3]}, C{g.k[4], g.k[5]};
+        return ff_add(A, ff_mul(il2, ff_add(B, ff_mul(C, il2))));
+    }
+    if (g.kind == 2) {
+        ff s = ff_make(1.0f);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const ff Bi{g.k[2 * i], g.k[2 * i + 1]}, Ci{g.k[6 + 2 * i], g.k[7 + 2 * i]};
+            s = ff_add(s, ff_div(ff_mul(Bi, l2), ff_sub(l2, Ci)));
+        }
+        return ff_sqrt(s);
+    }
+    return ff_make(1.0f);
+}
+
+// Below this value of 1 - eta^2 sin^2(theta_i) the plain-FP32 tracer
+// recomputes the transmitted cosine in FP64 (near grazing / critical angle).
+constexpr float kGrazingK = 1.0e-2f;
+
+// Closest root of c t^2 + 2 B t + E = 0 on the hemisphere that contains the
+// vertex (c q_z < 1) lying ahead of the previous point (t0 + t > 0).  Both
+// roots come from the cancellation-free pair E/qd and qd/c.  Returns +inf for
+// a miss.
+__host__ __device__ __forceinline__ float sphere_root(float B, float E, float disc, float c,
+                                                      float R, float pz, float dz, float t0)
+{
+    if (!(disc >= 0.0f))
+        return INFINITY;
+    const float sq = sqrtf(disc);
+    const float qd = -B - (B >= 0.0f ? sq : -sq);
+    float t = INFINITY;
+    if (qd != 0.0f) {
+        const float ta = E / qd;
+        if (t0 + ta > 0.0f && c * fmaf(ta, dz, pz) < 1.0f)
+            t = ta;
+    }
+    if (c != 0.0f) {
+        const float tb = qd * R;
+        if (t0 + tb > 0.0f && tb < t && c * fmaf(tb, dz, pz) < 1.0f)
+            t = tb;
+    }
+    return t;
+}
+
+// ------------------------------------------------------ compensated trace --
+
+__host__ __device__ __forceinline__ RayOut trace_one_ff(const TraceTable &T, float x, float y,
+                                                        float dx0, float dy0, float dz0,
+                                                        float lam_nm)
+{
+    RayOut o;
+    o.valid = false;
+    // unit input direction (double-word)
+    ff dx, dy, dz;
+    {
+        const ff n2 = ff_add(ff_add(two_prod(dx0, dx0), two_prod(dy0, dy0)), two_prod(dz0, dz0));
+        const ff nrm = ff_sqrt(n2);
+        dx = ff_div(ff_make(dx0), nrm);
+        dy = ff_div(ff_make(dy0), nrm);
+        dz = ff_div(ff_make(dz0), nrm);
+    }
+    const ff lum = ff_div(ff_make(lam_nm), ff_make(1000.0f));
+    const ff l2 = ff_sqr(lum);
+    const ff il2 = ff_div(ff_make(1.0f), l2);
+    ff ncur = T.glass_start == kAirCode ? ff_make(1.0f) : glass_n_ff(T.glass[T.glass_start], l2, il2);
+    ff px = ff_make(x), py = ff_make(y), pz = ff_make(0.0f);
+    float I = 1.0f;
+    const int nsteps = T.nsteps;
+    for (int s = 0; s < nsteps; ++s) {
+        const StepGeom G = T.geom[s];
+        const uint32_t code = T.code[s];
+        const int type = code & 0xF;
+        const uint32_t g2 = (code >> 4) & 0xFF;
+        const ff c{G.c_h, G.c_l};
+        pz = ff_add(pz, ff{G.zs_h, G.zs_l});
+
+        // --- positional operator: first guess in FP32 from the leading words
+        const float ch = G.c_h;
+        float t0 = 0.0f;
+        float xh = px.h, yh = py.h, zh = pz.h;
+        if (fabsf(dz.h) > 1.0e-3f) {
+            // via the vertex tangent plane: the long transfer only slides the
+            // point along the ray
+            t0 = -zh / dz.h;
+            xh = fmaf(t0, dx.h, xh);
+            yh = fmaf(t0, dy.h, yh);
+            zh = fmaf(t0, dz.h, zh);
+        }
+        const float od = fmaf(xh, dx.h, fmaf(yh, dy.h, zh * dz.h));
+        const float oo = fmaf(xh, xh, fmaf(yh, yh, zh * zh));
+        const float B = fmaf(ch, od, -dz.h);
+        const float E = fmaf(ch, oo, -2.0f * zh);
+        const float t1 = sphere_root(B, E, fmaf(B, B, -ch * E), ch, G.R, zh, dz.h, t0);
+        if (!(t1 < INFINITY))
+            return o;
+        const float t = t0 + t1;
+        // hit point in double-word, then one Newton step on F(q) = c|q|^2 - 2 q_z
+        ff qx = ff_add(px, ff_mul_f(dx, t));
+        ff qy = ff_add(py, ff_mul_f(dy, t));
+        ff qz = ff_add(pz, ff_mul_f(dz, t));
+        {
+            const ff q2 = ff_add(ff_add(ff_sqr(qx), ff_sqr(qy)), ff_sqr(qz));
+            const ff F = ff_sub(ff_mul(c, q2), ff_add(qz, qz));
+            const float g = fmaf(ch, fmaf(qx.h, dx.h, fmaf(qy.h, dy.h, qz.h * dz.h)), -dz.h);
+            const float dt = -F.h / (2.0f * g);
+            if (g != 0.0f) {
+                qx = ff_add_f(qx, dt * dx.h);
+                qy = ff_add_f(qy, dt * dy.h);
+                qz = ff_add_f(qz, dt * dz.h);
+            }
+        }
+        // clear aperture (closed disk), decided in double-word
+        {
+            const ff h2 = ff_add(ff_sqr(qx), ff_sqr(qy));
+            const ff m = ff_sub(h2, ff{G.sd2_h, G.sd2_l});
+            if (!(m.h <= 0.0f))  // also rejects NaN
+                return o;
+        }
+        px = qx;
+        py = qy;
+        pz = qz;
+        if (type == kStepStop)
+            continue;
+
+        // --- normal of the sphere through the vertex, against the ray
+        ff nx = ff_mul(c, qx), ny = ff_mul(c, qy), nz = ff_add_f(ff_mul(c, qz), -1.0f);
+        ff dn = ff_add(ff_add(ff_mul(nx, dx), ff_mul(ny, dy)), ff_mul(nz, dz));
+        if (dn.h > 0.0f) {
+            nx = ff_neg(nx);
+            ny = ff_neg(ny);
+            nz = ff_neg(nz);
+            dn = ff_neg(dn);
+        }
+        const ff ci = ff_neg(dn);
+        const ff n2 = g2 == kAirCode ? ff_make(1.0f) : glass_n_ff(T.glass[g2], l2, il2);
+        const ff n1 = ncur;
+        const ff eta = ff_div(n1, n2);
+        const ff sin2 = ff_sub(ff_make(1.0f), ff_sqr(ci));
+        const ff k = ff_sub(ff_make(1.0f), ff_mul(ff_sqr(eta), sin2));
+        const bool tir = k.h < 0.0f;
+        const ff ct = tir ? ff_make(0.0f) : ff_sqrt(k);
+        // Fresnel factors in FP32 from the leading words
+        const float a1 = n1.h * ci.h, b2 = n2.h * ct.h;  // s-polarisation terms
+        const float a2 = n2.h * ci.h, b1 = n1.h * ct.h;  // p-polarisation terms
+        if (type == kStepT) {
+            if (tir)
+                return o;
+            // --- directional operator: vector Snell
+            const ff a = ff_sub(ff_mul(eta, ci), ct);
+            dx = ff_add(ff_mul(eta, dx), ff_mul(a, nx));
+            dy = ff_add(ff_mul(eta, dy), ff_mul(a, ny));
+            dz = ff_add(ff_mul(eta, dz), ff_mul(a, nz));
+            // --- Fresnel: unpolarised transmittance, 2ab/(a+b)^2 over s and p
+            const float ss = a1 + b2, pp = a2 + b1;
+            I *= 2.0f * (a1 * b2 / (ss * ss) + a2 * b1 / (pp * pp));
+            ncur = n2;
+        } else {
+            // --- directional operator: mirror reflection
+            const ff a = ff_add(ci, ci);
+            dx = ff_add(dx, ff_mul(a, nx));
+            dy = ff_add(dy, ff_mul(a, ny));
+            dz = ff_add(dz, ff_mul(a, nz));
+            float R = 1.0f;
+            if (!tir) {
+                const float rs = (a1 - b2) / (a1 + b2);
+                const float rp = (a2 - b1) / (a2 + b1);
+                R = 0.5f * fmaf(rs, rs, rp * rp);
+            }
+            I *= R;
+        }
+        // |n| = 1 on the sphere and |d| = 1, so both updates keep |d| = 1 to
+        // double-word accuracy; no renormalisation is needed.
+    }
+    // output plane, reached along the signed line
+    if (!(dz.h < 0.0f))
+        return o;
+    const ff t = ff_div(ff_sub(ff{T.z_exit_h, T.z_exit_l}, pz), dz);
+    o.x = ff_to_f(ff_add(px, ff_mul(t, dx)));
+    o.y = ff_to_f(ff_add(py, ff_mul(t, dy)));
+    o.dx = ff_to_f(dx);
+    o.dy = ff_to_f(dy);
+    o.dz = ff_to_f(dz);
+    o.I = I;
+    o.valid = true;
+    return o;
+}
+
+// ------------------------------------------------------------ plain FP32 --
+
+__host__ __device__ __forceinline__ RayOut trace_one_fast(const TraceTable &T, float x, float y,
+                                                          float dx, float dy, float dz,
+                                                          float lam_nm)
+{
+    RayOut o;
+    o.valid = false;
+    {
+        const float inv = 1.0f / sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+        dx *= inv;
+        dy *= inv;
+        dz *= inv;
+    }
+    const float lum = lam_nm * 1.0e-3f;
+    const float l2 = lum * lum;
+    const float il2 = 1.0f / l2;
+    float ncur = T.glass_start == kAirCode ? 1.0f : glass_n_f(T.glass[T.glass_start], l2, il2);
+    float px = x, py = y, pz = 0.0f;
+    float I = 1.0f;
+    const int nsteps = T.nsteps;
+    for (int s = 0; s < nsteps; ++s) {
+        const StepGeom G = T.geom[s];
+        const uint32_t code = T.code[s];
+        const int type = code & 0xF;
+        const uint32_t g2 = (code >> 4) & 0xFF;
+        pz += G.zs_h;
+        const float c = G.c_h;
+        float t0 = 0.0f;
+        if (fabsf(dz) > 1.0e-3f) {
+            t0 = -pz / dz;
+            px = fmaf(t0, dx, px);
+            py = fmaf(t0, dy, py);
+            pz = fmaf(t0, dz, pz);
+        }
+        const float od = fmaf(px, dx, fmaf(py, dy, pz * dz));
+        const float oo = fmaf(px, px, fmaf(py, py, pz * pz));
+        const float B = fmaf(c, od, -dz);
+        const float E = fmaf(c, oo, -2.0f * pz);
+        float disc;
+        if (code & (kFlagF64Disc << 12)) {
+            const double Bd = (double)c * ((double)px * dx + (double)py * dy + (double)pz * dz) - dz;
+            const double Ed = (double)c * ((double)px * px + (double)py * py + (double)pz * pz) - 2.0 * pz;
+            disc = (float)(Bd * Bd - (double)c * Ed);
+        } else {
+            disc = fmaf(B, B, -c * E);
+        }
+        const float t = sphere_root(B, E, disc, c, G.R, pz, dz, t0);
+        if (!(t < INFINITY))
+            return o;
+        const float qx = fmaf(t, dx, px);
+        const float qy = fmaf(t, dy, py);
+        const float qz = fmaf(t, dz, pz);
+        if (!(fmaf(qx, qx, qy * qy) <= G.sd2_h))  // also rejects NaN
+            return o;
+        px = qx;
+        py = qy;
+        pz = qz;
+        if (type == kStepStop)
+            continue;
+        float nx = c * qx, ny = c * qy, nz = fmaf(c, qz, -1.0f);
+        float dn = fmaf(nx, dx, fmaf(ny, dy, nz * dz));
+        if (dn > 0.0f) {
+            nx = -nx;
+            ny = -ny;
+            nz = -nz;
+            dn = -dn;
+        }
+        const float ci = -dn;
+        const float n2 = g2 == kAirCode ? 1.0f : glass_n_f(T.glass[g2], l2, il2);
+        const float n1 = ncur;
+        const float eta = n1 / n2;
+        const float sin2 = (1.0f - ci) * (1.0f + ci);
+        const float k = fmaf(-eta * eta, sin2, 1.0f);
+        float ct;
+        bool tir;
+        if (k < kGrazingK) {
+            const double kd = 1.0 - (double)eta * (double)eta * (1.0 - (double)ci * (double)ci);
+            tir = kd < 0.0;
+            ct = tir ? 0.0f : (float)sqrt(kd);
+        } else {
+            tir = false;
+            ct = sqrtf(k);
+        }
+        const float a1 = n1 * ci, b2 = n2 * ct;
+        const float a2 = n2 * ci, b1 = n1 * ct;
+        if (type == kStepT) {
+            if (tir)
+                return o;
+            const float a = fmaf(eta, ci, -ct);
+            dx = fmaf(eta, dx, a * nx);
+            dy = fmaf(eta, dy, a * ny);
+            dz = fmaf(eta, dz, a * nz);
+            const float ss = a1 + b2, pp = a2 + b1;
+            I *= 2.0f * (a1 * b2 / (ss * ss) + a2 * b1 / (pp * pp));
+            ncur = n2;
+        } else {
+            const float a = 2.0f * ci;
+            dx = fmaf(a, nx, dx);
+            dy = fmaf(a, ny, dy);
+            dz = fmaf(a, nz, dz);
+            float R = 1.0f;
+            if (!tir) {
+                const float rs = (a1 - b2) / (a1 + b2);
+                const float rp = (a2 - b1) / (a2 + b1);
+                R = 0.5f * fmaf(rs, rs, rp * rp);
+            }
+            I *= R;
+        }
+        const float inv = 1.0f / sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+        dx *= inv;
+        dy *= inv;
+        dz *= inv;
+    }
+    if (!(dz < 0.0f))
+        return o;
+    const float t = (T.z_exit_h - pz) / dz;
+    o.x = fmaf(t, dx, px);
+    o.y = fmaf(t, dy, py);
+    o.dx = dx;
+    o.dy = dy;
+    o.dz = dz;
+    o.I = I;
+    o.valid = true;
+    return o;
+}
+
+}  // namespace lt

@@ -1,0 +1,131 @@
+"""The C-ABI library loads, exports every symbol include/lt.h declares, and
+its host-side logic (validation, error codes, path bookkeeping) behaves as
+documented.  No GPU work is launched here."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2605_04017_amd as lt
+import synth
+from paper_2605_04017_amd import _native as N
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "lt.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lt_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_header_symbols():
+    names = header_functions()
+    assert "lt_trace" in names and "lt_lens_create" in names
+    out = subprocess.run(["nm", "-D", "--defined-only", N.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (lt_[a-z0-9_]+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    L = N.lib()
+    for n in names:
+        assert hasattr(L, n)
+    # the binding declares a signature for every header function
+    assert set(names) <= set(N.SIGNATURES)
+
+
+def test_status_strings():
+    L = N.lib()
+    assert L.lt_status_str(0) == b"LT_OK"
+    assert L.lt_status_str(2) == b"LT_ERR_LENS"
+    assert L.lt_version() >= 100
+
+
+def test_lens_create_and_query():
+    lens = synth.config_lens(2)
+    h = lt.lt_lens_create(lens.surfaces, lens.glasses)
+    assert (h.n_surfaces, h.n_refracting, h.n_ghost_paths) == (12, 11, 55)
+    assert lt.lt_lens_query(h) == (12, 11, 55)
+    h.close()
+
+
+@pytest.mark.parametrize("mutate,msg", [
+    (lambda s, g: s[0].__setattr__("thickness", -1.0), "negative thickness"),
+    (lambda s, g: s[0].__setattr__("semi_diameter", 0.0), "semi-diameter"),
+    (lambda s, g: s[0].__setattr__("semi_diameter", abs(s[0].radius) * 1.01), "smaller than"),
+    (lambda s, g: s[0].__setattr__("glass_after", 99), "glass index"),
+    (lambda s, g: s[5].__setattr__("radius", 50.0), "flat"),
+    (lambda s, g: s[1].__setattr__("is_stop", 1), "stop"),
+    (lambda s, g: g[1].coef.__setitem__(0, 0.2), "index not real"),
+])
+def test_lens_validation(mutate, msg):
+    import copy
+    lens = copy.deepcopy(synth.config_lens(2))
+    mutate(lens.surfaces, lens.glasses)
+    with pytest.raises(lt.LtError) as e:
+        lt.lt_lens_create(lens.surfaces, lens.glasses)
+    assert e.value.status in (N.LT_ERR_LENS, N.LT_ERR_ARG)
+    assert msg in str(e.value)
+
+
+def test_lens_limits():
+    lens = synth.config_lens(1)
+    with pytest.raises(lt.LtError) as e:
+        lt.lt_lens_create([], lens.glasses)
+    assert e.value.status == N.LT_ERR_ARG
+    too_many = [lens.surfaces[1]] * (N.LT_MAX_SURFACES + 1)
+    with pytest.raises(lt.LtError):
+        lt.lt_lens_create(too_many, lens.glasses)
+
+
+def test_ghost_index_roundtrip():
+    for n in (2, 3, 11, 22):
+        seen = set()
+        for j in range(1, n + 1):
+            for i in range(j + 1, n + 1):
+                k = lt.lt_ghost_index(n, j, i)
+                assert 0 <= k < n * (n - 1) // 2
+                assert lt.lt_ghost_path(n, k) == (1, j, i)
+                seen.add(k)
+        assert len(seen) == n * (n - 1) // 2
+    assert lt.lt_ghost_index(11, 3, 3) == -1
+    with pytest.raises(lt.LtError):
+        lt.lt_ghost_path(11, 55)
+
+
+def test_trace_argument_errors_without_gpu():
+    lens = synth.config_lens(2)
+    h = lt.lt_lens_create(lens.surfaces, lens.glasses)
+    L = N.lib()
+    rays, ex = N.lt_rays(), N.lt_exit()
+    # bad path is reported before any device work
+    p = N.lt_path(1, 5, 5)
+    assert L.lt_trace(h.handle, C.byref(p), C.byref(rays), C.byref(ex), 10, None) == N.LT_ERR_PATH
+    p = N.lt_path(0, 0, 0)
+    # n = 0 is a no-op, negative n and NULL fields are argument errors
+    assert L.lt_trace(h.handle, C.byref(p), C.byref(rays), C.byref(ex), 0, None) == N.LT_OK
+    assert L.lt_trace(h.handle, C.byref(p), C.byref(rays), C.byref(ex), -1, None) == N.LT_ERR_ARG
+    assert L.lt_trace(h.handle, C.byref(p), C.byref(rays), C.byref(ex), 5, None) == N.LT_ERR_ARG
+    assert b"NULL" in L.lt_last_error()
+    assert L.lt_trace(None, C.byref(p), C.byref(rays), C.byref(ex), 5, None) == N.LT_ERR_ARG
+    assert L.lt_trace_ex(h.handle, C.byref(p), C.byref(rays), C.byref(ex), 0, 0x80, None) == N.LT_ERR_ARG
+
+
+@pytest.mark.parametrize("desc", [(5, 128, 5, 1, 0), (6, 100, 5, 1, 0), (6, 128, 0, 1, 0),
+                                  (6, 128, 9, 1, 0), (6, 128, 5, 0, 0), (6, 128, 5, 65, 0),
+                                  (6, 128, 5, 1, 7)])
+def test_map_desc_validation(desc):
+    """Bad shapes are rejected before any device allocation."""
+    d = N.lt_map_desc(*desc)
+    h = C.c_void_p()
+    assert N.lib().lt_map_create(C.byref(d), C.byref(h)) == N.LT_ERR_ARG
+    assert h.value is None
+
+
+def test_map_null_handles():
+    L = N.lib()
+    assert L.lt_map_num_params(None) == -1
+    assert L.lt_map_eval(None, 1, None, None, 0, None) == N.LT_ERR_ARG
+    assert L.lt_map_destroy(None) == N.LT_OK

@@ -1,0 +1,151 @@
+"""GPU parity of the brute-force tracer (lt_trace) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+from parity import compare_trace, to_numpy
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch.device("cuda:0")
+
+
+def _to_dev(rays, dev):
+    import torch
+    return {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in rays.items()}
+
+
+def _gpu_trace(lens, rays, dev, path=(0, 0, 0), flags=0):
+    import torch
+    import paper_2605_04017_amd as lt
+    h = lt.lt_lens_create(lens.surfaces, lens.glasses)
+    r = _to_dev(rays, dev)
+    n = int(rays["x"].shape[0])
+    out = lt.empty_exit(n, dev)
+    if flags:
+        lt.lt_trace_ex(h, path, r, out, n, flags)
+    else:
+        lt.lt_trace(h, path, r, out, n)
+    torch.cuda.synchronize()
+    return to_numpy(out)
+
+
+def _report(name, st):
+    print(f"[parity] {name}: {st}", flush=True)
+
+
+def test_c1_doublet_full(dev):
+    """Cemented doublet + stop, 65,536 rays: transmit and all three ghosts."""
+    L = synth.config_lens(1)
+    rays = synth.config_rays(1)
+    for path in [(0, 0, 0), (1, 1, 2), (1, 1, 3), (1, 2, 3)]:
+        st = compare_trace(_gpu_trace(L, rays, dev, path), oracle.trace(L, rays, path, diag=True))
+        _report(f"C1 {path}", st)
+        assert st["valid"] > 1000
+
+
+def test_c2_double_gauss_full_size(dev):
+    """11-surface lens, 4,194,304 rays (the benchmark workload), transmit,
+    every ray compared."""
+    L = synth.config_lens(2)
+    rays = synth.config_rays(2)
+    st = compare_trace(_gpu_trace(L, rays, dev), oracle.trace(L, rays, diag=True))
+    _report("C2 transmit 4M", st)
+    assert st["valid"] > 500000
+
+
+def test_c2_all_55_ghosts(dev):
+    L = synth.config_lens(2)
+    rays = synth.config_rays(2, 131072)
+    worst = 0.0
+    for j in range(1, 12):
+        for i in range(j + 1, 12):
+            st = compare_trace(_gpu_trace(L, rays, dev, (1, j, i)),
+                               oracle.trace(L, rays, (1, j, i), diag=True))
+            worst = max(worst, st.get("pos_max", 0.0))
+    print(f"[parity] C2 55 ghosts worst position error {worst:.3e} mm", flush=True)
+
+
+def test_c3_size_sampled(dev):
+    """16,777,216 rays traced in one launch; every 16th ray compared."""
+    L = synth.config_lens(3)
+    rays = synth.config_rays(3)
+    sel = np.arange(0, rays["x"].shape[0], 16)
+    sub = {k: v[sel] for k, v in rays.items()}
+    for path in [(0, 0, 0), (1, 2, 9)]:
+        g = _gpu_trace(L, rays, dev, path)
+        st = compare_trace(g, oracle.trace(L, sub, path, diag=True), sel=sel)
+        _report(f"C3 16M {path} sampled", st)
+
+
+def test_serving_lenses(dev):
+    """The eight mixed lenses (4..22 surfaces, Cauchy and Sellmeier glasses)."""
+    for L in synth.serve_lenses():
+        rays = synth.make_rays(L, 32768, 4242)
+        nr = L.n_refracting
+        for path in [(0, 0, 0), (1, 1, nr), (1, nr // 2, nr // 2 + 1)]:
+            st = compare_trace(_gpu_trace(L, rays, dev, path), oracle.trace(L, rays, path, diag=True))
+        _report(L.name, st)
+
+
+@pytest.mark.parametrize("n", [1, 63, 257, 1000])
+def test_ragged_sizes(dev, n):
+    L = synth.config_lens(2)
+    rays = synth.make_rays(L, n, 17)
+    compare_trace(_gpu_trace(L, rays, dev), oracle.trace(L, rays, diag=True))
+
+
+def test_empty_launch(dev):
+    import torch
+    import paper_2605_04017_amd as lt
+    L = synth.config_lens(2)
+    h = lt.lt_lens_create(L.surfaces, L.glasses)
+    r = _to_dev(synth.make_rays(L, 4, 1), dev)
+    out = lt.lt_trace(h, (0, 0, 0), r, None, n=0)
+    torch.cuda.synchronize()
+    assert out["x"].numel() == 0
+
+
+def test_degenerate_rays(dev):
+    """On-axis ray, rays pointing away from the lens, NaN and zero directions:
+    no crash, the invalid ones get mask 0."""
+    L = synth.config_lens(2)
+    f = np.float32
+    rays = {"x": np.array([0, 1, 0, np.nan, 2, 0], f), "y": np.array([0, 1, 0, 0, 1, 0], f),
+            "dx": np.array([0, 0, 0, 0, 0, 0.1], f), "dy": np.array([0, 0, 0, 0, 0, 0], f),
+            "dz": np.array([-1, 1, 0, -1, -1, np.nan], f),
+            "lambda_nm": np.array([550, 550, 550, 550, 550, 550], f)}
+    g = _gpu_trace(L, rays, dev)
+    o = oracle.trace(L, rays, diag=True)
+    assert g["mask"][0] == 1 and abs(g["x"][0]) < 1e-7 and abs(g["y"][0]) < 1e-7
+    assert list(g["mask"][1:4]) == [0, 0, 0] and g["mask"][5] == 0
+    assert g["mask"][4] == o["mask"][4]
+    assert abs(g["throughput"][0] - o["throughput"][0]) < 1e-6
+
+
+def test_deterministic(dev):
+    L = synth.config_lens(2)
+    rays = synth.make_rays(L, 100000, 9)
+    a = _gpu_trace(L, rays, dev, (1, 3, 8))
+    b = _gpu_trace(L, rays, dev, (1, 3, 8))
+    for k in a:
+        assert np.array_equal(a[k], b[k], equal_nan=True)
+
+
+def test_plain_fp32_variant(dev):
+    """The plain-FP32 option: same masks outside the boundary band; its
+    exit errors are larger and are checked against looser bounds derived from
+    FP32 rounding amplified along the path (5e-4 mm, 2e-6 rad)."""
+    L = synth.config_lens(2)
+    rays = synth.config_rays(2, 262144)
+    for path in [(0, 0, 0), (1, 1, 2), (1, 10, 11)]:
+        st = compare_trace(_gpu_trace(L, rays, dev, path, flags=1),
+                           oracle.trace(L, rays, path, diag=True), pos_tol=5e-4, ang_tol=2e-6)
+        _report(f"plain FP32 {path}", st)
