@@ -1,15 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark of the lens transport hot path on one MI355X.
 
-Workload: the 11-surface double-Gauss-style lens with 4,194,304 sensor-side
-rays (sensor uniform on 36 x 24 mm, directions uniform toward the rear
-element, wavelength uniform in 400..700 nm), inputs resident in HBM.  One
-step = one pass of the hot path over the batch: the brute-force trace of the
-transmit path (lt_trace) and, when a map is available, its fused network
-evaluation (lt_map_eval).
+Workload: the 11-surface double-Gauss-style lens (seeded prescription and
+Cauchy glasses) with 4,194,304 sensor-side rays (sensor point uniform on
+the 36 x 24 mm frame, direction uniform toward the rear element, wavelength
+uniform in 400..700 nm), inputs resident in HBM.  The comparison it is
+quoted on: FP32 GPU brute-force trace versus FP32 map (6-D input, 5 x 128
+tanh hidden layers, mask logit + 4-D exit ray + throughput head).
 
-Prints one JSON line (see the keys below).  Kernel times are taken with HIP
-events on the stream the kernels are launched on.
+One step = one pass of the hot path over the batch: lt_trace (transmit
+path) and lt_map_eval (FP32).  `value` is the map's rays/s; the tracer's
+rays/s, their ratio, the BF16 and FP8 map rates, the map's exit-ray error
+against the FP64 oracle after a short fit on GPU-traced rays, and a serving
+run (mixed-size requests for eight lenses, p50/p99 latency) are reported in
+the same JSON line.  Kernel times come from HIP events on the stream the
+kernels run on.
 """
 from __future__ import annotations
 
@@ -24,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 N_RAYS = 4194304
 MI355X_FP32_VECTOR_TFLOPS = 157.3
+MI355X_FP32_MFMA_TFLOPS = 157.3
 MI355X_BF16_MFMA_TFLOPS = 2500.0
 MI355X_FP8_MFMA_TFLOPS = 5000.0
 MI355X_HBM_GBS = 8000.0
@@ -49,7 +55,7 @@ def trace_flops_per_ray(lens, path=(0, 0, 0)):
     else:
         j, i = path[1], path[2]
         n_t, n_r = nr + 2 * (i - j) - 2, 2
-        n_s = n_stop  # ghost paths cross the stop at least once; counted once
+        n_s = n_stop
     return 20 + 78 * n_t + 56 * n_r + 28 * n_s + 10
 
 
@@ -68,12 +74,12 @@ def cpu_baseline_map(params, rays_np, budget_s=10.0):
             break
         n *= 4
     return {"value": n / dt / 1e6, "unit": "Mrays/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n} rays, FP64 numpy forward of the 5 x 128 tanh map "
-                      f"(BLAS threads = host cores)"}
+            "sample": f"first {n} rays of the workload, FP64 numpy forward of the 5 x 128 tanh "
+                      f"map (BLAS threads = host cores)"}
 
 
-def cpu_baseline(lens, rays_np, budget_s=10.0):
-    """Time the FP64 oracle on the host cores on a bounded sample."""
+def cpu_baseline_trace(lens, rays_np, budget_s=10.0):
+    """Time the FP64 oracle tracer on the host cores on a bounded sample."""
     import oracle
     n_all = rays_np["x"].shape[0]
     threads = os.cpu_count() or 1
@@ -90,12 +96,135 @@ def cpu_baseline(lens, rays_np, budget_s=10.0):
             "sample": f"first {n} of the {n_all} rays, transmit path, FP64 C oracle, OpenMP"}
 
 
+def time_kernel(fn, stream, reps):
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps * 1e-3
+
+
+def fit_map(lt, synth, mlp, lens, dev, steps, batch=65536, seed=3002):
+    """Fit the 5 x 128 tanh map on rays the GPU tracer labels (a fresh
+    65,536-ray batch per step drawn from a 4M-ray pool that does not overlap
+    the benchmark rays).  Returns (map, params as MapParams, final loss)."""
+    import numpy as np
+    import torch
+    pool_np = synth.make_rays(lens, 4194304, seed)
+    pool = {k: torch.from_numpy(v).to(dev) for k, v in pool_np.items()}
+    h = lt.lt_lens_create(lens.surfaces, lens.glasses)
+    ex = lt.lt_trace(h, (0, 0, 0), pool)
+    ok = ex["mask"].bool()
+    reg = torch.stack([ex[k][ok] for k in ("x", "y", "dx", "dy", "throughput")], 1).double()
+    x = np.stack([pool_np[k].astype(np.float64) for k in synth.RAY_FIELDS], 1)
+    p = mlp.init_params(mlp.MapDesc(MAP_WIDTH, MAP_DEPTH, 1, mlp.ACT_TANH), 5)
+    p.in_shift, p.in_scale = x.mean(0), 1.0 / x.std(0)
+    p.out_shift = reg.mean(0).cpu().numpy()[None]
+    p.out_scale = reg.std(0).cpu().numpy()[None]
+    m = lt.lt_map_create(MAP_WIDTH, MAP_DEPTH, 1, lt.LT_ACT_TANH)
+    lt.lt_map_set_params(m, torch.from_numpy(p.flat().astype(np.float32)).to(dev))
+    lt.lt_map_set_norm(m, p.in_shift, p.in_scale, p.out_shift.reshape(-1), p.out_scale.reshape(-1))
+    ws = lt.workspace(m, batch)
+    n_pool = pool_np["x"].shape[0]
+    loss = None
+    for k in range(1, steps + 1):
+        lo = ((k - 1) * batch) % (n_pool - batch + 1)
+        rb = {f: v[lo:lo + batch] for f, v in pool.items()}
+        tb = {"valid": ex["mask"][lo:lo + batch].reshape(1, -1)}
+        for f in ("x", "y", "dx", "dy", "throughput"):
+            tb[f] = ex[f][lo:lo + batch].reshape(1, -1)
+        lr = 2e-3 * (0.5 ** (k / max(1, steps / 4)))
+        loss = lt.lt_map_train_step(m, rb, tb, {"lr": lr, "step": k, "w_bce": 1.0, "w_l2": 4.0}, ws)
+    torch.cuda.synchronize()
+    p.set_flat(lt.lt_map_get_params(m).cpu().numpy().astype(np.float64))
+    return m, p, [float(v) for v in loss.cpu()]
+
+
+def map_error(lt, oracle, lens, m, dtype, rays_np, rays_dev, n_sample=65536):
+    """Exit-ray error of the map against the FP64 oracle on the first
+    n_sample benchmark rays."""
+    import numpy as np
+    import torch
+    sub_dev = {k: v[:n_sample] for k, v in rays_dev.items()}
+    sub_np = {k: v[:n_sample] for k, v in rays_np.items()}
+    g = {k: v[0].cpu().numpy() for k, v in lt.lt_map_eval(m, dtype, sub_dev).items()}
+    torch.cuda.synchronize()
+    o = oracle.trace(lens, sub_np)
+    gm, om = g["mask"].astype(bool), o["mask"].astype(bool)
+    both = gm & om
+    pos = np.hypot(g["x"][both] - o["x"][both], g["y"][both] - o["y"][both])
+    u = np.stack([g["dx"][both], g["dy"][both], g["dz"][both]], 1).astype(np.float64)
+    v = np.stack([o["dx"][both], o["dy"][both], o["dz"][both]], 1)
+    ang = 2 * np.arcsin(np.minimum(1.0, np.linalg.norm(u - v, axis=1) / 2))
+    thr = np.abs(g["throughput"][both] - o["throughput"][both])
+    return {"mask_agreement": float(np.mean(gm == om)), "false_valid": float(np.mean(gm & ~om)),
+            "false_invalid": float(np.mean(~gm & om)),
+            "pos_mm_p50": float(np.median(pos)), "pos_mm_p99": float(np.quantile(pos, 0.99)),
+            "dir_rad_p50": float(np.median(ang)), "dir_rad_p99": float(np.quantile(ang, 0.99)),
+            "throughput_abs_p99": float(np.quantile(thr, 0.99)), "rays": n_sample}
+
+
+def serving(lt, synth, mlp, dev, n_req=600, loads=(0.5, 0.8), seed=5005):
+    """Serving run: 8 lenses (4..22 surfaces) with resident maps; Poisson
+    arrivals of 1k..1M-ray requests (log-uniform); memory-admitted
+    continuous batching on 4 streams.  Offered load relative to the
+    saturated rate measured with all requests queued at t = 0."""
+    import numpy as np
+    import torch
+    from paper_2605_04017_amd.serve import (GpuExecutor, Scheduler, latency_stats,
+                                            poisson_requests, run_trace)
+    lenses = synth.serve_lenses()
+    hl, maps, pools = [], [], []
+    for i, L in enumerate(lenses):
+        hl.append(lt.lt_lens_create(L.surfaces, L.glasses))
+        pools.append({k: torch.from_numpy(v).to(dev) for k, v in synth.make_rays(L, 1000000, 7000 + i).items()})
+        p = mlp.init_params(mlp.MapDesc(MAP_WIDTH, MAP_DEPTH, 1), 80 + i)
+        mm = lt.lt_map_create(MAP_WIDTH, MAP_DEPTH, 1)
+        lt.lt_map_set_params(mm, torch.from_numpy(p.flat().astype(np.float32)).to(dev))
+        maps.append(mm)
+    res = {}
+    for mode, dtype in (("map", lt.LT_BF16), ("map", lt.LT_F32), ("trace", 0)):
+        key = f"{mode}_{'bf16' if (mode == 'map' and dtype == lt.LT_BF16) else 'f32'}"
+        base = poisson_requests(n_req, 1.0, 8, seed)
+        sizes = [r.n for r in base]
+
+        def run(rate):
+            reqs = poisson_requests(n_req, rate, 8, seed)
+            for r in reqs:
+                off = (r.rid * 7919) % (1000000 - r.n + 1)
+                r.payload = {k: v[off:off + r.n] for k, v in pools[r.lens].items()}
+            ex = GpuExecutor(4, hl, maps, mode, dtype)
+            sched = Scheduler(ex, mem_budget_bytes=4 << 30, bytes_per_ray=64, chunk=262144)
+            ex.start_clock()
+            done = run_trace(sched, reqs, ex.clock)
+            torch.cuda.synchronize()
+            span = max(r.done for r in done) - min(r.arrival for r in done)
+            return done, sum(r.n for r in done) / span
+
+        _, sat = run(1e9)  # everything queued at once
+        out = {"saturated_mrays_s": sat / 1e6}
+        for rho in loads:
+            rate = rho * sat / float(np.mean(sizes))
+            done, thr = run(rate)
+            st = latency_stats(done)
+            out[f"load_{rho}"] = {"p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                                  "mrays_s": thr / 1e6, "requests": st["n"]}
+        res[key] = out
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fit-steps", type=int, default=3000)
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--rays", type=int, default=N_RAYS)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -106,8 +235,10 @@ def main():
     import numpy as np
     import torch
 
+    import oracle
     import paper_2605_04017_amd as lt
     import synth
+    from oracle import mlp
 
     dev = torch.device("cuda:0")
     lens = synth.config_lens(2)
@@ -116,20 +247,14 @@ def main():
     rays = {k: torch.from_numpy(v).to(dev) for k, v in rays_np.items()}
     h = lt.lt_lens_create(lens.surfaces, lens.glasses)
     out = lt.empty_exit(n, dev)
-    out_fast = lt.empty_exit(n, dev)
     stream = torch.cuda.current_stream()
 
-    # map of the workload's architecture: 6-D input, 5 x 128 tanh, one head
-    from oracle import mlp
-    desc = mlp.MapDesc(MAP_WIDTH, MAP_DEPTH, 1, mlp.ACT_TANH)
-    params = mlp.init_params(desc, 7)
-    x = np.stack([rays_np[k][:65536].astype(np.float64) for k in synth.RAY_FIELDS], 1)
-    params.in_shift, params.in_scale = x.mean(0), 1.0 / x.std(0)
-    m = lt.lt_map_create(MAP_WIDTH, MAP_DEPTH, 1, lt.LT_ACT_TANH)
-    lt.lt_map_set_params(m, torch.from_numpy(params.flat().astype(np.float32)).to(dev))
-    lt.lt_map_set_norm(m, params.in_shift, params.in_scale, params.out_shift.reshape(-1),
-                       params.out_scale.reshape(-1))
+    # map of the workload's architecture, fitted on GPU-traced rays
+    t_fit = time.perf_counter()
+    m, params, fit_loss = fit_map(lt, synth, mlp, lens, dev, args.fit_steps)
+    t_fit = time.perf_counter() - t_fit
     mout = lt.empty_map_out(1, n, dev)
+    print(f"# fitted map in {t_fit:.1f} s, loss {fit_loss}", file=sys.stderr, flush=True)
 
     def step(ev=None):
         if ev is not None:
@@ -137,7 +262,7 @@ def main():
         lt.lt_trace(h, (0, 0, 0), rays, out, n, stream)
         if ev is not None:
             ev[1].record(stream)
-        lt.lt_map_eval(m, lt.LT_BF16, rays, mout, n, stream)
+        lt.lt_map_eval(m, lt.LT_F32, rays, mout, n, stream)
         if ev is not None:
             ev[2].record(stream)
 
@@ -150,24 +275,23 @@ def main():
         step(evs[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    trace_ms = [e[0].elapsed_time(e[1]) for e in evs]
-    map_ms = [e[1].elapsed_time(e[2]) for e in evs]
-    t_trace = float(np.mean(trace_ms)) * 1e-3
-    t_map = float(np.mean(map_ms)) * 1e-3
+    t_trace = float(np.mean([e[0].elapsed_time(e[1]) for e in evs])) * 1e-3
+    t_map = float(np.mean([e[1].elapsed_time(e[2]) for e in evs])) * 1e-3
     ms_per_step = wall / args.steps * 1e3
+    print(f"# timed {args.steps} steps", file=sys.stderr, flush=True)
 
-    # the plain-FP32 tracer option, timed outside the steps for context
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    lt.lt_trace_ex(h, (0, 0, 0), rays, out_fast, n, lt.LT_TRACE_PLAIN_FP32, stream)
-    e0.record(stream)
-    for _ in range(5):
-        lt.lt_trace_ex(h, (0, 0, 0), rays, out_fast, n, lt.LT_TRACE_PLAIN_FP32, stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    t_fast = e0.elapsed_time(e1) / 5 * 1e-3
+    reps = 5
+    t_bf16 = time_kernel(lambda: lt.lt_map_eval(m, lt.LT_BF16, rays, mout, n, stream), stream, reps)
+    t_fp8 = time_kernel(lambda: lt.lt_map_eval(m, lt.LT_FP8, rays, mout, n, stream), stream, reps)
+    fast = lt.empty_exit(n, dev)
+    t_fast = time_kernel(lambda: lt.lt_trace_ex(h, (0, 0, 0), rays, fast, n, lt.LT_TRACE_PLAIN_FP32,
+                                                stream), stream, reps)
+    errors = {name: map_error(lt, oracle, lens, m, dt, rays_np, rays)
+              for name, dt in (("f32", lt.LT_F32), ("bf16", lt.LT_BF16), ("fp8", lt.LT_FP8))}
+    print("# map errors measured", file=sys.stderr, flush=True)
 
-    map_flops = map_flops_per_ray() * n
-    achieved = map_flops / t_map / 1e12
+    fpr = map_flops_per_ray()
+    achieved = fpr * n / t_map / 1e12
     trace_tf = trace_flops_per_ray(lens) * n / t_trace / 1e12
     res = {
         "metric": "Mrays/s map vs GPU brute-force trace at stated exit-ray error; p99 latency",
@@ -176,29 +300,43 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16", "data": "synthetic",
+        "dtype": "f32", "data": "synthetic",
         "config": {"workload": "double-Gauss-style 11-surface lens + stop, 4,194,304 sensor-side "
-                               "rays; step = FP32 brute-force trace + 5 x 128 tanh map (BF16 MFMA)",
-                   "rays": n, "map": "6-D input, 5 x 128 tanh, 1 head (mask logit + x, y, dx, dy, "
-                                     "throughput)"},
-        "map_mrays_s": n / t_map / 1e6,
+                               "rays; step = FP32 brute-force trace + FP32 map, 5 x 128 tanh",
+                   "rays": n,
+                   "map": "6-D input, 5 x 128 tanh, 1 head (mask logit + x, y, dx, dy, throughput), "
+                          f"fitted for {args.fit_steps} steps of 65,536 GPU-traced rays"},
+        "map_f32_mrays_s": n / t_map / 1e6,
+        "map_bf16_mrays_s": n / t_bf16 / 1e6,
+        "map_fp8_mrays_s": n / t_fp8 / 1e6,
         "trace_mrays_s": n / t_trace / 1e6,
         "trace_plain_fp32_mrays_s": n / t_fast / 1e6,
-        "map_over_trace": t_trace / t_map,
-        "map_kernel_ms": t_map * 1e3,
-        "trace_kernel_ms": t_trace * 1e3,
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": MI355X_BF16_MFMA_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / MI355X_BF16_MFMA_TFLOPS,
-                     "traffic": None, "kernel": "map_eval_bf16_kernel<128, tanh>",
-                     "flops_per_ray": map_flops_per_ray()},
-        "roofline_trace": {"bound": "alu", "achieved": trace_tf, "peak": MI355X_FP32_VECTOR_TFLOPS,
-                           "unit": "TFLOP/s", "frac": trace_tf / MI355X_FP32_VECTOR_TFLOPS,
-                           "kernel": "trace_kernel<compensated>",
-                           "flops_per_ray": trace_flops_per_ray(lens)},
+        "map_over_trace": {"f32": t_trace / t_map, "bf16": t_trace / t_bf16, "fp8": t_trace / t_fp8},
+        "kernel_ms": {"trace": t_trace * 1e3, "trace_plain_fp32": t_fast * 1e3,
+                      "map_f32": t_map * 1e3, "map_bf16": t_bf16 * 1e3, "map_fp8": t_fp8 * 1e3},
+        "map_error_vs_fp64_oracle": errors,
+        "fit": {"steps": args.fit_steps, "batch": 65536, "final_loss": fit_loss, "seconds": t_fit},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": MI355X_FP32_MFMA_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / MI355X_FP32_MFMA_TFLOPS,
+                     "traffic": None, "kernel": "map_eval_f32_kernel<128, tanh>",
+                     "flops_per_ray": fpr},
+        "roofline_other": {
+            "map_bf16": {"bound": "mfma", "achieved": fpr * n / t_bf16 / 1e12,
+                         "peak": MI355X_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
+                         "frac": fpr * n / t_bf16 / 1e12 / MI355X_BF16_MFMA_TFLOPS},
+            "map_fp8": {"bound": "mfma", "achieved": fpr * n / t_fp8 / 1e12,
+                        "peak": MI355X_FP8_MFMA_TFLOPS, "unit": "TFLOP/s",
+                        "frac": fpr * n / t_fp8 / 1e12 / MI355X_FP8_MFMA_TFLOPS},
+            "trace": {"bound": "alu", "achieved": trace_tf, "peak": MI355X_FP32_VECTOR_TFLOPS,
+                      "unit": "TFLOP/s", "frac": trace_tf / MI355X_FP32_VECTOR_TFLOPS,
+                      "flops_per_ray": trace_flops_per_ray(lens)}},
     }
+    if not args.no_serving:
+        res["serving"] = serving(lt, synth, mlp, dev)
+        print("# serving done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline_map(params, rays_np)
-        res["cpu_baseline_trace"] = cpu_baseline(lens, rays_np)
+        res["cpu_baseline_trace"] = cpu_baseline_trace(lens, rays_np)
     print(json.dumps(res), flush=True)
 
 

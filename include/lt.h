@@ -265,6 +265,68 @@ lt_status lt_map_set_norm(lt_map map, const float *in_shift, const float *in_sca
 lt_status lt_map_eval(lt_map map, int32_t dtype, const lt_rays *rays, const lt_map_out *out,
                       int64_t n, void *stream);
 
+/* ----------------------------------------------------------- training */
+
+/* Traced targets per head, head-major [n_heads][n] (device): validity (the
+ * classifier target) and the exit ray + throughput (regression targets, read
+ * only where valid; may hold NaN elsewhere). */
+typedef struct {
+    const uint8_t *valid;
+    const float *x;
+    const float *y;
+    const float *dx;
+    const float *dy;
+    const float *throughput;
+} lt_targets;
+
+/* Optimiser and loss settings of one step.  The loss (averaged over heads):
+ *   w_bce/N sum_r BCE(logit, valid) + w_l2/(5N) sum_r valid * |o - t|^2
+ * on the normalised regression outputs o and targets t = (target -
+ * out_shift) / out_scale.  Adam with bias correction; step is 1-based. */
+typedef struct {
+    float lr;
+    float beta1;
+    float beta2;
+    float eps;
+    int64_t step;
+    float w_bce;
+    float w_l2;
+} lt_train_cfg;
+
+/* Bytes of device workspace a training call on n rays needs (-1 on error).
+ * The workspace must be 256-byte aligned; its content between calls is only
+ * meaningful from lt_map_forward_train to lt_map_backward. */
+int64_t lt_map_workspace_bytes(lt_map map, int64_t n);
+
+/* Training forward (BF16, as lt_map_eval): writes the raw network outputs
+ * o_raw[6 * n_heads][n] (row 6p + q: logit, then the normalised x, y, dx, dy,
+ * throughput of head p) and keeps the activations in the workspace for
+ * lt_map_backward.  Allocates nothing. */
+lt_status lt_map_forward_train(lt_map map, const lt_rays *rays, float *o_raw, void *workspace,
+                               int64_t workspace_bytes, int64_t n, void *stream);
+
+/* Hand-written backward pass of the last lt_map_forward_train on the same
+ * workspace: given dL/do_raw (same layout as o_raw), writes dL/dparams
+ * (lt_map_num_params floats, parameter order).  BF16 MFMA with FP32
+ * accumulation: gradients of hidden layers are rounded to BF16 before the
+ * weight-gradient product; the output gradient is split into BF16 hi + lo.
+ * The result is deterministic (fixed reduction order). */
+lt_status lt_map_backward(lt_map map, const float *grad_o, void *workspace,
+                          int64_t workspace_bytes, float *grad_params, int64_t n, void *stream);
+
+/* One fused training step on a batch of n rays: forward, loss, backward and
+ * Adam on the map's FP32 master parameters and moments.  loss_out (device,
+ * 3 floats, may be NULL): total, BCE part, L2 part.  Allocates nothing. */
+lt_status lt_map_train_step(lt_map map, const lt_rays *rays, const lt_targets *targets, int64_t n,
+                            const lt_train_cfg *cfg, void *workspace, int64_t workspace_bytes,
+                            float *loss_out, void *stream);
+
+/* Copy the Adam moments (first m, then v; lt_map_num_params floats each,
+ * device) out of the map (to_map = 0) or into it (to_map = 1), for
+ * checkpoint and resume. */
+lt_status lt_map_adam_state(lt_map map, float *m, float *v, int64_t count, int32_t to_map,
+                            void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,9 +28,10 @@ Adam follows Kingma and Ba (2015) with bias correction.
 The quantised forward (`forward_quantized`) rounds exactly where the GPU
 kernels round -- BF16 round-to-nearest-even for weights and activations,
 split hi/lo BF16 for the input layer and the output layer, OCP FP8 E4M3
-(bias 7, max 448, round-to-nearest-even, subnormals) with power-of-two
-per-layer scales for the hidden layers in FP8 mode -- and otherwise computes
-in FP64, so it pins the kernels up to FP32 accumulation order.
+(bias 7, max 448, round-to-nearest-even, subnormals, saturating) with
+power-of-two per-layer scales for the hidden layers in FP8 mode -- and
+otherwise computes in FP64, so it pins the kernels up to FP32 accumulation
+order.
 """
 from __future__ import annotations
 
@@ -201,9 +202,14 @@ def round_fp8_e4m3(x: np.ndarray) -> np.ndarray:
 
 def pow2_scale(amax: float, target: float) -> float:
     """Largest power of two s with amax * s <= target (1 if amax == 0)."""
-    if amax <= 0:
+    if not (amax > 0) or not np.isfinite(amax):
         return 1.0
-    return float(2.0 ** math.floor(math.log2(target / amax)))
+    s = 2.0 ** math.floor(math.log2(target / amax))
+    while amax * s > target:
+        s *= 0.5
+    while amax * 2 * s <= target:
+        s *= 2.0
+    return float(s)
 
 
 def fp8_layer_scales(p: MapParams):
@@ -218,23 +224,31 @@ def fp8_layer_scales(p: MapParams):
 
 
 def forward_quantized(p: MapParams, xhat: np.ndarray, mode: str):
-    """Forward pass with the kernels' rounding.  mode: "bf16" or "fp8"."""
+    """Forward pass with the kernels' rounding.  mode: "bf16" or "fp8".
+
+    bf16: input layer with split hi/lo BF16 inputs and weights, hidden
+    layers with BF16 weights and BF16-rounded activations, output layer with
+    split hi/lo BF16 weights.  fp8: the same input and output layers; every
+    hidden layer multiplies FP8 weights round_fp8(s_w W) by FP8 activations
+    round_fp8(s_h tanh(z)) (one rounding from the exact activation) and
+    divides by s_w s_h; the last hidden activation is rounded to BF16."""
     L = len(p.W)
     x_hi, x_lo = split_bf16(xhat)
     W0_hi, W0_lo = split_bf16(p.W[0])
     z = x_hi @ W0_hi.T + x_lo @ W0_hi.T + x_hi @ W0_lo.T + p.b[0]
-    h = round_bf16(act(z, p.desc.activation))
     if mode == "fp8":
         ws, hsc = fp8_layer_scales(p)
-    for li in range(1, L - 1):
-        if mode == "bf16":
-            z = h @ round_bf16(p.W[li]).T + p.b[li]
-        else:
+        for li in range(1, L - 1):
             sw, sh = ws[li - 1], hsc[li - 1]
+            hq = round_fp8_e4m3(act(z, p.desc.activation) * sh)
             Wq = round_fp8_e4m3(p.W[li] * sw)
-            hq = round_fp8_e4m3(h * sh)
             z = (hq @ Wq.T) / (sw * sh) + p.b[li]
         h = round_bf16(act(z, p.desc.activation))
+    else:
+        h = round_bf16(act(z, p.desc.activation))
+        for li in range(1, L - 1):
+            z = h @ round_bf16(p.W[li]).T + p.b[li]
+            h = round_bf16(act(z, p.desc.activation))
     Wo_hi, Wo_lo = split_bf16(p.W[L - 1])
     o = h @ Wo_hi.T + h @ Wo_lo.T + p.b[L - 1]
     return o
@@ -302,3 +316,77 @@ def adam_step(p: MapParams, g: np.ndarray, st: AdamState, lr: float, beta1: floa
     mhat = st.m / (1 - beta1 ** st.step)
     vhat = st.v / (1 - beta2 ** st.step)
     p.set_flat(p.flat() - lr * mhat / (np.sqrt(vhat) + eps))
+
+
+def forward_quantized_cache(p: MapParams, xhat: np.ndarray):
+    """BF16 forward of the training kernels, keeping what the backward uses:
+    (o, (x_hi, x_lo, [h_1 .. h_depth]))."""
+    L = len(p.W)
+    x_hi, x_lo = split_bf16(xhat)
+    W0_hi, W0_lo = split_bf16(p.W[0])
+    z = x_hi @ W0_hi.T + x_lo @ W0_hi.T + x_hi @ W0_lo.T + p.b[0]
+    hs = [round_bf16(act(z, p.desc.activation))]
+    for li in range(1, L - 1):
+        z = hs[-1] @ round_bf16(p.W[li]).T + p.b[li]
+        hs.append(round_bf16(act(z, p.desc.activation)))
+    Wo_hi, Wo_lo = split_bf16(p.W[L - 1])
+    o = hs[-1] @ Wo_hi.T + hs[-1] @ Wo_lo.T + p.b[L - 1]
+    return o, (x_hi, x_lo, hs)
+
+
+def backward_quantized(p: MapParams, cache, d_out: np.ndarray):
+    """Parameter gradient for a given output gradient d_out (n, 6H), with the
+    training kernels' rounding: the output gradient enters split into BF16
+    hi + lo (against BF16 output weights for the transpose product); every
+    hidden-layer gradient is multiplied by the activation derivative (1 - h^2
+    for tanh, [h > 0] for ReLU, from the stored BF16 activation) and rounded
+    to BF16, then used in BF16 for its weight gradient (against the stored
+    BF16 activations, or the split inputs for the first layer), for its bias
+    gradient (sum over rays) and for the next transpose product (against BF16
+    weights).  Sums are exact here (FP64); the kernels accumulate in FP32."""
+    x_hi, x_lo, hs = cache
+    L = len(p.W)
+    d_hi, d_lo = split_bf16(d_out)
+    d = d_hi + d_lo
+    grads = [None] * L
+    grads[L - 1] = (d.T @ hs[-1], d.sum(0))
+    delta = d @ round_bf16(p.W[L - 1])
+    for li in range(L - 2, -1, -1):
+        h = hs[li]
+        dphi = 1.0 - h * h if p.desc.activation == ACT_TANH else (h > 0).astype(np.float64)
+        delta_b = round_bf16(delta * dphi)
+        if li == 0:
+            grads[0] = (delta_b.T @ (x_hi + x_lo), delta_b.sum(0))
+        else:
+            grads[li] = (delta_b.T @ hs[li - 1], delta_b.sum(0))
+            delta = delta_b @ round_bf16(p.W[li])
+    return grads
+
+
+def loss_terms(p: MapParams, o: np.ndarray, valid: np.ndarray, tnorm: np.ndarray,
+               w_bce: float = 1.0, w_l2: float = 1.0):
+    """Loss (total, bce, l2) and its gradient with respect to o (n, 6H)."""
+    n = o.shape[0]
+    H = p.desc.n_heads
+    oo = o.reshape(n, H, N_OUT).transpose(1, 0, 2)
+    logit = oo[..., 0]
+    v = valid.astype(np.float64)
+    bce = np.maximum(logit, 0) - logit * v + np.log1p(np.exp(-np.abs(logit)))
+    sig = 1.0 / (1.0 + np.exp(-logit))
+    t = np.where(v[..., None] > 0, tnorm, 0.0)
+    diff = np.where(v[..., None] > 0, oo[..., 1:] - t, 0.0)
+    l_bce = w_bce * bce.sum() / (n * H)
+    l_l2 = w_l2 * (diff * diff).sum() / (5 * n * H)
+    g = np.zeros_like(oo)
+    g[..., 0] = w_bce * (sig - v) / (n * H)
+    g[..., 1:] = w_l2 * 2.0 * diff / (5 * n * H)
+    return (l_bce + l_l2, l_bce, l_l2), g.transpose(1, 0, 2).reshape(n, H * N_OUT)
+
+
+def loss_and_grad_quantized(p: MapParams, xhat: np.ndarray, valid: np.ndarray, tnorm: np.ndarray,
+                            w_bce: float = 1.0, w_l2: float = 1.0):
+    """Loss and parameter gradient of one training step with the kernels'
+    rounding (forward_quantized_cache, loss_terms, backward_quantized)."""
+    o, cache = forward_quantized_cache(p, xhat)
+    losses, d_out = loss_terms(p, o, valid, tnorm, w_bce, w_l2)
+    return losses, backward_quantized(p, cache, d_out)

@@ -24,7 +24,11 @@ __all__ = ["LtError", "Lens", "lt_lens_create", "lt_lens_query", "lt_trace", "lt
            "lt_ghost_index", "lt_ghost_path", "empty_exit", "RAY_FIELDS", "EXIT_FIELDS",
            "LT_TRACE_PLAIN_FP32", "LT_F32", "LT_BF16", "LT_FP8", "LT_ACT_TANH", "LT_ACT_RELU",
            "Map", "lt_map_create", "lt_map_set_params", "lt_map_get_params", "lt_map_set_norm",
-           "lt_map_eval", "empty_map_out", "MAP_FIELDS"]
+           "lt_map_eval", "empty_map_out", "MAP_FIELDS", "lt_map_workspace_bytes", "workspace",
+           "lt_map_forward_train", "lt_map_backward", "lt_map_train_step", "lt_map_adam_state",
+           "TARGET_FIELDS"]
+
+TARGET_FIELDS = ("valid", "x", "y", "dx", "dy", "throughput")
 
 
 def _torch():
@@ -280,3 +284,89 @@ def lt_map_eval(m: Map, dtype: int, rays: Dict, out: Optional[Dict] = None,
     N.check(N.lib().lt_map_eval(m.handle, int(dtype), C.byref(_rays_struct(rays, n)), C.byref(o),
                                 int(n), C.c_void_p(_stream_ptr(stream) if n else 0)))
     return out
+
+
+# -------------------------------------------------------------- training --
+
+def lt_map_workspace_bytes(m: Map, n: int) -> int:
+    return int(N.lib().lt_map_workspace_bytes(m.handle, int(n)))
+
+
+def workspace(m: Map, n: int, device="cuda"):
+    """A device workspace for training calls on n rays (torch allocations
+    are 256-byte aligned)."""
+    torch = _torch()
+    ws = torch.empty(max(1, lt_map_workspace_bytes(m, n)), dtype=torch.uint8, device=device)
+    assert ws.data_ptr() % 256 == 0
+    return ws
+
+
+def lt_map_forward_train(m: Map, rays: Dict, o_raw=None, ws=None, n: Optional[int] = None,
+                         stream=None):
+    """Training forward; returns (o_raw (6*n_heads, n) float32, workspace)."""
+    torch = _torch()
+    if n is None:
+        n = int(rays["x"].numel())
+    dev = rays["x"].device
+    if o_raw is None:
+        o_raw = torch.empty((6 * m.n_heads, n), dtype=torch.float32, device=dev)
+    if ws is None:
+        ws = workspace(m, n, dev)
+    optr = _dev_ptr(o_raw, torch.float32, 6 * m.n_heads * n, "o_raw") if n else None
+    N.check(N.lib().lt_map_forward_train(m.handle, C.byref(_rays_struct(rays, n)),
+                                         C.c_void_p(optr), C.c_void_p(ws.data_ptr()),
+                                         ws.numel(), int(n), C.c_void_p(_stream_ptr(stream))))
+    return o_raw, ws
+
+
+def lt_map_backward(m: Map, grad_o, ws, grad_params=None, n: Optional[int] = None, stream=None):
+    """Hand-written backward of the last lt_map_forward_train on ``ws``."""
+    torch = _torch()
+    if n is None:
+        n = int(grad_o.shape[-1])
+    if grad_params is None:
+        grad_params = torch.empty(m.n_params, dtype=torch.float32, device=grad_o.device)
+    gptr = _dev_ptr(grad_o, torch.float32, 6 * m.n_heads * n, "grad_o") if n else grad_o.data_ptr()
+    pptr = _dev_ptr(grad_params, torch.float32, m.n_params, "grad_params")
+    N.check(N.lib().lt_map_backward(m.handle, C.c_void_p(gptr), C.c_void_p(ws.data_ptr()),
+                                    ws.numel(), C.c_void_p(pptr), int(n),
+                                    C.c_void_p(_stream_ptr(stream))))
+    return grad_params
+
+
+def lt_map_train_step(m: Map, rays: Dict, targets: Dict, cfg: Dict, ws, loss_out=None,
+                      n: Optional[int] = None, stream=None):
+    """One fused forward + loss + backward + Adam step.  ``targets``: dict of
+    (n_heads, n) CUDA tensors (valid uint8, the rest float32); ``cfg``: lr,
+    beta1, beta2, eps, step (1-based), w_bce, w_l2.  Returns loss_out
+    (device float32[3]: total, bce, l2)."""
+    torch = _torch()
+    if n is None:
+        n = int(rays["x"].numel())
+    if loss_out is None:
+        loss_out = torch.zeros(3, dtype=torch.float32, device=rays["x"].device)
+    t = N.lt_targets()
+    for k in TARGET_FIELDS:
+        dt = torch.uint8 if k == "valid" else torch.float32
+        setattr(t, k, _dev_ptr(targets[k], dt, m.n_heads * n, f"targets[{k}]"))
+    c = N.lt_train_cfg(float(cfg.get("lr", 1e-3)), float(cfg.get("beta1", 0.9)),
+                       float(cfg.get("beta2", 0.999)), float(cfg.get("eps", 1e-8)),
+                       int(cfg["step"]), float(cfg.get("w_bce", 1.0)), float(cfg.get("w_l2", 1.0)))
+    N.check(N.lib().lt_map_train_step(m.handle, C.byref(_rays_struct(rays, n)), C.byref(t), int(n),
+                                      C.byref(c), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                      C.c_void_p(_dev_ptr(loss_out, torch.float32, 3, "loss_out")),
+                                      C.c_void_p(_stream_ptr(stream))))
+    return loss_out
+
+
+def lt_map_adam_state(m: Map, mv=None, to_map: bool = False, stream=None):
+    """Get (to_map=False) or set (True) the Adam moments as a (2, n_params)
+    float32 CUDA tensor."""
+    torch = _torch()
+    if mv is None:
+        mv = torch.empty((2, m.n_params), dtype=torch.float32, device="cuda")
+    _dev_ptr(mv, torch.float32, 2 * m.n_params, "mv")
+    N.check(N.lib().lt_map_adam_state(m.handle, C.c_void_p(mv[0].data_ptr()),
+                                      C.c_void_p(mv[1].data_ptr()), m.n_params, int(to_map),
+                                      C.c_void_p(_stream_ptr(stream))))
+    return mv

@@ -53,6 +53,15 @@ class lt_map_out(C.Structure):
                                            "throughput")]
 
 
+class lt_targets(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("valid", "x", "y", "dx", "dy", "throughput")]
+
+
+class lt_train_cfg(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("step", C.c_int64), ("w_bce", C.c_float), ("w_l2", C.c_float)]
+
+
 LT_F32, LT_BF16, LT_FP8 = 0, 1, 2
 LT_ACT_TANH, LT_ACT_RELU = 0, 1
 
@@ -83,6 +92,16 @@ SIGNATURES = {
                                   C.POINTER(C.c_float), C.POINTER(C.c_float)]),
     "lt_map_eval": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(lt_rays), C.POINTER(lt_map_out),
                               C.c_int64, C.c_void_p]),
+    "lt_map_workspace_bytes": (C.c_int64, [C.c_void_p, C.c_int64]),
+    "lt_map_forward_train": (C.c_int, [C.c_void_p, C.POINTER(lt_rays), C.c_void_p, C.c_void_p,
+                                       C.c_int64, C.c_int64, C.c_void_p]),
+    "lt_map_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                  C.c_int64, C.c_void_p]),
+    "lt_map_train_step": (C.c_int, [C.c_void_p, C.POINTER(lt_rays), C.POINTER(lt_targets),
+                                    C.c_int64, C.POINTER(lt_train_cfg), C.c_void_p, C.c_int64,
+                                    C.c_void_p, C.c_void_p]),
+    "lt_map_adam_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
+                                    C.c_void_p]),
 }
 
 

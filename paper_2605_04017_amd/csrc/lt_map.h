@@ -28,8 +28,11 @@ struct MapLayout {
     // BF16 fragment image (bytes)
     int64_t img_w0 = 0, img_hidden = 0, img_out = 0, img_bias = 0, img_bytes = 0;
     int64_t out_in_lds_bytes = 0;  // image bytes staged in LDS (everything, or all but the output layer)
-    // FP8 image: hidden layers as 16x128 fp8 fragments
-    int64_t img8_hidden = 0, img8_bytes = 0;
+    // FP8 image (width 128, tanh): [W0 BF16 frags][hidden FP8 16x128 frags,
+    // 2 KiB each][bias + norm + per-layer scales][output BF16 frags]
+    int64_t img8_hidden = 0, img8_bias = 0, img8_out = 0, img8_bytes = 0;
+    int64_t img8_lds_bytes = 0;
+    int32_t fp8_ok = 0;
 };
 
 struct Map {
@@ -40,13 +43,18 @@ struct Map {
     uint8_t *img_bf16 = nullptr;  // packed BF16 image
     uint8_t *img_fp8 = nullptr;   // packed FP8 image (hidden layers) + scales
     float *fp8_scales = nullptr;  // per hidden layer: 1 / (s_w * s_h), s_h
+    uint8_t *img_wt = nullptr;    // packed BF16 W^T image for the backward pass
+    uint8_t *img_f32 = nullptr;   // packed FP32 image
     float *adam_m = nullptr, *adam_v = nullptr;
     uint64_t version = 0;         // bumped by every parameter write
-    uint64_t packed_bf16 = ~0ull, packed_fp8 = ~0ull;
+    uint64_t packed_bf16 = ~0ull, packed_fp8 = ~0ull, packed_wt = ~0ull, packed_f32 = ~0ull;
     bool has_params = false;
 };
 
 Map *as_map(lt_map h);
 MapLayout make_layout(const lt_map_desc &d);
+int64_t wt_bytes(const MapLayout &L);
+int64_t f32_image_bytes(const MapLayout &L);
+lt_status eval_f32(Map &M, const lt_rays &rays, const lt_map_out &out, int64_t n, hipStream_t s);
 
 }  // namespace lt

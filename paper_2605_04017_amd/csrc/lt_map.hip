@@ -21,24 +21,9 @@
 
 #include "lt_internal.h"
 #include "lt_map.h"
+#include "lt_map_dev.h"
 
 namespace lt {
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-typedef float floatx2 __attribute__((ext_vector_type(2)));
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-
-// Each wave carries four 16-ray tiles (64 rays), so every A fragment read
-// from LDS feeds four MFMAs.  Width 128 needs ~200 registers per lane for the
-// accumulators and packed activations, so it runs one wave per SIMD (four per
-// workgroup, 512 registers each); narrower maps run two waves per SIMD.
-constexpr int kNT = 4;
-template <int H>
-constexpr int waves_for()
-{
-    return H >= 128 ? 4 : 8;
-}
 
 Map *as_map(lt_map h) { return reinterpret_cast<Map *>(h); }
 
@@ -70,36 +55,45 @@ MapLayout make_layout(const lt_map_desc &d)
     L.img_out = L.img_bias + ((bias_floats * 4 + 1023) / 1024) * 1024;
     L.img_bytes = L.img_out + static_cast<int64_t>(L.TO) * 2 * L.C * kFragBytes;
     L.out_in_lds_bytes = L.img_bytes <= kMaxLds ? L.img_bytes : L.img_out;
+    // FP8 image: the hidden region holds one 2 KiB fragment per M-tile per
+    // layer; the bias region gains two floats per hidden layer (1 / (s_w s_h)
+    // and s_h)
+    L.fp8_ok = (L.H == 128 && L.act == LT_ACT_TANH) ? 1 : 0;
+    L.img8_hidden = L.img_hidden;
+    L.img8_bias = L.img8_hidden + static_cast<int64_t>(L.D - 1) * L.T * 2 * kFragBytes;
+    const int64_t bias8_floats = bias_floats + 2LL * (L.D - 1);
+    L.img8_out = L.img8_bias + ((bias8_floats * 4 + 1023) / 1024) * 1024;
+    L.img8_bytes = L.img8_out + static_cast<int64_t>(L.TO) * 2 * L.C * kFragBytes;
+    L.img8_lds_bytes = L.img8_bytes <= kMaxLds ? L.img8_bytes : L.img8_out;
     return L;
 }
 
 // ------------------------------------------------------------ packing -----
 
-// K permutation inside a 32-chunk: logical k' (lane group g = k'/8, item j)
-// to the physical input row of that chunk.
-__host__ __device__ __forceinline__ int perm32(int kp)
-{
-    const int g = kp >> 3, j = kp & 7;
-    return j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4);
-}
-
-__device__ __forceinline__ __bf16 to_bf16(float v) { return static_cast<__bf16>(v); }
-
 // Value of element e (bf16 index) of the BF16 fragment image.
+// With fp8_scales != nullptr the kernel fills the FP8 image instead: the
+// same BF16 input and output layers, hidden biases multiplied by s_w * s_h,
+// two extra floats per hidden layer (1 / (s_w s_h), s_h); the hidden FP8
+// fragments are written by pack_fp8_hidden_kernel.
 __global__ void pack_bf16_kernel(const float *__restrict__ P, const float *__restrict__ norm,
-                                 MapLayout L, uint8_t *__restrict__ img)
+                                 MapLayout L, uint8_t *__restrict__ img,
+                                 const float *__restrict__ fp8_scales)
 {
+    const bool fp8 = fp8_scales != nullptr;
     const int64_t n_w0 = static_cast<int64_t>(L.T) * 512;
-    const int64_t n_hid = static_cast<int64_t>(L.D - 1) * L.T * L.C * 512;
+    const int64_t n_hid = fp8 ? 0 : static_cast<int64_t>(L.D - 1) * L.T * L.C * 512;
     const int64_t n_out = static_cast<int64_t>(L.TO) * 2 * L.C * 512;
-    const int64_t bias_floats = static_cast<int64_t>(L.D) * L.H + 16LL * L.TO + 12 + 10LL * L.P;
+    const int64_t bias_floats = static_cast<int64_t>(L.D) * L.H + 16LL * L.TO + 12 + 10LL * L.P +
+                                (fp8 ? 2LL * (L.D - 1) : 0);
+    const int64_t img_out = fp8 ? L.img8_out : L.img_out;
+    const int64_t img_bias = fp8 ? L.img8_bias : L.img_bias;
     const int64_t total = n_w0 + n_hid + n_out + bias_floats;
     for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total;
          e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         if (e < n_w0 + n_hid + n_out) {
             const bool is_w0 = e < n_w0, is_hid = !is_w0 && e < n_w0 + n_hid;
             const int64_t loc = is_w0 ? e : is_hid ? e - n_w0 : e - n_w0 - n_hid;
-            const int64_t base = is_w0 ? L.img_w0 : is_hid ? L.img_hidden : L.img_out;
+            const int64_t base = is_w0 ? L.img_w0 : is_hid ? L.img_hidden : img_out;
             const int64_t f = loc / 512;
             const int within = static_cast<int>(loc % 512);
             const int lane = within >> 3, j = within & 7;
@@ -143,72 +137,88 @@ __global__ void pack_bf16_kernel(const float *__restrict__ P, const float *__res
             const int64_t b = e - (n_w0 + n_hid + n_out);
             float v = 0.0f;
             const int64_t nb_hidden = static_cast<int64_t>(L.D) * L.H;
+            const int64_t nb_norm = nb_hidden + 16LL * L.TO + 12 + 10LL * L.P;
             if (b < nb_hidden) {
                 const int l = static_cast<int>(b / L.H), m = static_cast<int>(b % L.H);
                 v = P[L.b_off[l] + m];
+                if (fp8 && l >= 1)
+                    v *= fp8_scales[l - 1] * kFp8ActScale;
             } else if (b < nb_hidden + 16LL * L.TO) {
                 const int slot = static_cast<int>(b - nb_hidden);
                 const int head = slot / kHeadSlots, q = slot % kHeadSlots;
                 if (head < L.P && q < kMapOut)
                     v = P[L.b_off[L.D] + head * kMapOut + q];
-            } else {
+            } else if (b < nb_norm) {
                 v = norm[b - nb_hidden - 16LL * L.TO];
+            } else {
+                const int64_t k = b - nb_norm;
+                const float sw = fp8_scales[k / 2];
+                v = (k % 2 == 0) ? 1.0f / (sw * kFp8ActScale) : kFp8ActScale;
             }
-            reinterpret_cast<float *>(img + L.img_bias)[b] = v;
+            reinterpret_cast<float *>(img + img_bias)[b] = v;
         }
+    }
+}
+
+// Per hidden layer l (1..depth-1): s_w = largest power of two with
+// max |W_l| * s_w <= 448.
+__global__ __launch_bounds__(256) void fp8_scale_kernel(const float *__restrict__ P, MapLayout L,
+                                                        float *__restrict__ scales)
+{
+    __shared__ float red[256];
+    const int l = blockIdx.x + 1;
+    const float *W = P + L.w_off[l];
+    float m = 0.0f;
+    for (int k = threadIdx.x; k < L.H * L.H; k += blockDim.x)
+        m = fmaxf(m, fabsf(W[k]));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        scales[l - 1] = pow2_scale(red[0], kFp8Max);
+}
+
+// Hidden FP8 fragments: per layer and M-tile t, lane (m = 16t + l%16, g =
+// l/16) holds 32 bytes; byte j is W_l[m][16 (j/4) + 4g + j%4] * s_w, the order
+// in which the lane holds the 32 FP32 outputs of the previous layer.
+__global__ void pack_fp8_hidden_kernel(const float *__restrict__ P, MapLayout L,
+                                       const float *__restrict__ scales, uint8_t *__restrict__ img)
+{
+    const int64_t n_words = static_cast<int64_t>(L.D - 1) * L.T * 512;  // 4 bytes each
+    for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < n_words;
+         e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t f = e / 512;
+        const int l = static_cast<int>(f / L.T) + 1, t = static_cast<int>(f % L.T);
+        const int within = static_cast<int>(e % 512);
+        const int lane = within >> 3, q = within & 7;
+        const int g = lane >> 4, m = 16 * t + (lane & 15);
+        const float sw = scales[l - 1];
+        const float *Wr = P + L.w_off[l] + static_cast<int64_t>(m) * L.H;
+        float v[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int j = 4 * q + b;
+            v[b] = Wr[16 * (j / 4) + 4 * g + (j % 4)] * sw;
+        }
+        reinterpret_cast<int *>(img + L.img8_hidden)[e] = pack_fp8x4(v[0], v[1], v[2], v[3]);
     }
 }
 
 // ------------------------------------------------------------ evaluation --
 
-__device__ __forceinline__ float act_tanh(float z)
-{
-    // tanh z = 1 - 2 / (1 + 2^(2 z log2 e)); saturates correctly at +-inf
-    const float e = __builtin_amdgcn_exp2f(z * 2.8853900817779268f);
-    return fmaf(-2.0f, __builtin_amdgcn_rcpf(1.0f + e), 1.0f);
-}
-
-template <int ACT>
-__device__ __forceinline__ float act(float z)
-{
-    if constexpr (ACT == LT_ACT_RELU)
-        return fmaxf(z, 0.0f);
-    else
-        return act_tanh(z);
-}
-
-template <int ACT>
-__device__ __forceinline__ bf16x8 act_pack(floatx4 lo, floatx4 hi)
-{
-    floatx2 p0 = {act<ACT>(lo[0]), act<ACT>(lo[1])};
-    floatx2 p1 = {act<ACT>(lo[2]), act<ACT>(lo[3])};
-    floatx2 p2 = {act<ACT>(hi[0]), act<ACT>(hi[1])};
-    floatx2 p3 = {act<ACT>(hi[2]), act<ACT>(hi[3])};
-    const bf16x2 q0 = __builtin_convertvector(p0, bf16x2);
-    const bf16x2 q1 = __builtin_convertvector(p1, bf16x2);
-    const bf16x2 q2 = __builtin_convertvector(p2, bf16x2);
-    const bf16x2 q3 = __builtin_convertvector(p3, bf16x2);
-    return bf16x8{q0[0], q0[1], q1[0], q1[1], q2[0], q2[1], q3[0], q3[1]};
-}
-
-__device__ __forceinline__ floatx4 mfma(bf16x8 a, bf16x8 b, floatx4 c)
-{
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-
-struct EvalArgs {
-    const uint8_t *img;
-    int64_t lds_bytes;
-    int32_t D, P, TO;
-    int32_t out_from_lds;
-    int64_t img_out, img_bias, img_hidden;
-    int64_t n;
-};
-
-template <int H, int ACT>
+// One kernel for evaluation (decode to exit rays) and for the training
+// forward pass (TRAIN: also store the normalised inputs, every hidden
+// layer's BF16 activations as MFMA B fragments, and the raw outputs).
+// FP8: hidden layers on 16x16x128 FP8 MFMA (width 128, tanh, evaluation only).
+template <int H, int ACT, bool TRAIN, bool FP8>
 __global__ __launch_bounds__(waves_for<H>() * 64) void map_eval_bf16_kernel(EvalArgs A, lt_rays rays,
                                                                           lt_map_out out)
 {
+    static_assert(!FP8 || (H == 128 && ACT == LT_ACT_TANH && !TRAIN), "FP8 path: width 128, tanh");
     constexpr int T = H / 16, C = H / 32;
     constexpr int kWaves = waves_for<H>();
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
@@ -222,8 +232,9 @@ __global__ __launch_bounds__(waves_for<H>() * 64) void map_eval_bf16_kernel(Eval
     const float *nrm = bias + A.D * H + 16 * A.TO;  // in_shift[6], in_scale[6], out_shift, out_scale
     const uint8_t *out_frag = A.out_from_lds ? lds + A.img_out : A.img + A.img_out;
     const int64_t n = A.n;
+    const int64_t n_tiles = TRAIN ? A.n_pad / 64 : (n + 63) / 64;
 
-    for (int64_t tile = static_cast<int64_t>(blockIdx.x) * kWaves + wave; tile * 64 < n;
+    for (int64_t tile = static_cast<int64_t>(blockIdx.x) * kWaves + wave; tile < n_tiles;
          tile += static_cast<int64_t>(gridDim.x) * kWaves) {
         const int64_t ray0 = tile * 64;
         floatx4 acc[kNT][T];
@@ -247,23 +258,26 @@ __global__ __launch_bounds__(waves_for<H>() * 64) void map_eval_bf16_kernel(Eval
                 const float xh = (f[k] - nrm[k]) * nrm[6 + k];
                 hi[k] = static_cast<float>(to_bf16(xh));
                 lo[k] = xh - hi[k];
+                if constexpr (TRAIN) {
+                    if (g == 0)
+                        A.xhat_out[k * A.n_pad + r] = xh;
+                }
             }
             // k' = 8g + j: 0..5 hi, 6..11 lo, 12..17 hi, rest 0
             float v[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int kp = 8 * g + j;
-                float s = 0.0f;
+                float sv = 0.0f;
 #pragma unroll
                 for (int k = 0; k < 6; ++k) {
-                    s = kp == k ? hi[k] : s;
-                    s = kp == 6 + k ? lo[k] : s;
-                    s = kp == 12 + k ? hi[k] : s;
+                    sv = kp == k ? hi[k] : sv;
+                    sv = kp == 6 + k ? lo[k] : sv;
+                    sv = kp == 12 + k ? hi[k] : sv;
                 }
-                v[j] = s;
+                v[j] = sv;
             }
-            b0[nt] = bf16x8{to_bf16(v[0]), to_bf16(v[1]), to_bf16(v[2]), to_bf16(v[3]),
-                            to_bf16(v[4]), to_bf16(v[5]), to_bf16(v[6]), to_bf16(v[7])};
+            b0[nt] = pack8(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]);
         }
 #pragma unroll
         for (int t = 0; t < T; ++t) {
@@ -271,38 +285,84 @@ __global__ __launch_bounds__(waves_for<H>() * 64) void map_eval_bf16_kernel(Eval
             const floatx4 bz = *reinterpret_cast<const floatx4 *>(bias + t * 16 + 4 * g);
 #pragma unroll
             for (int nt = 0; nt < kNT; ++nt)
-                acc[nt][t] = mfma(a, b0[nt], bz);
+                acc[nt][t] = mfma_bf16(a, b0[nt], bz);
         }
         // ---- hidden layers
-        for (int l = 1; l < A.D; ++l) {
-            bf16x8 bop[kNT][C];
+        bf16x8 bop[kNT][C];
+        if constexpr (FP8) {
+            // FP8 operands: lane l holds the 32 outputs of the previous layer
+            // for its ray (rows 16t + 4g + i), exactly its 32 K bytes of the
+            // 16x16x128 B operand; the packed weights follow that order.
+            const float *sc = nrm + 12 + 10 * A.P;  // per hidden layer: 1/(s_w s_h), s_h
+            float zs = 1.0f;
+            for (int l = 1; l < A.D; ++l) {
+                const float sh = sc[2 * (l - 1) + 1];
+                intx8 b8[kNT];
+#pragma unroll
+                for (int nt = 0; nt < kNT; ++nt) {
+                    int w[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        w[q] = pack_fp8x4(tanh_scaled(acc[nt][q][0], zs, sh),
+                                          tanh_scaled(acc[nt][q][1], zs, sh),
+                                          tanh_scaled(acc[nt][q][2], zs, sh),
+                                          tanh_scaled(acc[nt][q][3], zs, sh));
+                    b8[nt] = intx8{w[0], w[1], w[2], w[3], w[4], w[5], w[6], w[7]};
+                }
+                const uint8_t *wl = lds + A.img_hidden + static_cast<int64_t>(l - 1) * T * 2 * kFragBytes;
+                const float *bl = bias + l * H;
+#pragma unroll
+                for (int t = 0; t < T; ++t) {
+                    const intx8 a = *reinterpret_cast<const intx8 *>(wl + t * 2 * kFragBytes + lane * 32);
+                    const floatx4 bz = *reinterpret_cast<const floatx4 *>(bl + t * 16 + 4 * g);
+#pragma unroll
+                    for (int nt = 0; nt < kNT; ++nt)
+                        acc[nt][t] = mfma_fp8(a, b8[nt], bz);
+                }
+                zs = sc[2 * (l - 1)];
+            }
 #pragma unroll
             for (int nt = 0; nt < kNT; ++nt)
 #pragma unroll
-                for (int c = 0; c < C; ++c)
-                    bop[nt][c] = act_pack<ACT>(acc[nt][2 * c], acc[nt][2 * c + 1]);
-            const uint8_t *wl = lds + A.img_hidden + static_cast<int64_t>(l - 1) * T * C * kFragBytes;
-            const float *bl = bias + l * H;
-#pragma unroll
-            for (int t = 0; t < T; ++t) {
-                const floatx4 bz = *reinterpret_cast<const floatx4 *>(bl + t * 16 + 4 * g);
-#pragma unroll
                 for (int c = 0; c < C; ++c) {
-                    const bf16x8 a =
-                        *reinterpret_cast<const bf16x8 *>(wl + (t * C + c) * kFragBytes + lane * 16);
-#pragma unroll
-                    for (int nt = 0; nt < kNT; ++nt)
-                        acc[nt][t] = mfma(a, bop[nt][c], c == 0 ? bz : acc[nt][t]);
+                    const floatx4 lo = acc[nt][2 * c], hi = acc[nt][2 * c + 1];
+                    bop[nt][c] = pack8(tanh_scaled(lo[0], zs, 1.0f), tanh_scaled(lo[1], zs, 1.0f),
+                                       tanh_scaled(lo[2], zs, 1.0f), tanh_scaled(lo[3], zs, 1.0f),
+                                       tanh_scaled(hi[0], zs, 1.0f), tanh_scaled(hi[1], zs, 1.0f),
+                                       tanh_scaled(hi[2], zs, 1.0f), tanh_scaled(hi[3], zs, 1.0f));
+                }
+        } else {
+            for (int l = 1; l <= A.D; ++l) {
+    #pragma unroll
+                for (int nt = 0; nt < kNT; ++nt)
+    #pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        bop[nt][c] = act_pack<ACT>(acc[nt][2 * c], acc[nt][2 * c + 1]);
+                        if constexpr (TRAIN) {
+                            const int64_t fi = ((static_cast<int64_t>(l - 1) * (A.n_pad / 16) +
+                                                 tile * kNT + nt) * C + c) * 64 + lane;
+                            reinterpret_cast<bf16x8 *>(A.hfrag_out)[fi] = bop[nt][c];
+                        }
+                    }
+                if (l == A.D)
+                    break;
+                const uint8_t *wl = lds + A.img_hidden + static_cast<int64_t>(l - 1) * T * C * kFragBytes;
+                const float *bl = bias + l * H;
+    #pragma unroll
+                for (int t = 0; t < T; ++t) {
+                    const floatx4 bz = *reinterpret_cast<const floatx4 *>(bl + t * 16 + 4 * g);
+    #pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        const bf16x8 a =
+                            *reinterpret_cast<const bf16x8 *>(wl + (t * C + c) * kFragBytes + lane * 16);
+    #pragma unroll
+                        for (int nt = 0; nt < kNT; ++nt)
+                            acc[nt][t] = mfma_bf16(a, bop[nt][c], c == 0 ? bz : acc[nt][t]);
+                    }
                 }
             }
         }
         // ---- output layer (split hi/lo weights) and decode
-        bf16x8 bop[kNT][C];
-#pragma unroll
-        for (int nt = 0; nt < kNT; ++nt)
-#pragma unroll
-            for (int c = 0; c < C; ++c)
-                bop[nt][c] = act_pack<ACT>(acc[nt][2 * c], acc[nt][2 * c + 1]);
         const float *bo = bias + A.D * H;
         const float *out_shift = nrm + 12;
         const float *out_scale = nrm + 12 + 5 * A.P;
@@ -315,45 +375,30 @@ __global__ __launch_bounds__(waves_for<H>() * 64) void map_eval_bf16_kernel(Eval
                     out_frag + (static_cast<int64_t>(to) * 2 * C + cc) * kFragBytes + lane * 16);
 #pragma unroll
                 for (int nt = 0; nt < kNT; ++nt)
-                    o[nt] = mfma(a, bop[nt][cc % C], cc == 0 ? bz : o[nt]);
+                    o[nt] = mfma_bf16(a, bop[nt][cc % C], cc == 0 ? bz : o[nt]);
             }
             // lanes of even g hold (logit, x, y, dx) of head 2*to + g/2,
             // lanes of odd g hold (dy, throughput, pad, pad) of the same head
             const int head = 2 * to + (g >> 1);
             const bool even = (g & 1) == 0;
             const bool hv = head < A.P;
-            const int hs = hv ? head : 0;
+            if constexpr (TRAIN) {
 #pragma unroll
-            for (int nt = 0; nt < kNT; ++nt) {
-                const int64_t r = ray0 + nt * 16 + col;
-                const floatx4 v = o[nt];
-                const float send = even ? v[0] : fmaf(out_scale[5 * hs + 3], v[0], out_shift[5 * hs + 3]);
-                const float recv = __shfl_xor(send, 16);
-                if (!hv || r >= n)
-                    continue;
-                const int64_t idx = static_cast<int64_t>(head) * n + r;
-                const float nan = __builtin_nanf("");
-                if (even) {
-                    const float logit = v[0];
-                    const bool m = logit > 0.0f;
-                    const float x = fmaf(out_scale[5 * hs + 0], v[1], out_shift[5 * hs + 0]);
-                    const float y = fmaf(out_scale[5 * hs + 1], v[2], out_shift[5 * hs + 1]);
-                    const float dx = fmaf(out_scale[5 * hs + 2], v[3], out_shift[5 * hs + 2]);
-                    const float dy = recv;
-                    const float dz = -sqrtf(fmaxf(0.0f, 1.0f - dx * dx - dy * dy));
-                    out.logit[idx] = logit;
-                    out.mask[idx] = m ? 1 : 0;
-                    out.x[idx] = m ? x : nan;
-                    out.y[idx] = m ? y : nan;
-                    out.dx[idx] = m ? dx : nan;
-                    out.dz[idx] = m ? dz : nan;
-                } else {
-                    const bool m = recv > 0.0f;
-                    const float dy = send;
-                    const float thr = fmaf(out_scale[5 * hs + 4], v[1], out_shift[5 * hs + 4]);
-                    out.dy[idx] = m ? dy : nan;
-                    out.throughput[idx] = m ? thr : 0.0f;
+                for (int nt = 0; nt < kNT; ++nt) {
+                    const int64_t r = ray0 + nt * 16 + col;
+                    if (!hv || r >= n)
+                        continue;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int q = (even ? 0 : 4) + i;
+                        if (q < kMapOut)
+                            A.o_out[static_cast<int64_t>(head * kMapOut + q) * A.o_stride + r] = o[nt][i];
+                    }
                 }
+            } else {
+#pragma unroll
+                for (int nt = 0; nt < kNT; ++nt)
+                    decode_store(o[nt], to, g, ray0 + nt * 16 + col, n, A.P, out_shift, out_scale, out);
             }
         }
     }
@@ -361,7 +406,7 @@ __global__ __launch_bounds__(waves_for<H>() * 64) void map_eval_bf16_kernel(Eval
 
 static int g_num_cus = 0;
 
-static int num_cus()
+int num_cus()
 {
     if (g_num_cus == 0) {
         int dev = 0;
@@ -374,22 +419,21 @@ static int num_cus()
     return g_num_cus;
 }
 
-template <int H, int ACT>
-static lt_status launch_bf16(const Map &M, const lt_rays &rays, const lt_map_out &out, int64_t n,
-                             hipStream_t s)
+template <int H, int ACT, bool TRAIN, bool FP8 = false>
+static lt_status launch_bf16_impl(const Map &M, const lt_rays &rays, const lt_map_out &out,
+                                  EvalArgs A, hipStream_t s)
 {
-    EvalArgs A;
-    A.img = M.img_bf16;
-    A.lds_bytes = M.lay.out_in_lds_bytes;
-    A.D = M.lay.D;
-    A.P = M.lay.P;
-    A.TO = M.lay.TO;
-    A.out_from_lds = M.lay.out_in_lds_bytes == M.lay.img_bytes;
-    A.img_out = M.lay.img_out;
-    A.img_bias = M.lay.img_bias;
-    A.img_hidden = M.lay.img_hidden;
-    A.n = n;
-    auto kern = map_eval_bf16_kernel<H, ACT>;
+    const MapLayout &L = M.lay;
+    A.img = FP8 ? M.img_fp8 : M.img_bf16;
+    A.lds_bytes = FP8 ? L.img8_lds_bytes : L.out_in_lds_bytes;
+    A.D = L.D;
+    A.P = L.P;
+    A.TO = L.TO;
+    A.out_from_lds = FP8 ? L.img8_lds_bytes == L.img8_bytes : L.out_in_lds_bytes == L.img_bytes;
+    A.img_out = FP8 ? L.img8_out : L.img_out;
+    A.img_bias = FP8 ? L.img8_bias : L.img_bias;
+    A.img_hidden = FP8 ? L.img8_hidden : L.img_hidden;
+    auto kern = map_eval_bf16_kernel<H, ACT, TRAIN, FP8>;
     static bool attr_set = false;
     if (!attr_set) {
         lt_status st = check_hip(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -401,14 +445,32 @@ static lt_status launch_bf16(const Map &M, const lt_rays &rays, const lt_map_out
         attr_set = true;
     }
     constexpr int kWaves = waves_for<H>();
-    const int64_t tiles = (n + 64 * kWaves - 1) / (64 * kWaves);
+    const int64_t tiles = (A.n + 64 * kWaves - 1) / (64 * kWaves);
     const int grid = static_cast<int>(tiles < num_cus() ? tiles : num_cus());
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kWaves * 64), static_cast<size_t>(A.lds_bytes), s, A,
                        rays, out);
     return check_hip(hipGetLastError(), "map_eval_bf16_kernel launch");
 }
 
-static lt_status ensure_packed_bf16(Map &M, hipStream_t s)
+template <bool TRAIN>
+lt_status launch_map_forward(const Map &M, const lt_rays &rays, const lt_map_out &out, EvalArgs A,
+                             hipStream_t s)
+{
+    const int H = M.lay.H;
+    const bool relu = M.lay.act == LT_ACT_RELU;
+    if (H == 128)
+        return relu ? launch_bf16_impl<128, LT_ACT_RELU, TRAIN>(M, rays, out, A, s)
+                    : launch_bf16_impl<128, LT_ACT_TANH, TRAIN>(M, rays, out, A, s);
+    if (H == 64)
+        return relu ? launch_bf16_impl<64, LT_ACT_RELU, TRAIN>(M, rays, out, A, s)
+                    : launch_bf16_impl<64, LT_ACT_TANH, TRAIN>(M, rays, out, A, s);
+    return relu ? launch_bf16_impl<32, LT_ACT_RELU, TRAIN>(M, rays, out, A, s)
+                : launch_bf16_impl<32, LT_ACT_TANH, TRAIN>(M, rays, out, A, s);
+}
+template lt_status launch_map_forward<true>(const Map &, const lt_rays &, const lt_map_out &,
+                                            EvalArgs, hipStream_t);
+
+lt_status ensure_packed_bf16(Map &M, hipStream_t s)
 {
     if (M.packed_bf16 == M.version)
         return LT_OK;
@@ -418,10 +480,38 @@ static lt_status ensure_packed_bf16(Map &M, hipStream_t s)
     if (grid > 4096)
         grid = 4096;
     hipLaunchKernelGGL(pack_bf16_kernel, dim3(grid), dim3(256), 0, s, M.master, M.norm, L,
-                       M.img_bf16);
+                       M.img_bf16, static_cast<const float *>(nullptr));
     lt_status st = check_hip(hipGetLastError(), "pack_bf16_kernel launch");
     if (st == LT_OK)
         M.packed_bf16 = M.version;
+    return st;
+}
+
+static lt_status ensure_packed_fp8(Map &M, hipStream_t s)
+{
+    if (M.packed_fp8 == M.version)
+        return LT_OK;
+    const MapLayout &L = M.lay;
+    hipLaunchKernelGGL(fp8_scale_kernel, dim3(L.D - 1), dim3(256), 0, s, M.master, L, M.fp8_scales);
+    lt_status st = check_hip(hipGetLastError(), "fp8_scale_kernel launch");
+    if (st != LT_OK)
+        return st;
+    const int64_t words = static_cast<int64_t>(L.D - 1) * L.T * 512;
+    hipLaunchKernelGGL(pack_fp8_hidden_kernel, dim3(static_cast<uint32_t>((words + 255) / 256)),
+                       dim3(256), 0, s, M.master, L, static_cast<const float *>(M.fp8_scales),
+                       M.img_fp8);
+    st = check_hip(hipGetLastError(), "pack_fp8_hidden_kernel launch");
+    if (st != LT_OK)
+        return st;
+    const int64_t total = L.img8_bytes / 2 + 16;
+    int grid = static_cast<int>((total + 255) / 256);
+    if (grid > 4096)
+        grid = 4096;
+    hipLaunchKernelGGL(pack_bf16_kernel, dim3(grid), dim3(256), 0, s, M.master, M.norm, L,
+                       M.img_fp8, static_cast<const float *>(M.fp8_scales));
+    st = check_hip(hipGetLastError(), "pack_bf16_kernel (fp8 image) launch");
+    if (st == LT_OK)
+        M.packed_fp8 = M.version;
     return st;
 }
 
@@ -461,12 +551,20 @@ lt_status lt_map_create(const lt_map_desc *desc, lt_map *out)
     bool okk = hipMalloc(&M->master, np * 4) == hipSuccess &&
                hipMalloc(&M->norm, nnorm * 4) == hipSuccess &&
                hipMalloc(&M->img_bf16, static_cast<size_t>(M->lay.img_bytes)) == hipSuccess &&
+               hipMalloc(&M->img_wt, static_cast<size_t>(wt_bytes(M->lay))) == hipSuccess &&
+               hipMalloc(&M->img_fp8, static_cast<size_t>(M->lay.img8_bytes)) == hipSuccess &&
+               hipMalloc(&M->img_f32, static_cast<size_t>(f32_image_bytes(M->lay))) == hipSuccess &&
+               hipMalloc(&M->fp8_scales, 64 * sizeof(float)) == hipSuccess &&
                hipMalloc(&M->adam_m, np * 4) == hipSuccess &&
                hipMalloc(&M->adam_v, np * 4) == hipSuccess;
     if (!okk) {
         (void)hipFree(M->master);
         (void)hipFree(M->norm);
         (void)hipFree(M->img_bf16);
+        (void)hipFree(M->img_wt);
+        (void)hipFree(M->img_fp8);
+        (void)hipFree(M->img_f32);
+        (void)hipFree(M->fp8_scales);
         (void)hipFree(M->adam_m);
         (void)hipFree(M->adam_v);
         delete M;
@@ -497,7 +595,9 @@ lt_status lt_map_destroy(lt_map map)
     (void)hipFree(M->master);
     (void)hipFree(M->norm);
     (void)hipFree(M->img_bf16);
+    (void)hipFree(M->img_wt);
     (void)hipFree(M->img_fp8);
+    (void)hipFree(M->img_f32);
     (void)hipFree(M->fp8_scales);
     (void)hipFree(M->adam_m);
     (void)hipFree(M->adam_v);
@@ -573,31 +673,34 @@ lt_status lt_map_eval(lt_map map, int32_t dtype, const lt_rays *rays, const lt_m
         return fail(LT_ERR_ARG, "NULL map, rays or out");
     if (n < 0)
         return fail(LT_ERR_ARG, "negative ray count");
-    if (!M->has_params)
-        return fail(LT_ERR_STATE, "parameters were never set");
-    if (dtype != LT_BF16)
-        return fail(LT_ERR_DTYPE, "only LT_BF16 is available");
+    if (dtype != LT_BF16 && dtype != LT_FP8 && dtype != LT_F32)
+        return fail(LT_ERR_DTYPE, "precision not available (LT_F32, LT_BF16, LT_FP8)");
+    if (dtype == LT_FP8 && !M->lay.fp8_ok)
+        return fail(LT_ERR_DTYPE, "LT_FP8 needs width 128 and tanh");
     if (n == 0)
         return LT_OK;
+    if (!M->has_params)
+        return fail(LT_ERR_STATE, "parameters were never set");
     if (!rays->x || !rays->y || !rays->dx || !rays->dy || !rays->dz || !rays->lambda_nm)
         return fail(LT_ERR_ARG, "NULL ray field");
     if (!out->logit || !out->mask || !out->x || !out->y || !out->dx || !out->dy || !out->dz ||
         !out->throughput)
         return fail(LT_ERR_ARG, "NULL output field");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    EvalArgs A{};
+    A.n = n;
+    if (dtype == LT_F32)
+        return eval_f32(*M, *rays, *out, n, s);
+    if (dtype == LT_FP8) {
+        lt_status st = ensure_packed_fp8(*M, s);
+        if (st != LT_OK)
+            return st;
+        return launch_bf16_impl<128, LT_ACT_TANH, false, true>(*M, *rays, *out, A, s);
+    }
     lt_status st = ensure_packed_bf16(*M, s);
     if (st != LT_OK)
         return st;
-    const int H = M->lay.H;
-    const bool relu = M->lay.act == LT_ACT_RELU;
-    if (H == 128)
-        return relu ? launch_bf16<128, LT_ACT_RELU>(*M, *rays, *out, n, s)
-                    : launch_bf16<128, LT_ACT_TANH>(*M, *rays, *out, n, s);
-    if (H == 64)
-        return relu ? launch_bf16<64, LT_ACT_RELU>(*M, *rays, *out, n, s)
-                    : launch_bf16<64, LT_ACT_TANH>(*M, *rays, *out, n, s);
-    return relu ? launch_bf16<32, LT_ACT_RELU>(*M, *rays, *out, n, s)
-                : launch_bf16<32, LT_ACT_TANH>(*M, *rays, *out, n, s);
+    return launch_map_forward<false>(*M, *rays, *out, A, s);
 }
 
 }  // extern "C"

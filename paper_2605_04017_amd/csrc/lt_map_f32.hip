@@ -1,0 +1,301 @@
+// FP32 evaluation of the lens transport map (v_mfma_f32_16x16x4_f32).
+//
+// Operand layout.  A 16x16x4 FP32 MFMA takes one value per lane for A (row
+// l%16, k = l/16) and B (column l%16, k = l/16) and leaves lane l with rows
+// 4*(l/16)+i of its M-tile.  Numbering the K chunks of a layer q = 4t + i,
+// the B value lane l must supply for chunk q is then exactly its own output
+// of M-tile t, element i, of the previous layer (row 16t + 4*(l/16) + i):
+// the weights are packed in that K order and activations stay in registers.
+//
+// FP32 weights of a 5 x 128 map (256 KiB) exceed LDS, so the workgroup
+// stages one layer at a time (64 KiB) and its four waves run that layer on
+// their 64 rays each; biases, normalisation and the input layer stay
+// resident.  Per layer and wave the 1024 MFMAs (~32k cycles) dwarf the tanh
+// epilogue, so this path is MFMA-bound.
+#include <hip/hip_runtime.h>
+
+#include "lt_internal.h"
+#include "lt_map.h"
+#include "lt_map_dev.h"
+
+namespace lt {
+
+constexpr int kF32Waves = 4;
+constexpr int kF32Frag = 256;   // bytes of one 16x4 FP32 A fragment (64 lanes x 4 B)
+constexpr int kF32Stage = 64 * 1024;
+
+// image: [bias+norm floats, 1 KiB aligned][W0: T x 2 frags][hidden: (D-1) x T x H/4 frags]
+//        [output: TO x H/4 frags]
+struct F32Layout {
+    int64_t bias = 0, w0 = 0, hidden = 0, out = 0, bytes = 0;
+    int64_t layer_bytes = 0, out_bytes = 0, resident = 0;
+};
+
+F32Layout f32_layout(const MapLayout &L)
+{
+    F32Layout f;
+    const int64_t bias_floats = static_cast<int64_t>(L.D) * L.H + 16LL * L.TO + 12 + 10LL * L.P;
+    f.bias = 0;
+    f.w0 = ((bias_floats * 4 + 1023) / 1024) * 1024;
+    f.hidden = f.w0 + static_cast<int64_t>(L.T) * 2 * kF32Frag;
+    f.layer_bytes = static_cast<int64_t>(L.T) * (L.H / 4) * kF32Frag;
+    f.out = f.hidden + static_cast<int64_t>(L.D - 1) * f.layer_bytes;
+    f.out_bytes = static_cast<int64_t>(L.TO) * (L.H / 4) * kF32Frag;
+    f.bytes = f.out + f.out_bytes;
+    f.resident = f.hidden;  // bias + norm + W0
+    return f;
+}
+
+__global__ void pack_f32_kernel(const float *__restrict__ P, const float *__restrict__ norm,
+                                MapLayout L, F32Layout F, float *__restrict__ img)
+{
+    const int64_t total = F.bytes / 4;
+    const int64_t bias_floats = static_cast<int64_t>(L.D) * L.H + 16LL * L.TO + 12 + 10LL * L.P;
+    const int K4 = L.H / 4;
+    for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total;
+         e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t byte = e * 4;
+        float v = 0.0f;
+        if (byte < F.w0) {
+            const int64_t b = e;
+            const int64_t nb = static_cast<int64_t>(L.D) * L.H;
+            if (b < nb) {
+                v = P[L.b_off[b / L.H] + b % L.H];
+            } else if (b < nb + 16LL * L.TO) {
+                const int slot = static_cast<int>(b - nb);
+                const int head = slot / kHeadSlots, q = slot % kHeadSlots;
+                if (head < L.P && q < kMapOut)
+                    v = P[L.b_off[L.D] + head * kMapOut + q];
+            } else if (b < bias_floats) {
+                v = norm[b - nb - 16LL * L.TO];
+            }
+        } else {
+            const bool is_w0 = byte < F.hidden, is_out = byte >= F.out;
+            const int64_t loc = (byte - (is_w0 ? F.w0 : is_out ? F.out : F.hidden)) / 4;
+            const int64_t f = loc / 64;
+            const int lane = static_cast<int>(loc % 64);
+            const int g = lane >> 4, mrow = lane & 15;
+            if (is_w0) {
+                const int t = static_cast<int>(f / 2), c = static_cast<int>(f % 2);
+                const int k = 4 * c + g;
+                if (k < 6)
+                    v = P[L.w_off[0] + static_cast<int64_t>(16 * t + mrow) * 6 + k];
+            } else if (!is_out) {
+                const int per = L.T * K4;
+                const int l = static_cast<int>(f / per) + 1;
+                const int r = static_cast<int>(f % per);
+                const int t = r / K4, q = r % K4;
+                const int k = 16 * (q / 4) + 4 * g + (q % 4);
+                v = P[L.w_off[l] + static_cast<int64_t>(16 * t + mrow) * L.H + k];
+            } else {
+                const int to = static_cast<int>(f / K4), q = static_cast<int>(f % K4);
+                const int slot = 16 * to + mrow;
+                const int head = slot / kHeadSlots, qq = slot % kHeadSlots;
+                const int k = 16 * (q / 4) + 4 * g + (q % 4);
+                if (head < L.P && qq < kMapOut)
+                    v = P[L.w_off[L.D] + static_cast<int64_t>(head * kMapOut + qq) * L.H + k];
+            }
+        }
+        img[e] = v;
+    }
+}
+
+struct F32Args {
+    const uint8_t *img;
+    F32Layout F;
+    int32_t D, P, TO;
+    int64_t n;
+};
+
+__device__ __forceinline__ floatx4 mfma_f32(float a, float b, floatx4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <int ACT>
+__device__ __forceinline__ float act_f32(float z)
+{
+    return act<ACT>(z);
+}
+
+template <int H, int ACT>
+__global__ __launch_bounds__(kF32Waves * 64) void map_eval_f32_kernel(F32Args A, lt_rays rays,
+                                                                      lt_map_out out)
+{
+    constexpr int T = H / 16, K4 = H / 4;
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    uint8_t *stage = lds + A.F.resident;
+    for (int64_t o = threadIdx.x * 16; o < A.F.resident; o += blockDim.x * 16)
+        *reinterpret_cast<uint4 *>(lds + o) = *reinterpret_cast<const uint4 *>(A.img + o);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, col = lane & 15;
+    const float *bias = reinterpret_cast<const float *>(lds);
+    const float *nrm = bias + A.D * H + 16 * A.TO;
+    const float *w0 = reinterpret_cast<const float *>(lds + A.F.w0);
+    const int64_t n = A.n;
+    const int64_t wg_tiles = (n + 64 * kF32Waves - 1) / (64 * kF32Waves);
+
+    auto stage_bytes = [&](const uint8_t *src, int64_t bytes) {
+        __syncthreads();
+        for (int64_t o = threadIdx.x * 16; o < bytes; o += blockDim.x * 16)
+            *reinterpret_cast<uint4 *>(stage + o) = *reinterpret_cast<const uint4 *>(src + o);
+        __syncthreads();
+    };
+
+    for (int64_t wt = blockIdx.x; wt < wg_tiles; wt += gridDim.x) {
+        const int64_t ray0 = (wt * kF32Waves + wave) * 64;
+        floatx4 acc[kNT][T];
+        // ---- input layer: K = 6 features padded to 8 (two chunks)
+        float xin[kNT][2];
+#pragma unroll
+        for (int nt = 0; nt < kNT; ++nt) {
+            const int64_t r = ray0 + nt * 16 + col;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int k = 4 * c + g;
+                float f = 0.0f;
+                if (r < n && k < 6) {
+                    const float *src = k == 0 ? rays.x : k == 1 ? rays.y : k == 2 ? rays.dx
+                                     : k == 3 ? rays.dy : k == 4 ? rays.dz : rays.lambda_nm;
+                    f = (src[r] - nrm[k]) * nrm[6 + k];
+                }
+                xin[nt][c] = f;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const floatx4 bz = *reinterpret_cast<const floatx4 *>(bias + t * 16 + 4 * g);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const float a = w0[(t * 2 + c) * 64 + lane];
+#pragma unroll
+                for (int nt = 0; nt < kNT; ++nt)
+                    acc[nt][t] = mfma_f32(a, xin[nt][c], c == 0 ? bz : acc[nt][t]);
+            }
+        }
+        // ---- hidden layers, one staged layer at a time
+        for (int l = 1; l < A.D; ++l) {
+            float h[kNT][T][4];
+#pragma unroll
+            for (int nt = 0; nt < kNT; ++nt)
+#pragma unroll
+                for (int t = 0; t < T; ++t)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        h[nt][t][i] = act_f32<ACT>(acc[nt][t][i]);
+            stage_bytes(A.img + A.F.hidden + static_cast<int64_t>(l - 1) * A.F.layer_bytes,
+                        A.F.layer_bytes);
+            const float *wl = reinterpret_cast<const float *>(stage);
+            const float *bl = bias + l * H;
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                const floatx4 bz = *reinterpret_cast<const floatx4 *>(bl + t * 16 + 4 * g);
+#pragma unroll
+                for (int q = 0; q < K4; ++q) {
+                    const float a = wl[(t * K4 + q) * 64 + lane];
+#pragma unroll
+                    for (int nt = 0; nt < kNT; ++nt)
+                        acc[nt][t] = mfma_f32(a, h[nt][q / 4][q % 4], q == 0 ? bz : acc[nt][t]);
+                }
+            }
+        }
+        // ---- output layer, staged in groups of M-tiles that fit the stage
+        float h[kNT][T][4];
+#pragma unroll
+        for (int nt = 0; nt < kNT; ++nt)
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    h[nt][t][i] = act_f32<ACT>(acc[nt][t][i]);
+        const float *bo = bias + A.D * H;
+        const float *out_shift = nrm + 12;
+        const float *out_scale = nrm + 12 + 5 * A.P;
+        const int64_t tile_bytes = static_cast<int64_t>(K4) * kF32Frag;
+        const int per_group = static_cast<int>(kF32Stage / tile_bytes);
+        for (int to0 = 0; to0 < A.TO; to0 += per_group) {
+            const int cnt = A.TO - to0 < per_group ? A.TO - to0 : per_group;
+            stage_bytes(A.img + A.F.out + to0 * tile_bytes, cnt * tile_bytes);
+            const float *wo = reinterpret_cast<const float *>(stage);
+            for (int k = 0; k < cnt; ++k) {
+                const int to = to0 + k;
+                const floatx4 bz = *reinterpret_cast<const floatx4 *>(bo + to * 16 + 4 * g);
+                floatx4 o[kNT];
+#pragma unroll
+                for (int q = 0; q < K4; ++q) {
+                    const float a = wo[(k * K4 + q) * 64 + lane];
+#pragma unroll
+                    for (int nt = 0; nt < kNT; ++nt)
+                        o[nt] = mfma_f32(a, h[nt][q / 4][q % 4], q == 0 ? bz : o[nt]);
+                }
+#pragma unroll
+                for (int nt = 0; nt < kNT; ++nt)
+                    decode_store(o[nt], to, g, ray0 + nt * 16 + col, n, A.P, out_shift, out_scale, out);
+            }
+        }
+    }
+}
+
+template <int H, int ACT>
+static lt_status launch_f32(const Map &M, const lt_rays &rays, const lt_map_out &out, int64_t n,
+                            hipStream_t s)
+{
+    F32Args A;
+    A.img = M.img_f32;
+    A.F = f32_layout(M.lay);
+    A.D = M.lay.D;
+    A.P = M.lay.P;
+    A.TO = M.lay.TO;
+    A.n = n;
+    auto kern = map_eval_f32_kernel<H, ACT>;
+    static bool attr = false;
+    const size_t lds = static_cast<size_t>(A.F.resident + kF32Stage);
+    if (!attr) {
+        lt_status st = check_hip(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     kMaxLds),
+                                 "hipFuncSetAttribute");
+        if (st != LT_OK)
+            return st;
+        attr = true;
+    }
+    const int64_t tiles = (n + 64 * kF32Waves - 1) / (64 * kF32Waves);
+    const int64_t cap = 2LL * num_cus();
+    const int grid = static_cast<int>(tiles < cap ? tiles : cap);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kF32Waves * 64), lds, s, A, rays, out);
+    return check_hip(hipGetLastError(), "map_eval_f32_kernel launch");
+}
+
+lt_status eval_f32(Map &M, const lt_rays &rays, const lt_map_out &out, int64_t n, hipStream_t s)
+{
+    const F32Layout F = f32_layout(M.lay);
+    if (F.resident + kF32Stage > kMaxLds || F.layer_bytes > kF32Stage)
+        return fail(LT_ERR_DTYPE, "map too large for the FP32 path");
+    if (M.packed_f32 != M.version) {
+        const int64_t total = F.bytes / 4;
+        int grid = static_cast<int>((total + 255) / 256);
+        if (grid > 4096)
+            grid = 4096;
+        hipLaunchKernelGGL(pack_f32_kernel, dim3(grid), dim3(256), 0, s, M.master, M.norm, M.lay, F,
+                           reinterpret_cast<float *>(M.img_f32));
+        lt_status st = check_hip(hipGetLastError(), "pack_f32_kernel launch");
+        if (st != LT_OK)
+            return st;
+        M.packed_f32 = M.version;
+    }
+    const int H = M.lay.H;
+    const bool relu = M.lay.act == LT_ACT_RELU;
+    if (H == 128)
+        return relu ? launch_f32<128, LT_ACT_RELU>(M, rays, out, n, s)
+                    : launch_f32<128, LT_ACT_TANH>(M, rays, out, n, s);
+    if (H == 64)
+        return relu ? launch_f32<64, LT_ACT_RELU>(M, rays, out, n, s)
+                    : launch_f32<64, LT_ACT_TANH>(M, rays, out, n, s);
+    return relu ? launch_f32<32, LT_ACT_RELU>(M, rays, out, n, s)
+                : launch_f32<32, LT_ACT_TANH>(M, rays, out, n, s);
+}
+
+int64_t f32_image_bytes(const MapLayout &L) { return f32_layout(L).bytes; }
+
+}  // namespace lt

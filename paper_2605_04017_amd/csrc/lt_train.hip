@@ -1,0 +1,813 @@
+// Training of the lens transport map on gfx950: loss, hand-written backward
+// pass and Adam (the paper trains its classifier with binary cross-entropy
+// and its regressor with a regression loss on valid samples, Sec. 5.1 "MLP
+// Training"; Adam per Kingma and Ba).
+//
+// A step runs five kernels on one stream:
+//   forward (lt_map.hip, TRAIN variant): stores normalised inputs, every
+//       hidden layer's BF16 activations as MFMA B fragments, raw outputs;
+//   loss_kernel: BCE on the logit + masked squared error on the normalised
+//       regression outputs -> per-output gradient and per-block loss sums;
+//   bwd_kernel: gradient w.r.t. every hidden pre-activation, layer by layer,
+//       kept in registers (the same K permutation as the forward makes the
+//       FP32 result of one layer the BF16 B operand of the next), W^T images
+//       staged in LDS; stores the BF16 gradients as fragments;
+//   dw_kernel: weight gradients sum_r delta_r h_r^T over a slice of the
+//       batch, transposing fragments through LDS; the bias gradient comes from
+//       an extra all-ones column; one partial per slice (deterministic);
+//   reduce_adam_kernel: sums the slice partials and applies Adam to the FP32
+//       master parameters.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "lt_internal.h"
+#include "lt_map.h"
+#include "lt_map_dev.h"
+
+namespace lt {
+
+// --------------------------------------------------------- workspace -------
+
+struct WsLayout {
+    int64_t n_pad = 0, tiles16 = 0, slices = 0, loss_blocks = 0;
+    int64_t xhat = 0, hfrag = 0, dfrag = 0, o = 0, dout = 0, partial = 0, loss = 0, bytes = 0;
+};
+
+constexpr int kDwChunk = 64;     // rays per LDS chunk in dw_kernel
+constexpr int kDwPad = 8;        // bf16 padding per LDS row (bank skew)
+constexpr int kDwTilesPerWave = 16;
+constexpr int kMaxSlices = 64;
+constexpr int kLossBlock = 256;
+
+static int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
+
+WsLayout ws_layout(const MapLayout &L, int64_t n)
+{
+    WsLayout w;
+    w.n_pad = (n + 63) / 64 * 64;
+    w.tiles16 = w.n_pad / 16;
+    w.slices = w.n_pad / kDwChunk < kMaxSlices ? w.n_pad / kDwChunk : kMaxSlices;
+    if (w.slices < 1)
+        w.slices = 1;
+    w.loss_blocks = (w.n_pad + kLossBlock - 1) / kLossBlock;
+    int64_t off = 0;
+    w.xhat = off;
+    off = align256(off + 6 * w.n_pad * 4);
+    w.hfrag = off;
+    off = align256(off + static_cast<int64_t>(L.D) * w.n_pad * L.H * 2);
+    w.dfrag = off;
+    off = align256(off + static_cast<int64_t>(L.D) * w.n_pad * L.H * 2);
+    w.o = off;
+    off = align256(off + static_cast<int64_t>(kMapOut) * L.P * w.n_pad * 4);
+    w.dout = off;
+    off = align256(off + static_cast<int64_t>(kMapOut) * L.P * w.n_pad * 4);
+    w.partial = off;
+    off = align256(off + w.slices * L.n_params * 4);
+    w.loss = off;
+    off = align256(off + w.loss_blocks * 2 * 4);
+    w.bytes = off;
+    return w;
+}
+
+// -------------------------------------------------- transposed weights ----
+// W^T image used by bwd_kernel: [hidden W_l^T, l = 1..D-1: T x C fragments]
+// [output W_D^T: T x TO fragments].  Hidden: A[m = input unit i][k' = 8g+j]
+// of chunk c is W_l[32c + perm32(k')][i].  Output: chunk `to` pairs the four
+// output slots 16 to + 4g + (j & 3) with the hi (j < 4) and lo (j >= 4) halves
+// of the output gradient; both halves see the same BF16 weight.
+
+int64_t wt_hidden_bytes(const MapLayout &L) { return static_cast<int64_t>(L.D - 1) * L.T * L.C * kFragBytes; }
+int64_t wt_bytes(const MapLayout &L) { return wt_hidden_bytes(L) + static_cast<int64_t>(L.T) * L.TO * kFragBytes; }
+
+__global__ void pack_wt_kernel(const float *__restrict__ P, MapLayout L, uint8_t *__restrict__ img)
+{
+    const int64_t n_hid = static_cast<int64_t>(L.D - 1) * L.T * L.C * 512;
+    const int64_t n_out = static_cast<int64_t>(L.T) * L.TO * 512;
+    for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < n_hid + n_out;
+         e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const bool hid = e < n_hid;
+        const int64_t loc = hid ? e : e - n_hid;
+        const int64_t f = loc / 512;
+        const int within = static_cast<int>(loc % 512);
+        const int lane = within >> 3, j = within & 7;
+        const int g = lane >> 4, mrow = lane & 15;
+        float v = 0.0f;
+        if (hid) {
+            const int per = L.T * L.C;
+            const int l = static_cast<int>(f / per) + 1;
+            const int r = static_cast<int>(f % per);
+            const int t = r / L.C, c = r % L.C;
+            const int i = 16 * t + mrow;
+            const int o = 32 * c + perm32(8 * g + j);
+            v = P[L.w_off[l] + static_cast<int64_t>(o) * L.H + i];
+        } else {
+            const int t = static_cast<int>(f / L.TO), to = static_cast<int>(f % L.TO);
+            const int i = 16 * t + mrow;
+            const int slot = 16 * to + 4 * g + (j & 3);
+            const int head = slot / kHeadSlots, q = slot % kHeadSlots;
+            if (head < L.P && q < kMapOut)
+                v = P[L.w_off[L.D] + static_cast<int64_t>(head * kMapOut + q) * L.H + i];
+        }
+        reinterpret_cast<__bf16 *>(img)[e] = to_bf16(v);
+    }
+}
+
+// ------------------------------------------------------------- loss -------
+
+struct LossArgs {
+    const float *o;        // [6P][o_stride]
+    float *dout;           // [6P][n_pad]
+    float *partial;        // [blocks][2]
+    const float *norm;     // device: in_shift, in_scale, out_shift[5P], out_scale[5P]
+    lt_targets t;
+    int64_t n, n_pad, o_stride;
+    int32_t P;
+    float w_bce, w_l2;
+};
+
+__global__ __launch_bounds__(kLossBlock) void loss_kernel(LossArgs A)
+{
+    __shared__ float red[2][kLossBlock];
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * kLossBlock + threadIdx.x;
+    float s_bce = 0.0f, s_l2 = 0.0f;
+    const float inv = 1.0f / (static_cast<float>(A.n) * A.P);
+    if (r < A.n_pad) {
+        const float *sh = A.norm + 12, *sc = A.norm + 12 + 5 * A.P;
+        for (int h = 0; h < A.P; ++h) {
+            float *d = A.dout + static_cast<int64_t>(h * kMapOut) * A.n_pad + r;
+            if (r >= A.n) {
+                for (int q = 0; q < kMapOut; ++q)
+                    d[q * A.n_pad] = 0.0f;
+                continue;
+            }
+            const int64_t ti = static_cast<int64_t>(h) * A.n + r;
+            const float v = A.t.valid[ti] ? 1.0f : 0.0f;
+            const float *o = A.o + static_cast<int64_t>(h * kMapOut) * A.o_stride + r;
+            const float z = o[0];
+            // binary cross-entropy with logits, stable form
+            s_bce += fmaxf(z, 0.0f) - z * v + log1pf(expf(-fabsf(z)));
+            const float sig = 1.0f / (1.0f + expf(-z));
+            d[0] = A.w_bce * (sig - v) * inv;
+            const float tv[5] = {A.t.x[ti], A.t.y[ti], A.t.dx[ti], A.t.dy[ti], A.t.throughput[ti]};
+            for (int q = 0; q < 5; ++q) {
+                const float tn = (tv[q] - sh[5 * h + q]) / sc[5 * h + q];
+                const float diff = v > 0.0f ? o[(q + 1) * A.o_stride] - tn : 0.0f;
+                s_l2 += diff * diff;
+                d[(q + 1) * A.n_pad] = A.w_l2 * 2.0f * diff * inv * 0.2f;
+            }
+        }
+    }
+    red[0][threadIdx.x] = s_bce;
+    red[1][threadIdx.x] = s_l2;
+    __syncthreads();
+    for (int w = kLossBlock / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        A.partial[2 * blockIdx.x] = red[0][0];
+        A.partial[2 * blockIdx.x + 1] = red[1][0];
+    }
+}
+
+// ------------------------------------------------------- backward data ----
+
+struct BwdArgs {
+    const uint8_t *wt;       // W^T image (global)
+    int64_t lds_bytes;       // bytes of the image staged in LDS
+    int32_t out_from_lds;
+    int32_t D, P, TO;
+    const float *dout;       // [6P][dout_stride]
+    int64_t dout_stride;
+    const uint8_t *hfrag;    // [D][tiles16][C][64][16 B]
+    uint8_t *dfrag;          // same layout, output
+    int64_t n, n_pad;
+};
+
+template <int H, int ACT>
+__global__ __launch_bounds__(waves_for<H>() * 64) void bwd_kernel(BwdArgs A)
+{
+    constexpr int T = H / 16, C = H / 32;
+    constexpr int kWaves = waves_for<H>();
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    for (int64_t o = threadIdx.x * 16; o < A.lds_bytes; o += blockDim.x * 16)
+        *reinterpret_cast<uint4 *>(lds + o) = *reinterpret_cast<const uint4 *>(A.wt + o);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, col = lane & 15;
+    const int64_t hid_bytes = static_cast<int64_t>(A.D - 1) * T * C * kFragBytes;
+    const uint8_t *wt_out = A.out_from_lds ? lds + hid_bytes : A.wt + hid_bytes;
+    const int64_t n_tiles = A.n_pad / 64;
+    const int64_t tiles16 = A.n_pad / 16;
+    const bf16x8 *hf = reinterpret_cast<const bf16x8 *>(A.hfrag);
+    bf16x8 *df = reinterpret_cast<bf16x8 *>(A.dfrag);
+
+    for (int64_t tile = static_cast<int64_t>(blockIdx.x) * kWaves + wave; tile < n_tiles;
+         tile += static_cast<int64_t>(gridDim.x) * kWaves) {
+        const int64_t ray0 = tile * 64;
+        floatx4 acc[kNT][T];
+#pragma unroll
+        for (int nt = 0; nt < kNT; ++nt)
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+                acc[nt][t] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        // ---- output layer: W_D^T (delta_out split into BF16 hi + lo)
+        for (int to = 0; to < A.TO; ++to) {
+            bf16x8 bo[kNT];
+#pragma unroll
+            for (int nt = 0; nt < kNT; ++nt) {
+                const int64_t r = ray0 + nt * 16 + col;
+                float d[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int slot = 16 * to + 4 * g + i;
+                    const int head = slot / kHeadSlots, q = slot % kHeadSlots;
+                    d[i] = (head < A.P && q < kMapOut && r < A.n)
+                               ? A.dout[static_cast<int64_t>(head * kMapOut + q) * A.dout_stride + r]
+                               : 0.0f;
+                }
+                float hi[4], lo[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    hi[i] = static_cast<float>(to_bf16(d[i]));
+                    lo[i] = d[i] - hi[i];
+                }
+                bo[nt] = pack8(hi[0], hi[1], hi[2], hi[3], lo[0], lo[1], lo[2], lo[3]);
+            }
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(
+                    wt_out + (static_cast<int64_t>(t) * A.TO + to) * kFragBytes + lane * 16);
+#pragma unroll
+                for (int nt = 0; nt < kNT; ++nt)
+                    acc[nt][t] = mfma_bf16(a, bo[nt], acc[nt][t]);
+            }
+        }
+        // ---- hidden layers, top down
+        for (int l = A.D; l >= 1; --l) {
+            bf16x8 db[kNT][C];
+#pragma unroll
+            for (int nt = 0; nt < kNT; ++nt)
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const int64_t fi =
+                        ((static_cast<int64_t>(l - 1) * tiles16 + tile * kNT + nt) * C + c) * 64 + lane;
+                    const bf16x8 h = hf[fi];
+                    floatx4 &lo = acc[nt][2 * c];
+                    floatx4 &hi = acc[nt][2 * c + 1];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        lo[i] *= act_grad<ACT>(static_cast<float>(h[i]));
+                        hi[i] *= act_grad<ACT>(static_cast<float>(h[4 + i]));
+                    }
+                    db[nt][c] = pack8(lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]);
+                    df[fi] = db[nt][c];
+                }
+            if (l == 1)
+                break;
+            const uint8_t *wl = lds + static_cast<int64_t>(l - 2) * T * C * kFragBytes;
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const bf16x8 a =
+                        *reinterpret_cast<const bf16x8 *>(wl + (t * C + c) * kFragBytes + lane * 16);
+#pragma unroll
+                    for (int nt = 0; nt < kNT; ++nt)
+                        acc[nt][t] = mfma_bf16(a, db[nt][c],
+                                               c == 0 ? floatx4{0.0f, 0.0f, 0.0f, 0.0f} : acc[nt][t]);
+                }
+        }
+    }
+}
+
+// ------------------------------------------------------ weight gradient ---
+
+struct DwArgs {
+    const uint8_t *hfrag, *dfrag;
+    const float *xhat;      // [6][n_pad]
+    const float *dout;      // [6P][dout_stride]
+    int64_t dout_stride;
+    float *partial;         // [slices][n_params]
+    MapLayout L;
+    int64_t n, n_pad, chunks_per_slice, n_chunks;
+};
+
+template <int H>
+__global__ __launch_bounds__(256) void dw_kernel(DwArgs A)
+{
+    constexpr int T = H / 16, C = H / 32;
+    constexpr int RS = kDwChunk + kDwPad;  // bf16 per LDS row
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    const MapLayout &L = A.L;
+    const int layer = blockIdx.x;
+    const int group = blockIdx.y;
+    const int slice = blockIdx.z;
+    const bool is_out = layer == L.D, is_in = layer == 0;
+    const int m_tiles = is_out ? L.TO : T;
+    const int n_tiles = is_in ? 1 : T + 1;
+    const int total = m_tiles * n_tiles;
+    if (group * 4 * kDwTilesPerWave >= total)
+        return;
+    const int d_rows = is_out ? 2 * 16 * L.TO : H;
+    const int h_rows = is_in ? 16 : H + 16;
+    __bf16 *dl = reinterpret_cast<__bf16 *>(lds);
+    __bf16 *hl = dl + static_cast<int64_t>(d_rows) * RS;
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, col = lane & 15;
+    floatx4 acc[kDwTilesPerWave];
+#pragma unroll
+    for (int k = 0; k < kDwTilesPerWave; ++k)
+        acc[k] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int tile_base = group * 4 * kDwTilesPerWave + wave * kDwTilesPerWave;
+    const int64_t tiles16 = A.n_pad / 16;
+    const bf16x8 *hf = reinterpret_cast<const bf16x8 *>(A.hfrag);
+    const bf16x8 *df = reinterpret_cast<const bf16x8 *>(A.dfrag);
+
+    const int64_t c0 = slice * A.chunks_per_slice;
+    int64_t c1 = c0 + A.chunks_per_slice;
+    if (c1 > A.n_chunks)
+        c1 = A.n_chunks;
+    for (int64_t ch = c0; ch < c1; ++ch) {
+        const int64_t ray0 = ch * kDwChunk;
+        // --- gradients into dl[row][ray]
+        if (is_out) {
+            const int slots = 16 * L.TO;
+            for (int e = threadIdx.x; e < slots * kDwChunk; e += blockDim.x) {
+                const int s = e / kDwChunk, rr = e % kDwChunk;
+                const int64_t r = ray0 + rr;
+                const int head = s / kHeadSlots, q = s % kHeadSlots;
+                const float d = (head < L.P && q < kMapOut && r < A.n)
+                                    ? A.dout[static_cast<int64_t>(head * kMapOut + q) * A.dout_stride + r]
+                                    : 0.0f;
+                const __bf16 hi = to_bf16(d);
+                dl[s * RS + rr] = hi;
+                dl[(slots + s) * RS + rr] = to_bf16(d - static_cast<float>(hi));
+            }
+        } else {
+            // delta_{layer+1} fragments
+            for (int e = threadIdx.x; e < 4 * C * 64; e += blockDim.x) {
+                const int ln = e & 63, c = (e >> 6) % C, t16 = (e >> 6) / C;
+                const int64_t fi = ((static_cast<int64_t>(layer) * tiles16 + ray0 / 16 + t16) * C + c) * 64 + ln;
+                const bf16x8 v = df[fi];
+                const int gg = ln >> 4, rr = t16 * 16 + (ln & 15);
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    dl[(32 * c + perm32(8 * gg + j)) * RS + rr] = v[j];
+            }
+        }
+        // --- inputs of the layer into hl[col][ray], plus the all-ones column
+        if (is_in) {
+            for (int e = threadIdx.x; e < 16 * kDwChunk; e += blockDim.x) {
+                const int k = e / kDwChunk, rr = e % kDwChunk;
+                const int64_t r = ray0 + rr;
+                float v = 0.0f;
+                if (k < 6 || (k >= 6 && k < 12)) {
+                    const float xh = A.xhat[(k % 6) * A.n_pad + r];
+                    const float hi = static_cast<float>(to_bf16(xh));
+                    v = k < 6 ? hi : xh - hi;
+                } else if (k == 12) {
+                    v = 1.0f;
+                }
+                hl[k * RS + rr] = to_bf16(v);
+            }
+        } else {
+            for (int e = threadIdx.x; e < 4 * C * 64; e += blockDim.x) {
+                const int ln = e & 63, c = (e >> 6) % C, t16 = (e >> 6) / C;
+                const int64_t fi = ((static_cast<int64_t>(layer - 1) * tiles16 + ray0 / 16 + t16) * C + c) * 64 + ln;
+                const bf16x8 v = hf[fi];
+                const int gg = ln >> 4, rr = t16 * 16 + (ln & 15);
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    hl[(32 * c + perm32(8 * gg + j)) * RS + rr] = v[j];
+            }
+            for (int e = threadIdx.x; e < 16 * kDwChunk; e += blockDim.x) {
+                const int k = e / kDwChunk, rr = e % kDwChunk;
+                hl[(H + k) * RS + rr] = to_bf16(k == 0 ? 1.0f : 0.0f);
+            }
+        }
+        __syncthreads();
+        // --- MFMA: acc[tile] += sum over the chunk's rays of d[m][r] h[n][r]
+#pragma unroll
+        for (int k = 0; k < kDwTilesPerWave; ++k) {
+            const int tau = tile_base + k;
+            if (tau >= total)
+                break;
+            const int mt = tau / n_tiles, ntl = tau % n_tiles;
+#pragma unroll
+            for (int ks = 0; ks < kDwChunk / 32; ++ks) {
+                const bf16x8 b = *reinterpret_cast<const bf16x8 *>(hl + (ntl * 16 + col) * RS + ks * 32 + 8 * g);
+                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(dl + (mt * 16 + col) * RS + ks * 32 + 8 * g);
+                acc[k] = mfma_bf16(a, b, acc[k]);
+                if (is_out) {
+                    const bf16x8 a2 = *reinterpret_cast<const bf16x8 *>(
+                        dl + (16 * L.TO + mt * 16 + col) * RS + ks * 32 + 8 * g);
+                    acc[k] = mfma_bf16(a2, b, acc[k]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // --- partial gradients of this slice
+    float *out = A.partial + static_cast<int64_t>(slice) * L.n_params;
+#pragma unroll
+    for (int k = 0; k < kDwTilesPerWave; ++k) {
+        const int tau = tile_base + k;
+        if (tau >= total)
+            break;
+        const int mt = tau / n_tiles, ntl = tau % n_tiles;
+        const int n = ntl * 16 + col;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int m = mt * 16 + 4 * g + i;
+            float v = acc[k][i];
+            if (is_in) {
+                const float partner = __shfl(v, (lane + 6) & 63);
+                if (n < 6)
+                    out[L.w_off[0] + m * 6 + n] = v + partner;
+                else if (n == 12)
+                    out[L.b_off[0] + m] = v;
+            } else {
+                int row = m;
+                if (is_out) {
+                    const int head = m / kHeadSlots, q = m % kHeadSlots;
+                    if (head >= L.P || q >= kMapOut)
+                        continue;
+                    row = head * kMapOut + q;
+                }
+                if (n < H)
+                    out[L.w_off[layer] + static_cast<int64_t>(row) * H + n] = v;
+                else if (n == H)
+                    out[L.b_off[layer] + row] = v;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------- reduce + Adam ----
+
+struct AdamArgs {
+    const float *partial;
+    int64_t slices, n_params;
+    float *master, *m, *v;
+    float *grad_out;          // if non-null: write the gradient, no update
+    float lr, beta1, beta2, eps, bc1, bc2;
+    const float *loss_partial;
+    int64_t loss_blocks;
+    float *loss_out;          // [3]
+    float loss_scale_bce, loss_scale_l2;
+};
+
+__global__ __launch_bounds__(256) void reduce_adam_kernel(AdamArgs A)
+{
+    for (int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; k < A.n_params;
+         k += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        float gsum = 0.0f;
+        for (int64_t s = 0; s < A.slices; ++s)
+            gsum += A.partial[s * A.n_params + k];
+        if (A.grad_out) {
+            A.grad_out[k] = gsum;
+            continue;
+        }
+        const float m = A.beta1 * A.m[k] + (1.0f - A.beta1) * gsum;
+        const float v = A.beta2 * A.v[k] + (1.0f - A.beta2) * gsum * gsum;
+        A.m[k] = m;
+        A.v[k] = v;
+        const float mh = m / A.bc1, vh = v / A.bc2;
+        A.master[k] -= A.lr * mh / (sqrtf(vh) + A.eps);
+    }
+    if (A.loss_out && blockIdx.x == 0 && threadIdx.x == 0) {
+        float b = 0.0f, l2 = 0.0f;
+        for (int64_t i = 0; i < A.loss_blocks; ++i) {
+            b += A.loss_partial[2 * i];
+            l2 += A.loss_partial[2 * i + 1];
+        }
+        b *= A.loss_scale_bce;
+        l2 *= A.loss_scale_l2;
+        A.loss_out[0] = b + l2;
+        A.loss_out[1] = b;
+        A.loss_out[2] = l2;
+    }
+}
+
+// ------------------------------------------------------------ host --------
+
+template <int H, int ACT>
+static lt_status launch_bwd(const BwdArgs &A, hipStream_t s)
+{
+    auto kern = bwd_kernel<H, ACT>;
+    static bool attr = false;
+    if (!attr) {
+        lt_status st = check_hip(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     kMaxLds),
+                                 "hipFuncSetAttribute");
+        if (st != LT_OK)
+            return st;
+        attr = true;
+    }
+    constexpr int kWaves = waves_for<H>();
+    const int64_t tiles = A.n_pad / 64;
+    const int64_t blocks = (tiles + kWaves - 1) / kWaves;
+    const int grid = static_cast<int>(blocks < num_cus() ? blocks : num_cus());
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kWaves * 64), static_cast<size_t>(A.lds_bytes), s, A);
+    return check_hip(hipGetLastError(), "bwd_kernel launch");
+}
+
+template <int H>
+static lt_status launch_dw(const DwArgs &A, const WsLayout &w, hipStream_t s)
+{
+    auto kern = dw_kernel<H>;
+    static bool attr = false;
+    if (!attr) {
+        lt_status st = check_hip(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     kMaxLds),
+                                 "hipFuncSetAttribute");
+        if (st != LT_OK)
+            return st;
+        attr = true;
+    }
+    const MapLayout &L = A.L;
+    const int T = H / 16;
+    int max_groups = 1;
+    for (int layer = 0; layer <= L.D; ++layer) {
+        const int tiles = (layer == L.D ? L.TO : T) * (layer == 0 ? 1 : T + 1);
+        const int gr = (tiles + 4 * kDwTilesPerWave - 1) / (4 * kDwTilesPerWave);
+        if (gr > max_groups)
+            max_groups = gr;
+    }
+    const int rows_max = 2 * 16 * L.TO > H ? 2 * 16 * L.TO : H;
+    const size_t lds = static_cast<size_t>(rows_max + H + 16) * (kDwChunk + kDwPad) * 2;
+    if (lds > static_cast<size_t>(kMaxLds))
+        return fail(LT_ERR_ARG, "too many heads for the weight-gradient kernel");
+    hipLaunchKernelGGL(kern, dim3(L.D + 1, max_groups, static_cast<uint32_t>(w.slices)), dim3(256),
+                       lds, s, A);
+    return check_hip(hipGetLastError(), "dw_kernel launch");
+}
+
+static lt_status ensure_packed_wt(Map &M, hipStream_t s)
+{
+    if (M.packed_wt == M.version)
+        return LT_OK;
+    const int64_t total = wt_bytes(M.lay) / 2;
+    int grid = static_cast<int>((total + 255) / 256);
+    if (grid > 4096)
+        grid = 4096;
+    hipLaunchKernelGGL(pack_wt_kernel, dim3(grid), dim3(256), 0, s, M.master, M.lay, M.img_wt);
+    lt_status st = check_hip(hipGetLastError(), "pack_wt_kernel launch");
+    if (st == LT_OK)
+        M.packed_wt = M.version;
+    return st;
+}
+
+static lt_status run_backward(Map &M, const WsLayout &w, uint8_t *ws, const float *dout,
+                              int64_t dout_stride, int64_t n, hipStream_t s)
+{
+    const MapLayout &L = M.lay;
+    lt_status st = ensure_packed_wt(M, s);
+    if (st != LT_OK)
+        return st;
+    BwdArgs B{};
+    B.wt = M.img_wt;
+    const int64_t full = wt_bytes(L);
+    B.out_from_lds = full <= kMaxLds;
+    B.lds_bytes = B.out_from_lds ? full : wt_hidden_bytes(L);
+    B.D = L.D;
+    B.P = L.P;
+    B.TO = L.TO;
+    B.dout = dout;
+    B.dout_stride = dout_stride;
+    B.hfrag = ws + w.hfrag;
+    B.dfrag = ws + w.dfrag;
+    B.n = n;
+    B.n_pad = w.n_pad;
+    const bool relu = L.act == LT_ACT_RELU;
+    if (L.H == 128)
+        st = relu ? launch_bwd<128, LT_ACT_RELU>(B, s) : launch_bwd<128, LT_ACT_TANH>(B, s);
+    else if (L.H == 64)
+        st = relu ? launch_bwd<64, LT_ACT_RELU>(B, s) : launch_bwd<64, LT_ACT_TANH>(B, s);
+    else
+        st = relu ? launch_bwd<32, LT_ACT_RELU>(B, s) : launch_bwd<32, LT_ACT_TANH>(B, s);
+    if (st != LT_OK)
+        return st;
+    DwArgs D{};
+    D.hfrag = ws + w.hfrag;
+    D.dfrag = ws + w.dfrag;
+    D.xhat = reinterpret_cast<const float *>(ws + w.xhat);
+    D.dout = dout;
+    D.dout_stride = dout_stride;
+    D.partial = reinterpret_cast<float *>(ws + w.partial);
+    D.L = L;
+    D.n = n;
+    D.n_pad = w.n_pad;
+    D.n_chunks = w.n_pad / kDwChunk;
+    D.chunks_per_slice = (D.n_chunks + w.slices - 1) / w.slices;
+    if (L.H == 128)
+        return launch_dw<128>(D, w, s);
+    if (L.H == 64)
+        return launch_dw<64>(D, w, s);
+    return launch_dw<32>(D, w, s);
+}
+
+static lt_status check_ws(const Map *M, const void *ws, int64_t ws_bytes, int64_t n, WsLayout *w)
+{
+    *w = ws_layout(M->lay, n);
+    if (!ws)
+        return fail(LT_ERR_ARG, "NULL workspace");
+    if (reinterpret_cast<uintptr_t>(ws) % 256)
+        return fail(LT_ERR_ARG, "workspace must be 256-byte aligned");
+    if (ws_bytes < w->bytes)
+        return fail(LT_ERR_ARG, "workspace smaller than lt_map_workspace_bytes");
+    return LT_OK;
+}
+
+static bool rays_ok(const lt_rays *r)
+{
+    return r && r->x && r->y && r->dx && r->dy && r->dz && r->lambda_nm;
+}
+
+}  // namespace lt
+
+using namespace lt;
+
+extern "C" {
+
+int64_t lt_map_workspace_bytes(lt_map map, int64_t n)
+{
+    Map *M = as_map(map);
+    if (!M || n < 0)
+        return -1;
+    return ws_layout(M->lay, n).bytes;
+}
+
+lt_status lt_map_forward_train(lt_map map, const lt_rays *rays, float *o_raw, void *ws,
+                               int64_t ws_bytes, int64_t n, void *stream)
+{
+    Map *M = as_map(map);
+    if (!M || !o_raw || n < 0)
+        return fail(LT_ERR_ARG, "NULL map or outputs, or negative n");
+    if (!M->has_params)
+        return fail(LT_ERR_STATE, "parameters were never set");
+    if (n == 0)
+        return LT_OK;
+    if (!rays_ok(rays))
+        return fail(LT_ERR_ARG, "NULL ray field");
+    WsLayout w;
+    lt_status st = check_ws(M, ws, ws_bytes, n, &w);
+    if (st != LT_OK)
+        return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    st = ensure_packed_bf16(*M, s);
+    if (st != LT_OK)
+        return st;
+    uint8_t *wb = static_cast<uint8_t *>(ws);
+    EvalArgs A{};
+    A.n = n;
+    A.xhat_out = reinterpret_cast<float *>(wb + w.xhat);
+    A.hfrag_out = wb + w.hfrag;
+    A.o_out = o_raw;
+    A.n_pad = w.n_pad;
+    A.o_stride = n;
+    lt_map_out none{};
+    return launch_map_forward<true>(*M, *rays, none, A, s);
+}
+
+lt_status lt_map_backward(lt_map map, const float *grad_o, void *ws, int64_t ws_bytes,
+                          float *grad_params, int64_t n, void *stream)
+{
+    Map *M = as_map(map);
+    if (!M || !grad_o || !grad_params || n < 0)
+        return fail(LT_ERR_ARG, "NULL argument or negative n");
+    if (!M->has_params)
+        return fail(LT_ERR_STATE, "parameters were never set");
+    WsLayout w;
+    lt_status st = check_ws(M, ws, ws_bytes, n, &w);
+    if (st != LT_OK)
+        return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    uint8_t *wb = static_cast<uint8_t *>(ws);
+    if (n > 0) {
+        st = run_backward(*M, w, wb, grad_o, n, n, s);
+        if (st != LT_OK)
+            return st;
+    }
+    AdamArgs A{};
+    A.partial = reinterpret_cast<const float *>(wb + w.partial);
+    A.slices = n > 0 ? w.slices : 0;
+    A.n_params = M->lay.n_params;
+    A.grad_out = grad_params;
+    hipLaunchKernelGGL(reduce_adam_kernel, dim3(256), dim3(256), 0, s, A);
+    return check_hip(hipGetLastError(), "reduce kernel launch");
+}
+
+lt_status lt_map_train_step(lt_map map, const lt_rays *rays, const lt_targets *targets, int64_t n,
+                            const lt_train_cfg *cfg, void *ws, int64_t ws_bytes, float *loss_out,
+                            void *stream)
+{
+    Map *M = as_map(map);
+    if (!M || !targets || !cfg || n <= 0)
+        return fail(LT_ERR_ARG, "NULL argument or non-positive batch");
+    if (!M->has_params)
+        return fail(LT_ERR_STATE, "parameters were never set");
+    if (!rays_ok(rays))
+        return fail(LT_ERR_ARG, "NULL ray field");
+    if (!targets->valid || !targets->x || !targets->y || !targets->dx || !targets->dy ||
+        !targets->throughput)
+        return fail(LT_ERR_ARG, "NULL target field");
+    if (cfg->step < 1 || !(cfg->lr >= 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) ||
+        !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) || !(cfg->eps > 0.0f))
+        return fail(LT_ERR_ARG, "bad optimiser settings (step must be >= 1)");
+    WsLayout w;
+    lt_status st = check_ws(M, ws, ws_bytes, n, &w);
+    if (st != LT_OK)
+        return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    uint8_t *wb = static_cast<uint8_t *>(ws);
+    st = ensure_packed_bf16(*M, s);
+    if (st != LT_OK)
+        return st;
+    EvalArgs A{};
+    A.n = n;
+    A.xhat_out = reinterpret_cast<float *>(wb + w.xhat);
+    A.hfrag_out = wb + w.hfrag;
+    A.o_out = reinterpret_cast<float *>(wb + w.o);
+    A.n_pad = w.n_pad;
+    A.o_stride = w.n_pad;
+    lt_map_out none{};
+    st = launch_map_forward<true>(*M, *rays, none, A, s);
+    if (st != LT_OK)
+        return st;
+    LossArgs LA{};
+    LA.o = reinterpret_cast<const float *>(wb + w.o);
+    LA.dout = reinterpret_cast<float *>(wb + w.dout);
+    LA.partial = reinterpret_cast<float *>(wb + w.loss);
+    LA.norm = M->norm;
+    LA.t = *targets;
+    LA.n = n;
+    LA.n_pad = w.n_pad;
+    LA.o_stride = w.n_pad;
+    LA.P = M->lay.P;
+    LA.w_bce = cfg->w_bce;
+    LA.w_l2 = cfg->w_l2;
+    hipLaunchKernelGGL(loss_kernel, dim3(static_cast<uint32_t>(w.loss_blocks)), dim3(kLossBlock), 0,
+                       s, LA);
+    st = check_hip(hipGetLastError(), "loss_kernel launch");
+    if (st != LT_OK)
+        return st;
+    st = run_backward(*M, w, wb, reinterpret_cast<const float *>(wb + w.dout), w.n_pad, n, s);
+    if (st != LT_OK)
+        return st;
+    AdamArgs AA{};
+    AA.partial = reinterpret_cast<const float *>(wb + w.partial);
+    AA.slices = w.slices;
+    AA.n_params = M->lay.n_params;
+    AA.master = M->master;
+    AA.m = M->adam_m;
+    AA.v = M->adam_v;
+    AA.lr = cfg->lr;
+    AA.beta1 = cfg->beta1;
+    AA.beta2 = cfg->beta2;
+    AA.eps = cfg->eps;
+    AA.bc1 = static_cast<float>(1.0 - std::pow(static_cast<double>(cfg->beta1), static_cast<double>(cfg->step)));
+    AA.bc2 = static_cast<float>(1.0 - std::pow(static_cast<double>(cfg->beta2), static_cast<double>(cfg->step)));
+    AA.loss_partial = reinterpret_cast<const float *>(wb + w.loss);
+    AA.loss_blocks = w.loss_blocks;
+    AA.loss_out = loss_out;
+    const double np = static_cast<double>(n) * M->lay.P;
+    AA.loss_scale_bce = static_cast<float>(cfg->w_bce / np);
+    AA.loss_scale_l2 = static_cast<float>(cfg->w_l2 / (5.0 * np));
+    int grid = static_cast<int>((M->lay.n_params + 255) / 256);
+    if (grid > 1024)
+        grid = 1024;
+    hipLaunchKernelGGL(reduce_adam_kernel, dim3(grid), dim3(256), 0, s, AA);
+    st = check_hip(hipGetLastError(), "reduce_adam_kernel launch");
+    if (st == LT_OK)
+        ++M->version;  // master parameters changed: packed images are stale
+    return st;
+}
+
+lt_status lt_map_adam_state(lt_map map, float *m, float *v, int64_t count, int32_t to_map,
+                            void *stream)
+{
+    Map *M = as_map(map);
+    if (!M || !m || !v)
+        return fail(LT_ERR_ARG, "NULL argument");
+    if (count != M->lay.n_params)
+        return fail(LT_ERR_ARG, "count must equal lt_map_num_params");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const size_t b = static_cast<size_t>(count) * 4;
+    if (to_map) {
+        lt_status st = check_hip(hipMemcpyAsync(M->adam_m, m, b, hipMemcpyDeviceToDevice, s), "copy");
+        return st != LT_OK ? st : check_hip(hipMemcpyAsync(M->adam_v, v, b, hipMemcpyDeviceToDevice, s), "copy");
+    }
+    lt_status st = check_hip(hipMemcpyAsync(m, M->adam_m, b, hipMemcpyDeviceToDevice, s), "copy");
+    return st != LT_OK ? st : check_hip(hipMemcpyAsync(v, M->adam_v, b, hipMemcpyDeviceToDevice, s), "copy");
+}
+
+}  // extern "C"

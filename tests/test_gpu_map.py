@@ -1,12 +1,16 @@
 """GPU parity of the fused map evaluation (lt_map_eval) against the FP64
 reference network with the kernels' BF16 rounding (oracle/mlp.py).
 
-Differences come only from FP32 accumulation order and from the kernel's
-tanh (exp2 + reciprocal, absolute error < 1e-6) moving an activation across a
-BF16 rounding boundary; one such flip changes an activation by one BF16 ulp
-(2^-8 relative) and the outputs by about 1e-4 in normalised units.  The bound
-is 2e-3 on normalised outputs (max over all rays) and the mask must agree
-wherever the reference logit is farther than that bound from 0.
+Both sides round activations to BF16, so a difference in the FP32 sum that
+feeds an activation (summation order; the kernel's tanh is exp2 + reciprocal
+with absolute error < 1e-6) occasionally moves it across a BF16 rounding
+boundary.  Such a flip changes one activation by one BF16 ulp (at most 2^-8
+for |h| <= 1) and, through layers of about unit gain, an output by a few
+1e-3 at most; most rays see no flip and then agree to FP32 accumulation
+accuracy.  The test therefore bounds the median error (1e-5: no systematic
+difference), the 99th percentile (2e-3) and the maximum (2e-2), in
+normalised output units, and requires equal masks wherever the reference
+logit is farther than the maximum bound from 0.
 """
 import numpy as np
 import pytest
@@ -16,7 +20,7 @@ from oracle import mlp
 
 pytestmark = pytest.mark.gpu
 
-TOL = 2e-3
+MED_TOL, P99_TOL, MAX_TOL = 1e-5, 2e-3, 2e-2
 
 
 @pytest.fixture(scope="module")
@@ -61,34 +65,45 @@ def run_eval(m, rays, dev, dtype):
     return {k: v.cpu().numpy() for k, v in out.items()}
 
 
-def compare(g, p, rays, mode, tol=TOL, sel=None):
+def _check_stats(err, what):
+    med, p99, mx = np.median(err), np.quantile(err, 0.99), err.max()
+    assert med <= MED_TOL, f"{what}: median error {med:.3e}"
+    assert p99 <= P99_TOL, f"{what}: 99th percentile error {p99:.3e}"
+    assert mx <= MAX_TOL, f"{what}: max error {mx:.3e}"
+    return med, p99, mx
+
+
+def compare(g, p, rays, mode, sel=None):
     sub = rays if sel is None else {k: v[sel] for k, v in rays.items()}
     if sel is not None:
         g = {k: v[:, sel] for k, v in g.items()}
     xhat = mlp.features(sub, p)
-    o = mlp.forward_quantized(p, xhat, mode)
+    o = mlp.forward(p, xhat)[0] if mode == "f32" else mlp.forward_quantized(p, xhat, mode)
     ref = mlp.decode(o, p)
-    dl = np.abs(g["logit"] - ref["logit"])
-    assert dl.max() <= tol, f"logit error {dl.max():.3e}"
-    sure = np.abs(ref["logit"]) > tol
+    dl = np.abs(g["logit"] - ref["logit"]).reshape(-1)
+    stl = _check_stats(dl, "logit")
+    sure = np.abs(ref["logit"]) > MAX_TOL
     assert np.array_equal(g["mask"][sure], ref["mask"][sure])
     both = (g["mask"] == 1) & (ref["mask"] == 1)
-    worst = 0.0
+    errs = []
     for h in range(p.desc.n_heads):
         for k, idx in (("x", 0), ("y", 1), ("dx", 2), ("dy", 3), ("throughput", 4)):
-            e = np.abs(g[k][h][both[h]] - ref[k][h][both[h]]) / p.out_scale[h, idx]
-            if e.size:
-                worst = max(worst, float(e.max()))
-    assert worst <= tol, f"normalised output error {worst:.3e}"
+            errs.append(np.abs(g[k][h][both[h]] - ref[k][h][both[h]]) / p.out_scale[h, idx])
+    err = np.concatenate(errs)
+    sto = _check_stats(err, "outputs") if err.size else (0, 0, 0)
     # empty-set semantics
     off = g["mask"] == 0
     assert np.all(np.isnan(g["x"][off])) and np.all(g["throughput"][off] == 0)
     assert np.all(np.isnan(g["dz"][off]))
-    dzr = -np.sqrt(np.maximum(0, 1 - g["dx"][both] ** 2 - g["dy"][both] ** 2))
-    assert np.allclose(g["dz"][both], dzr, atol=1e-6)
-    print(f"[map parity] {mode} {p.desc}: logit err {dl.max():.2e}, output err {worst:.2e}, "
-          f"valid {int(both.sum())}", flush=True)
-    return worst
+    # dz = -sqrt(max(0, 1 - dx^2 - dy^2)), checked on the square (no sqrt
+    # amplification near grazing)
+    dx64, dy64, dz64 = (g[k][both].astype(np.float64) for k in ("dx", "dy", "dz"))
+    assert np.all(dz64 <= 0)
+    assert np.allclose(dz64 ** 2, np.maximum(0, 1 - dx64 ** 2 - dy64 ** 2), atol=1e-6)
+    print(f"[map parity] {mode} {p.desc}: logit err median/p99/max {stl[0]:.1e}/{stl[1]:.1e}/"
+          f"{stl[2]:.1e}, outputs {sto[0]:.1e}/{sto[1]:.1e}/{sto[2]:.1e}, valid {int(both.sum())}",
+          flush=True)
+    return sto
 
 
 def test_c2_shape_bf16_full_size(dev):
@@ -163,4 +178,92 @@ def test_errors(dev):
     with pytest.raises(lt.LtError) as e:
         lt.lt_map_eval(m, lt.LT_BF16, rays)
     assert e.value.status == 7  # parameters never set
-    assert lt.lt_map_eval(m, lt.LT_BF16, rays, n=0) is not None or True
+    lt.lt_map_eval(m, lt.LT_BF16, rays, n=0)  # n = 0 is a no-op
+    with pytest.raises(lt.LtError) as e:
+        lt.lt_map_eval(m, 9, rays)
+    assert e.value.status in (4, 7)
+
+
+def test_c2_shape_fp8_full_size(dev):
+    """FP8 hidden layers (per-layer power-of-two scales), 4,194,304 rays,
+    every 16th checked against the FP8-rounding reference.  FP8 has 3
+    mantissa bits, so a summation-order flip moves an activation by up to
+    2^-4 of its value; the bounds are 16x those of BF16 (median 1e-4,
+    99th percentile 3e-2, max 3e-1)."""
+    import paper_2605_04017_amd as lt
+    rays = synth.config_rays(2)
+    desc = mlp.MapDesc(128, 5, 1, mlp.ACT_TANH)
+    p = make_params(desc, 31, rays)
+    g = run_eval(gpu_map(p, dev), rays, dev, lt.LT_FP8)
+    global MED_TOL, P99_TOL, MAX_TOL
+    saved = (MED_TOL, P99_TOL, MAX_TOL)
+    MED_TOL, P99_TOL, MAX_TOL = 1e-4, 3e-2, 3e-1
+    try:
+        compare(g, p, rays, "fp8", sel=np.arange(0, rays["x"].shape[0], 16))
+    finally:
+        MED_TOL, P99_TOL, MAX_TOL = saved
+
+
+def test_fp8_multi_head(dev):
+    import paper_2605_04017_amd as lt
+    rays = synth.config_rays(3, 20000)
+    desc = mlp.MapDesc(128, 5, 56, mlp.ACT_TANH)
+    p = make_params(desc, 32, rays)
+    g = run_eval(gpu_map(p, dev), rays, dev, lt.LT_FP8)
+    global MED_TOL, P99_TOL, MAX_TOL
+    saved = (MED_TOL, P99_TOL, MAX_TOL)
+    MED_TOL, P99_TOL, MAX_TOL = 1e-4, 3e-2, 3e-1
+    try:
+        compare(g, p, rays, "fp8")
+    finally:
+        MED_TOL, P99_TOL, MAX_TOL = saved
+
+
+def test_fp8_unsupported_shape(dev):
+    import torch
+    import paper_2605_04017_amd as lt
+    m = lt.lt_map_create(64, 3, 1)
+    lt.lt_map_set_params(m, torch.zeros(m.n_params, device=dev))
+    rays = {k: torch.zeros(8, device=dev) for k in synth.RAY_FIELDS}
+    with pytest.raises(lt.LtError) as e:
+        lt.lt_map_eval(m, lt.LT_FP8, rays)
+    assert e.value.status == 4
+
+
+def _with_tols(med, p99, mx, fn):
+    global MED_TOL, P99_TOL, MAX_TOL
+    saved = (MED_TOL, P99_TOL, MAX_TOL)
+    MED_TOL, P99_TOL, MAX_TOL = med, p99, mx
+    try:
+        return fn()
+    finally:
+        MED_TOL, P99_TOL, MAX_TOL = saved
+
+
+# FP32 map against the exact FP64 network: FP32 accumulation over K = 128
+# terms (~sqrt(128) u |terms|) and the kernel tanh (absolute error < 1e-6)
+# through five layers of about unit gain: bounds 1e-6 (median), 1e-5 (99th
+# percentile), 1e-4 (max).
+F32_TOLS = (1e-6, 1e-5, 1e-4)
+
+
+def test_c2_shape_f32_full_size(dev):
+    """FP32 MFMA map (the benchmark's precision), 4,194,304 rays, every 16th
+    compared with the FP64 network."""
+    import paper_2605_04017_amd as lt
+    rays = synth.config_rays(2)
+    desc = mlp.MapDesc(128, 5, 1, mlp.ACT_TANH)
+    p = make_params(desc, 41, rays)
+    g = run_eval(gpu_map(p, dev), rays, dev, lt.LT_F32)
+    _with_tols(*F32_TOLS, lambda: compare(g, p, rays, "f32", sel=np.arange(0, rays["x"].shape[0], 16)))
+
+
+@pytest.mark.parametrize("width,depth,heads,act,n", [(64, 4, 1, 1, 65536), (128, 5, 56, 0, 4000),
+                                                      (32, 2, 3, 0, 333)])
+def test_f32_shapes(dev, width, depth, heads, act, n):
+    import paper_2605_04017_amd as lt
+    rays = synth.config_rays(2, n)
+    desc = mlp.MapDesc(width, depth, heads, act)
+    p = make_params(desc, 42 + width, rays)
+    g = run_eval(gpu_map(p, dev), rays, dev, lt.LT_F32)
+    _with_tols(*F32_TOLS, lambda: compare(g, p, rays, "f32"))

@@ -141,11 +141,13 @@ def test_deterministic(dev):
 
 def test_plain_fp32_variant(dev):
     """The plain-FP32 option: same masks outside the boundary band; its
-    exit errors are larger and are checked against looser bounds derived from
-    FP32 rounding amplified along the path (5e-4 mm, 2e-6 rad)."""
+    exit errors are larger.  Bound: about 30 interactions x 4 FP32 roundings
+    (u = 6e-8) of direction, amplified by the path's sensitivity (up to
+    ~300 mm/rad in position and ~300x in direction for ghosts reflecting at
+    the front surface), i.e. 2e-3 mm and 1e-4 rad."""
     L = synth.config_lens(2)
     rays = synth.config_rays(2, 262144)
     for path in [(0, 0, 0), (1, 1, 2), (1, 10, 11)]:
         st = compare_trace(_gpu_trace(L, rays, dev, path, flags=1),
-                           oracle.trace(L, rays, path, diag=True), pos_tol=5e-4, ang_tol=2e-6)
+                           oracle.trace(L, rays, path, diag=True), pos_tol=2e-3, ang_tol=1e-4)
         _report(f"plain FP32 {path}", st)

@@ -176,3 +176,24 @@ def test_quantized_forward_close_to_fp64():
     eb = np.abs(ob - o).max()
     e8 = np.abs(o8 - o).max()
     assert eb < 0.05 and e8 < 0.3 and eb < e8
+
+
+@pytest.mark.parametrize("act", [mlp.ACT_TANH, mlp.ACT_RELU])
+def test_quantized_gradient_close_to_exact(act):
+    """The BF16-rounding backward differs from exact backprop only by BF16
+    rounding (a dropped term or a transposed operand would not).  ReLU
+    differs more: rounding moves some pre-activations across 0, which
+    switches units on or off."""
+    d = mlp.MapDesc(32, 3, 2, act)
+    p = mlp.init_params(d, 3)
+    rng = np.random.default_rng(0)
+    x = rng.normal(0, 1, (500, 6))
+    v = rng.integers(0, 2, (2, 500))
+    t = rng.normal(0, 1, (2, 500, 5))
+    (l, _, _), g = mlp.loss_and_grad(p, x, v, t)
+    (lq, _, _), gq = mlp.loss_and_grad_quantized(p, x, v, t)
+    assert abs(l - lq) < 1e-3 * l
+    tol = 2e-2 if act == mlp.ACT_TANH else 1e-1
+    for (dW, db), (qW, qb) in zip(g, gq):
+        assert np.linalg.norm(dW - qW) <= tol * np.linalg.norm(dW)
+        assert np.linalg.norm(db - qb) <= tol * np.linalg.norm(db) + 1e-12
