@@ -217,6 +217,110 @@ def serving(lt, synth, mlp, dev, n_req=600, loads=(0.5, 0.8), seed=5005):
     return res
 
 
+def multi_path(lt, synth, mlp, dev, n=16777216):
+    """The 16,777,216-ray configuration: transmit + all 55 two-reflection
+    ghosts of the 11-surface lens.  Tracer: one launch per path (56).  Map:
+    one 5 x 128 trunk with 56 heads in one launch, FP32 / BF16 / FP8.  Both
+    write every path's exit rays (the tracer reuses one output set per path
+    launch; the map writes [56][n] fields)."""
+    import numpy as np
+    import torch
+    lens = synth.config_lens(3)
+    rays_np = synth.config_rays(3, n)
+    rays = {k: torch.from_numpy(v).to(dev) for k, v in rays_np.items()}
+    del rays_np
+    h = lt.lt_lens_create(lens.surfaces, lens.glasses)
+    nr = lens.n_refracting
+    paths = [(0, 0, 0)] + [(1, j, i) for j in range(1, nr + 1) for i in range(j + 1, nr + 1)]
+    out = lt.empty_exit(n, dev)
+    stream = torch.cuda.current_stream()
+
+    def trace_all():
+        for p in paths:
+            lt.lt_trace(h, p, rays, out, n, stream)
+    t_trace = time_kernel(trace_all, stream, 2)
+    res = {"paths": len(paths), "rays": n, "trace_all_paths_ms": t_trace * 1e3,
+           "trace_ray_paths_per_s_M": n * len(paths) / t_trace / 1e6}
+    P = len(paths)
+    p = mlp.init_params(mlp.MapDesc(MAP_WIDTH, MAP_DEPTH, P, mlp.ACT_TANH), 9)
+    m = lt.lt_map_create(MAP_WIDTH, MAP_DEPTH, P, lt.LT_ACT_TANH)
+    lt.lt_map_set_params(m, torch.from_numpy(p.flat().astype(np.float32)).to(dev))
+    mout = lt.empty_map_out(P, n, dev)
+    fpr = map_flops_per_ray(heads=P)
+    for name, dt in (("f32", lt.LT_F32), ("bf16", lt.LT_BF16), ("fp8", lt.LT_FP8)):
+        t = time_kernel(lambda: lt.lt_map_eval(m, dt, rays, mout, n, stream), stream, 2)
+        res[f"map_{name}_ms"] = t * 1e3
+        res[f"map_{name}_over_trace"] = t_trace / t
+        res[f"map_{name}_tflops"] = fpr * n / t / 1e12
+    res["map_output_gb"] = P * n * 29 / 1e9
+    del mout, out, rays
+    torch.cuda.empty_cache()
+    return res
+
+
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "map_f32_c2_4M_traffic.md")
+MAP_F32_SOURCES = ("paper_2605_04017_amd/csrc/lt_map_f32.hip", "paper_2605_04017_amd/csrc/lt_map_dev.h",
+                   "paper_2605_04017_amd/csrc/lt_map.h")
+COPY_PROBE_BYTES = 512 << 20
+
+
+def map_f32_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in MAP_F32_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP32 map kernel from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by the
+    counter's reading for a plain copy of known size), or None when the
+    kernel sources changed since the counters were taken."""
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    blk = text.split("```json", 1)[-1].split("```", 1)[0] if "```json" in text else ""
+    try:
+        d = json.loads(blk)
+    except ValueError:
+        return None
+    if d.get("source_hash") != map_f32_source_hash():
+        return None
+    return d
+
+
+def traffic_probe(n=N_RAYS):
+    """Short program for the counter runs: one plain copy of COPY_PROBE_BYTES
+    (a negate kernel: reads and writes that many bytes), then three FP32 map
+    launches on the benchmark workload (random weights: the kernel has no
+    data-dependent control flow)."""
+    import numpy as np
+    import torch
+    import paper_2605_04017_amd as lt
+    import synth
+    from oracle import mlp  # parameter initialiser only
+    dev = torch.device("cuda:0")
+    src = torch.ones(COPY_PROBE_BYTES // 4, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    rays = {k: torch.from_numpy(v).to(dev) for k, v in synth.config_rays(2, n).items()}
+    p = mlp.init_params(mlp.MapDesc(MAP_WIDTH, MAP_DEPTH, 1, mlp.ACT_TANH), 5)
+    m = lt.lt_map_create(MAP_WIDTH, MAP_DEPTH, 1, lt.LT_ACT_TANH)
+    lt.lt_map_set_params(m, torch.from_numpy(p.flat().astype(np.float32)).to(dev))
+    out = lt.empty_map_out(1, n, dev)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        lt.lt_map_eval(m, lt.LT_F32, rays, out, n)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "traffic", "copy_bytes": COPY_PROBE_BYTES, "rays": n,
+                      "source_hash": map_f32_source_hash()}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -225,12 +329,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fit-steps", type=int, default=3000)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-multi-path", action="store_true")
     ap.add_argument("--rays", type=int, default=N_RAYS)
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="only run the short program the HBM counter runs profile")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: every box in this setup has one MI355X; "
               "multi-GPU sharding is described in DESIGN.md, not run.", file=sys.stderr)
         sys.exit(2)
+    if args.traffic_probe:
+        traffic_probe(args.rays)
+        return
 
     import numpy as np
     import torch
@@ -293,6 +403,10 @@ def main():
     fpr = map_flops_per_ray()
     achieved = fpr * n / t_map / 1e12
     trace_tf = trace_flops_per_ray(lens) * n / t_trace / 1e12
+    tr = measured_traffic()
+    traffic = None
+    if tr is not None and tr.get("rays") == n:
+        traffic = tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]
     res = {
         "metric": "Mrays/s map vs GPU brute-force trace at stated exit-ray error; p99 latency",
         "value": n / t_map / 1e6,
@@ -318,8 +432,9 @@ def main():
         "fit": {"steps": args.fit_steps, "batch": 65536, "final_loss": fit_loss, "seconds": t_fit},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": MI355X_FP32_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / MI355X_FP32_MFMA_TFLOPS,
-                     "traffic": None, "kernel": "map_eval_f32_kernel<128, tanh>",
-                     "flops_per_ray": fpr},
+                     "traffic": traffic, "kernel": "map_eval_f32_kernel<128, tanh>",
+                     "flops_per_ray": fpr, "algorithmic_bytes": 53 * n,
+                     "traffic_detail": tr},
         "roofline_other": {
             "map_bf16": {"bound": "mfma", "achieved": fpr * n / t_bf16 / 1e12,
                          "peak": MI355X_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
@@ -331,6 +446,9 @@ def main():
                       "unit": "TFLOP/s", "frac": trace_tf / MI355X_FP32_VECTOR_TFLOPS,
                       "flops_per_ray": trace_flops_per_ray(lens)}},
     }
+    if not args.no_multi_path:
+        res["multi_path_16M"] = multi_path(lt, synth, mlp, dev)
+        print("# multi-path done", file=sys.stderr, flush=True)
     if not args.no_serving:
         res["serving"] = serving(lt, synth, mlp, dev)
         print("# serving done", file=sys.stderr, flush=True)
