@@ -214,11 +214,15 @@ __global__ void pack_fp8_hidden_kernel(const float *__restrict__ P, MapLayout L,
 // forward pass (TRAIN: also store the normalised inputs, every hidden
 // layer's BF16 activations as MFMA B fragments, and the raw outputs).
 // FP8: hidden layers on 16x16x128 FP8 MFMA (width 128, tanh, evaluation only).
-template <int H, int ACT, bool TRAIN, bool FP8>
+// BIG: the output-layer fragments do not fit in LDS (many heads); they are
+// streamed from L2 with one tile of prefetch, and each output tile is
+// transposed through LDS before decoding (evaluation only).
+template <int H, int ACT, bool TRAIN, bool FP8, bool BIG>
 __global__ __launch_bounds__(waves_for<H>() * 64) void map_eval_bf16_kernel(EvalArgs A, lt_rays rays,
                                                                           lt_map_out out)
 {
     static_assert(!FP8 || (H == 128 && ACT == LT_ACT_TANH && !TRAIN), "FP8 path: width 128, tanh");
+    static_assert(!(BIG && TRAIN), "streamed output layer: evaluation only");
     constexpr int T = H / 16, C = H / 32;
     constexpr int kWaves = waves_for<H>();
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
@@ -366,6 +370,78 @@ __global__ __launch_bounds__(waves_for<H>() * 64) void map_eval_bf16_kernel(Eval
         const float *bo = bias + A.D * H;
         const float *out_shift = nrm + 12;
         const float *out_scale = nrm + 12 + 5 * A.P;
+        if constexpr (BIG) {
+            // Output tile `to` (16 rows = slots of heads 2 to and 2 to + 1,
+            // 64 rays) is written to this wave's LDS buffer as [ray][16]
+            // floats, 16-byte chunks XOR-swizzled by ray bits 2..3 (both the
+            // write and the read then touch distinct banks), and read back
+            // one ray per lane: every lane decodes both heads of its own ray
+            // and each store covers 64 consecutive rays of one field.
+            float *xb = reinterpret_cast<float *>(lds + A.xpose) + wave * 1024;
+            const bf16x8 *of = reinterpret_cast<const bf16x8 *>(A.img + A.img_out) + lane;
+            bf16x8 nx[2 * C];
+#pragma unroll
+            for (int cc = 0; cc < 2 * C; ++cc)
+                nx[cc] = of[cc * 64];
+            const int64_t r = ray0 + lane;
+            const float nan = __builtin_nanf("");
+            for (int to = 0; to < A.TO; ++to) {
+                bf16x8 cur[2 * C];
+#pragma unroll
+                for (int cc = 0; cc < 2 * C; ++cc)
+                    cur[cc] = nx[cc];
+                if (to + 1 < A.TO) {
+#pragma unroll
+                    for (int cc = 0; cc < 2 * C; ++cc)
+                        nx[cc] = of[(static_cast<int64_t>(to + 1) * 2 * C + cc) * 64];
+                }
+                const floatx4 bz = *reinterpret_cast<const floatx4 *>(bo + to * 16 + 4 * g);
+                floatx4 o[kNT];
+#pragma unroll
+                for (int cc = 0; cc < 2 * C; ++cc)
+#pragma unroll
+                    for (int nt = 0; nt < kNT; ++nt)
+                        o[nt] = mfma_bf16(cur[cc], bop[nt][cc % C], cc == 0 ? bz : o[nt]);
+#pragma unroll
+                for (int nt = 0; nt < kNT; ++nt)
+                    *reinterpret_cast<floatx4 *>(xb + (nt * 16 + col) * 16 + 4 * (g ^ (col >> 2))) = o[nt];
+                float v[16];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const floatx4 q =
+                        *reinterpret_cast<const floatx4 *>(xb + lane * 16 + 4 * (j ^ ((lane >> 2) & 3)));
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        v[4 * j + i] = q[i];
+                }
+#pragma unroll
+                for (int hh = 0; hh < 2; ++hh) {
+                    const int head = 2 * to + hh;
+                    if (head >= A.P || r >= n)
+                        break;
+                    const float *w = v + 8 * hh;
+                    const float *sh = out_shift + 5 * head, *sc = out_scale + 5 * head;
+                    const float logit = w[0];
+                    const bool m = logit > 0.0f;
+                    const float x = fmaf(sc[0], w[1], sh[0]);
+                    const float y = fmaf(sc[1], w[2], sh[1]);
+                    const float dx = fmaf(sc[2], w[3], sh[2]);
+                    const float dy = fmaf(sc[3], w[4], sh[3]);
+                    const float thr = fmaf(sc[4], w[5], sh[4]);
+                    const float dz = -sqrtf(fmaxf(0.0f, 1.0f - dx * dx - dy * dy));
+                    const int64_t idx = static_cast<int64_t>(head) * n + r;
+                    out.logit[idx] = logit;
+                    out.mask[idx] = m ? 1 : 0;
+                    out.x[idx] = m ? x : nan;
+                    out.y[idx] = m ? y : nan;
+                    out.dx[idx] = m ? dx : nan;
+                    out.dy[idx] = m ? dy : nan;
+                    out.dz[idx] = m ? dz : nan;
+                    out.throughput[idx] = m ? thr : 0.0f;
+                }
+            }
+            continue;
+        }
         for (int to = 0; to < A.TO; ++to) {
             const floatx4 bz = *reinterpret_cast<const floatx4 *>(bo + to * 16 + 4 * g);
             floatx4 o[kNT];
@@ -419,6 +495,29 @@ int num_cus()
     return g_num_cus;
 }
 
+template <int H, int ACT, bool TRAIN, bool FP8, bool BIG>
+static lt_status launch_kernel(EvalArgs A, int64_t dyn_lds, const lt_rays &rays,
+                               const lt_map_out &out, hipStream_t s)
+{
+    auto kern = map_eval_bf16_kernel<H, ACT, TRAIN, FP8, BIG>;
+    static bool attr_set = false;
+    if (!attr_set) {
+        lt_status st = check_hip(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     kMaxLds),
+                                 "hipFuncSetAttribute");
+        if (st != LT_OK)
+            return st;
+        attr_set = true;
+    }
+    constexpr int kWaves = waves_for<H>();
+    const int64_t tiles = (A.n + 64 * kWaves - 1) / (64 * kWaves);
+    const int grid = static_cast<int>(tiles < num_cus() ? tiles : num_cus());
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kWaves * 64), static_cast<size_t>(dyn_lds), s, A,
+                       rays, out);
+    return check_hip(hipGetLastError(), "map_eval_bf16_kernel launch");
+}
+
 template <int H, int ACT, bool TRAIN, bool FP8 = false>
 static lt_status launch_bf16_impl(const Map &M, const lt_rays &rays, const lt_map_out &out,
                                   EvalArgs A, hipStream_t s)
@@ -433,23 +532,17 @@ static lt_status launch_bf16_impl(const Map &M, const lt_rays &rays, const lt_ma
     A.img_out = FP8 ? L.img8_out : L.img_out;
     A.img_bias = FP8 ? L.img8_bias : L.img_bias;
     A.img_hidden = FP8 ? L.img8_hidden : L.img_hidden;
-    auto kern = map_eval_bf16_kernel<H, ACT, TRAIN, FP8>;
-    static bool attr_set = false;
-    if (!attr_set) {
-        lt_status st = check_hip(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                     kMaxLds),
-                                 "hipFuncSetAttribute");
-        if (st != LT_OK)
-            return st;
-        attr_set = true;
-    }
     constexpr int kWaves = waves_for<H>();
-    const int64_t tiles = (A.n + 64 * kWaves - 1) / (64 * kWaves);
-    const int grid = static_cast<int>(tiles < num_cus() ? tiles : num_cus());
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kWaves * 64), static_cast<size_t>(A.lds_bytes), s, A,
-                       rays, out);
-    return check_hip(hipGetLastError(), "map_eval_bf16_kernel launch");
+    if constexpr (!TRAIN) {
+        // the staged part ends on a 1 KiB boundary; the transpose buffers follow it
+        const int64_t big_lds = A.lds_bytes + kWaves * 4096;
+        if (!A.out_from_lds && big_lds <= kMaxLds) {
+            A.xpose = A.lds_bytes;
+            return launch_kernel<H, ACT, TRAIN, FP8, true>(A, big_lds, rays, out, s);
+        }
+    }
+    A.xpose = -1;
+    return launch_kernel<H, ACT, TRAIN, FP8, false>(A, A.lds_bytes, rays, out, s);
 }
 
 template <bool TRAIN>

@@ -135,6 +135,7 @@ struct EvalArgs {
     int32_t D, P, TO;
     int32_t out_from_lds;
     int64_t img_out, img_bias, img_hidden;
+    int64_t xpose;        // LDS offset of the per-wave output transpose buffers (4 KiB each)
     int64_t n;
     // training forward only
     float *xhat_out;      // [6][n_pad]

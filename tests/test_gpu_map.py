@@ -135,6 +135,47 @@ def test_multi_head_56_bf16(dev):
     compare(run_eval(gpu_map(p, dev), rays, dev, lt.LT_BF16), p, rays, "bf16")
 
 
+@pytest.mark.parametrize("width,heads,n,dtype", [(128, 5, 3001, 1), (128, 64, 4099, 1), (64, 64, 2050, 1),
+                                                 (128, 33, 1000, 2), (128, 64, 130, 2)])
+def test_streamed_output_layer(dev, width, heads, n, dtype):
+    """Head counts whose output layer does not fit in LDS (streamed from L2,
+    transposed through LDS before decoding): odd head counts, the maximum
+    of 64, width 64 (eight waves) and ragged ray counts."""
+    import paper_2605_04017_amd as lt
+    rays = synth.config_rays(3, n)
+    desc = mlp.MapDesc(width, 5, heads, mlp.ACT_TANH)
+    p = make_params(desc, 40 + heads + width, synth.config_rays(3, 4096))
+    g = run_eval(gpu_map(p, dev), rays, dev, dtype)
+    global MED_TOL, P99_TOL, MAX_TOL
+    saved = (MED_TOL, P99_TOL, MAX_TOL)
+    if dtype == lt.LT_FP8:
+        MED_TOL, P99_TOL, MAX_TOL = 1e-4, 3e-2, 3e-1
+    try:
+        compare(g, p, rays, "bf16" if dtype == lt.LT_BF16 else "fp8")
+    finally:
+        MED_TOL, P99_TOL, MAX_TOL = saved
+
+
+def test_multi_head_full_size_sampled(dev):
+    """The 56-head map on 16,777,216 rays (the launch the benchmark times),
+    every 1024th ray checked for every head."""
+    import torch
+    import paper_2605_04017_amd as lt
+    n = 16777216
+    rays = synth.config_rays(3, n)
+    desc = mlp.MapDesc(128, 5, 56, mlp.ACT_TANH)
+    p = make_params(desc, 45, {k: v[:65536] for k, v in rays.items()})
+    m = gpu_map(p, dev)
+    r = {k: torch.from_numpy(v).to(dev) for k, v in rays.items()}
+    out = lt.lt_map_eval(m, lt.LT_BF16, r)
+    torch.cuda.synchronize()
+    sel = np.arange(0, n, 1024)
+    g = {k: v[:, ::1024].cpu().numpy() for k, v in out.items()}
+    del out, r
+    torch.cuda.empty_cache()
+    compare(g, p, {k: v[sel] for k, v in rays.items()}, "bf16")
+
+
 @pytest.mark.parametrize("width,heads", [(32, 3), (64, 2)])
 def test_small_widths(dev, width, heads):
     import paper_2605_04017_amd as lt
