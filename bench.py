@@ -239,8 +239,21 @@ def multi_path(lt, synth, mlp, dev, n=16777216):
         for p in paths:
             lt.lt_trace(h, p, rays, out, n, stream)
     t_trace = time_kernel(trace_all, stream, 2)
+    cout = {k: torch.empty(n, dtype=torch.float32, device=dev) for k in lt.EXIT_FIELDS[1:]}
+    cidx = torch.empty(n, dtype=torch.int64, device=dev)
+    counts = torch.empty(len(paths), dtype=torch.int64, device=dev)
+
+    def trace_all_compact():
+        for k, p in enumerate(paths):
+            lt.lt_trace_compact(h, p, rays, cout, cidx, counts[k:k + 1], n, 0, stream)
+    t_compact = time_kernel(trace_all_compact, stream, 2)
+    valid = counts.cpu().numpy()
     res = {"paths": len(paths), "rays": n, "trace_all_paths_ms": t_trace * 1e3,
-           "trace_ray_paths_per_s_M": n * len(paths) / t_trace / 1e6}
+           "trace_ray_paths_per_s_M": n * len(paths) / t_trace / 1e6,
+           "trace_all_paths_compact_ms": t_compact * 1e3,
+           "valid_fraction_transmit": float(valid[0]) / n,
+           "valid_fraction_ghost_mean": float(valid[1:].mean()) / n}
+    del cout, cidx
     P = len(paths)
     p = mlp.init_params(mlp.MapDesc(MAP_WIDTH, MAP_DEPTH, P, mlp.ACT_TANH), 9)
     m = lt.lt_map_create(MAP_WIDTH, MAP_DEPTH, P, lt.LT_ACT_TANH)
@@ -251,6 +264,7 @@ def multi_path(lt, synth, mlp, dev, n=16777216):
         t = time_kernel(lambda: lt.lt_map_eval(m, dt, rays, mout, n, stream), stream, 2)
         res[f"map_{name}_ms"] = t * 1e3
         res[f"map_{name}_over_trace"] = t_trace / t
+        res[f"map_{name}_over_trace_compact"] = t_compact / t
         res[f"map_{name}_tflops"] = fpr * n / t / 1e12
     res["map_output_gb"] = P * n * 29 / 1e9
     del mout, out, rays

@@ -142,6 +142,19 @@ typedef struct {
 int32_t lt_ghost_index(int32_t n_refracting, int32_t j, int32_t i);
 lt_status lt_ghost_path(int32_t n_refracting, int32_t index, lt_path *out);
 
+/* Binary path id (Sec. 3, path-decomposition figure: a path's sequence of scattering events
+ * converted to a binary number).  The paper fixes neither the bit order nor
+ * whether the stop counts; here: a leading 1 (sentinel), then one bit per
+ * refracting-surface interaction (stop excluded) in scene-to-sensor order,
+ * first interaction most significant, reflect = 1.  Transmit = 2^N; ghost
+ * (j, i) has N + 2(i - j) interaction bits with ones at the scene-side
+ * reflection at i and the later one at j.  Host-only helpers.
+ * Errors: LT_ERR_ARG (NULL, N outside 1..LT_MAX_SURFACES), LT_ERR_PATH (invalid
+ * path, an id longer than 64 bits, or an id that is not a transmit or
+ * two-reflection path of an N-surface lens). */
+lt_status lt_path_encode(int32_t n_refracting, const lt_path *path, uint64_t *id);
+lt_status lt_path_decode(int32_t n_refracting, uint64_t id, lt_path *out);
+
 /* ------------------------------------------------------------------ rays */
 
 /* Sensor-side rays, structure of arrays, n entries each (device, float32). */
@@ -190,6 +203,20 @@ lt_status lt_trace(lt_lens lens, const lt_path *path, const lt_rays *rays,
 /* lt_trace with options (0 = same as lt_trace).  Unknown flags: LT_ERR_ARG. */
 lt_status lt_trace_ex(lt_lens lens, const lt_path *path, const lt_rays *rays,
                       const lt_exit *out, int64_t n, uint32_t flags, void *stream);
+
+/* Compacted trace: the same per-ray result as lt_trace_ex, written only for
+ * rays whose path is valid (mask 1; Sec. 4.2: the empty set elsewhere).
+ * out->x .. out->throughput and idx_out (device, capacity n each) receive the
+ * valid rays densely: entry k holds the exit ray of input ray idx_out[k];
+ * *n_valid (device int64) receives their count.  out->mask is not used (may
+ * be NULL).  Rays of one block of 256 consecutive inputs keep their input
+ * order; the order of blocks is unspecified (it follows the order in which
+ * workgroups finish), so sort by idx_out for a canonical order.  The count
+ * is cleared by a kernel on the stream (capture-safe).  n = 0 writes a zero
+ * count.  Errors as lt_trace_ex; NULL count: LT_ERR_ARG. */
+lt_status lt_trace_compact(lt_lens lens, const lt_path *path, const lt_rays *rays,
+                           const lt_exit *out, int64_t *idx_out, int64_t *n_valid, int64_t n,
+                           uint32_t flags, void *stream);
 
 /* ------------------------------------------------------------------ map */
 
@@ -251,6 +278,14 @@ lt_status lt_map_get_params(lt_map map, float *params, int64_t count, void *stre
  * head).  Synchronous copy. */
 lt_status lt_map_set_norm(lt_map map, const float *in_shift, const float *in_scale,
                           const float *out_shift, const float *out_scale);
+
+/* Build the packed copy of the parameters that lt_map_eval uses for dtype
+ * now, on the stream (otherwise the first evaluation after
+ * lt_map_set_params / a training step does it).  Evaluations that may run
+ * concurrently on several streams should be preceded by this call, since
+ * the lazy repack is not serialised between streams.  Errors: LT_ERR_ARG,
+ * LT_ERR_DTYPE, LT_ERR_STATE (parameters never set). */
+lt_status lt_map_quantize(lt_map map, int32_t dtype, void *stream);
 
 /* Evaluate the map for n rays (Sec. 4.2: output f(x) where g(x) = 1).
  * LT_BF16: BF16 MFMA with FP32 accumulation; input layer and output layer

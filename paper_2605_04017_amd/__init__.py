@@ -26,7 +26,8 @@ __all__ = ["LtError", "Lens", "lt_lens_create", "lt_lens_query", "lt_trace", "lt
            "Map", "lt_map_create", "lt_map_set_params", "lt_map_get_params", "lt_map_set_norm",
            "lt_map_eval", "empty_map_out", "MAP_FIELDS", "lt_map_workspace_bytes", "workspace",
            "lt_map_forward_train", "lt_map_backward", "lt_map_train_step", "lt_map_adam_state",
-           "TARGET_FIELDS"]
+           "TARGET_FIELDS", "lt_path_encode", "lt_path_decode", "lt_trace_compact",
+           "lt_map_quantize"]
 
 TARGET_FIELDS = ("valid", "x", "y", "dx", "dy", "throughput")
 
@@ -141,6 +142,21 @@ def lt_ghost_path(n_refracting: int, index: int) -> Tuple[int, int, int]:
     return (p.kind, p.j, p.i)
 
 
+def lt_path_encode(n_refracting: int, path) -> int:
+    """Binary id of a path: sentinel 1, then one bit per refracting-surface
+    interaction in scene-to-sensor order (reflect = 1)."""
+    v = C.c_uint64()
+    p = _path(path)
+    N.check(N.lib().lt_path_encode(n_refracting, C.byref(p), C.byref(v)))
+    return int(v.value)
+
+
+def lt_path_decode(n_refracting: int, path_id: int) -> Tuple[int, int, int]:
+    p = N.lt_path()
+    N.check(N.lib().lt_path_decode(n_refracting, int(path_id), C.byref(p)))
+    return (p.kind, p.j, p.i)
+
+
 def _path(path) -> N.lt_path:
     if isinstance(path, N.lt_path):
         return path
@@ -189,6 +205,34 @@ def lt_trace_ex(lens: Lens, path, rays: Dict, out: Optional[Dict] = None,
                                 C.byref(e), int(n), int(flags),
                                 C.c_void_p(_stream_ptr(stream) if n else 0)))
     return out
+
+
+def lt_trace_compact(lens: Lens, path, rays: Dict, out: Optional[Dict] = None, idx=None,
+                     count=None, n: Optional[int] = None, flags: int = 0, stream=None):
+    """Trace and keep only valid rays: returns (out, idx, count) where the
+    first count[0] entries of out[x .. throughput] are the exit rays of input
+    rays idx[:count[0]] (block order unspecified; sort by idx for a canonical
+    order)."""
+    torch = _torch()
+    if n is None:
+        n = int(rays["x"].numel())
+    dev = rays["x"].device
+    if out is None:
+        out = {k: torch.empty(n, dtype=torch.float32, device=dev) for k in EXIT_FIELDS[1:]}
+    if idx is None:
+        idx = torch.empty(n, dtype=torch.int64, device=dev)
+    if count is None:
+        count = torch.empty(1, dtype=torch.int64, device=dev)
+    e = N.lt_exit()
+    for k in EXIT_FIELDS[1:]:
+        setattr(e, k, _dev_ptr(out[k], torch.float32, n, f"out[{k}]") if n else None)
+    e.mask = None
+    p = _path(path)
+    N.check(N.lib().lt_trace_compact(lens.handle, C.byref(p), C.byref(_rays_struct(rays, n)),
+                                     C.byref(e), _dev_ptr(idx, torch.int64, n, "idx") if n else None,
+                                     _dev_ptr(count, torch.int64, 1, "count"), int(n), int(flags),
+                                     C.c_void_p(_stream_ptr(stream))))
+    return out, idx, count
 
 
 # ------------------------------------------------------------------- map --
@@ -264,6 +308,11 @@ def empty_map_out(n_heads: int, n: int, device="cuda") -> Dict:
         out[k] = torch.empty((n_heads, n), dtype=torch.uint8 if k == "mask" else torch.float32,
                              device=device)
     return out
+
+
+def lt_map_quantize(m: Map, dtype: int, stream=None) -> None:
+    """Build the packed weights lt_map_eval uses for ``dtype`` now."""
+    N.check(N.lib().lt_map_quantize(m.handle, int(dtype), C.c_void_p(_stream_ptr(stream))))
 
 
 def lt_map_eval(m: Map, dtype: int, rays: Dict, out: Optional[Dict] = None,

@@ -79,6 +79,12 @@ SIGNATURES = {
                                 C.POINTER(C.c_int32)]),
     "lt_ghost_index": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32]),
     "lt_ghost_path": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(lt_path)]),
+    "lt_path_encode": (C.c_int, [C.c_int32, C.POINTER(lt_path), C.POINTER(C.c_uint64)]),
+    "lt_path_decode": (C.c_int, [C.c_int32, C.c_uint64, C.POINTER(lt_path)]),
+    "lt_trace_compact": (C.c_int, [C.c_void_p, C.POINTER(lt_path), C.POINTER(lt_rays),
+                                   C.POINTER(lt_exit), C.c_void_p, C.c_void_p, C.c_int64,
+                                   C.c_uint32, C.c_void_p]),
+    "lt_map_quantize": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "lt_trace": (C.c_int, [C.c_void_p, C.POINTER(lt_path), C.POINTER(lt_rays),
                            C.POINTER(lt_exit), C.c_int64, C.c_void_p]),
     "lt_trace_ex": (C.c_int, [C.c_void_p, C.POINTER(lt_path), C.POINTER(lt_rays),

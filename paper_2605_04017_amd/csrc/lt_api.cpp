@@ -246,4 +246,54 @@ lt_status lt_ghost_path(int32_t n, int32_t index, lt_path *out)
     return LT_OK;
 }
 
+lt_status lt_path_encode(int32_t n, const lt_path *path, uint64_t *id)
+{
+    if (!path || !id)
+        return fail(LT_ERR_ARG, "NULL path or output");
+    if (n < 1 || n > LT_MAX_SURFACES)
+        return fail(LT_ERR_ARG, "refracting-surface count out of range");
+    if (path->kind == 0) {
+        *id = 1ull << n;
+        return LT_OK;
+    }
+    if (path->kind != 1 || path->j < 1 || path->i <= path->j || path->i > n)
+        return fail(LT_ERR_PATH, "invalid path");
+    // scene-side order: T at 1..i-1, R at i, T at i-1..j+1, R at j, T at j+1..n
+    const int32_t K = n + 2 * (path->i - path->j);
+    if (K > 63)
+        return fail(LT_ERR_PATH, "path id needs more than 64 bits");
+    const int32_t pos_i = path->i - 1, pos_j = 2 * path->i - path->j - 1;
+    *id = (1ull << K) | (1ull << (K - 1 - pos_i)) | (1ull << (K - 1 - pos_j));
+    return LT_OK;
+}
+
+lt_status lt_path_decode(int32_t n, uint64_t id, lt_path *out)
+{
+    if (!out)
+        return fail(LT_ERR_ARG, "NULL output");
+    if (n < 1 || n > LT_MAX_SURFACES)
+        return fail(LT_ERR_ARG, "refracting-surface count out of range");
+    if (id == 0)
+        return fail(LT_ERR_PATH, "no sentinel bit");
+    const int32_t K = 63 - __builtin_clzll(id);
+    const uint64_t body = id & ~(1ull << K);
+    if (body == 0 && K == n) {
+        out->kind = 0;
+        out->j = out->i = 0;
+        return LT_OK;
+    }
+    if (__builtin_popcountll(body) != 2 || K <= n || (K - n) % 2 != 0)
+        return fail(LT_ERR_PATH, "not a transmit or two-reflection id for this lens");
+    // positions in scene order of the two reflections
+    const int32_t hi_bit = 63 - __builtin_clzll(body), lo_bit = __builtin_ctzll(body);
+    const int32_t pos_i = K - 1 - hi_bit, pos_j = K - 1 - lo_bit;
+    const int32_t i = pos_i + 1, j = 2 * i - 1 - pos_j;
+    if (j < 1 || i <= j || i > n || K != n + 2 * (i - j))
+        return fail(LT_ERR_PATH, "not a transmit or two-reflection id for this lens");
+    out->kind = 1;
+    out->j = j;
+    out->i = i;
+    return LT_OK;
+}
+
 }  // extern "C"

@@ -758,6 +758,23 @@ lt_status lt_map_set_norm(lt_map map, const float *in_shift, const float *in_sca
     return st;
 }
 
+lt_status lt_map_quantize(lt_map map, int32_t dtype, void *stream)
+{
+    Map *M = as_map(map);
+    if (!M)
+        return fail(LT_ERR_ARG, "NULL map");
+    if (dtype != LT_BF16 && dtype != LT_FP8 && dtype != LT_F32)
+        return fail(LT_ERR_DTYPE, "precision not available (LT_F32, LT_BF16, LT_FP8)");
+    if (dtype == LT_FP8 && !M->lay.fp8_ok)
+        return fail(LT_ERR_DTYPE, "LT_FP8 needs width 128 and tanh");
+    if (!M->has_params)
+        return fail(LT_ERR_STATE, "parameters were never set");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (dtype == LT_F32)
+        return ensure_packed_f32(*M, s);
+    return dtype == LT_FP8 ? ensure_packed_fp8(*M, s) : ensure_packed_bf16(*M, s);
+}
+
 lt_status lt_map_eval(lt_map map, int32_t dtype, const lt_rays *rays, const lt_map_out *out,
                       int64_t n, void *stream)
 {

@@ -267,23 +267,30 @@ static lt_status launch_f32(const Map &M, const lt_rays &rays, const lt_map_out 
     return check_hip(hipGetLastError(), "map_eval_f32_kernel launch");
 }
 
-lt_status eval_f32(Map &M, const lt_rays &rays, const lt_map_out &out, int64_t n, hipStream_t s)
+lt_status ensure_packed_f32(Map &M, hipStream_t s)
 {
     const F32Layout F = f32_layout(M.lay);
     if (F.resident + kF32Stage > kMaxLds || F.layer_bytes > kF32Stage)
         return fail(LT_ERR_DTYPE, "map too large for the FP32 path");
-    if (M.packed_f32 != M.version) {
-        const int64_t total = F.bytes / 4;
-        int grid = static_cast<int>((total + 255) / 256);
-        if (grid > 4096)
-            grid = 4096;
-        hipLaunchKernelGGL(pack_f32_kernel, dim3(grid), dim3(256), 0, s, M.master, M.norm, M.lay, F,
-                           reinterpret_cast<float *>(M.img_f32));
-        lt_status st = check_hip(hipGetLastError(), "pack_f32_kernel launch");
-        if (st != LT_OK)
-            return st;
+    if (M.packed_f32 == M.version)
+        return LT_OK;
+    const int64_t total = F.bytes / 4;
+    int grid = static_cast<int>((total + 255) / 256);
+    if (grid > 4096)
+        grid = 4096;
+    hipLaunchKernelGGL(pack_f32_kernel, dim3(grid), dim3(256), 0, s, M.master, M.norm, M.lay, F,
+                       reinterpret_cast<float *>(M.img_f32));
+    lt_status st = check_hip(hipGetLastError(), "pack_f32_kernel launch");
+    if (st == LT_OK)
         M.packed_f32 = M.version;
-    }
+    return st;
+}
+
+lt_status eval_f32(Map &M, const lt_rays &rays, const lt_map_out &out, int64_t n, hipStream_t s)
+{
+    lt_status st = ensure_packed_f32(M, s);
+    if (st != LT_OK)
+        return st;
     const int H = M.lay.H;
     const bool relu = M.lay.act == LT_ACT_RELU;
     if (H == 128)

@@ -39,9 +39,107 @@ __global__ __launch_bounds__(kTraceBlock) void trace_kernel(
     othr[r] = o.valid ? o.I : 0.0f;
 }
 
+// Compacted variant: only rays whose path is valid are written, densely.
+// Each workgroup counts its valid rays (wave ballots), reserves a range
+// with one atomic add on the global counter and writes its rays in input
+// order inside that range; the order of the ranges follows the order in
+// which workgroups reach the atomic.
+template <bool kFast>
+__global__ __launch_bounds__(kTraceBlock) void trace_compact_kernel(
+    TraceTable T, const float *__restrict__ x, const float *__restrict__ y,
+    const float *__restrict__ dx, const float *__restrict__ dy, const float *__restrict__ dz,
+    const float *__restrict__ lam, float *__restrict__ ox, float *__restrict__ oy,
+    float *__restrict__ odx, float *__restrict__ ody, float *__restrict__ odz,
+    float *__restrict__ othr, int64_t *__restrict__ idx, unsigned long long *count, int64_t n)
+{
+    constexpr int kWaves = kTraceBlock / 64;
+    __shared__ int wave_cnt[kWaves];
+    __shared__ unsigned long long base;
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * kTraceBlock + threadIdx.x;
+    RayOut o{};
+    bool valid = false;
+    if (r < n) {
+        o = kFast ? trace_one_fast(T, x[r], y[r], dx[r], dy[r], dz[r], lam[r])
+                  : trace_one_ff(T, x[r], y[r], dx[r], dy[r], dz[r], lam[r]);
+        valid = o.valid;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const unsigned long long bal = __ballot(valid);
+    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0)
+        wave_cnt[wave] = __popcll(bal);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int total = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w)
+            total += wave_cnt[w];
+        base = total ? atomicAdd(count, static_cast<unsigned long long>(total)) : 0ull;
+    }
+    __syncthreads();
+    if (!valid)
+        return;
+    int off = before;
+    for (int w = 0; w < wave; ++w)
+        off += wave_cnt[w];
+    const int64_t k = static_cast<int64_t>(base) + off;
+    ox[k] = o.x;
+    oy[k] = o.y;
+    odx[k] = o.dx;
+    ody[k] = o.dy;
+    odz[k] = o.dz;
+    othr[k] = o.I;
+    idx[k] = r;
+}
+
+// Clears the compaction counter with an ordinary kernel store (usable under
+// stream capture).
+__global__ void zero_count_kernel(unsigned long long *count)
+{
+    if (threadIdx.x == 0)
+        *count = 0ull;
+}
+
 }  // namespace lt
 
 using namespace lt;
+
+extern "C" lt_status lt_trace_compact(lt_lens lens, const lt_path *path, const lt_rays *rays,
+                                      const lt_exit *out, int64_t *idx_out, int64_t *n_valid,
+                                      int64_t n, uint32_t flags, void *stream)
+{
+    Lens *L = as_lens(lens);
+    if (!L || !path || !rays || !out || !n_valid)
+        return fail(LT_ERR_ARG, "NULL lens, path, rays, out or count");
+    if (n < 0)
+        return fail(LT_ERR_ARG, "negative ray count");
+    if (flags & ~static_cast<uint32_t>(LT_TRACE_PLAIN_FP32))
+        return fail(LT_ERR_ARG, "unknown trace flag");
+    TraceTable table;
+    lt_status st = build_trace_table(*L, *path, &table);
+    if (st != LT_OK)
+        return st;
+    if (n > 0) {
+        if (!rays->x || !rays->y || !rays->dx || !rays->dy || !rays->dz || !rays->lambda_nm)
+            return fail(LT_ERR_ARG, "NULL ray field");
+        if (!out->x || !out->y || !out->dx || !out->dy || !out->dz || !out->throughput || !idx_out)
+            return fail(LT_ERR_ARG, "NULL output field or index array");
+    }
+    const int64_t blocks = (n + kTraceBlock - 1) / kTraceBlock;
+    if (blocks > 0x7fffffffLL)
+        return fail(LT_ERR_ARG, "too many rays for one launch");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    unsigned long long *count = reinterpret_cast<unsigned long long *>(n_valid);
+    hipLaunchKernelGGL(zero_count_kernel, dim3(1), dim3(64), 0, s, count);
+    st = check_hip(hipGetLastError(), "zero_count_kernel launch");
+    if (st != LT_OK || n == 0)
+        return st;
+    auto kern = (flags & LT_TRACE_PLAIN_FP32) ? trace_compact_kernel<true> : trace_compact_kernel<false>;
+    hipLaunchKernelGGL(kern, dim3(static_cast<uint32_t>(blocks)), dim3(kTraceBlock), 0, s, table,
+                       rays->x, rays->y, rays->dx, rays->dy, rays->dz, rays->lambda_nm, out->x, out->y,
+                       out->dx, out->dy, out->dz, out->throughput, idx_out, count, n);
+    return check_hip(hipGetLastError(), "trace_compact_kernel launch");
+}
 
 extern "C" lt_status lt_trace_ex(lt_lens lens, const lt_path *path, const lt_rays *rays,
                                  const lt_exit *out, int64_t n, uint32_t flags, void *stream)

@@ -186,6 +186,12 @@ class GpuExecutor:
         self.events = [None] * n_slots
         self.lenses, self.maps = lenses, maps
         self.mode, self.dtype = mode, dtype
+        if mode == "map":
+            # packed weights built once, before chunks of one map run on several streams
+            import paper_2605_04017_amd as lt
+            for m in maps:
+                lt.lt_map_quantize(m, dtype)
+            torch.cuda.synchronize()
         self.outputs = outputs if outputs is not None else {}
         self.t0_event = torch.cuda.Event(enable_timing=True)
         self.t0_host = None

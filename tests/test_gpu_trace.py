@@ -151,3 +151,52 @@ def test_plain_fp32_variant(dev):
         st = compare_trace(_gpu_trace(L, rays, dev, path, flags=1),
                            oracle.trace(L, rays, path, diag=True), pos_tol=2e-3, ang_tol=1e-4)
         _report(f"plain FP32 {path}", st)
+
+
+@pytest.mark.parametrize("cfg,path,n,flags", [(1, (0, 0, 0), 65536, 0), (2, (1, 2, 7), 100003, 0),
+                                              (2, (0, 0, 0), 1, 0), (2, (1, 4, 9), 70001, 1),
+                                              (3, (1, 1, 11), 1 << 20, 0)])
+def test_trace_compact_matches_trace(dev, cfg, path, n, flags):
+    """lt_trace_compact writes exactly the valid rays of lt_trace_ex, with
+    bit-identical fields; indices are unique, and within each block of 256
+    input rays they appear in input order."""
+    import torch
+    import paper_2605_04017_amd as lt
+    L = synth.config_lens(cfg)
+    rays = synth.config_rays(cfg, n)
+    h = lt.lt_lens_create(L.surfaces, L.glasses)
+    r = _to_dev(rays, dev)
+    full = lt.lt_trace_ex(h, path, r, None, n, flags)
+    out, idx, cnt = lt.lt_trace_compact(h, path, r, flags=flags)
+    torch.cuda.synchronize()
+    c = int(cnt.item())
+    m = full["mask"].bool()
+    assert c == int(m.sum().item())
+    got = idx[:c]
+    order = torch.argsort(got)
+    sidx = got[order]
+    assert torch.equal(sidx, torch.nonzero(m).flatten())
+    for k in ("x", "y", "dx", "dy", "dz", "throughput"):
+        assert torch.equal(out[k][:c][order], full[k][sidx]), k
+    blk = (got // 256).cpu().numpy()
+    g = got.cpu().numpy()
+    # each block's rays are contiguous and increasing
+    starts = np.flatnonzero(np.r_[True, blk[1:] != blk[:-1]])
+    assert len(np.unique(blk)) == len(starts)
+    same = blk[1:] == blk[:-1]
+    assert np.all(g[1:][same] > g[:-1][same])
+    print(f"[compact] cfg {cfg} path {path} n {n}: {c} valid", flush=True)
+
+
+def test_trace_compact_empty_and_errors(dev):
+    import torch
+    import paper_2605_04017_amd as lt
+    L = synth.config_lens(1)
+    h = lt.lt_lens_create(L.surfaces, L.glasses)
+    r = _to_dev(synth.config_rays(1, 16), dev)
+    cnt = torch.full((1,), -5, dtype=torch.int64, device=dev)
+    lt.lt_trace_compact(h, (0, 0, 0), r, count=cnt, n=0)
+    torch.cuda.synchronize()
+    assert int(cnt.item()) == 0
+    with pytest.raises(lt.LtError):
+        lt.lt_trace_compact(h, (1, 2, 2), r)
