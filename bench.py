@@ -108,10 +108,12 @@ def time_kernel(fn, stream, reps):
     return e0.elapsed_time(e1) / reps * 1e-3
 
 
-def fit_map(lt, synth, mlp, lens, dev, steps, batch=65536, seed=3002):
+def fit_map(lt, synth, mlp, lens, dev, steps, batch=65536, seed=3002, canonical=False):
     """Fit the 5 x 128 tanh map on rays the GPU tracer labels (a fresh
     65,536-ray batch per step drawn from a 4M-ray pool that does not overlap
-    the benchmark rays).  Returns (map, params as MapParams, final loss)."""
+    the benchmark rays).  canonical: symmetry-reduced input frame (the
+    normalisation statistics are then taken in that frame).  Returns (map,
+    params as MapParams, final loss)."""
     import numpy as np
     import torch
     pool_np = synth.make_rays(lens, 4194304, seed)
@@ -119,13 +121,21 @@ def fit_map(lt, synth, mlp, lens, dev, steps, batch=65536, seed=3002):
     h = lt.lt_lens_create(lens.surfaces, lens.glasses)
     ex = lt.lt_trace(h, (0, 0, 0), pool)
     ok = ex["mask"].bool()
-    reg = torch.stack([ex[k][ok] for k in ("x", "y", "dx", "dy", "throughput")], 1).double()
-    x = np.stack([pool_np[k].astype(np.float64) for k in synth.RAY_FIELDS], 1)
-    p = mlp.init_params(mlp.MapDesc(MAP_WIDTH, MAP_DEPTH, 1, mlp.ACT_TANH), 5)
-    p.in_shift, p.in_scale = x.mean(0), 1.0 / x.std(0)
-    p.out_shift = reg.mean(0).cpu().numpy()[None]
-    p.out_scale = reg.std(0).cpu().numpy()[None]
-    m = lt.lt_map_create(MAP_WIDTH, MAP_DEPTH, 1, lt.LT_ACT_TANH)
+    reg = torch.stack([ex[k][ok] for k in ("x", "y", "dx", "dy", "throughput")], 1).double().cpu().numpy()
+    src = pool_np
+    if canonical:
+        src, c, s, flip = mlp.canonical_frame(pool_np)
+        okn = ok.cpu().numpy()
+        reg[:, 0], reg[:, 1], reg[:, 2], reg[:, 3] = mlp.to_canonical_frame(
+            reg[:, 0], reg[:, 1], reg[:, 2], reg[:, 3], c[okn], s[okn], flip[okn])
+    x = np.stack([src[k].astype(np.float64) for k in synth.RAY_FIELDS], 1)
+    sd = x.std(0)
+    sd[sd == 0] = 1.0
+    p = mlp.init_params(mlp.MapDesc(MAP_WIDTH, MAP_DEPTH, 1, mlp.ACT_TANH, canonical), 5)
+    p.in_shift, p.in_scale = x.mean(0), 1.0 / sd
+    p.out_shift = reg.mean(0)[None]
+    p.out_scale = reg.std(0)[None]
+    m = lt.lt_map_create(MAP_WIDTH, MAP_DEPTH, 1, lt.LT_ACT_TANH, canonical)
     lt.lt_map_set_params(m, torch.from_numpy(p.flat().astype(np.float32)).to(dev))
     lt.lt_map_set_norm(m, p.in_shift, p.in_scale, p.out_shift.reshape(-1), p.out_scale.reshape(-1))
     ws = lt.workspace(m, batch)
@@ -215,6 +225,77 @@ def serving(lt, synth, mlp, dev, n_req=600, loads=(0.5, 0.8), seed=5005):
                                   "mrays_s": thr / 1e6, "requests": st["n"]}
         res[key] = out
     return res
+
+
+def train_epoch(lt, synth, mlp, dev, n_total=67108864, batch=65536, seed=4004):
+    """One training epoch of the 5 x 128 map on the training workload: the
+    67,108,864 rays are drawn on the device (lt_rays_generate), labelled by
+    the FP32 tracer (transmit path), and consumed in 1,024 steps of 65,536
+    (lt_map_train_step: forward, BCE + masked L2, backward, Adam).  Times are
+    HIP events on the stream; the wall time of the step loop (Python call
+    overhead included) is reported beside them."""
+    import numpy as np
+    import torch
+    lens = synth.config_lens(4)
+    h = lt.lt_lens_create(lens.surfaces, lens.glasses)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record(stream)
+    rays = lt.lt_rays_generate(h, n_total, seed, stream=stream)
+    ev[1].record(stream)
+    ex = lt.lt_trace(h, (0, 0, 0), rays, None, n_total, stream)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    t_gen = ev[0].elapsed_time(ev[1]) * 1e-3
+    t_trace = ev[1].elapsed_time(ev[2]) * 1e-3
+    tgt = {"valid": ex["mask"].reshape(1, -1)}
+    for f in ("x", "y", "dx", "dy", "throughput"):
+        tgt[f] = ex[f].reshape(1, -1)
+    # normalisation from the first batch (inputs) and its valid rays (outputs)
+    p = mlp.init_params(mlp.MapDesc(MAP_WIDTH, MAP_DEPTH, 1, mlp.ACT_TANH), 6)
+    x0 = np.stack([rays[k][:batch].double().cpu().numpy() for k in synth.RAY_FIELDS], 1)
+    ok = ex["mask"][:batch].bool()
+    reg = torch.stack([ex[k][:batch][ok] for k in ("x", "y", "dx", "dy", "throughput")], 1).double()
+    p.in_shift, p.in_scale = x0.mean(0), 1.0 / x0.std(0)
+    p.out_shift = reg.mean(0).cpu().numpy()[None]
+    p.out_scale = reg.std(0).cpu().numpy()[None]
+    m = lt.lt_map_create(MAP_WIDTH, MAP_DEPTH, 1, lt.LT_ACT_TANH)
+    lt.lt_map_set_params(m, torch.from_numpy(p.flat().astype(np.float32)).to(dev))
+    lt.lt_map_set_norm(m, p.in_shift, p.in_scale, p.out_shift.reshape(-1), p.out_scale.reshape(-1))
+    ws = lt.workspace(m, batch)
+    loss = torch.zeros(3, dtype=torch.float32, device=dev)
+    steps = n_total // batch
+    batches = []
+    for k in range(steps):
+        lo, hi = k * batch, (k + 1) * batch
+        batches.append(({f: v[lo:hi] for f, v in rays.items()},
+                        {f: v[:, lo:hi] for f, v in tgt.items()}))
+    torch.cuda.synchronize()
+    first_loss = None
+    w0 = time.perf_counter()
+    ev[2].record(stream)
+    for k, (rb, tb) in enumerate(batches, 1):
+        lr = 2e-3 * (0.5 ** (k / (steps / 4)))
+        lt.lt_map_train_step(m, rb, tb, {"lr": lr, "step": k, "w_bce": 1.0, "w_l2": 4.0}, ws, loss,
+                             batch, stream)
+        if k == 1:
+            first_loss = loss.clone()
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    t_train = ev[2].elapsed_time(ev[3]) * 1e-3
+    fpr = map_flops_per_ray()
+    valid = float(ex["mask"].float().mean())
+    del batches, rays, ex, tgt, ws
+    torch.cuda.empty_cache()
+    return {"rays": n_total, "batch": batch, "steps": steps,
+            "generate_ms": t_gen * 1e3, "trace_ms": t_trace * 1e3, "train_ms": t_train * 1e3,
+            "step_ms": t_train / steps * 1e3, "train_wall_s": wall,
+            "train_mrays_s": n_total / t_train / 1e6,
+            "train_tflops_3x_forward": 3 * fpr * n_total / t_train / 1e12,
+            "valid_fraction": valid,
+            "loss_first_step": [float(v) for v in first_loss.cpu()],
+            "loss_last_step": [float(v) for v in loss.cpu()]}
 
 
 def multi_path(lt, synth, mlp, dev, n=16777216):
@@ -344,6 +425,7 @@ def main():
     ap.add_argument("--fit-steps", type=int, default=3000)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-multi-path", action="store_true")
+    ap.add_argument("--no-train-epoch", action="store_true")
     ap.add_argument("--rays", type=int, default=N_RAYS)
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only run the short program the HBM counter runs profile")
@@ -412,6 +494,14 @@ def main():
                                                 stream), stream, reps)
     errors = {name: map_error(lt, oracle, lens, m, dt, rays_np, rays)
               for name, dt in (("f32", lt.LT_F32), ("bf16", lt.LT_BF16), ("fp8", lt.LT_FP8))}
+    # the symmetry-reduced input frame, fitted with the same budget
+    t_c = time.perf_counter()
+    mc, _, fit_loss_c = fit_map(lt, synth, mlp, lens, dev, args.fit_steps, canonical=True)
+    t_c = time.perf_counter() - t_c
+    errors["f32_canonical_input"] = map_error(lt, oracle, lens, mc, lt.LT_F32, rays_np, rays)
+    errors["f32_canonical_input"]["fit_final_loss"] = fit_loss_c
+    t_map_c = time_kernel(lambda: lt.lt_map_eval(mc, lt.LT_F32, rays, mout, n, stream), stream, 3)
+    del mc
     print("# map errors measured", file=sys.stderr, flush=True)
 
     fpr = map_flops_per_ray()
@@ -441,7 +531,8 @@ def main():
         "trace_plain_fp32_mrays_s": n / t_fast / 1e6,
         "map_over_trace": {"f32": t_trace / t_map, "bf16": t_trace / t_bf16, "fp8": t_trace / t_fp8},
         "kernel_ms": {"trace": t_trace * 1e3, "trace_plain_fp32": t_fast * 1e3,
-                      "map_f32": t_map * 1e3, "map_bf16": t_bf16 * 1e3, "map_fp8": t_fp8 * 1e3},
+                      "map_f32": t_map * 1e3, "map_bf16": t_bf16 * 1e3, "map_fp8": t_fp8 * 1e3,
+                      "map_f32_canonical_input": t_map_c * 1e3},
         "map_error_vs_fp64_oracle": errors,
         "fit": {"steps": args.fit_steps, "batch": 65536, "final_loss": fit_loss, "seconds": t_fit},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": MI355X_FP32_MFMA_TFLOPS,
@@ -460,6 +551,9 @@ def main():
                       "unit": "TFLOP/s", "frac": trace_tf / MI355X_FP32_VECTOR_TFLOPS,
                       "flops_per_ray": trace_flops_per_ray(lens)}},
     }
+    if not args.no_train_epoch:
+        res["train_epoch_67M"] = train_epoch(lt, synth, mlp, dev)
+        print("# training epoch done", file=sys.stderr, flush=True)
     if not args.no_multi_path:
         res["multi_path_16M"] = multi_path(lt, synth, mlp, dev)
         print("# multi-path done", file=sys.stderr, flush=True)

@@ -167,6 +167,37 @@ typedef struct {
     const float *lambda_nm;
 } lt_rays;
 
+/* Writable ray arrays for lt_rays_generate (device, float32, n entries each). */
+typedef struct {
+    float *x;
+    float *y;
+    float *dx;
+    float *dy;
+    float *dz;
+    float *lambda_nm;
+} lt_ray_buffers;
+
+/* Settings of the on-device ray generator. */
+typedef struct {
+    uint64_t seed;          /* Philox key word 0 (word 1 is 0) */
+    uint64_t first;         /* counter of ray 0; ray k uses (first + k, 0, 0, 0) */
+    float half_width_mm;    /* sensor frame half extents (36 x 24 mm frame: 18, 12) */
+    float half_height_mm;
+    float lambda_min_nm;    /* wavelength range, uniform */
+    float lambda_max_nm;
+} lt_raygen;
+
+/* Draw n sensor-side rays on the device (training data for Sec. 5.1 "MLP
+ * Training": the paper samples sensor-side inputs and labels them with the
+ * tracer).  Random numbers: Philox4x64-10 (Salmon et al., SC 2011), counter-
+ * based, so ray k depends only on (seed, first + k).  Sensor point uniform on
+ * the frame, target uniform by area on the last surface's clear-aperture disk
+ * in its vertex plane, direction = normalised difference (FP32), wavelength
+ * uniform.  Errors: LT_ERR_ARG (NULL, n < 0, bad extents or range),
+ * LT_ERR_LENS (last surface not in front of the sensor), LT_ERR_DEVICE. */
+lt_status lt_rays_generate(lt_lens lens, const lt_raygen *cfg, const lt_ray_buffers *out,
+                           int64_t n, void *stream);
+
 /* Exit rays on the output plane z = 0 (device, n entries each). */
 typedef struct {
     uint8_t *mask;
@@ -244,6 +275,18 @@ typedef struct {
     int32_t depth;       /* hidden layers, 1..8 */
     int32_t n_heads;     /* paths, 1..64 */
     int32_t activation;  /* lt_activation */
+    int32_t canonical;   /* 1: symmetry-reduced input (Sec. 4.1, geometric
+                            simplification).  Each ray is rotated about the axis
+                            so its sensor point lies on +x and mirrored so its
+                            direction has dy >= 0 (FP32, one rounding per
+                            operation: r = sqrt(x*x + y*y), c = x/r, s = y/r,
+                            dx' = c*dx + s*dy, dy' = |c*dy - s*dx|; identity for
+                            r = 0); the network sees (r, 0, dx', dy', dz, lambda)
+                            and its exit position/direction are mapped back, so
+                            the map is exactly rotation- and mirror-equivariant.
+                            Training targets are moved into the same frame; the
+                            raw outputs of lt_map_forward_train are in it.
+                            0: plain input. */
 } lt_map_desc;
 
 typedef struct lt_map_s *lt_map;

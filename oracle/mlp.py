@@ -52,6 +52,7 @@ class MapDesc:
     depth: int = 5          # hidden layers
     n_heads: int = 1
     activation: int = ACT_TANH
+    canonical: bool = False  # symmetry-reduced input (Sec. 4.1), see canonical_frame
 
 
 @dataclasses.dataclass
@@ -113,7 +114,55 @@ def init_params(desc: MapDesc, seed: int) -> MapParams:
     return MapParams(desc, W, b, np.zeros(6), np.ones(6), np.zeros((H, 5)), np.ones((H, 5)))
 
 
+def canonical_frame(rays: Dict[str, np.ndarray]):
+    """Symmetry reduction of the input (Sec. 4.1, geometric simplification):
+    rotate about the optical axis so the sensor point lies on the +x half
+    line, then mirror in the plane through the axis and that point so the
+    direction's y component is >= 0.  The map commutes with both, so the
+    network only sees r >= 0, y = 0, dy >= 0 and the outputs are mapped back.
+
+    Evaluated in float32 with one rounding per operation (the products,
+    sums, square root and quotients below, in this order), as the kernels do,
+    so both sides feed the network identical canonical inputs.  A sensor
+    point on the axis keeps the identity rotation.  Returns (canonical rays
+    (float32), c, s, flip) with c, s float32 and flip bool."""
+    f32 = np.float32
+    x, y = rays["x"].astype(f32), rays["y"].astype(f32)
+    dx, dy = rays["dx"].astype(f32), rays["dy"].astype(f32)
+    r = np.sqrt(x * x + y * y)
+    pos = r > 0
+    safe = np.where(pos, r, f32(1))
+    c = np.where(pos, x / safe, f32(1)).astype(f32)
+    s = np.where(pos, y / safe, f32(0)).astype(f32)
+    dxr = c * dx + s * dy
+    dyr = c * dy - s * dx
+    flip = dyr < 0
+    dyr = np.where(flip, -dyr, dyr).astype(f32)
+    out = {"x": r.astype(f32), "y": np.zeros_like(r, dtype=f32), "dx": dxr.astype(f32), "dy": dyr,
+           "dz": rays["dz"].astype(f32), "lambda_nm": rays["lambda_nm"].astype(f32)}
+    return out, c, s, flip
+
+
+def to_lab_frame(xo, yo, dxo, dyo, c, s, flip):
+    """Inverse of canonical_frame for exit positions and directions (float64)."""
+    c = np.asarray(c, np.float64)
+    s = np.asarray(s, np.float64)
+    sg = np.where(flip, -1.0, 1.0)
+    yo, dyo = yo * sg, dyo * sg
+    return c * xo - s * yo, s * xo + c * yo, c * dxo - s * dyo, s * dxo + c * dyo
+
+
+def to_canonical_frame(xo, yo, dxo, dyo, c, s, flip):
+    """Lab-frame exit positions and directions into the canonical frame."""
+    c = np.asarray(c, np.float64)
+    s = np.asarray(s, np.float64)
+    sg = np.where(flip, -1.0, 1.0)
+    return c * xo + s * yo, (c * yo - s * xo) * sg, c * dxo + s * dyo, (c * dyo - s * dxo) * sg
+
+
 def features(rays: Dict[str, np.ndarray], p: MapParams) -> np.ndarray:
+    if p.desc.canonical:
+        rays = canonical_frame(rays)[0]
     x = np.stack([rays[k].astype(np.float64) for k in ("x", "y", "dx", "dy", "dz", "lambda_nm")], 1)
     return (x - p.in_shift) * p.in_scale
 
@@ -142,8 +191,9 @@ def forward(p: MapParams, xhat: np.ndarray):
     return h, (hs, zs)
 
 
-def decode(o: np.ndarray, p: MapParams) -> Dict[str, np.ndarray]:
-    """Head outputs (arrays of shape (H, n)) from raw network outputs."""
+def decode(o: np.ndarray, p: MapParams, rays: Dict[str, np.ndarray] = None) -> Dict[str, np.ndarray]:
+    """Head outputs (arrays of shape (H, n)) from raw network outputs; a
+    canonical-input map needs the input rays to map its outputs back."""
     n = o.shape[0]
     H = p.desc.n_heads
     o = o.reshape(n, H, N_OUT).transpose(1, 0, 2)  # (H, n, 6)
@@ -151,6 +201,11 @@ def decode(o: np.ndarray, p: MapParams) -> Dict[str, np.ndarray]:
     mask = logit > 0
     reg = p.out_shift[:, None, :] + p.out_scale[:, None, :] * o[..., 1:]
     x, y, dx, dy, thr = (reg[..., k] for k in range(5))
+    if p.desc.canonical:
+        if rays is None:
+            raise ValueError("a canonical-input map needs the rays to decode")
+        _, c, s, flip = canonical_frame(rays)
+        x, y, dx, dy = to_lab_frame(x, y, dx, dy, c[None], s[None], flip[None])
     dz = -np.sqrt(np.maximum(0.0, 1.0 - dx * dx - dy * dy))
     res = {"logit": logit, "mask": mask.astype(np.uint8)}
     for k, v in (("x", x), ("y", y), ("dx", dx), ("dy", dy), ("dz", dz)):
@@ -256,8 +311,15 @@ def forward_quantized(p: MapParams, xhat: np.ndarray, mode: str):
 
 # ------------------------------------------------------------ training ----
 
-def normalise_targets(t: Dict[str, np.ndarray], p: MapParams) -> np.ndarray:
-    """(H, n, 5) normalised regression targets from per-head traced exit rays."""
+def normalise_targets(t: Dict[str, np.ndarray], p: MapParams,
+                      rays: Dict[str, np.ndarray] = None) -> np.ndarray:
+    """(H, n, 5) normalised regression targets from per-head traced exit rays
+    (for a canonical-input map first moved into each ray's canonical frame)."""
+    t = {k: np.asarray(v, np.float64) for k, v in t.items()}
+    if p.desc.canonical:
+        _, c, s, flip = canonical_frame(rays)
+        t["x"], t["y"], t["dx"], t["dy"] = to_canonical_frame(t["x"], t["y"], t["dx"], t["dy"],
+                                                              c[None], s[None], flip[None])
     stk = np.stack([t[k] for k in ("x", "y", "dx", "dy", "throughput")], -1)  # (H, n, 5)
     return (stk - p.out_shift[:, None, :]) / p.out_scale[:, None, :]
 

@@ -27,7 +27,7 @@ __all__ = ["LtError", "Lens", "lt_lens_create", "lt_lens_query", "lt_trace", "lt
            "lt_map_eval", "empty_map_out", "MAP_FIELDS", "lt_map_workspace_bytes", "workspace",
            "lt_map_forward_train", "lt_map_backward", "lt_map_train_step", "lt_map_adam_state",
            "TARGET_FIELDS", "lt_path_encode", "lt_path_decode", "lt_trace_compact",
-           "lt_map_quantize"]
+           "lt_map_quantize", "lt_rays_generate"]
 
 TARGET_FIELDS = ("valid", "x", "y", "dx", "dy", "throughput")
 
@@ -207,6 +207,25 @@ def lt_trace_ex(lens: Lens, path, rays: Dict, out: Optional[Dict] = None,
     return out
 
 
+def lt_rays_generate(lens: Lens, n: int, seed: int, first: int = 0, half_width: float = 18.0,
+                     half_height: float = 12.0, lam_range=(400.0, 700.0), out: Optional[Dict] = None,
+                     device="cuda", stream=None) -> Dict:
+    """n sensor-side rays drawn on the device (Philox4x64-10, ray k from
+    counter first + k); returns a dict of float32 tensors."""
+    torch = _torch()
+    if out is None:
+        out = {k: torch.empty(n, dtype=torch.float32, device=device) for k in RAY_FIELDS}
+    b = N.lt_ray_buffers()
+    for k in RAY_FIELDS:
+        setattr(b, k, _dev_ptr(out[k], torch.float32, n, f"out[{k}]") if n else None)
+    cfg = N.lt_raygen(int(seed) & 0xFFFFFFFFFFFFFFFF, int(first) & 0xFFFFFFFFFFFFFFFF,
+                      float(half_width), float(half_height), float(lam_range[0]),
+                      float(lam_range[1]))
+    N.check(N.lib().lt_rays_generate(lens.handle, C.byref(cfg), C.byref(b), int(n),
+                                     C.c_void_p(_stream_ptr(stream) if n else 0)))
+    return out
+
+
 def lt_trace_compact(lens: Lens, path, rays: Dict, out: Optional[Dict] = None, idx=None,
                      count=None, n: Optional[int] = None, flags: int = 0, stream=None):
     """Trace and keep only valid rays: returns (out, idx, count) where the
@@ -262,11 +281,15 @@ class Map:
 
 
 def lt_map_create(width: int = 128, depth: int = 5, n_heads: int = 1,
-                  activation: int = N.LT_ACT_TANH) -> Map:
-    d = N.lt_map_desc(6, int(width), int(depth), int(n_heads), int(activation))
+                  activation: int = N.LT_ACT_TANH, canonical: bool = False) -> Map:
+    """``canonical``: symmetry-reduced input frame (rotation + mirror about
+    the optical axis), see lt_map_desc in include/lt.h."""
+    d = N.lt_map_desc(6, int(width), int(depth), int(n_heads), int(activation), int(bool(canonical)))
     h = C.c_void_p()
     N.check(N.lib().lt_map_create(C.byref(d), C.byref(h)))
-    return Map(h.value, width, depth, n_heads, activation)
+    m = Map(h.value, width, depth, n_heads, activation)
+    m.canonical = bool(canonical)
+    return m
 
 
 def lt_map_set_params(m: Map, params, stream=None):

@@ -34,6 +34,7 @@ MapLayout make_layout(const lt_map_desc &d)
     L.D = d.depth;
     L.P = d.n_heads;
     L.act = d.activation;
+    L.canon = d.canonical;
     L.T = L.H / 16;
     L.C = L.H / 32;
     L.TO = (L.P * kHeadSlots + 15) / 16;
@@ -218,13 +219,15 @@ __global__ void pack_fp8_hidden_kernel(const float *__restrict__ P, MapLayout L,
 // streamed from L2 with one tile of prefetch, and each output tile is
 // transposed through LDS before decoding (evaluation only).
 template <int H, int ACT, bool TRAIN, bool FP8, bool BIG>
-__global__ __launch_bounds__(waves_for<H>() * 64) void map_eval_bf16_kernel(EvalArgs A, lt_rays rays,
-                                                                          lt_map_out out)
+__global__ __launch_bounds__((eval_waves<H, TRAIN>() * 64)) void map_eval_bf16_kernel(EvalArgs A, lt_rays rays,
+                                                                                  lt_map_out out)
 {
     static_assert(!FP8 || (H == 128 && ACT == LT_ACT_TANH && !TRAIN), "FP8 path: width 128, tanh");
     static_assert(!(BIG && TRAIN), "streamed output layer: evaluation only");
     constexpr int T = H / 16, C = H / 32;
-    constexpr int kWaves = waves_for<H>();
+    constexpr int kWaves = eval_waves<H, TRAIN>();
+    constexpr int NT = eval_subtiles<H, TRAIN>();  // 16-ray MFMA N tiles per wave
+    constexpr int RPW = 16 * NT;                   // rays per wave tile
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     for (int64_t o = threadIdx.x * 16; o < A.lds_bytes; o += blockDim.x * 16)
         *reinterpret_cast<uint4 *>(lds + o) = *reinterpret_cast<const uint4 *>(A.img + o);
@@ -236,16 +239,17 @@ __global__ __launch_bounds__(waves_for<H>() * 64) void map_eval_bf16_kernel(Eval
     const float *nrm = bias + A.D * H + 16 * A.TO;  // in_shift[6], in_scale[6], out_shift, out_scale
     const uint8_t *out_frag = A.out_from_lds ? lds + A.img_out : A.img + A.img_out;
     const int64_t n = A.n;
-    const int64_t n_tiles = TRAIN ? A.n_pad / 64 : (n + 63) / 64;
+    const int64_t n_tiles = TRAIN ? A.n_pad / RPW : (n + RPW - 1) / RPW;
 
     for (int64_t tile = static_cast<int64_t>(blockIdx.x) * kWaves + wave; tile < n_tiles;
          tile += static_cast<int64_t>(gridDim.x) * kWaves) {
-        const int64_t ray0 = tile * 64;
-        floatx4 acc[kNT][T];
+        const int64_t ray0 = tile * RPW;
+        floatx4 acc[NT][T];
         // ---- input layer: split hi/lo features, one MFMA per M-tile
-        bf16x8 b0[kNT];
+        bf16x8 b0[NT];
+        CanonFrame fr[NT];
 #pragma unroll
-        for (int nt = 0; nt < kNT; ++nt) {
+        for (int nt = 0; nt < NT; ++nt) {
             const int64_t r = ray0 + nt * 16 + col;
             float f[6] = {0, 0, 0, 0, 0, 0};
             if (r < n) {
@@ -255,6 +259,17 @@ __global__ __launch_bounds__(waves_for<H>() * 64) void map_eval_bf16_kernel(Eval
                 f[3] = rays.dy[r];
                 f[4] = rays.dz[r];
                 f[5] = rays.lambda_nm[r];
+            }
+            fr[nt] = CanonFrame{1.0f, 0.0f, 1.0f};
+            if (A.canonical) {
+                fr[nt] = canon_in(f);
+                if constexpr (TRAIN) {
+                    if (g == 0 && A.canon_out) {
+                        A.canon_out[r] = fr[nt].c;
+                        A.canon_out[A.n_pad + r] = fr[nt].s;
+                        A.canon_out[2 * A.n_pad + r] = fr[nt].sg;
+                    }
+                }
             }
             float hi[6], lo[6];
 #pragma unroll
@@ -288,11 +303,11 @@ __global__ __launch_bounds__(waves_for<H>() * 64) void map_eval_bf16_kernel(Eval
             const bf16x8 a = *reinterpret_cast<const bf16x8 *>(lds + t * kFragBytes + lane * 16);
             const floatx4 bz = *reinterpret_cast<const floatx4 *>(bias + t * 16 + 4 * g);
 #pragma unroll
-            for (int nt = 0; nt < kNT; ++nt)
+            for (int nt = 0; nt < NT; ++nt)
                 acc[nt][t] = mfma_bf16(a, b0[nt], bz);
         }
         // ---- hidden layers
-        bf16x8 bop[kNT][C];
+        bf16x8 bop[NT][C];
         if constexpr (FP8) {
             // FP8 operands: lane l holds the 32 outputs of the previous layer
             // for its ray (rows 16t + 4g + i), exactly its 32 K bytes of the
@@ -301,9 +316,9 @@ __global__ __launch_bounds__(waves_for<H>() * 64) void map_eval_bf16_kernel(Eval
             float zs = 1.0f;
             for (int l = 1; l < A.D; ++l) {
                 const float sh = sc[2 * (l - 1) + 1];
-                intx8 b8[kNT];
+                intx8 b8[NT];
 #pragma unroll
-                for (int nt = 0; nt < kNT; ++nt) {
+                for (int nt = 0; nt < NT; ++nt) {
                     int w[8];
 #pragma unroll
                     for (int q = 0; q < 8; ++q)
@@ -320,13 +335,13 @@ __global__ __launch_bounds__(waves_for<H>() * 64) void map_eval_bf16_kernel(Eval
                     const intx8 a = *reinterpret_cast<const intx8 *>(wl + t * 2 * kFragBytes + lane * 32);
                     const floatx4 bz = *reinterpret_cast<const floatx4 *>(bl + t * 16 + 4 * g);
 #pragma unroll
-                    for (int nt = 0; nt < kNT; ++nt)
+                    for (int nt = 0; nt < NT; ++nt)
                         acc[nt][t] = mfma_fp8(a, b8[nt], bz);
                 }
                 zs = sc[2 * (l - 1)];
             }
 #pragma unroll
-            for (int nt = 0; nt < kNT; ++nt)
+            for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
                     const floatx4 lo = acc[nt][2 * c], hi = acc[nt][2 * c + 1];
@@ -338,13 +353,13 @@ __global__ __launch_bounds__(waves_for<H>() * 64) void map_eval_bf16_kernel(Eval
         } else {
             for (int l = 1; l <= A.D; ++l) {
     #pragma unroll
-                for (int nt = 0; nt < kNT; ++nt)
+                for (int nt = 0; nt < NT; ++nt)
     #pragma unroll
                     for (int c = 0; c < C; ++c) {
                         bop[nt][c] = act_pack<ACT>(acc[nt][2 * c], acc[nt][2 * c + 1]);
                         if constexpr (TRAIN) {
                             const int64_t fi = ((static_cast<int64_t>(l - 1) * (A.n_pad / 16) +
-                                                 tile * kNT + nt) * C + c) * 64 + lane;
+                                                 tile * NT + nt) * C + c) * 64 + lane;
                             reinterpret_cast<bf16x8 *>(A.hfrag_out)[fi] = bop[nt][c];
                         }
                     }
@@ -352,16 +367,23 @@ __global__ __launch_bounds__(waves_for<H>() * 64) void map_eval_bf16_kernel(Eval
                     break;
                 const uint8_t *wl = lds + A.img_hidden + static_cast<int64_t>(l - 1) * T * C * kFragBytes;
                 const float *bl = bias + l * H;
+                // M tiles in pairs, K chunks inside: 2 x NT independent
+                // accumulator chains between dependent MFMAs
     #pragma unroll
-                for (int t = 0; t < T; ++t) {
-                    const floatx4 bz = *reinterpret_cast<const floatx4 *>(bl + t * 16 + 4 * g);
+                for (int t0 = 0; t0 < T; t0 += 2) {
+                    const floatx4 bz0 = *reinterpret_cast<const floatx4 *>(bl + t0 * 16 + 4 * g);
+                    const floatx4 bz1 = *reinterpret_cast<const floatx4 *>(bl + (t0 + 1) * 16 + 4 * g);
     #pragma unroll
                     for (int c = 0; c < C; ++c) {
-                        const bf16x8 a =
-                            *reinterpret_cast<const bf16x8 *>(wl + (t * C + c) * kFragBytes + lane * 16);
     #pragma unroll
-                        for (int nt = 0; nt < kNT; ++nt)
-                            acc[nt][t] = mfma_bf16(a, bop[nt][c], c == 0 ? bz : acc[nt][t]);
+                        for (int u = 0; u < 2; ++u) {
+                            const int t = t0 + u;
+                            const bf16x8 a =
+                                *reinterpret_cast<const bf16x8 *>(wl + (t * C + c) * kFragBytes + lane * 16);
+    #pragma unroll
+                            for (int nt = 0; nt < NT; ++nt)
+                                acc[nt][t] = mfma_bf16(a, bop[nt][c], c == 0 ? (u ? bz1 : bz0) : acc[nt][t]);
+                        }
                     }
                 }
             }
@@ -372,19 +394,28 @@ __global__ __launch_bounds__(waves_for<H>() * 64) void map_eval_bf16_kernel(Eval
         const float *out_scale = nrm + 12 + 5 * A.P;
         if constexpr (BIG) {
             // Output tile `to` (16 rows = slots of heads 2 to and 2 to + 1,
-            // 64 rays) is written to this wave's LDS buffer as [ray][16]
+            // RPW rays) is written to this wave's LDS buffer as [ray][16]
             // floats, 16-byte chunks XOR-swizzled by ray bits 2..3 (both the
             // write and the read then touch distinct banks), and read back
-            // one ray per lane: every lane decodes both heads of its own ray
-            // and each store covers 64 consecutive rays of one field.
-            float *xb = reinterpret_cast<float *>(lds + A.xpose) + wave * 1024;
+            // by ray: lane l decodes ray l % RPW, both heads when a wave tile
+            // has 64 rays, head l / 32 when it has 32, so every store covers
+            // RPW consecutive rays of one field.
+            constexpr int kHeadsPerLane = RPW / 32;
+            float *xb = reinterpret_cast<float *>(lds + A.xpose) + wave * (RPW * 16);
             const bf16x8 *of = reinterpret_cast<const bf16x8 *>(A.img + A.img_out) + lane;
             bf16x8 nx[2 * C];
 #pragma unroll
             for (int cc = 0; cc < 2 * C; ++cc)
                 nx[cc] = of[cc * 64];
-            const int64_t r = ray0 + lane;
+            const int rl = lane % RPW;          // this lane's ray in the wave tile
+            const int hh0 = lane / RPW;         // first head slot it decodes (0 or 1)
+            const int64_t r = ray0 + rl;
             const float nan = __builtin_nanf("");
+            CanonFrame myfr = fr[0];
+#pragma unroll
+            for (int nt = 1; nt < NT; ++nt)
+                if ((rl >> 4) == nt)
+                    myfr = fr[nt];
             for (int to = 0; to < A.TO; ++to) {
                 bf16x8 cur[2 * C];
 #pragma unroll
@@ -396,38 +427,41 @@ __global__ __launch_bounds__(waves_for<H>() * 64) void map_eval_bf16_kernel(Eval
                         nx[cc] = of[(static_cast<int64_t>(to + 1) * 2 * C + cc) * 64];
                 }
                 const floatx4 bz = *reinterpret_cast<const floatx4 *>(bo + to * 16 + 4 * g);
-                floatx4 o[kNT];
+                floatx4 o[NT];
 #pragma unroll
                 for (int cc = 0; cc < 2 * C; ++cc)
 #pragma unroll
-                    for (int nt = 0; nt < kNT; ++nt)
+                    for (int nt = 0; nt < NT; ++nt)
                         o[nt] = mfma_bf16(cur[cc], bop[nt][cc % C], cc == 0 ? bz : o[nt]);
 #pragma unroll
-                for (int nt = 0; nt < kNT; ++nt)
+                for (int nt = 0; nt < NT; ++nt)
                     *reinterpret_cast<floatx4 *>(xb + (nt * 16 + col) * 16 + 4 * (g ^ (col >> 2))) = o[nt];
-                float v[16];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const floatx4 q =
-                        *reinterpret_cast<const floatx4 *>(xb + lane * 16 + 4 * (j ^ ((lane >> 2) & 3)));
+                for (int k2 = 0; k2 < kHeadsPerLane; ++k2) {
+                    const int hh = kHeadsPerLane == 2 ? k2 : hh0;
+                    float w[8];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        v[4 * j + i] = q[i];
-                }
+                    for (int jj = 0; jj < 2; ++jj) {
+                        const int j = 2 * hh + jj;
+                        const floatx4 q =
+                            *reinterpret_cast<const floatx4 *>(xb + rl * 16 + 4 * (j ^ ((rl >> 2) & 3)));
 #pragma unroll
-                for (int hh = 0; hh < 2; ++hh) {
+                        for (int i = 0; i < 4; ++i)
+                            w[4 * jj + i] = q[i];
+                    }
                     const int head = 2 * to + hh;
                     if (head >= A.P || r >= n)
-                        break;
-                    const float *w = v + 8 * hh;
+                        continue;
                     const float *sh = out_shift + 5 * head, *sc = out_scale + 5 * head;
                     const float logit = w[0];
                     const bool m = logit > 0.0f;
-                    const float x = fmaf(sc[0], w[1], sh[0]);
-                    const float y = fmaf(sc[1], w[2], sh[1]);
-                    const float dx = fmaf(sc[2], w[3], sh[2]);
-                    const float dy = fmaf(sc[3], w[4], sh[3]);
+                    float x = fmaf(sc[0], w[1], sh[0]);
+                    float y = fmaf(sc[1], w[2], sh[1]);
+                    float dx = fmaf(sc[2], w[3], sh[2]);
+                    float dy = fmaf(sc[3], w[4], sh[3]);
                     const float thr = fmaf(sc[4], w[5], sh[4]);
+                    if (A.canonical)
+                        canon_out(myfr, x, y, dx, dy);
                     const float dz = -sqrtf(fmaxf(0.0f, 1.0f - dx * dx - dy * dy));
                     const int64_t idx = static_cast<int64_t>(head) * n + r;
                     out.logit[idx] = logit;
@@ -444,13 +478,13 @@ __global__ __launch_bounds__(waves_for<H>() * 64) void map_eval_bf16_kernel(Eval
         }
         for (int to = 0; to < A.TO; ++to) {
             const floatx4 bz = *reinterpret_cast<const floatx4 *>(bo + to * 16 + 4 * g);
-            floatx4 o[kNT];
+            floatx4 o[NT];
 #pragma unroll
             for (int cc = 0; cc < 2 * C; ++cc) {
                 const bf16x8 a = *reinterpret_cast<const bf16x8 *>(
                     out_frag + (static_cast<int64_t>(to) * 2 * C + cc) * kFragBytes + lane * 16);
 #pragma unroll
-                for (int nt = 0; nt < kNT; ++nt)
+                for (int nt = 0; nt < NT; ++nt)
                     o[nt] = mfma_bf16(a, bop[nt][cc % C], cc == 0 ? bz : o[nt]);
             }
             // lanes of even g hold (logit, x, y, dx) of head 2*to + g/2,
@@ -460,7 +494,7 @@ __global__ __launch_bounds__(waves_for<H>() * 64) void map_eval_bf16_kernel(Eval
             const bool hv = head < A.P;
             if constexpr (TRAIN) {
 #pragma unroll
-                for (int nt = 0; nt < kNT; ++nt) {
+                for (int nt = 0; nt < NT; ++nt) {
                     const int64_t r = ray0 + nt * 16 + col;
                     if (!hv || r >= n)
                         continue;
@@ -473,8 +507,9 @@ __global__ __launch_bounds__(waves_for<H>() * 64) void map_eval_bf16_kernel(Eval
                 }
             } else {
 #pragma unroll
-                for (int nt = 0; nt < kNT; ++nt)
-                    decode_store(o[nt], to, g, ray0 + nt * 16 + col, n, A.P, out_shift, out_scale, out);
+                for (int nt = 0; nt < NT; ++nt)
+                    decode_store(o[nt], to, g, ray0 + nt * 16 + col, n, A.P, out_shift, out_scale, out,
+                                 A.canonical != 0, fr[nt]);
             }
         }
     }
@@ -510,8 +545,9 @@ static lt_status launch_kernel(EvalArgs A, int64_t dyn_lds, const lt_rays &rays,
             return st;
         attr_set = true;
     }
-    constexpr int kWaves = waves_for<H>();
-    const int64_t tiles = (A.n + 64 * kWaves - 1) / (64 * kWaves);
+    constexpr int kWaves = eval_waves<H, TRAIN>();
+    constexpr int kRays = 16 * eval_subtiles<H, TRAIN>() * kWaves;  // rays per workgroup pass
+    const int64_t tiles = (A.n + kRays - 1) / kRays;
     const int grid = static_cast<int>(tiles < num_cus() ? tiles : num_cus());
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kWaves * 64), static_cast<size_t>(dyn_lds), s, A,
                        rays, out);
@@ -532,10 +568,12 @@ static lt_status launch_bf16_impl(const Map &M, const lt_rays &rays, const lt_ma
     A.img_out = FP8 ? L.img8_out : L.img_out;
     A.img_bias = FP8 ? L.img8_bias : L.img_bias;
     A.img_hidden = FP8 ? L.img8_hidden : L.img_hidden;
-    constexpr int kWaves = waves_for<H>();
+    A.canonical = L.canon;
     if constexpr (!TRAIN) {
-        // the staged part ends on a 1 KiB boundary; the transpose buffers follow it
-        const int64_t big_lds = A.lds_bytes + kWaves * 4096;
+        // the staged part ends on a 1 KiB boundary; the transpose buffers
+        // (16 floats per ray of a wave tile) follow it
+        constexpr int kWaves = eval_waves<H, TRAIN>();
+        const int64_t big_lds = A.lds_bytes + kWaves * (16 * eval_subtiles<H, TRAIN>()) * 64;
         if (!A.out_from_lds && big_lds <= kMaxLds) {
             A.xpose = A.lds_bytes;
             return launch_kernel<H, ACT, TRAIN, FP8, true>(A, big_lds, rays, out, s);
@@ -630,6 +668,8 @@ lt_status lt_map_create(const lt_map_desc *desc, lt_map *out)
         return fail(LT_ERR_ARG, "n_heads must be in 1..64");
     if (d.activation != LT_ACT_TANH && d.activation != LT_ACT_RELU)
         return fail(LT_ERR_ARG, "unknown activation");
+    if (d.canonical != 0 && d.canonical != 1)
+        return fail(LT_ERR_ARG, "canonical must be 0 or 1");
     Map *M = new (std::nothrow) Map();
     if (!M)
         return fail(LT_ERR_OOM, "host allocation");

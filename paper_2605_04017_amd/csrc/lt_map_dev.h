@@ -24,6 +24,22 @@ constexpr int waves_for()
     return H >= 128 ? 4 : 8;
 }
 
+// Evaluation at width 128 runs eight waves of 32 rays (two N tiles) so that
+// two waves share each SIMD and one's tanh epilogue overlaps the other's
+// MFMAs; the training forward keeps four waves of 64 rays (its stored
+// fragment layout and the backward kernels assume 64-ray wave tiles).
+template <int H, bool TRAIN>
+constexpr int eval_subtiles()
+{
+    return (H >= 128 && !TRAIN) ? 2 : kNT;
+}
+
+template <int H, bool TRAIN>
+constexpr int eval_waves()
+{
+    return (H >= 128 && !TRAIN) ? 8 : waves_for<H>();
+}
+
 // K permutation inside a 32-chunk: logical k' (lane group g = k'/8, item j)
 // to the physical row of that chunk.  With it, the FP32 accumulators of
 // M-tiles 2c and 2c+1 (lane l holds rows 4*(l/16)+i of each) are exactly the
@@ -136,6 +152,8 @@ struct EvalArgs {
     int32_t out_from_lds;
     int64_t img_out, img_bias, img_hidden;
     int64_t xpose;        // LDS offset of the per-wave output transpose buffers (4 KiB each)
+    int32_t canonical;    // symmetry-reduced input frame
+    float *canon_out;     // training forward: [3][n_pad] frame (c, s, sg) per ray, or null
     int64_t n;
     // training forward only
     float *xhat_out;      // [6][n_pad]
@@ -144,14 +162,64 @@ struct EvalArgs {
     int64_t n_pad, o_stride;
 };
 
+// Symmetry-reduced input frame (Sec. 4.1): rotation taking the sensor point
+// to the +x half line, then the mirror y -> -y when the rotated direction has
+// dy < 0.  One FP32 rounding per operation (contraction off), the same
+// sequence the host reference evaluates.  f[0..3] = x, y, dx, dy are replaced
+// by r, 0, dx', dy'; (c, s, sg) describe the frame (sg = -1 when mirrored).
+struct CanonFrame {
+    float c, s, sg;
+};
+
+__device__ __forceinline__ CanonFrame canon_in(float *f)
+{
+#pragma clang fp contract(off)
+    const float x = f[0], y = f[1], dx = f[2], dy = f[3];
+    const float xx = x * x, yy = y * y;
+    const float r = sqrtf(xx + yy);
+    CanonFrame F{1.0f, 0.0f, 1.0f};
+    if (r > 0.0f) {
+        F.c = x / r;
+        F.s = y / r;
+    }
+    const float a = F.c * dx, b = F.s * dy;
+    const float dxr = a + b;
+    const float e = F.c * dy, q = F.s * dx;
+    float dyr = e - q;
+    if (dyr < 0.0f) {
+        dyr = -dyr;
+        F.sg = -1.0f;
+    }
+    f[0] = r;
+    f[1] = 0.0f;
+    f[2] = dxr;
+    f[3] = dyr;
+    return F;
+}
+
+// Exit position and direction from the canonical frame back to the lens frame.
+__device__ __forceinline__ void canon_out(const CanonFrame &F, float &x, float &y, float &dx, float &dy)
+{
+#pragma clang fp contract(off)
+    const float ym = y * F.sg, dym = dy * F.sg;
+    const float X = F.c * x - F.s * ym, Y = F.s * x + F.c * ym;
+    const float DX = F.c * dx - F.s * dym, DY = F.s * dx + F.c * dym;
+    x = X;
+    y = Y;
+    dx = DX;
+    dy = DY;
+}
+
 // Decode one output-layer MFMA tile (output slots 16 to + 4g + i of ray r)
 // into per-head exit rays.  Lanes of even g hold (logit, x, y, dx) of head
 // 2 to + g/2, lanes of odd g hold (dy, throughput, pad, pad) of the same head;
-// one lane exchange (lane ^ 16) brings dy and the logit together.  Every lane
-// must call this (it contains a cross-lane shuffle).
+// one lane exchange (lane ^ 16) brings dy and the logit together, and the
+// even lanes write every field but the throughput.  With `canon` the exit
+// position and direction are mapped back from the ray's canonical frame F.
+// Every lane must call this (it contains a cross-lane shuffle).
 __device__ __forceinline__ void decode_store(floatx4 v, int to, int g, int64_t r, int64_t n, int P,
                                              const float *out_shift, const float *out_scale,
-                                             const lt_map_out &out)
+                                             const lt_map_out &out, bool canon, const CanonFrame &F)
 {
     const int head = 2 * to + (g >> 1);
     const bool even = (g & 1) == 0;
@@ -166,21 +234,23 @@ __device__ __forceinline__ void decode_store(floatx4 v, int to, int g, int64_t r
     if (even) {
         const float logit = v[0];
         const bool m = logit > 0.0f;
-        const float x = fmaf(out_scale[5 * hs + 0], v[1], out_shift[5 * hs + 0]);
-        const float y = fmaf(out_scale[5 * hs + 1], v[2], out_shift[5 * hs + 1]);
-        const float dx = fmaf(out_scale[5 * hs + 2], v[3], out_shift[5 * hs + 2]);
-        const float dy = recv;
+        float x = fmaf(out_scale[5 * hs + 0], v[1], out_shift[5 * hs + 0]);
+        float y = fmaf(out_scale[5 * hs + 1], v[2], out_shift[5 * hs + 1]);
+        float dx = fmaf(out_scale[5 * hs + 2], v[3], out_shift[5 * hs + 2]);
+        float dy = recv;
+        if (canon)
+            canon_out(F, x, y, dx, dy);
         const float dz = -sqrtf(fmaxf(0.0f, 1.0f - dx * dx - dy * dy));
         out.logit[idx] = logit;
         out.mask[idx] = m ? 1 : 0;
         out.x[idx] = m ? x : nan;
         out.y[idx] = m ? y : nan;
         out.dx[idx] = m ? dx : nan;
+        out.dy[idx] = m ? dy : nan;
         out.dz[idx] = m ? dz : nan;
     } else {
         const bool m = recv > 0.0f;
         const float thr = fmaf(out_scale[5 * hs + 4], v[1], out_shift[5 * hs + 4]);
-        out.dy[idx] = m ? send : nan;
         out.throughput[idx] = m ? thr : 0.0f;
     }
 }

@@ -104,6 +104,7 @@ struct F32Args {
     const uint8_t *img;
     F32Layout F;
     int32_t D, P, TO;
+    int32_t canonical;
     int64_t n;
 };
 
@@ -118,8 +119,15 @@ __device__ __forceinline__ float act_f32(float z)
     return act<ACT>(z);
 }
 
+// Each hidden layer (64 KiB at width 128) and each group of output tiles is
+// staged into the workgroup's LDS buffer by all its threads between two
+// barriers.  Two workgroups of four waves (32 rays each) share a CU, so the
+// MFMAs of one cover the other's staging; the registers of a wave (two
+// 16-ray N tiles) fit two waves per SIMD.
+constexpr int kF32NT = 2;
+
 template <int H, int ACT>
-__global__ __launch_bounds__(kF32Waves * 64) void map_eval_f32_kernel(F32Args A, lt_rays rays,
+__global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args A, lt_rays rays,
                                                                       lt_map_out out)
 {
     constexpr int T = H / 16, K4 = H / 4;
@@ -134,23 +142,72 @@ __global__ __launch_bounds__(kF32Waves * 64) void map_eval_f32_kernel(F32Args A,
     const float *nrm = bias + A.D * H + 16 * A.TO;
     const float *w0 = reinterpret_cast<const float *>(lds + A.F.w0);
     const int64_t n = A.n;
-    const int64_t wg_tiles = (n + 64 * kF32Waves - 1) / (64 * kF32Waves);
+    const int64_t wg_tiles = (n + 16 * kF32NT * kF32Waves - 1) / (16 * kF32NT * kF32Waves);
+    const int64_t tile_bytes = static_cast<int64_t>(K4) * kF32Frag;
+    const int per_group = static_cast<int>(kF32Stage / tile_bytes);
 
+    // eight 16-byte loads in flight per thread (addresses clamped into the
+    // copy, so no branch separates them), then their LDS writes.  Plain
+    // variables rather than an array keep them in registers, and the
+    // scheduling groups stop the scheduler from pairing each load with its
+    // write (which would expose one memory latency per 16 bytes).  The
+    // writes are unconditional: base is a multiple of 8 chunks = 32 KiB below
+    // bytes <= 64 KiB, so every write lands inside the stage (bytes past
+    // `bytes` receive clamped copies that nothing reads).
     auto stage_bytes = [&](const uint8_t *src, int64_t bytes) {
+        constexpr int64_t kChunk = kF32Waves * 64 * 16;
         __syncthreads();
-        for (int64_t o = threadIdx.x * 16; o < bytes; o += blockDim.x * 16)
-            *reinterpret_cast<uint4 *>(stage + o) = *reinterpret_cast<const uint4 *>(src + o);
+        for (int64_t base = 0; base < bytes; base += 8 * kChunk) {
+            const int64_t o = base + threadIdx.x * 16;
+            auto ld = [&](int64_t off) {
+                return *reinterpret_cast<const uint4 *>(src + (off < bytes ? off : bytes - 16));
+            };
+            const uint4 v0 = ld(o), v1 = ld(o + kChunk), v2 = ld(o + 2 * kChunk), v3 = ld(o + 3 * kChunk);
+            const uint4 v4 = ld(o + 4 * kChunk), v5 = ld(o + 5 * kChunk), v6 = ld(o + 6 * kChunk);
+            const uint4 v7 = ld(o + 7 * kChunk);
+            uint4 *d = reinterpret_cast<uint4 *>(stage + o);
+            constexpr int64_t s16 = kChunk / 16;
+            d[0] = v0;
+            d[s16] = v1;
+            d[2 * s16] = v2;
+            d[3 * s16] = v3;
+            d[4 * s16] = v4;
+            d[5 * s16] = v5;
+            d[6 * s16] = v6;
+            d[7 * s16] = v7;
+            __builtin_amdgcn_sched_group_barrier(0x0020, 8, 0);   // the VMEM reads
+            __builtin_amdgcn_sched_group_barrier(0x0200, 8, 0);   // then the DS writes
+        }
         __syncthreads();
     };
 
     for (int64_t wt = blockIdx.x; wt < wg_tiles; wt += gridDim.x) {
-        const int64_t ray0 = (wt * kF32Waves + wave) * 64;
-        floatx4 acc[kNT][T];
+        const int64_t ray0 = (wt * kF32Waves + wave) * (16 * kF32NT);
+        floatx4 acc[kF32NT][T];
         // ---- input layer: K = 6 features padded to 8 (two chunks)
-        float xin[kNT][2];
+        float xin[kF32NT][2];
+        CanonFrame fr[kF32NT];
 #pragma unroll
-        for (int nt = 0; nt < kNT; ++nt) {
+        for (int nt = 0; nt < kF32NT; ++nt) {
             const int64_t r = ray0 + nt * 16 + col;
+            fr[nt] = CanonFrame{1.0f, 0.0f, 1.0f};
+            if (A.canonical) {
+                // every lane needs its ray's x, y, dx, dy for the frame
+                float f[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                if (r < n) {
+                    f[0] = rays.x[r];
+                    f[1] = rays.y[r];
+                    f[2] = rays.dx[r];
+                    f[3] = rays.dy[r];
+                }
+                fr[nt] = canon_in(f);
+                const float fz = r < n ? rays.dz[r] : 0.0f, fl = r < n ? rays.lambda_nm[r] : 0.0f;
+                // k = g (0..3) and 4 + g (dz, lambda, pad, pad)
+                const float f0 = g == 0 ? f[0] : g == 1 ? f[1] : g == 2 ? f[2] : f[3];
+                xin[nt][0] = r < n ? (f0 - nrm[g]) * nrm[6 + g] : 0.0f;
+                xin[nt][1] = (r < n && g < 2) ? ((g == 0 ? fz : fl) - nrm[4 + g]) * nrm[10 + g] : 0.0f;
+                continue;
+            }
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 const int k = 4 * c + g;
@@ -170,40 +227,48 @@ __global__ __launch_bounds__(kF32Waves * 64) void map_eval_f32_kernel(F32Args A,
             for (int c = 0; c < 2; ++c) {
                 const float a = w0[(t * 2 + c) * 64 + lane];
 #pragma unroll
-                for (int nt = 0; nt < kNT; ++nt)
+                for (int nt = 0; nt < kF32NT; ++nt)
                     acc[nt][t] = mfma_f32(a, xin[nt][c], c == 0 ? bz : acc[nt][t]);
             }
         }
         // ---- hidden layers, one staged layer at a time
         for (int l = 1; l < A.D; ++l) {
-            float h[kNT][T][4];
+            stage_bytes(A.img + A.F.hidden + static_cast<int64_t>(l - 1) * A.F.layer_bytes,
+                        A.F.layer_bytes);
+            float h[kF32NT][T][4];
 #pragma unroll
-            for (int nt = 0; nt < kNT; ++nt)
+            for (int nt = 0; nt < kF32NT; ++nt)
 #pragma unroll
                 for (int t = 0; t < T; ++t)
 #pragma unroll
                     for (int i = 0; i < 4; ++i)
                         h[nt][t][i] = act_f32<ACT>(acc[nt][t][i]);
-            stage_bytes(A.img + A.F.hidden + static_cast<int64_t>(l - 1) * A.F.layer_bytes,
-                        A.F.layer_bytes);
             const float *wl = reinterpret_cast<const float *>(stage);
             const float *bl = bias + l * H;
+            // K outermost: the T x kF32NT accumulators form independent
+            // chains, so consecutive MFMAs never wait on each other
 #pragma unroll
-            for (int t = 0; t < T; ++t) {
-                const floatx4 bz = *reinterpret_cast<const floatx4 *>(bl + t * 16 + 4 * g);
+            for (int q = 0; q < K4; ++q) {
 #pragma unroll
-                for (int q = 0; q < K4; ++q) {
+                for (int t = 0; t < T; ++t) {
                     const float a = wl[(t * K4 + q) * 64 + lane];
+                    const floatx4 bz = q == 0 ? *reinterpret_cast<const floatx4 *>(bl + t * 16 + 4 * g)
+                                              : acc[0][t];
 #pragma unroll
-                    for (int nt = 0; nt < kNT; ++nt)
+                    for (int nt = 0; nt < kF32NT; ++nt)
                         acc[nt][t] = mfma_f32(a, h[nt][q / 4][q % 4], q == 0 ? bz : acc[nt][t]);
                 }
             }
         }
         // ---- output layer, staged in groups of M-tiles that fit the stage
-        float h[kNT][T][4];
+        // (the first group before the last activations are formed)
+        {
+            const int cnt0 = A.TO < per_group ? A.TO : per_group;
+            stage_bytes(A.img + A.F.out, cnt0 * tile_bytes);
+        }
+        float h[kF32NT][T][4];
 #pragma unroll
-        for (int nt = 0; nt < kNT; ++nt)
+        for (int nt = 0; nt < kF32NT; ++nt)
 #pragma unroll
             for (int t = 0; t < T; ++t)
 #pragma unroll
@@ -212,26 +277,26 @@ __global__ __launch_bounds__(kF32Waves * 64) void map_eval_f32_kernel(F32Args A,
         const float *bo = bias + A.D * H;
         const float *out_shift = nrm + 12;
         const float *out_scale = nrm + 12 + 5 * A.P;
-        const int64_t tile_bytes = static_cast<int64_t>(K4) * kF32Frag;
-        const int per_group = static_cast<int>(kF32Stage / tile_bytes);
         for (int to0 = 0; to0 < A.TO; to0 += per_group) {
             const int cnt = A.TO - to0 < per_group ? A.TO - to0 : per_group;
-            stage_bytes(A.img + A.F.out + to0 * tile_bytes, cnt * tile_bytes);
+            if (to0 > 0)
+                stage_bytes(A.img + A.F.out + to0 * tile_bytes, cnt * tile_bytes);
             const float *wo = reinterpret_cast<const float *>(stage);
             for (int k = 0; k < cnt; ++k) {
                 const int to = to0 + k;
                 const floatx4 bz = *reinterpret_cast<const floatx4 *>(bo + to * 16 + 4 * g);
-                floatx4 o[kNT];
+                floatx4 o[kF32NT];
 #pragma unroll
                 for (int q = 0; q < K4; ++q) {
                     const float a = wo[(k * K4 + q) * 64 + lane];
 #pragma unroll
-                    for (int nt = 0; nt < kNT; ++nt)
+                    for (int nt = 0; nt < kF32NT; ++nt)
                         o[nt] = mfma_f32(a, h[nt][q / 4][q % 4], q == 0 ? bz : o[nt]);
                 }
 #pragma unroll
-                for (int nt = 0; nt < kNT; ++nt)
-                    decode_store(o[nt], to, g, ray0 + nt * 16 + col, n, A.P, out_shift, out_scale, out);
+                for (int nt = 0; nt < kF32NT; ++nt)
+                    decode_store(o[nt], to, g, ray0 + nt * 16 + col, n, A.P, out_shift, out_scale, out,
+                                 A.canonical != 0, fr[nt]);
             }
         }
     }
@@ -247,6 +312,7 @@ static lt_status launch_f32(const Map &M, const lt_rays &rays, const lt_map_out 
     A.D = M.lay.D;
     A.P = M.lay.P;
     A.TO = M.lay.TO;
+    A.canonical = M.lay.canon;
     A.n = n;
     auto kern = map_eval_f32_kernel<H, ACT>;
     static bool attr = false;
@@ -260,7 +326,7 @@ static lt_status launch_f32(const Map &M, const lt_rays &rays, const lt_map_out 
             return st;
         attr = true;
     }
-    const int64_t tiles = (n + 64 * kF32Waves - 1) / (64 * kF32Waves);
+    const int64_t tiles = (n + 16 * kF32NT * kF32Waves - 1) / (16 * kF32NT * kF32Waves);
     const int64_t cap = 2LL * num_cus();
     const int grid = static_cast<int>(tiles < cap ? tiles : cap);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kF32Waves * 64), lds, s, A, rays, out);

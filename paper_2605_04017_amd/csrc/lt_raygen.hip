@@ -1,0 +1,123 @@
+// On-device generator of sensor-side training rays (the data path of the
+// training configuration: rays are drawn on the GPU, traced by lt_trace and
+// fed to lt_map_train_step without leaving HBM).
+//
+// Random numbers: Philox4x64-10 (Salmon, Moraes, Dror and Shaw, "Parallel
+// random numbers: as easy as 1, 2, 3", SC 2011), a counter-based generator:
+// ray k uses counter (first + k, 0, 0, 0) and key (seed, 0), so any slice of
+// the stream can be regenerated independently.  Uniforms take 24 bits of an
+// output word and are exact in FP32.
+//
+// Distribution (the same recipe as the seeded host generator): sensor point
+// uniform on the frame, target point uniform by area on the disk of the last
+// surface's semi-diameter in its vertex plane, direction = normalised
+// (target - sensor point), wavelength uniform in [lambda_min, lambda_max].
+#include <hip/hip_runtime.h>
+
+#include "lt_internal.h"
+
+namespace lt {
+
+struct U64x4 {
+    uint64_t v[4];
+};
+
+__device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                              uint64_t k0, uint64_t k1)
+{
+    constexpr uint64_t kM0 = 0xD2E7470EE14C6C93ull, kM1 = 0xCA5A826395121157ull;
+    constexpr uint64_t kW0 = 0x9E3779B97F4A7C15ull, kW1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t lo0 = kM0 * c0, hi0 = __umul64hi(kM0, c0);
+        const uint64_t lo1 = kM1 * c2, hi1 = __umul64hi(kM1, c2);
+        const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += kW0;
+        k1 += kW1;
+    }
+    return U64x4{{c0, c1, c2, c3}};
+}
+
+// 24-bit uniform in [0, 1) from bits [shift, shift + 24) of a word
+__device__ __forceinline__ float u24(uint64_t w, int shift)
+{
+    return static_cast<float>(static_cast<uint32_t>((w >> shift) & 0xFFFFFFull)) * 0x1.0p-24f;
+}
+
+struct RaygenArgs {
+    uint64_t seed, first;
+    float hw, hh, lam0, lam1;
+    float sd, dist;   // last surface: semi-diameter, sensor-to-vertex distance
+    int64_t n;
+};
+
+__global__ __launch_bounds__(256) void raygen_kernel(RaygenArgs A, float *__restrict__ x,
+                                                     float *__restrict__ y, float *__restrict__ dx,
+                                                     float *__restrict__ dy, float *__restrict__ dz,
+                                                     float *__restrict__ lam)
+{
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= A.n)
+        return;
+    const U64x4 o = philox4x64_10(A.first + static_cast<uint64_t>(k), 0, 0, 0, A.seed, 0);
+    const float u0 = u24(o.v[0], 40), u1 = u24(o.v[1], 40), u2 = u24(o.v[2], 40);
+    const float u3 = u24(o.v[3], 40), u4 = u24(o.v[0], 16);
+    const float sx = fmaf(2.0f * A.hw, u0, -A.hw);
+    const float sy = fmaf(2.0f * A.hh, u1, -A.hh);
+    const float rho = A.sd * sqrtf(u2);
+    float sphi, cphi;
+    sincospif(2.0f * u3, &sphi, &cphi);
+    const float vx = rho * cphi - sx, vy = rho * sphi - sy, vz = -A.dist;
+    const float inv = 1.0f / sqrtf(vx * vx + vy * vy + vz * vz);
+    x[k] = sx;
+    y[k] = sy;
+    dx[k] = vx * inv;
+    dy[k] = vy * inv;
+    dz[k] = vz * inv;
+    lam[k] = fmaf(A.lam1 - A.lam0, u4, A.lam0);
+}
+
+}  // namespace lt
+
+using namespace lt;
+
+extern "C" lt_status lt_rays_generate(lt_lens lens, const lt_raygen *cfg, const lt_ray_buffers *out,
+                                      int64_t n, void *stream)
+{
+    Lens *L = as_lens(lens);
+    if (!L || !cfg || !out)
+        return fail(LT_ERR_ARG, "NULL lens, config or output");
+    if (n < 0)
+        return fail(LT_ERR_ARG, "negative ray count");
+    if (!(cfg->half_width_mm > 0.0f) || !(cfg->half_height_mm > 0.0f) ||
+        !(cfg->lambda_min_nm > 0.0f) || !(cfg->lambda_max_nm >= cfg->lambda_min_nm))
+        return fail(LT_ERR_ARG, "invalid sensor extent or wavelength range");
+    if (n == 0)
+        return LT_OK;
+    if (!out->x || !out->y || !out->dx || !out->dy || !out->dz || !out->lambda_nm)
+        return fail(LT_ERR_ARG, "NULL output field");
+    const lt_surface &last = L->surf[L->ns - 1];
+    if (!(last.thickness_mm > 0.0))
+        return fail(LT_ERR_LENS, "last surface must lie in front of the sensor");
+    RaygenArgs A;
+    A.seed = cfg->seed;
+    A.first = cfg->first;
+    A.hw = cfg->half_width_mm;
+    A.hh = cfg->half_height_mm;
+    A.lam0 = cfg->lambda_min_nm;
+    A.lam1 = cfg->lambda_max_nm;
+    A.sd = static_cast<float>(last.semi_diameter_mm);
+    A.dist = static_cast<float>(last.thickness_mm);
+    A.n = n;
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks > 0x7fffffffLL)
+        return fail(LT_ERR_ARG, "too many rays for one launch");
+    hipLaunchKernelGGL(raygen_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0,
+                       reinterpret_cast<hipStream_t>(stream), A, out->x, out->y, out->dx, out->dy,
+                       out->dz, out->lambda_nm);
+    return check_hip(hipGetLastError(), "raygen_kernel launch");
+}

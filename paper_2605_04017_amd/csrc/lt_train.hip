@@ -31,7 +31,7 @@ namespace lt {
 
 struct WsLayout {
     int64_t n_pad = 0, tiles16 = 0, slices = 0, loss_blocks = 0;
-    int64_t xhat = 0, hfrag = 0, dfrag = 0, o = 0, dout = 0, partial = 0, loss = 0, bytes = 0;
+    int64_t xhat = 0, hfrag = 0, dfrag = 0, o = 0, dout = 0, partial = 0, loss = 0, canon = 0, bytes = 0;
 };
 
 constexpr int kDwChunk = 64;     // rays per LDS chunk in dw_kernel
@@ -66,6 +66,8 @@ WsLayout ws_layout(const MapLayout &L, int64_t n)
     off = align256(off + w.slices * L.n_params * 4);
     w.loss = off;
     off = align256(off + w.loss_blocks * 2 * 4);
+    w.canon = off;   // canonical frame (c, s, sg) per ray for the loss (canonical maps)
+    off = align256(off + 3 * w.n_pad * 4);
     w.bytes = off;
     return w;
 }
@@ -121,6 +123,7 @@ struct LossArgs {
     float *partial;        // [blocks][2]
     const float *norm;     // device: in_shift, in_scale, out_shift[5P], out_scale[5P]
     lt_targets t;
+    const float *canon;    // [3][n_pad] (c, s, sg) per ray, or null (plain input)
     int64_t n, n_pad, o_stride;
     int32_t P;
     float w_bce, w_l2;
@@ -149,7 +152,16 @@ __global__ __launch_bounds__(kLossBlock) void loss_kernel(LossArgs A)
             s_bce += fmaxf(z, 0.0f) - z * v + log1pf(expf(-fabsf(z)));
             const float sig = 1.0f / (1.0f + expf(-z));
             d[0] = A.w_bce * (sig - v) * inv;
-            const float tv[5] = {A.t.x[ti], A.t.y[ti], A.t.dx[ti], A.t.dy[ti], A.t.throughput[ti]};
+            float tv[5] = {A.t.x[ti], A.t.y[ti], A.t.dx[ti], A.t.dy[ti], A.t.throughput[ti]};
+            if (A.canon) {
+                // targets into the ray's canonical frame (rotation by -phi, then the mirror)
+                const float c = A.canon[r], s = A.canon[A.n_pad + r], sg = A.canon[2 * A.n_pad + r];
+                const float x = tv[0], y = tv[1], dx = tv[2], dy = tv[3];
+                tv[0] = c * x + s * y;
+                tv[1] = (c * y - s * x) * sg;
+                tv[2] = c * dx + s * dy;
+                tv[3] = (c * dy - s * dx) * sg;
+            }
             for (int q = 0; q < 5; ++q) {
                 const float tn = (tv[q] - sh[5 * h + q]) / sc[5 * h + q];
                 const float diff = v > 0.0f ? o[(q + 1) * A.o_stride] - tn : 0.0f;
@@ -467,8 +479,19 @@ __global__ __launch_bounds__(256) void reduce_adam_kernel(AdamArgs A)
 {
     for (int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; k < A.n_params;
          k += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        // slices summed in order; eight loads in flight at a time
         float gsum = 0.0f;
-        for (int64_t s = 0; s < A.slices; ++s)
+        int64_t s = 0;
+        for (; s + 8 <= A.slices; s += 8) {
+            float p[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                p[j] = A.partial[(s + j) * A.n_params + k];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                gsum += p[j];
+        }
+        for (; s < A.slices; ++s)
             gsum += A.partial[s * A.n_params + k];
         if (A.grad_out) {
             A.grad_out[k] = gsum;
@@ -481,17 +504,30 @@ __global__ __launch_bounds__(256) void reduce_adam_kernel(AdamArgs A)
         const float mh = m / A.bc1, vh = v / A.bc2;
         A.master[k] -= A.lr * mh / (sqrtf(vh) + A.eps);
     }
-    if (A.loss_out && blockIdx.x == 0 && threadIdx.x == 0) {
+    if (A.loss_out && blockIdx.x == 0) {
+        // fixed-order tree over the per-block loss partials (deterministic)
+        __shared__ float red[2][256];
         float b = 0.0f, l2 = 0.0f;
-        for (int64_t i = 0; i < A.loss_blocks; ++i) {
+        for (int64_t i = threadIdx.x; i < A.loss_blocks; i += blockDim.x) {
             b += A.loss_partial[2 * i];
             l2 += A.loss_partial[2 * i + 1];
         }
-        b *= A.loss_scale_bce;
-        l2 *= A.loss_scale_l2;
-        A.loss_out[0] = b + l2;
-        A.loss_out[1] = b;
-        A.loss_out[2] = l2;
+        red[0][threadIdx.x] = b;
+        red[1][threadIdx.x] = l2;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (static_cast<int>(threadIdx.x) < w) {
+                red[0][threadIdx.x] += red[0][threadIdx.x + w];
+                red[1][threadIdx.x] += red[1][threadIdx.x + w];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            const float bs = red[0][0] * A.loss_scale_bce, ls = red[1][0] * A.loss_scale_l2;
+            A.loss_out[0] = bs + ls;
+            A.loss_out[1] = bs;
+            A.loss_out[2] = ls;
+        }
     }
 }
 
@@ -737,6 +773,7 @@ lt_status lt_map_train_step(lt_map map, const lt_rays *rays, const lt_targets *t
     A.xhat_out = reinterpret_cast<float *>(wb + w.xhat);
     A.hfrag_out = wb + w.hfrag;
     A.o_out = reinterpret_cast<float *>(wb + w.o);
+    A.canon_out = M->lay.canon ? reinterpret_cast<float *>(wb + w.canon) : nullptr;
     A.n_pad = w.n_pad;
     A.o_stride = w.n_pad;
     lt_map_out none{};
@@ -749,6 +786,7 @@ lt_status lt_map_train_step(lt_map map, const lt_rays *rays, const lt_targets *t
     LA.partial = reinterpret_cast<float *>(wb + w.loss);
     LA.norm = M->norm;
     LA.t = *targets;
+    LA.canon = M->lay.canon ? reinterpret_cast<const float *>(wb + w.canon) : nullptr;
     LA.n = n;
     LA.n_pad = w.n_pad;
     LA.o_stride = w.n_pad;

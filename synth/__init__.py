@@ -486,3 +486,65 @@ def config_rays(config: int, n: int | None = None) -> dict:
     sizes = {1: 65536, 2: 4194304, 3: 16777216, 4: 65536}
     lens = config_lens(config)
     return make_rays(lens, sizes[config] if n is None else n, 2000 + config)
+
+
+# counter-based ray generator (host twin of the device generator) ----------
+# Philox4x64-10 from its published definition (Salmon, Moraes, Dror and Shaw,
+# SC 2011): ten rounds of two 64x64->128-bit multiplies with the Weyl key
+# schedule.  Ray k uses counter (first + k, 0, 0, 0) and key (seed, 0).
+
+_M32 = np.uint64(0xFFFFFFFF)
+_PH_M = (np.uint64(0xD2E7470EE14C6C93), np.uint64(0xCA5A826395121157))
+_PH_W = (np.uint64(0x9E3779B97F4A7C15), np.uint64(0xBB67AE8584CAA73B))
+
+
+def _mulhilo64(a, b):
+    a = np.asarray(a, np.uint64)
+    b = np.asarray(b, np.uint64)
+    s32 = np.uint64(32)
+    a0, a1 = a & _M32, a >> s32
+    b0, b1 = b & _M32, b >> s32
+    p00, p01, p10, p11 = a0 * b0, a0 * b1, a1 * b0, a1 * b1
+    mid = (p00 >> s32) + (p01 & _M32) + (p10 & _M32)
+    return p11 + (p01 >> s32) + (p10 >> s32) + (mid >> s32), a * b
+
+
+def philox4x64_10(ctr, key):
+    """Philox4x64-10 of counter words ctr[0..3] (arrays) and key (k0, k1)."""
+    x0, x1, x2, x3 = (np.asarray(c, np.uint64).copy() for c in ctr)
+    k0, k1 = np.uint64(key[0]), np.uint64(key[1])
+    with np.errstate(over="ignore"):
+        for _ in range(10):
+            hi0, lo0 = _mulhilo64(_PH_M[0], x0)
+            hi1, lo1 = _mulhilo64(_PH_M[1], x2)
+            x0, x1, x2, x3 = hi1 ^ x1 ^ k0, lo1, hi0 ^ x3 ^ k1, lo0
+            k0 = k0 + _PH_W[0]
+            k1 = k1 + _PH_W[1]
+    return x0, x1, x2, x3
+
+
+def philox_rays(lens: Lens, n: int, seed: int, first: int = 0, half_w: float = SENSOR_HALF_W,
+                half_h: float = SENSOR_HALF_H, lam_range=(400.0, 700.0)) -> dict:
+    """Rays k = 0..n-1 of the counter-based generator, computed in float64
+    from the same 24-bit uniforms and rounded to float32 (the sensor point is
+    rounded before the direction is formed, as on the device)."""
+    ctr = np.arange(n, dtype=np.uint64) + np.uint64(first)
+    z = np.zeros(n, np.uint64)
+    o0, o1, o2, o3 = philox4x64_10((ctr, z, z, z), (seed, 0))
+    s40, s16, m24 = np.uint64(40), np.uint64(16), np.uint64(0xFFFFFF)
+    u0, u1, u2, u3 = ((o >> s40).astype(np.float64) * 2.0 ** -24 for o in (o0, o1, o2, o3))
+    u4 = ((o0 >> s16) & m24).astype(np.float64) * 2.0 ** -24
+    f32 = np.float32
+    hw, hh = float(f32(half_w)), float(f32(half_h))
+    sx = (2.0 * hw * u0 - hw).astype(f32)
+    sy = (2.0 * hh * u1 - hh).astype(f32)
+    rear = lens.surfaces[-1]
+    rho = float(f32(rear.semi_diameter)) * np.sqrt(u2)
+    phi = 2.0 * np.pi * u3
+    vx = rho * np.cos(phi) - sx.astype(np.float64)
+    vy = rho * np.sin(phi) - sy.astype(np.float64)
+    vz = np.full(n, -float(f32(rear.thickness)))
+    norm = np.sqrt(vx * vx + vy * vy + vz * vz)
+    l0, l1 = float(f32(lam_range[0])), float(f32(lam_range[1]))
+    return {"x": sx, "y": sy, "dx": (vx / norm).astype(f32), "dy": (vy / norm).astype(f32),
+            "dz": (vz / norm).astype(f32), "lambda_nm": ((l1 - l0) * u4 + l0).astype(f32)}

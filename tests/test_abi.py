@@ -115,7 +115,7 @@ def test_trace_argument_errors_without_gpu():
 
 @pytest.mark.parametrize("desc", [(5, 128, 5, 1, 0), (6, 100, 5, 1, 0), (6, 128, 0, 1, 0),
                                   (6, 128, 9, 1, 0), (6, 128, 5, 0, 0), (6, 128, 5, 65, 0),
-                                  (6, 128, 5, 1, 7)])
+                                  (6, 128, 5, 1, 7), (6, 128, 5, 1, 0, 2)])
 def test_map_desc_validation(desc):
     """Bad shapes are rejected before any device allocation."""
     d = N.lt_map_desc(*desc)

@@ -37,7 +37,9 @@ def make_params(desc, seed, rays):
         b[:] = rng.normal(0, 0.2, b.shape)
     x = np.stack([rays[k].astype(np.float64) for k in synth.RAY_FIELDS], 1)
     p.in_shift = x.mean(0).astype(np.float32).astype(np.float64)
-    p.in_scale = (1.0 / x.std(0)).astype(np.float32).astype(np.float64)
+    sd = x.std(0)
+    sd[sd == 0] = 1.0   # the y slot of canonical inputs is always 0
+    p.in_scale = (1.0 / sd).astype(np.float32).astype(np.float64)
     H = desc.n_heads
     p.out_shift = rng.normal(0, 1, (H, 5)).astype(np.float32).astype(np.float64)
     p.out_scale = rng.uniform(0.5, 2.0, (H, 5)).astype(np.float32).astype(np.float64)
@@ -49,7 +51,7 @@ def gpu_map(p, dev):
     import torch
     import paper_2605_04017_amd as lt
     d = p.desc
-    m = lt.lt_map_create(d.width, d.depth, d.n_heads, d.activation)
+    m = lt.lt_map_create(d.width, d.depth, d.n_heads, d.activation, d.canonical)
     assert m.n_params == mlp.n_params(d)
     lt.lt_map_set_params(m, torch.from_numpy(p.flat().astype(np.float32)).to(dev))
     lt.lt_map_set_norm(m, p.in_shift, p.in_scale, p.out_shift.reshape(-1), p.out_scale.reshape(-1))
@@ -79,7 +81,7 @@ def compare(g, p, rays, mode, sel=None):
         g = {k: v[:, sel] for k, v in g.items()}
     xhat = mlp.features(sub, p)
     o = mlp.forward(p, xhat)[0] if mode == "f32" else mlp.forward_quantized(p, xhat, mode)
-    ref = mlp.decode(o, p)
+    ref = mlp.decode(o, p, sub)
     dl = np.abs(g["logit"] - ref["logit"]).reshape(-1)
     stl = _check_stats(dl, "logit")
     sure = np.abs(ref["logit"]) > MAX_TOL
@@ -300,8 +302,15 @@ def test_c2_shape_f32_full_size(dev):
 
 
 @pytest.mark.parametrize("width,depth,heads,act,n", [(64, 4, 1, 1, 65536), (128, 5, 56, 0, 4000),
-                                                      (32, 2, 3, 0, 333)])
+                                                      (32, 2, 3, 0, 333), (128, 5, 1, 0, 300001),
+                                                      (128, 2, 1, 0, 300001), (128, 5, 6, 0, 3000),
+                                                      (128, 5, 8, 0, 3000), (128, 1, 2, 0, 1000)])
 def test_f32_shapes(dev, width, depth, heads, act, n):
+    """Double-buffered layer staging (output layer resident: up to 6 heads at
+    width 128) and synchronous staging (8 and 56 heads); 300,001 rays give
+    every workgroup several ray tiles, so the buffer swap wraps from the last
+    hidden layer to the first (depth 5: even number of swaps per tile; depth
+    2: odd)."""
     import paper_2605_04017_amd as lt
     rays = synth.config_rays(2, n)
     desc = mlp.MapDesc(width, depth, heads, act)
@@ -334,3 +343,53 @@ def test_quantize_then_eval(dev):
     with pytest.raises(lt.LtError) as e:
         lt.lt_map_quantize(m, lt.LT_FP8)
     assert e.value.status == 4
+
+
+@pytest.mark.parametrize("heads,dtype,n", [(1, 1, 70001), (56, 1, 5000), (3, 2, 20000), (1, 0, 30001),
+                                           (56, 2, 3000)])
+def test_canonical_input(dev, heads, dtype, n):
+    """Symmetry-reduced input frame: parity with the reference (which forms
+    the same FP32 canonical inputs and maps outputs back in FP64), for the
+    resident and the streamed output layer, BF16, FP8 and FP32."""
+    import paper_2605_04017_amd as lt
+    rays = synth.config_rays(2, n)
+    desc = mlp.MapDesc(128, 5, heads, mlp.ACT_TANH, canonical=True)
+    can = mlp.canonical_frame(rays)[0]
+    p = make_params(desc, 60 + heads + dtype, can)
+    g = run_eval(gpu_map(p, dev), rays, dev, dtype)
+    mode = {0: "f32", 1: "bf16", 2: "fp8"}[dtype]
+    if dtype == lt.LT_F32:
+        _with_tols(*F32_TOLS, lambda: compare(g, p, rays, "f32"))
+    elif dtype == lt.LT_FP8:
+        _with_tols(1e-4, 3e-2, 3e-1, lambda: compare(g, p, rays, "fp8"))
+    else:
+        compare(g, p, rays, mode)
+
+
+def test_canonical_map_equivariance_on_gpu(dev):
+    """Rotating and mirroring the input rays rotates and mirrors the GPU
+    map's exit rays (FP32 map; the canonical inputs agree to FP32 rounding)."""
+    import paper_2605_04017_amd as lt
+    rays = synth.config_rays(2, 20000)
+    desc = mlp.MapDesc(128, 5, 2, mlp.ACT_TANH, canonical=True)
+    p = make_params(desc, 71, mlp.canonical_frame(rays)[0])
+    m = gpu_map(p, dev)
+    a = run_eval(m, rays, dev, lt.LT_F32)
+    th = 1.1
+    c, s_ = np.cos(th), np.sin(th)
+    rr = dict(rays)
+    x, y = rays["x"].astype(np.float64), -rays["y"].astype(np.float64)
+    dx, dy = rays["dx"].astype(np.float64), -rays["dy"].astype(np.float64)
+    rr["x"], rr["y"] = (c * x - s_ * y).astype(np.float32), (s_ * x + c * y).astype(np.float32)
+    rr["dx"], rr["dy"] = (c * dx - s_ * dy).astype(np.float32), (s_ * dx + c * dy).astype(np.float32)
+    b = run_eval(m, rr, dev, lt.LT_F32)
+    ok = (a["mask"] == 1) & (b["mask"] == 1)
+    assert np.mean(a["mask"] == b["mask"]) > 0.999
+    ex, ey = a["x"].astype(np.float64), -a["y"].astype(np.float64)
+    edx, edy = a["dx"].astype(np.float64), -a["dy"].astype(np.float64)
+    tol = 1e-3 * np.abs(p.out_scale).max()
+    assert np.abs((c * ex - s_ * ey) - b["x"])[ok].max() < tol
+    assert np.abs((s_ * ex + c * ey) - b["y"])[ok].max() < tol
+    assert np.abs((c * edx - s_ * edy) - b["dx"])[ok].max() < tol
+    assert np.abs((s_ * edx + c * edy) - b["dy"])[ok].max() < tol
+    assert np.abs(a["throughput"] - b["throughput"])[ok].max() < tol

@@ -34,7 +34,9 @@ def make_params(desc, seed, rays):
         b[:] = rng.normal(0, 0.2, b.shape)
     x = np.stack([rays[k].astype(np.float64) for k in synth.RAY_FIELDS], 1)
     p.in_shift = x.mean(0).astype(np.float32).astype(np.float64)
-    p.in_scale = (1.0 / x.std(0)).astype(np.float32).astype(np.float64)
+    sd = x.std(0)
+    sd[sd == 0] = 1.0   # the y slot of canonical inputs is always 0
+    p.in_scale = (1.0 / sd).astype(np.float32).astype(np.float64)
     H = desc.n_heads
     p.out_shift = rng.normal(0, 1, (H, 5)).astype(np.float32).astype(np.float64)
     p.out_scale = rng.uniform(0.5, 2.0, (H, 5)).astype(np.float32).astype(np.float64)
@@ -46,7 +48,7 @@ def gpu_map(p, dev):
     import torch
     import paper_2605_04017_amd as lt
     d = p.desc
-    m = lt.lt_map_create(d.width, d.depth, d.n_heads, d.activation)
+    m = lt.lt_map_create(d.width, d.depth, d.n_heads, d.activation, d.canonical)
     lt.lt_map_set_params(m, torch.from_numpy(p.flat().astype(np.float32)).to(dev))
     lt.lt_map_set_norm(m, p.in_shift, p.in_scale, p.out_shift.reshape(-1), p.out_scale.reshape(-1))
     return m
@@ -241,3 +243,34 @@ def test_autograd_function(dev):
     g2 = lt.lt_map_backward(m, w.contiguous(), ws)
     assert torch.equal(o.detach(), o2)
     assert torch.equal(params.grad, g2)
+
+
+def test_canonical_train_step(dev):
+    """Canonical-input map: the fused step moves the traced targets into
+    each ray's canonical frame; loss and first Adam step match the reference
+    (oracle normalise_targets with the rays)."""
+    import torch
+    import paper_2605_04017_amd as lt
+    L = synth.config_lens(2)
+    n = 16384
+    rays = synth.config_rays(2, n)
+    desc = mlp.MapDesc(64, 3, 1, mlp.ACT_TANH, canonical=True)
+    p = make_params(desc, 29, mlp.canonical_frame(rays)[0])
+    m = gpu_map(p, dev)
+    r, t = _targets(L, rays, dev)
+    ws = lt.workspace(m, n)
+    cfg = {"lr": 1e-3, "step": 1, "w_bce": 1.0, "w_l2": 1.0}
+    loss = lt.lt_map_train_step(m, r, t, cfg, ws)
+    torch.cuda.synchronize()
+    tn = {k: v.cpu().numpy() for k, v in t.items()}
+    valid = tn["valid"].astype(np.int64)
+    tnorm = mlp.normalise_targets({k: tn[k] for k in ("x", "y", "dx", "dy", "throughput")}, p, rays)
+    (lref, bref, l2ref), gref = mlp.loss_and_grad_quantized(p, mlp.features(rays, p), valid, tnorm)
+    lg = loss.cpu().numpy()
+    assert abs(lg[0] - lref) <= 1e-3 * lref and abs(lg[2] - l2ref) <= 2e-3 * l2ref
+    new = lt.lt_map_get_params(m).cpu().numpy().astype(np.float64)
+    step = new - p.flat()
+    gr = mlp.grads_flat(gref)
+    big = np.abs(gr) > 1e-2 * np.abs(gr).max()
+    expect = -1e-3 * gr / (np.abs(gr) + 1e-8)
+    assert np.mean(np.abs(step[big] - expect[big]) < 1e-6) > 0.99
