@@ -387,11 +387,11 @@ def measured_traffic():
     return d
 
 
-def traffic_probe(n=N_RAYS):
+def traffic_probe(n=N_RAYS, dtype_name="f32"):
     """Short program for the counter runs: one plain copy of COPY_PROBE_BYTES
-    (a negate kernel: reads and writes that many bytes), then three FP32 map
-    launches on the benchmark workload (random weights: the kernel has no
-    data-dependent control flow)."""
+    (a negate kernel: reads and writes that many bytes), then three map
+    launches in the given precision on the benchmark workload (random
+    weights: the kernels have no data-dependent control flow)."""
     import numpy as np
     import torch
     import paper_2605_04017_amd as lt
@@ -409,11 +409,12 @@ def traffic_probe(n=N_RAYS):
     lt.lt_map_set_params(m, torch.from_numpy(p.flat().astype(np.float32)).to(dev))
     out = lt.empty_map_out(1, n, dev)
     torch.cuda.synchronize()
+    dt = {"f32": lt.LT_F32, "bf16": lt.LT_BF16, "fp8": lt.LT_FP8}[dtype_name]
     for _ in range(3):
-        lt.lt_map_eval(m, lt.LT_F32, rays, out, n)
+        lt.lt_map_eval(m, dt, rays, out, n)
     torch.cuda.synchronize()
-    print(json.dumps({"probe": "traffic", "copy_bytes": COPY_PROBE_BYTES, "rays": n,
-                      "source_hash": map_f32_source_hash()}), flush=True)
+    print(json.dumps({"probe": "traffic", "dtype": dtype_name, "copy_bytes": COPY_PROBE_BYTES,
+                      "rays": n, "source_hash": map_f32_source_hash()}), flush=True)
 
 
 def main():
@@ -427,15 +428,15 @@ def main():
     ap.add_argument("--no-multi-path", action="store_true")
     ap.add_argument("--no-train-epoch", action="store_true")
     ap.add_argument("--rays", type=int, default=N_RAYS)
-    ap.add_argument("--traffic-probe", action="store_true",
-                    help="only run the short program the HBM counter runs profile")
+    ap.add_argument("--traffic-probe", nargs="?", const="f32", choices=("f32", "bf16", "fp8"),
+                    help="only run the short program the counter runs profile (map precision)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: every box in this setup has one MI355X; "
               "multi-GPU sharding is described in DESIGN.md, not run.", file=sys.stderr)
         sys.exit(2)
     if args.traffic_probe:
-        traffic_probe(args.rays)
+        traffic_probe(args.rays, args.traffic_probe)
         return
 
     import numpy as np

@@ -367,23 +367,16 @@ __global__ __launch_bounds__((eval_waves<H, TRAIN>() * 64)) void map_eval_bf16_k
                     break;
                 const uint8_t *wl = lds + A.img_hidden + static_cast<int64_t>(l - 1) * T * C * kFragBytes;
                 const float *bl = bias + l * H;
-                // M tiles in pairs, K chunks inside: 2 x NT independent
-                // accumulator chains between dependent MFMAs
     #pragma unroll
-                for (int t0 = 0; t0 < T; t0 += 2) {
-                    const floatx4 bz0 = *reinterpret_cast<const floatx4 *>(bl + t0 * 16 + 4 * g);
-                    const floatx4 bz1 = *reinterpret_cast<const floatx4 *>(bl + (t0 + 1) * 16 + 4 * g);
+                for (int t = 0; t < T; ++t) {
+                    const floatx4 bz = *reinterpret_cast<const floatx4 *>(bl + t * 16 + 4 * g);
     #pragma unroll
                     for (int c = 0; c < C; ++c) {
+                        const bf16x8 a =
+                            *reinterpret_cast<const bf16x8 *>(wl + (t * C + c) * kFragBytes + lane * 16);
     #pragma unroll
-                        for (int u = 0; u < 2; ++u) {
-                            const int t = t0 + u;
-                            const bf16x8 a =
-                                *reinterpret_cast<const bf16x8 *>(wl + (t * C + c) * kFragBytes + lane * 16);
-    #pragma unroll
-                            for (int nt = 0; nt < NT; ++nt)
-                                acc[nt][t] = mfma_bf16(a, bop[nt][c], c == 0 ? (u ? bz1 : bz0) : acc[nt][t]);
-                        }
+                        for (int nt = 0; nt < NT; ++nt)
+                            acc[nt][t] = mfma_bf16(a, bop[nt][c], c == 0 ? bz : acc[nt][t]);
                     }
                 }
             }
