@@ -157,13 +157,18 @@ def fit_map(lt, synth, mlp, lens, dev, steps, batch=65536, seed=3002, canonical=
 def map_error(lt, oracle, lens, m, dtype, rays_np, rays_dev, n_sample=65536):
     """Exit-ray error of the map against the FP64 oracle on the first
     n_sample benchmark rays."""
-    import numpy as np
     import torch
     sub_dev = {k: v[:n_sample] for k, v in rays_dev.items()}
     sub_np = {k: v[:n_sample] for k, v in rays_np.items()}
     g = {k: v[0].cpu().numpy() for k, v in lt.lt_map_eval(m, dtype, sub_dev).items()}
     torch.cuda.synchronize()
-    o = oracle.trace(lens, sub_np)
+    return exit_error(g, oracle.trace(lens, sub_np), n_sample)
+
+
+def exit_error(g, o, n_sample):
+    """Mask agreement and exit-ray errors of map outputs g (one head, host
+    arrays) against oracle traces o."""
+    import numpy as np
     gm, om = g["mask"].astype(bool), o["mask"].astype(bool)
     both = gm & om
     pos = np.hypot(g["x"][both] - o["x"][both], g["y"][both] - o["y"][both])
@@ -176,6 +181,71 @@ def map_error(lt, oracle, lens, m, dtype, rays_np, rays_dev, n_sample=65536):
             "pos_mm_p50": float(np.median(pos)), "pos_mm_p99": float(np.quantile(pos, 0.99)),
             "dir_rad_p50": float(np.median(ang)), "dir_rad_p99": float(np.quantile(ang, 0.99)),
             "throughput_abs_p99": float(np.quantile(thr, 0.99)), "rays": n_sample}
+
+
+def paper_pair(lt, synth, mlp, oracle, lens, dev, steps, rays_np, rays, batch=65536, seed=3003,
+               w_cos=200.0):
+    """The paper's factorised form at its own size: a classifier of 2 x 32
+    tanh (BCE) and a regressor of 5 x 32 tanh (squared error on position and
+    throughput, cosine loss on direction), both fitted for `steps` steps on
+    GPU-traced rays; evaluation runs the classifier (LT_EVAL_MASK_ONLY) and
+    then the regressor under its mask (LT_EVAL_GATED)."""
+    import numpy as np
+    import torch
+    pool_np = synth.make_rays(lens, 4194304, seed)
+    pool = {k: torch.from_numpy(v).to(dev) for k, v in pool_np.items()}
+    h = lt.lt_lens_create(lens.surfaces, lens.glasses)
+    ex = lt.lt_trace(h, (0, 0, 0), pool)
+    ok = ex["mask"].bool()
+    reg_t = torch.stack([ex[k][ok] for k in ("x", "y", "dx", "dy", "throughput")], 1).double().cpu().numpy()
+    x = np.stack([pool_np[k].astype(np.float64) for k in synth.RAY_FIELDS], 1)
+    nets = {}
+    for name, depth in (("classifier", 2), ("regressor", 5)):
+        p = mlp.init_params(mlp.MapDesc(32, depth, 1, mlp.ACT_TANH), 11 + depth)
+        p.in_shift, p.in_scale = x.mean(0), 1.0 / x.std(0)
+        p.out_shift, p.out_scale = reg_t.mean(0)[None], reg_t.std(0)[None]
+        m = lt.lt_map_create(32, depth, 1, lt.LT_ACT_TANH)
+        lt.lt_map_set_params(m, torch.from_numpy(p.flat().astype(np.float32)).to(dev))
+        lt.lt_map_set_norm(m, p.in_shift, p.in_scale, p.out_shift.reshape(-1), p.out_scale.reshape(-1))
+        nets[name] = (m, lt.workspace(m, batch))
+    n_pool = pool_np["x"].shape[0]
+    t0 = time.perf_counter()
+    for k in range(1, steps + 1):
+        lo = ((k - 1) * batch) % (n_pool - batch + 1)
+        rb = {f: v[lo:lo + batch] for f, v in pool.items()}
+        tb = {"valid": ex["mask"][lo:lo + batch].reshape(1, -1)}
+        for f in ("x", "y", "dx", "dy", "throughput"):
+            tb[f] = ex[f][lo:lo + batch].reshape(1, -1)
+        lr = 2e-3 * (0.5 ** (k / max(1, steps / 4)))
+        m, ws = nets["classifier"]
+        lt.lt_map_train_step(m, rb, tb, {"lr": lr, "step": k, "w_bce": 1.0, "w_l2": 0.0}, ws)
+        m, ws = nets["regressor"]
+        lt.lt_map_train_step(m, rb, tb, {"lr": lr, "step": k, "w_bce": 0.0, "w_l2": 1.0, "w_cos": w_cos}, ws)
+    torch.cuda.synchronize()
+    t_fit = time.perf_counter() - t0
+    cls, reg = nets["classifier"][0], nets["regressor"][0]
+    n = rays["x"].numel()
+    stream = torch.cuda.current_stream()
+    out = lt.empty_map_out(1, n, dev)
+
+    def pair(dt, k=n):
+        sub = rays if k == n else {f: v[:k] for f, v in rays.items()}
+        o = out if k == n else lt.empty_map_out(1, k, dev)
+        lt.lt_map_eval_ex(cls, dt, sub, o, k, lt.LT_EVAL_MASK_ONLY, None, stream)
+        lt.lt_map_eval_ex(reg, dt, sub, o, k, lt.LT_EVAL_GATED, o["mask"], stream)
+        return o
+    res = {"classifier": "2 x 32 tanh, BCE", "regressor": f"5 x 32 tanh, MSE(x, y, I) + {w_cos:g} x (1 - cos)",
+           "fit_steps": steps, "fit_seconds": t_fit,
+           "flops_per_ray": map_flops_per_ray(32, 2, 1) + map_flops_per_ray(32, 5, 1)}
+    for name, dt in (("f32", lt.LT_F32), ("bf16", lt.LT_BF16)):
+        t = time_kernel(lambda: pair(dt), stream, 5)
+        res[f"{name}_ms"] = t * 1e3
+        res[f"{name}_mrays_s"] = n / t / 1e6
+        k = 65536
+        g = {f: v[0].cpu().numpy() for f, v in pair(dt, k).items()}
+        torch.cuda.synchronize()
+        res[f"{name}_error_vs_fp64_oracle"] = exit_error(g, oracle.trace(lens, {f: v[:k] for f, v in rays_np.items()}), k)
+    return res
 
 
 def serving(lt, synth, mlp, dev, n_req=600, loads=(0.5, 0.8), seed=5005):
@@ -427,6 +497,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-multi-path", action="store_true")
     ap.add_argument("--no-train-epoch", action="store_true")
+    ap.add_argument("--no-paper-pair", action="store_true")
     ap.add_argument("--rays", type=int, default=N_RAYS)
     ap.add_argument("--traffic-probe", nargs="?", const="f32", choices=("f32", "bf16", "fp8"),
                     help="only run the short program the counter runs profile (map precision)")
@@ -552,6 +623,10 @@ def main():
                       "unit": "TFLOP/s", "frac": trace_tf / MI355X_FP32_VECTOR_TFLOPS,
                       "flops_per_ray": trace_flops_per_ray(lens)}},
     }
+    if not args.no_paper_pair:
+        res["paper_pair_2x32_5x32"] = paper_pair(lt, synth, mlp, oracle, lens, dev, args.fit_steps,
+                                                 rays_np, rays)
+        print("# paper-size pair done", file=sys.stderr, flush=True)
     if not args.no_train_epoch:
         res["train_epoch_67M"] = train_epoch(lt, synth, mlp, dev)
         print("# training epoch done", file=sys.stderr, flush=True)

@@ -343,6 +343,22 @@ lt_status lt_map_quantize(lt_map map, int32_t dtype, void *stream);
 lt_status lt_map_eval(lt_map map, int32_t dtype, const lt_rays *rays, const lt_map_out *out,
                       int64_t n, void *stream);
 
+/* Evaluation options for lt_map_eval_ex, for the paper's factorised form
+ * (Sec. 4.2: a classifier g and a regressor f; the output is f(x) where
+ * g(x) = 1): */
+#define LT_EVAL_MASK_ONLY 1u  /* write only logit and mask (run a classifier) */
+#define LT_EVAL_GATED     2u  /* write only the exit fields, valid where mask_in[head][ray]
+                                 is non-zero (run a regressor under a classifier's mask);
+                                 out->logit and out->mask are not touched (may be NULL) */
+
+/* lt_map_eval with options (0 = lt_map_eval).  mask_in: device uint8
+ * [n_heads][n], required with LT_EVAL_GATED, ignored otherwise.  With
+ * LT_EVAL_MASK_ONLY the exit fields of out are not touched (may be NULL).
+ * Errors as lt_map_eval; unknown or conflicting flags, a missing mask_in:
+ * LT_ERR_ARG. */
+lt_status lt_map_eval_ex(lt_map map, int32_t dtype, const lt_rays *rays, const lt_map_out *out,
+                         int64_t n, uint32_t flags, const uint8_t *mask_in, void *stream);
+
 /* ----------------------------------------------------------- training */
 
 /* Traced targets per head, head-major [n_heads][n] (device): validity (the
@@ -360,7 +376,14 @@ typedef struct {
 /* Optimiser and loss settings of one step.  The loss (averaged over heads):
  *   w_bce/N sum_r BCE(logit, valid) + w_l2/(5N) sum_r valid * |o - t|^2
  * on the normalised regression outputs o and targets t = (target -
- * out_shift) / out_scale.  Adam with bias correction; step is 1-based. */
+ * out_shift) / out_scale.  With w_cos > 0 the direction is trained with a
+ * cosine loss instead (Sec. 5.1: MSE for position and intensity, cosine
+ * similarity for direction):
+ *   w_l2/(3N) sum_r valid * |o - t|^2 over x, y, throughput
+ *   + w_cos/N sum_r valid * (1 - cos(angle between predicted and target
+ *     exit directions)),
+ * a direction being (dx, dy, -sqrt(max(1e-6, 1 - dx^2 - dy^2))) in lens
+ * units.  Adam with bias correction; step is 1-based. */
 typedef struct {
     float lr;
     float beta1;
@@ -369,6 +392,7 @@ typedef struct {
     int64_t step;
     float w_bce;
     float w_l2;
+    float w_cos;
 } lt_train_cfg;
 
 /* Bytes of device workspace a training call on n rays needs (-1 on error).

@@ -325,33 +325,18 @@ def normalise_targets(t: Dict[str, np.ndarray], p: MapParams,
 
 
 def loss_and_grad(p: MapParams, xhat: np.ndarray, valid: np.ndarray, tnorm: np.ndarray,
-                  w_bce: float = 1.0, w_l2: float = 1.0):
-    """FP64 loss (total, bce, l2) and gradients (list of (dW, db)).
+                  w_bce: float = 1.0, w_l2: float = 1.0, w_cos: float = 0.0):
+    """FP64 loss (total, bce, regression) and gradients (list of (dW, db)).
 
     valid: (H, n) 0/1; tnorm: (H, n, 5), ignored where valid == 0."""
-    n = xhat.shape[0]
-    H = p.desc.n_heads
     o, (hs, zs) = forward(p, xhat)
-    oo = o.reshape(n, H, N_OUT).transpose(1, 0, 2)
-    logit = oo[..., 0]
-    v = valid.astype(np.float64)
-    # stable BCE with logits
-    bce = np.maximum(logit, 0) - logit * v + np.log1p(np.exp(-np.abs(logit)))
-    sig = 1.0 / (1.0 + np.exp(-logit))
-    t = np.where(v[..., None] > 0, tnorm, 0.0)
-    diff = (oo[..., 1:] - t) * v[..., None]
-    l_bce = w_bce * bce.sum() / (n * H)
-    l_l2 = w_l2 * (diff * diff).sum() / (5 * n * H)
-    g = np.zeros_like(oo)
-    g[..., 0] = w_bce * (sig - v) / (n * H)
-    g[..., 1:] = w_l2 * 2.0 * diff / (5 * n * H)
-    delta = g.transpose(1, 0, 2).reshape(n, H * N_OUT)
+    losses, delta = loss_terms(p, o, valid, tnorm, w_bce, w_l2, w_cos)
     grads = [None] * len(p.W)
     for li in range(len(p.W) - 1, -1, -1):
         grads[li] = (delta.T @ hs[li], delta.sum(0))
         if li > 0:
             delta = (delta @ p.W[li]) * act_grad_from_output(hs[li], zs[li - 1], p.desc.activation)
-    return (l_bce + l_l2, l_bce, l_l2), grads
+    return losses, grads
 
 
 @dataclasses.dataclass
@@ -425,30 +410,82 @@ def backward_quantized(p: MapParams, cache, d_out: np.ndarray):
     return grads
 
 
+COS_EPS = 1e-6   # floor of 1 - dx^2 - dy^2 under the square root of the direction loss
+
+
+def _dir3(dx, dy):
+    """Unit-sphere direction toward the object from (dx, dy): dz = -sqrt(s),
+    s = max(COS_EPS, 1 - dx^2 - dy^2); also returns s and whether s was
+    floored."""
+    s = 1.0 - dx * dx - dy * dy
+    floored = s < COS_EPS
+    s = np.where(floored, COS_EPS, s)
+    return -np.sqrt(s), s, floored
+
+
 def loss_terms(p: MapParams, o: np.ndarray, valid: np.ndarray, tnorm: np.ndarray,
-               w_bce: float = 1.0, w_l2: float = 1.0):
-    """Loss (total, bce, l2) and its gradient with respect to o (n, 6H)."""
+               w_bce: float = 1.0, w_l2: float = 1.0, w_cos: float = 0.0):
+    """Loss (total, bce, regression) and its gradient with respect to o (n, 6H).
+
+    Regression part, on rays whose target is valid:
+      w_cos == 0: w_l2 * mean squared error of the five normalised outputs;
+      w_cos > 0:  w_l2 * mean squared error of x, y, throughput (normalised)
+                  + w_cos * mean (1 - cos angle) between predicted and target
+                  exit directions (Sec. 5.1 trains directions with a cosine
+                  similarity loss); a direction is (dx, dy, -sqrt(1 - dx^2 -
+                  dy^2)) in lens units, the square root's argument floored
+                  at COS_EPS."""
     n = o.shape[0]
     H = p.desc.n_heads
     oo = o.reshape(n, H, N_OUT).transpose(1, 0, 2)
     logit = oo[..., 0]
     v = valid.astype(np.float64)
+    on = v[..., None] > 0
     bce = np.maximum(logit, 0) - logit * v + np.log1p(np.exp(-np.abs(logit)))
     sig = 1.0 / (1.0 + np.exp(-logit))
-    t = np.where(v[..., None] > 0, tnorm, 0.0)
-    diff = np.where(v[..., None] > 0, oo[..., 1:] - t, 0.0)
-    l_bce = w_bce * bce.sum() / (n * H)
-    l_l2 = w_l2 * (diff * diff).sum() / (5 * n * H)
+    t = np.where(on, tnorm, 0.0)
+    diff = np.where(on, oo[..., 1:] - t, 0.0)
     g = np.zeros_like(oo)
+    l_bce = w_bce * bce.sum() / (n * H)
     g[..., 0] = w_bce * (sig - v) / (n * H)
-    g[..., 1:] = w_l2 * 2.0 * diff / (5 * n * H)
-    return (l_bce + l_l2, l_bce, l_l2), g.transpose(1, 0, 2).reshape(n, H * N_OUT)
+    if w_cos == 0.0:
+        l_reg = w_l2 * (diff * diff).sum() / (5 * n * H)
+        g[..., 1:] = w_l2 * 2.0 * diff / (5 * n * H)
+    else:
+        pos = [0, 1, 4]   # x, y, throughput among the five regression outputs
+        l_reg = w_l2 * (diff[..., pos] ** 2).sum() / (3 * n * H)
+        for k in pos:
+            g[..., 1 + k] = w_l2 * 2.0 * diff[..., k] / (3 * n * H)
+        sh, sc = p.out_shift[:, None, :], p.out_scale[:, None, :]
+        dxp = sh[..., 2] + sc[..., 2] * oo[..., 3]
+        dyp = sh[..., 3] + sc[..., 3] * oo[..., 4]
+        dxt = sh[..., 2] + sc[..., 2] * t[..., 2]
+        dyt = sh[..., 3] + sc[..., 3] * t[..., 3]
+        dzp, sp, flp = _dir3(dxp, dyp)
+        dzt, _, _ = _dir3(dxt, dyt)
+        nt = np.sqrt(dxt * dxt + dyt * dyt + dzt * dzt)
+        qx, qy, qz = dxt / nt, dyt / nt, dzt / nt
+        nu = np.sqrt(dxp * dxp + dyp * dyp + dzp * dzp)
+        dot = dxp * qx + dyp * qy + dzp * qz
+        cosv = dot / nu
+        l_reg += w_cos * np.where(v > 0, 1.0 - cosv, 0.0).sum() / (n * H)
+        # d cos / d u = q / |u| - (u . q) u / |u|^3, and d dz / d(dx, dy) =
+        # (dx, dy) / sqrt(s) unless s was floored
+        gx = qx / nu - dot * dxp / nu ** 3
+        gy = qy / nu - dot * dyp / nu ** 3
+        gz = qz / nu - dot * dzp / nu ** 3
+        dzdx = np.where(flp, 0.0, dxp / np.sqrt(sp))
+        dzdy = np.where(flp, 0.0, dyp / np.sqrt(sp))
+        scale = -w_cos * v / (n * H)
+        g[..., 3] = scale * (gx + gz * dzdx) * sc[..., 2]
+        g[..., 4] = scale * (gy + gz * dzdy) * sc[..., 3]
+    return (l_bce + l_reg, l_bce, l_reg), g.transpose(1, 0, 2).reshape(n, H * N_OUT)
 
 
 def loss_and_grad_quantized(p: MapParams, xhat: np.ndarray, valid: np.ndarray, tnorm: np.ndarray,
-                            w_bce: float = 1.0, w_l2: float = 1.0):
+                            w_bce: float = 1.0, w_l2: float = 1.0, w_cos: float = 0.0):
     """Loss and parameter gradient of one training step with the kernels'
     rounding (forward_quantized_cache, loss_terms, backward_quantized)."""
     o, cache = forward_quantized_cache(p, xhat)
-    losses, d_out = loss_terms(p, o, valid, tnorm, w_bce, w_l2)
+    losses, d_out = loss_terms(p, o, valid, tnorm, w_bce, w_l2, w_cos)
     return losses, backward_quantized(p, cache, d_out)

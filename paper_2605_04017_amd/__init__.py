@@ -27,7 +27,8 @@ __all__ = ["LtError", "Lens", "lt_lens_create", "lt_lens_query", "lt_trace", "lt
            "lt_map_eval", "empty_map_out", "MAP_FIELDS", "lt_map_workspace_bytes", "workspace",
            "lt_map_forward_train", "lt_map_backward", "lt_map_train_step", "lt_map_adam_state",
            "TARGET_FIELDS", "lt_path_encode", "lt_path_decode", "lt_trace_compact",
-           "lt_map_quantize", "lt_rays_generate"]
+           "lt_map_quantize", "lt_rays_generate", "lt_map_eval_ex", "LT_EVAL_MASK_ONLY",
+           "LT_EVAL_GATED"]
 
 TARGET_FIELDS = ("valid", "x", "y", "dx", "dy", "throughput")
 
@@ -341,20 +342,49 @@ def lt_map_quantize(m: Map, dtype: int, stream=None) -> None:
 def lt_map_eval(m: Map, dtype: int, rays: Dict, out: Optional[Dict] = None,
                 n: Optional[int] = None, stream=None) -> Dict:
     """Evaluate the map for ``n`` rays; outputs are (n_heads, n) tensors."""
+    return lt_map_eval_ex(m, dtype, rays, out, n, 0, None, stream)
+
+
+LT_EVAL_MASK_ONLY, LT_EVAL_GATED = 1, 2
+
+
+def lt_map_eval_ex(m: Map, dtype: int, rays: Dict, out: Optional[Dict] = None,
+                   n: Optional[int] = None, flags: int = 0, mask_in=None, stream=None) -> Dict:
+    """lt_map_eval with options: LT_EVAL_MASK_ONLY (logit and mask only) or
+    LT_EVAL_GATED (exit fields only, valid where ``mask_in`` is set).
+    ``out`` needs only the fields the call writes."""
     torch = _torch()
     if n is None:
         n = int(rays["x"].numel())
+    if flags & LT_EVAL_GATED:
+        wanted = MAP_FIELDS[2:]
+    elif flags & LT_EVAL_MASK_ONLY:
+        wanted = MAP_FIELDS[:2]
+    else:
+        wanted = MAP_FIELDS
     if out is None:
-        out = empty_map_out(m.n_heads, n, rays["x"].device)
+        full = empty_map_out(m.n_heads, n, rays["x"].device) if wanted == MAP_FIELDS else None
+        out = full if full is not None else {
+            k: torch.empty((m.n_heads, n), dtype=torch.uint8 if k == "mask" else torch.float32,
+                           device=rays["x"].device) for k in wanted}
     o = N.lt_map_out()
     for k in MAP_FIELDS:
+        if k not in wanted:
+            setattr(o, k, None)
+            continue
         dt = torch.uint8 if k == "mask" else torch.float32
         t = out[k]
         if n and (t.dim() != 2 or t.shape[0] != m.n_heads or t.shape[1] != n):
             raise ValueError(f"out[{k}] must have shape ({m.n_heads}, {n})")
         setattr(o, k, _dev_ptr(t, dt, m.n_heads * n, f"out[{k}]") if n else None)
-    N.check(N.lib().lt_map_eval(m.handle, int(dtype), C.byref(_rays_struct(rays, n)), C.byref(o),
-                                int(n), C.c_void_p(_stream_ptr(stream) if n else 0)))
+    mp = None
+    if flags & LT_EVAL_GATED:
+        if mask_in is None:
+            raise ValueError("LT_EVAL_GATED needs mask_in")
+        mp = _dev_ptr(mask_in, torch.uint8, m.n_heads * n, "mask_in") if n else None
+    N.check(N.lib().lt_map_eval_ex(m.handle, int(dtype), C.byref(_rays_struct(rays, n)), C.byref(o),
+                                   int(n), int(flags), C.c_void_p(mp),
+                                   C.c_void_p(_stream_ptr(stream) if n else 0)))
     return out
 
 
@@ -410,7 +440,8 @@ def lt_map_train_step(m: Map, rays: Dict, targets: Dict, cfg: Dict, ws, loss_out
                       n: Optional[int] = None, stream=None):
     """One fused forward + loss + backward + Adam step.  ``targets``: dict of
     (n_heads, n) CUDA tensors (valid uint8, the rest float32); ``cfg``: lr,
-    beta1, beta2, eps, step (1-based), w_bce, w_l2.  Returns loss_out
+    beta1, beta2, eps, step (1-based), w_bce, w_l2, w_cos (cosine direction
+    loss; 0 = squared error on all five outputs).  Returns loss_out
     (device float32[3]: total, bce, l2)."""
     torch = _torch()
     if n is None:
@@ -423,7 +454,8 @@ def lt_map_train_step(m: Map, rays: Dict, targets: Dict, cfg: Dict, ws, loss_out
         setattr(t, k, _dev_ptr(targets[k], dt, m.n_heads * n, f"targets[{k}]"))
     c = N.lt_train_cfg(float(cfg.get("lr", 1e-3)), float(cfg.get("beta1", 0.9)),
                        float(cfg.get("beta2", 0.999)), float(cfg.get("eps", 1e-8)),
-                       int(cfg["step"]), float(cfg.get("w_bce", 1.0)), float(cfg.get("w_l2", 1.0)))
+                       int(cfg["step"]), float(cfg.get("w_bce", 1.0)), float(cfg.get("w_l2", 1.0)),
+                       float(cfg.get("w_cos", 0.0)))
     N.check(N.lib().lt_map_train_step(m.handle, C.byref(_rays_struct(rays, n)), C.byref(t), int(n),
                                       C.byref(c), C.c_void_p(ws.data_ptr()), ws.numel(),
                                       C.c_void_p(_dev_ptr(loss_out, torch.float32, 3, "loss_out")),

@@ -69,7 +69,7 @@ class lt_targets(C.Structure):
 
 class lt_train_cfg(C.Structure):
     _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
-                ("step", C.c_int64), ("w_bce", C.c_float), ("w_l2", C.c_float)]
+                ("step", C.c_int64), ("w_bce", C.c_float), ("w_l2", C.c_float), ("w_cos", C.c_float)]
 
 
 LT_F32, LT_BF16, LT_FP8 = 0, 1, 2
@@ -95,6 +95,8 @@ SIGNATURES = {
                                    C.POINTER(lt_exit), C.c_void_p, C.c_void_p, C.c_int64,
                                    C.c_uint32, C.c_void_p]),
     "lt_map_quantize": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "lt_map_eval_ex": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(lt_rays), C.POINTER(lt_map_out),
+                                 C.c_int64, C.c_uint32, C.c_void_p, C.c_void_p]),
     "lt_rays_generate": (C.c_int, [C.c_void_p, C.POINTER(lt_raygen), C.POINTER(lt_ray_buffers),
                                    C.c_int64, C.c_void_p]),
     "lt_trace": (C.c_int, [C.c_void_p, C.POINTER(lt_path), C.POINTER(lt_rays),

@@ -55,7 +55,8 @@ Map *as_map(lt_map h);
 MapLayout make_layout(const lt_map_desc &d);
 int64_t wt_bytes(const MapLayout &L);
 int64_t f32_image_bytes(const MapLayout &L);
-lt_status eval_f32(Map &M, const lt_rays &rays, const lt_map_out &out, int64_t n, hipStream_t s);
+lt_status eval_f32(Map &M, const lt_rays &rays, const lt_map_out &out, int64_t n, uint32_t flags,
+                   const uint8_t *mask_in, hipStream_t s);
 lt_status ensure_packed_f32(Map &M, hipStream_t s);
 
 }  // namespace lt

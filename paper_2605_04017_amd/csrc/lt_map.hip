@@ -446,8 +446,16 @@ __global__ __launch_bounds__((eval_waves<H, TRAIN>() * 64)) void map_eval_bf16_k
                     if (head >= A.P || r >= n)
                         continue;
                     const float *sh = out_shift + 5 * head, *sc = out_scale + 5 * head;
+                    const int64_t idx = static_cast<int64_t>(head) * n + r;
                     const float logit = w[0];
-                    const bool m = logit > 0.0f;
+                    const bool gated = (A.flags & LT_EVAL_GATED) != 0;
+                    const bool m = gated ? A.mask_in[idx] != 0 : logit > 0.0f;
+                    if (!gated) {
+                        out.logit[idx] = logit;
+                        out.mask[idx] = m ? 1 : 0;
+                    }
+                    if (A.flags & LT_EVAL_MASK_ONLY)
+                        continue;
                     float x = fmaf(sc[0], w[1], sh[0]);
                     float y = fmaf(sc[1], w[2], sh[1]);
                     float dx = fmaf(sc[2], w[3], sh[2]);
@@ -456,9 +464,6 @@ __global__ __launch_bounds__((eval_waves<H, TRAIN>() * 64)) void map_eval_bf16_k
                     if (A.canonical)
                         canon_out(myfr, x, y, dx, dy);
                     const float dz = -sqrtf(fmaxf(0.0f, 1.0f - dx * dx - dy * dy));
-                    const int64_t idx = static_cast<int64_t>(head) * n + r;
-                    out.logit[idx] = logit;
-                    out.mask[idx] = m ? 1 : 0;
                     out.x[idx] = m ? x : nan;
                     out.y[idx] = m ? y : nan;
                     out.dx[idx] = m ? dx : nan;
@@ -502,7 +507,7 @@ __global__ __launch_bounds__((eval_waves<H, TRAIN>() * 64)) void map_eval_bf16_k
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt)
                     decode_store(o[nt], to, g, ray0 + nt * 16 + col, n, A.P, out_shift, out_scale, out,
-                                 A.canonical != 0, fr[nt]);
+                                 A.canonical != 0, fr[nt], A.flags, A.mask_in);
             }
         }
     }
@@ -808,14 +813,18 @@ lt_status lt_map_quantize(lt_map map, int32_t dtype, void *stream)
     return dtype == LT_FP8 ? ensure_packed_fp8(*M, s) : ensure_packed_bf16(*M, s);
 }
 
-lt_status lt_map_eval(lt_map map, int32_t dtype, const lt_rays *rays, const lt_map_out *out,
-                      int64_t n, void *stream)
+lt_status lt_map_eval_ex(lt_map map, int32_t dtype, const lt_rays *rays, const lt_map_out *out,
+                         int64_t n, uint32_t flags, const uint8_t *mask_in, void *stream)
 {
     Map *M = as_map(map);
     if (!M || !rays || !out)
         return fail(LT_ERR_ARG, "NULL map, rays or out");
     if (n < 0)
         return fail(LT_ERR_ARG, "negative ray count");
+    if (flags & ~static_cast<uint32_t>(LT_EVAL_MASK_ONLY | LT_EVAL_GATED))
+        return fail(LT_ERR_ARG, "unknown evaluation flag");
+    if ((flags & LT_EVAL_MASK_ONLY) && (flags & LT_EVAL_GATED))
+        return fail(LT_ERR_ARG, "LT_EVAL_MASK_ONLY and LT_EVAL_GATED exclude each other");
     if (dtype != LT_BF16 && dtype != LT_FP8 && dtype != LT_F32)
         return fail(LT_ERR_DTYPE, "precision not available (LT_F32, LT_BF16, LT_FP8)");
     if (dtype == LT_FP8 && !M->lay.fp8_ok)
@@ -826,14 +835,19 @@ lt_status lt_map_eval(lt_map map, int32_t dtype, const lt_rays *rays, const lt_m
         return fail(LT_ERR_STATE, "parameters were never set");
     if (!rays->x || !rays->y || !rays->dx || !rays->dy || !rays->dz || !rays->lambda_nm)
         return fail(LT_ERR_ARG, "NULL ray field");
-    if (!out->logit || !out->mask || !out->x || !out->y || !out->dx || !out->dy || !out->dz ||
-        !out->throughput)
+    const bool gated = (flags & LT_EVAL_GATED) != 0, fields = (flags & LT_EVAL_MASK_ONLY) == 0;
+    if ((!gated && (!out->logit || !out->mask)) ||
+        (fields && (!out->x || !out->y || !out->dx || !out->dy || !out->dz || !out->throughput)))
         return fail(LT_ERR_ARG, "NULL output field");
+    if (gated && !mask_in)
+        return fail(LT_ERR_ARG, "LT_EVAL_GATED needs mask_in");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     EvalArgs A{};
     A.n = n;
+    A.flags = flags;
+    A.mask_in = mask_in;
     if (dtype == LT_F32)
-        return eval_f32(*M, *rays, *out, n, s);
+        return eval_f32(*M, *rays, *out, n, flags, mask_in, s);
     if (dtype == LT_FP8) {
         lt_status st = ensure_packed_fp8(*M, s);
         if (st != LT_OK)
@@ -844,6 +858,12 @@ lt_status lt_map_eval(lt_map map, int32_t dtype, const lt_rays *rays, const lt_m
     if (st != LT_OK)
         return st;
     return launch_map_forward<false>(*M, *rays, *out, A, s);
+}
+
+lt_status lt_map_eval(lt_map map, int32_t dtype, const lt_rays *rays, const lt_map_out *out,
+                      int64_t n, void *stream)
+{
+    return lt_map_eval_ex(map, dtype, rays, out, n, 0u, nullptr, stream);
 }
 
 }  // extern "C"

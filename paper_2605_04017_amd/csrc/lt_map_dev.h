@@ -154,6 +154,8 @@ struct EvalArgs {
     int64_t xpose;        // LDS offset of the per-wave output transpose buffers (4 KiB each)
     int32_t canonical;    // symmetry-reduced input frame
     float *canon_out;     // training forward: [3][n_pad] frame (c, s, sg) per ray, or null
+    uint32_t flags;       // LT_EVAL_MASK_ONLY / LT_EVAL_GATED
+    const uint8_t *mask_in;  // LT_EVAL_GATED: [P][n] validity from a classifier
     int64_t n;
     // training forward only
     float *xhat_out;      // [6][n_pad]
@@ -217,9 +219,12 @@ __device__ __forceinline__ void canon_out(const CanonFrame &F, float &x, float &
 // even lanes write every field but the throughput.  With `canon` the exit
 // position and direction are mapped back from the ray's canonical frame F.
 // Every lane must call this (it contains a cross-lane shuffle).
+// flags: LT_EVAL_MASK_ONLY writes only logit and mask; LT_EVAL_GATED writes
+// only the exit fields, valid where mask_in (from a classifier) is set.
 __device__ __forceinline__ void decode_store(floatx4 v, int to, int g, int64_t r, int64_t n, int P,
                                              const float *out_shift, const float *out_scale,
-                                             const lt_map_out &out, bool canon, const CanonFrame &F)
+                                             const lt_map_out &out, bool canon, const CanonFrame &F,
+                                             uint32_t flags, const uint8_t *mask_in)
 {
     const int head = 2 * to + (g >> 1);
     const bool even = (g & 1) == 0;
@@ -231,25 +236,30 @@ __device__ __forceinline__ void decode_store(floatx4 v, int to, int g, int64_t r
         return;
     const int64_t idx = static_cast<int64_t>(head) * n + r;
     const float nan = __builtin_nanf("");
+    const bool gated = (flags & LT_EVAL_GATED) != 0, fields = (flags & LT_EVAL_MASK_ONLY) == 0;
     if (even) {
         const float logit = v[0];
-        const bool m = logit > 0.0f;
-        float x = fmaf(out_scale[5 * hs + 0], v[1], out_shift[5 * hs + 0]);
-        float y = fmaf(out_scale[5 * hs + 1], v[2], out_shift[5 * hs + 1]);
-        float dx = fmaf(out_scale[5 * hs + 2], v[3], out_shift[5 * hs + 2]);
-        float dy = recv;
-        if (canon)
-            canon_out(F, x, y, dx, dy);
-        const float dz = -sqrtf(fmaxf(0.0f, 1.0f - dx * dx - dy * dy));
-        out.logit[idx] = logit;
-        out.mask[idx] = m ? 1 : 0;
-        out.x[idx] = m ? x : nan;
-        out.y[idx] = m ? y : nan;
-        out.dx[idx] = m ? dx : nan;
-        out.dy[idx] = m ? dy : nan;
-        out.dz[idx] = m ? dz : nan;
-    } else {
-        const bool m = recv > 0.0f;
+        const bool m = gated ? mask_in[idx] != 0 : logit > 0.0f;
+        if (!gated) {
+            out.logit[idx] = logit;
+            out.mask[idx] = m ? 1 : 0;
+        }
+        if (fields) {
+            float x = fmaf(out_scale[5 * hs + 0], v[1], out_shift[5 * hs + 0]);
+            float y = fmaf(out_scale[5 * hs + 1], v[2], out_shift[5 * hs + 1]);
+            float dx = fmaf(out_scale[5 * hs + 2], v[3], out_shift[5 * hs + 2]);
+            float dy = recv;
+            if (canon)
+                canon_out(F, x, y, dx, dy);
+            const float dz = -sqrtf(fmaxf(0.0f, 1.0f - dx * dx - dy * dy));
+            out.x[idx] = m ? x : nan;
+            out.y[idx] = m ? y : nan;
+            out.dx[idx] = m ? dx : nan;
+            out.dy[idx] = m ? dy : nan;
+            out.dz[idx] = m ? dz : nan;
+        }
+    } else if (fields) {
+        const bool m = gated ? mask_in[idx] != 0 : recv > 0.0f;
         const float thr = fmaf(out_scale[5 * hs + 4], v[1], out_shift[5 * hs + 4]);
         out.throughput[idx] = m ? thr : 0.0f;
     }

@@ -105,6 +105,8 @@ struct F32Args {
     F32Layout F;
     int32_t D, P, TO;
     int32_t canonical;
+    uint32_t flags;
+    const uint8_t *mask_in;
     int64_t n;
 };
 
@@ -296,7 +298,7 @@ __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args
 #pragma unroll
                 for (int nt = 0; nt < kF32NT; ++nt)
                     decode_store(o[nt], to, g, ray0 + nt * 16 + col, n, A.P, out_shift, out_scale, out,
-                                 A.canonical != 0, fr[nt]);
+                                 A.canonical != 0, fr[nt], A.flags, A.mask_in);
             }
         }
     }
@@ -304,9 +306,11 @@ __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args
 
 template <int H, int ACT>
 static lt_status launch_f32(const Map &M, const lt_rays &rays, const lt_map_out &out, int64_t n,
-                            hipStream_t s)
+                            uint32_t flags, const uint8_t *mask_in, hipStream_t s)
 {
     F32Args A;
+    A.flags = flags;
+    A.mask_in = mask_in;
     A.img = M.img_f32;
     A.F = f32_layout(M.lay);
     A.D = M.lay.D;
@@ -352,7 +356,8 @@ lt_status ensure_packed_f32(Map &M, hipStream_t s)
     return st;
 }
 
-lt_status eval_f32(Map &M, const lt_rays &rays, const lt_map_out &out, int64_t n, hipStream_t s)
+lt_status eval_f32(Map &M, const lt_rays &rays, const lt_map_out &out, int64_t n, uint32_t flags,
+                   const uint8_t *mask_in, hipStream_t s)
 {
     lt_status st = ensure_packed_f32(M, s);
     if (st != LT_OK)
@@ -360,13 +365,13 @@ lt_status eval_f32(Map &M, const lt_rays &rays, const lt_map_out &out, int64_t n
     const int H = M.lay.H;
     const bool relu = M.lay.act == LT_ACT_RELU;
     if (H == 128)
-        return relu ? launch_f32<128, LT_ACT_RELU>(M, rays, out, n, s)
-                    : launch_f32<128, LT_ACT_TANH>(M, rays, out, n, s);
+        return relu ? launch_f32<128, LT_ACT_RELU>(M, rays, out, n, flags, mask_in, s)
+                    : launch_f32<128, LT_ACT_TANH>(M, rays, out, n, flags, mask_in, s);
     if (H == 64)
-        return relu ? launch_f32<64, LT_ACT_RELU>(M, rays, out, n, s)
-                    : launch_f32<64, LT_ACT_TANH>(M, rays, out, n, s);
-    return relu ? launch_f32<32, LT_ACT_RELU>(M, rays, out, n, s)
-                : launch_f32<32, LT_ACT_TANH>(M, rays, out, n, s);
+        return relu ? launch_f32<64, LT_ACT_RELU>(M, rays, out, n, flags, mask_in, s)
+                    : launch_f32<64, LT_ACT_TANH>(M, rays, out, n, flags, mask_in, s);
+    return relu ? launch_f32<32, LT_ACT_RELU>(M, rays, out, n, flags, mask_in, s)
+                : launch_f32<32, LT_ACT_TANH>(M, rays, out, n, flags, mask_in, s);
 }
 
 int64_t f32_image_bytes(const MapLayout &L) { return f32_layout(L).bytes; }

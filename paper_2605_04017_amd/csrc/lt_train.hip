@@ -126,8 +126,10 @@ struct LossArgs {
     const float *canon;    // [3][n_pad] (c, s, sg) per ray, or null (plain input)
     int64_t n, n_pad, o_stride;
     int32_t P;
-    float w_bce, w_l2;
+    float w_bce, w_l2, w_cos;
 };
+
+constexpr float kCosEps = 1e-6f;  // floor of 1 - dx^2 - dy^2 in the direction loss
 
 __global__ __launch_bounds__(kLossBlock) void loss_kernel(LossArgs A)
 {
@@ -162,11 +164,47 @@ __global__ __launch_bounds__(kLossBlock) void loss_kernel(LossArgs A)
                 tv[2] = c * dx + s * dy;
                 tv[3] = (c * dy - s * dx) * sg;
             }
-            for (int q = 0; q < 5; ++q) {
-                const float tn = (tv[q] - sh[5 * h + q]) / sc[5 * h + q];
-                const float diff = v > 0.0f ? o[(q + 1) * A.o_stride] - tn : 0.0f;
-                s_l2 += diff * diff;
-                d[(q + 1) * A.n_pad] = A.w_l2 * 2.0f * diff * inv * 0.2f;
+            if (A.w_cos == 0.0f) {
+                for (int q = 0; q < 5; ++q) {
+                    const float tn = (tv[q] - sh[5 * h + q]) / sc[5 * h + q];
+                    const float diff = v > 0.0f ? o[(q + 1) * A.o_stride] - tn : 0.0f;
+                    s_l2 += A.w_l2 * 0.2f * diff * diff;
+                    d[(q + 1) * A.n_pad] = A.w_l2 * 2.0f * diff * inv * 0.2f;
+                }
+            } else {
+                // squared error on x, y, throughput
+                const float third = 1.0f / 3.0f;
+                for (int q = 0; q < 5; q += (q == 1 ? 3 : 1)) {
+                    const float tn = (tv[q] - sh[5 * h + q]) / sc[5 * h + q];
+                    const float diff = v > 0.0f ? o[(q + 1) * A.o_stride] - tn : 0.0f;
+                    s_l2 += A.w_l2 * third * diff * diff;
+                    d[(q + 1) * A.n_pad] = A.w_l2 * 2.0f * diff * inv * third;
+                }
+                // 1 - cos(angle) between predicted and target directions
+                float gdx = 0.0f, gdy = 0.0f;
+                if (v > 0.0f) {
+                    const float sx = sc[5 * h + 2], sy = sc[5 * h + 3];
+                    const float dxp = fmaf(sx, o[3 * A.o_stride], sh[5 * h + 2]);
+                    const float dyp = fmaf(sy, o[4 * A.o_stride], sh[5 * h + 3]);
+                    float sp = 1.0f - dxp * dxp - dyp * dyp;
+                    const bool flp = sp < kCosEps;
+                    sp = flp ? kCosEps : sp;
+                    const float rsp = sqrtf(sp), dzp = -rsp;
+                    const float dxt = tv[2], dyt = tv[3];
+                    const float dzt = -sqrtf(fmaxf(kCosEps, 1.0f - dxt * dxt - dyt * dyt));
+                    const float it = 1.0f / sqrtf(dxt * dxt + dyt * dyt + dzt * dzt);
+                    const float qx = dxt * it, qy = dyt * it, qz = dzt * it;
+                    const float nu = sqrtf(dxp * dxp + dyp * dyp + dzp * dzp), inu = 1.0f / nu;
+                    const float dot = dxp * qx + dyp * qy + dzp * qz;
+                    s_l2 += A.w_cos * (1.0f - dot * inu);
+                    const float k3 = dot * inu * inu * inu;
+                    const float gx = qx * inu - k3 * dxp, gy = qy * inu - k3 * dyp, gz = qz * inu - k3 * dzp;
+                    const float dzdx = flp ? 0.0f : dxp / rsp, dzdy = flp ? 0.0f : dyp / rsp;
+                    gdx = -A.w_cos * inv * (gx + gz * dzdx) * sx;
+                    gdy = -A.w_cos * inv * (gy + gz * dzdy) * sy;
+                }
+                d[3 * A.n_pad] = gdx;
+                d[4 * A.n_pad] = gdy;
             }
         }
     }
@@ -757,7 +795,8 @@ lt_status lt_map_train_step(lt_map map, const lt_rays *rays, const lt_targets *t
         !targets->throughput)
         return fail(LT_ERR_ARG, "NULL target field");
     if (cfg->step < 1 || !(cfg->lr >= 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) ||
-        !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) || !(cfg->eps > 0.0f))
+        !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) || !(cfg->eps > 0.0f) ||
+        !(cfg->w_cos >= 0.0f && cfg->w_cos < 1e30f))
         return fail(LT_ERR_ARG, "bad optimiser settings (step must be >= 1)");
     WsLayout w;
     lt_status st = check_ws(M, ws, ws_bytes, n, &w);
@@ -793,6 +832,7 @@ lt_status lt_map_train_step(lt_map map, const lt_rays *rays, const lt_targets *t
     LA.P = M->lay.P;
     LA.w_bce = cfg->w_bce;
     LA.w_l2 = cfg->w_l2;
+    LA.w_cos = cfg->w_cos;
     hipLaunchKernelGGL(loss_kernel, dim3(static_cast<uint32_t>(w.loss_blocks)), dim3(kLossBlock), 0,
                        s, LA);
     st = check_hip(hipGetLastError(), "loss_kernel launch");
@@ -819,7 +859,7 @@ lt_status lt_map_train_step(lt_map map, const lt_rays *rays, const lt_targets *t
     AA.loss_out = loss_out;
     const double np = static_cast<double>(n) * M->lay.P;
     AA.loss_scale_bce = static_cast<float>(cfg->w_bce / np);
-    AA.loss_scale_l2 = static_cast<float>(cfg->w_l2 / (5.0 * np));
+    AA.loss_scale_l2 = static_cast<float>(1.0 / np);   // the loss kernel applies the weights
     int grid = static_cast<int>((M->lay.n_params + 255) / 256);
     if (grid > 1024)
         grid = 1024;

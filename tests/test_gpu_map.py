@@ -393,3 +393,42 @@ def test_canonical_map_equivariance_on_gpu(dev):
     assert np.abs((c * edx - s_ * edy) - b["dx"])[ok].max() < tol
     assert np.abs((s_ * edx + c * edy) - b["dy"])[ok].max() < tol
     assert np.abs(a["throughput"] - b["throughput"])[ok].max() < tol
+
+
+@pytest.mark.parametrize("width,depth,heads,dtype", [(32, 2, 3, 1), (32, 5, 3, 0), (128, 5, 56, 1),
+                                                     (128, 5, 1, 2), (128, 5, 2, 0)])
+def test_eval_flags(dev, width, depth, heads, dtype):
+    """LT_EVAL_MASK_ONLY writes exactly lt_map_eval's logit and mask and
+    leaves the fields alone; LT_EVAL_GATED writes exactly its fields where
+    the given mask agrees with the map's own, valid values wherever the given
+    mask is set, and NaN / 0 where it is clear (the factorised classifier +
+    regressor evaluation)."""
+    import torch
+    import paper_2605_04017_amd as lt
+    n = 3001
+    rays = synth.config_rays(2, n)
+    p = make_params(mlp.MapDesc(width, depth, heads, mlp.ACT_TANH), 80 + width + heads, rays)
+    m = gpu_map(p, dev)
+    r = {k: torch.from_numpy(v).to(dev) for k, v in rays.items()}
+    full = lt.lt_map_eval(m, dtype, r)
+    mo = {k: torch.full((heads, n), 7.0 if k != "mask" else 7, device=dev,
+                        dtype=torch.uint8 if k == "mask" else torch.float32) for k in lt.MAP_FIELDS}
+    lt.lt_map_eval_ex(m, dtype, r, mo, flags=lt.LT_EVAL_MASK_ONLY)
+    ones = torch.ones((heads, n), dtype=torch.uint8, device=dev)
+    g1 = lt.lt_map_eval_ex(m, dtype, r, flags=lt.LT_EVAL_GATED, mask_in=ones)
+    g0 = lt.lt_map_eval_ex(m, dtype, r, flags=lt.LT_EVAL_GATED, mask_in=torch.zeros_like(ones))
+    torch.cuda.synchronize()
+    assert torch.equal(mo["logit"], full["logit"]) and torch.equal(mo["mask"], full["mask"])
+    for k in lt.MAP_FIELDS[2:]:
+        assert torch.all(mo[k] == 7.0)
+    own = full["mask"].bool()
+    for k in ("x", "y", "dx", "dy", "dz", "throughput"):
+        assert torch.equal(g1[k][own], full[k][own]), k
+        assert torch.isfinite(g1[k]).all(), k
+        if k == "throughput":
+            assert torch.all(g0[k] == 0)
+        else:
+            assert torch.isnan(g0[k]).all()
+    assert set(g1) == set(lt.MAP_FIELDS[2:])
+    with pytest.raises(lt.LtError):
+        lt.lt_map_eval_ex(m, dtype, r, flags=lt.LT_EVAL_GATED | lt.LT_EVAL_MASK_ONLY, mask_in=ones)

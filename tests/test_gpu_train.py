@@ -274,3 +274,42 @@ def test_canonical_train_step(dev):
     big = np.abs(gr) > 1e-2 * np.abs(gr).max()
     expect = -1e-3 * gr / (np.abs(gr) + 1e-8)
     assert np.mean(np.abs(step[big] - expect[big]) < 1e-6) > 0.99
+
+
+def test_cosine_direction_loss_train_step(dev):
+    """w_cos > 0: squared error on x, y, throughput plus 1 - cos of the exit
+    direction; the fused step's loss and first Adam step match the
+    reference (loss_and_grad_quantized with w_cos)."""
+    import torch
+    import paper_2605_04017_amd as lt
+    L = synth.config_lens(2)
+    n = 16384
+    rays = synth.config_rays(2, n)
+    desc = mlp.MapDesc(64, 3, 1, mlp.ACT_TANH)
+    p = make_params(desc, 37, rays)
+    r, t = _targets(L, rays, dev)
+    tv = {k: v.cpu().numpy()[0] for k, v in t.items()}
+    ok = tv["valid"] == 1
+    reg = np.stack([tv[k][ok] for k in ("x", "y", "dx", "dy", "throughput")], 1)
+    p.out_shift = reg.mean(0)[None].astype(np.float32).astype(np.float64)
+    p.out_scale = reg.std(0)[None].astype(np.float32).astype(np.float64)
+    m = gpu_map(p, dev)
+    ws = lt.workspace(m, n)
+    cfg = {"lr": 1e-3, "step": 1, "w_bce": 0.5, "w_l2": 1.0, "w_cos": 20.0}
+    loss = lt.lt_map_train_step(m, r, t, cfg, ws)
+    torch.cuda.synchronize()
+    tn = {k: v.cpu().numpy() for k, v in t.items()}
+    tnorm = mlp.normalise_targets({k: tn[k] for k in ("x", "y", "dx", "dy", "throughput")}, p)
+    (lref, bref, rref), gref = mlp.loss_and_grad_quantized(p, mlp.features(rays, p),
+                                                           tn["valid"].astype(np.int64), tnorm,
+                                                           0.5, 1.0, 20.0)
+    lg = loss.cpu().numpy()
+    assert abs(lg[0] - lref) <= 1e-3 * lref and abs(lg[2] - rref) <= 2e-3 * rref, (lg, lref, rref)
+    new = lt.lt_map_get_params(m).cpu().numpy().astype(np.float64)
+    step = new - p.flat()
+    gr = mlp.grads_flat(gref)
+    big = np.abs(gr) > 1e-2 * np.abs(gr).max()
+    expect = -1e-3 * gr / (np.abs(gr) + 1e-8)
+    assert np.mean(np.abs(step[big] - expect[big]) < 1e-6) > 0.99
+    with pytest.raises(lt.LtError):
+        lt.lt_map_train_step(m, r, t, {"lr": 1e-3, "step": 2, "w_cos": -1.0}, ws)

@@ -197,3 +197,87 @@ def test_quantized_gradient_close_to_exact(act):
     for (dW, db), (qW, qb) in zip(g, gq):
         assert np.linalg.norm(dW - qW) <= tol * np.linalg.norm(dW)
         assert np.linalg.norm(db - qb) <= tol * np.linalg.norm(db) + 1e-12
+
+
+# ---------------------------------------------------------------- cosine loss
+
+def _cos_setup(n=50, H=2, seed=0):
+    desc = mlp.MapDesc(32, 2, H, mlp.ACT_TANH)
+    p = mlp.init_params(desc, seed)
+    rng = np.random.default_rng(seed)
+    p.out_shift = rng.normal(0, 0.05, (H, 5))
+    p.out_scale = rng.uniform(0.05, 0.3, (H, 5))
+    o = rng.normal(0, 0.5, (n, 6 * H))
+    t = rng.normal(0, 0.5, (H, n, 5))
+    valid = rng.integers(0, 2, (H, n))
+    return p, o, t, valid
+
+
+def test_cosine_loss_zero_for_identical_directions():
+    p, o, t, valid = _cos_setup()
+    H, n = valid.shape
+    oo = o.reshape(n, H, 6)
+    t[..., 2] = oo[..., 3].T          # target direction = predicted direction
+    t[..., 3] = oo[..., 4].T
+    (tot, bce, reg), g = mlp.loss_terms(p, o, valid, t, 0.0, 0.0, 1.0)
+    assert abs(reg) < 1e-13 and abs(tot - reg) < 1e-13
+    gg = g.reshape(n, H, 6)
+    assert np.abs(gg[..., 3:5]).max() < 1e-12
+
+
+def test_cosine_loss_known_angle():
+    """Target and prediction in the x-z plane, the prediction turned by
+    theta: the loss is 1 - cos(theta) per valid ray."""
+    H, n = 1, 5
+    p = mlp.init_params(mlp.MapDesc(32, 2, H, mlp.ACT_TANH), 0)
+    a = np.linspace(0.05, 0.4, n)
+    theta = 0.1
+    o = np.zeros((n, 6))
+    o[:, 3] = np.sin(a + theta)       # out_shift 0, out_scale 1: raw = lens units
+    t = np.zeros((H, n, 5))
+    t[0, :, 2] = np.sin(a)
+    valid = np.ones((H, n), int)
+    (_, _, reg), _ = mlp.loss_terms(p, o, valid, t, 0.0, 0.0, 2.0)
+    assert abs(reg - 2.0 * (1 - np.cos(theta))) < 1e-12
+
+
+def test_cosine_loss_gradient_finite_differences():
+    p, o, t, valid = _cos_setup(n=40)
+    w = (0.7, 1.3, 2.1)
+    _, g = mlp.loss_terms(p, o, valid, t, *w)
+    rng = np.random.default_rng(3)
+    for idx in rng.choice(o.size, 60, replace=False):
+        i, j = divmod(int(idx), o.shape[1])
+        h = 1e-6
+        op, om = o.copy(), o.copy()
+        op[i, j] += h
+        om[i, j] -= h
+        fd = (mlp.loss_terms(p, op, valid, t, *w)[0][0] - mlp.loss_terms(p, om, valid, t, *w)[0][0]) / (2 * h)
+        assert abs(fd - g[i, j]) <= 1e-6 * max(1.0, abs(fd)), (i, j, fd, g[i, j])
+
+
+def test_cosine_loss_parameter_gradient():
+    """loss_and_grad with the cosine term against central differences of
+    the FP64 loss in the parameters."""
+    rng = np.random.default_rng(4)
+    desc = mlp.MapDesc(32, 3, 1, mlp.ACT_TANH)
+    p = mlp.init_params(desc, 4)
+    p.out_scale = np.array([[1.0, 1.0, 0.2, 0.2, 1.0]])
+    x = rng.normal(0, 1, (30, 6))
+    t = rng.normal(0, 0.5, (1, 30, 5))
+    valid = rng.integers(0, 2, (1, 30))
+    _, grads = mlp.loss_and_grad(p, x, valid, t, 1.0, 0.5, 1.5)
+    flat = mlp.grads_flat(grads)
+    theta = p.flat()
+    for k in rng.choice(theta.size, 25, replace=False):
+        h = 1e-6
+        q = p.copy()
+        th = theta.copy()
+        th[k] += h
+        q.set_flat(th)
+        lp = mlp.loss_and_grad(q, x, valid, t, 1.0, 0.5, 1.5)[0][0]
+        th[k] -= 2 * h
+        q.set_flat(th)
+        lm = mlp.loss_and_grad(q, x, valid, t, 1.0, 0.5, 1.5)[0][0]
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - flat[k]) <= 1e-6 * max(1.0, abs(fd)), (k, fd, flat[k])
