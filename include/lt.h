@@ -137,6 +137,12 @@ typedef struct {
     int32_t i;
 } lt_path;
 
+/* Planes of the lens frame (z along the axis, front vertex at z = 0):
+ * the forward input plane, 1 mm in front of the foremost point of the first
+ * surface within its clear aperture (where LT_TRACE_FORWARD rays start), and
+ * the sensor plane (where sensor-side rays start).  Host-only. */
+lt_status lt_lens_planes(lt_lens lens, double *z_forward_in, double *z_sensor);
+
 /* Index of a ghost path in [0, C(N,2)) ordered by (j, i) lexicographically,
  * and its inverse.  Return -1 / LT_ERR_PATH for an invalid path. */
 int32_t lt_ghost_index(int32_t n_refracting, int32_t j, int32_t i);
@@ -230,6 +236,13 @@ lt_status lt_trace(lt_lens lens, const lt_path *path, const lt_rays *rays,
                                    the transmitted cosine near grazing.  Faster, but
                                    exit-position errors reach a few 1e-5 mm on long
                                    ghost paths. */
+
+#define LT_TRACE_FORWARD 2u    /* forward light tracing (Sec. 3, the flare equation): rays start
+                                   on the forward input plane (lt_lens_planes) in air,
+                                   travelling toward the image (dz > 0), and follow the path's
+                                   interactions in reverse order (a ghost (j, i) reflects
+                                   first at i, then at j); exit rays are reported on the
+                                   sensor plane with dz > 0. */
 
 /* lt_trace with options (0 = same as lt_trace).  Unknown flags: LT_ERR_ARG. */
 lt_status lt_trace_ex(lt_lens lens, const lt_path *path, const lt_rays *rays,

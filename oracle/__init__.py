@@ -68,9 +68,11 @@ def lib():
                                         P(C.c_double), P(OrDiag)]
         L.or_trace_sequence.restype = C.c_int
         L.or_trace_batch.argtypes = ([P(OrSurface), C.c_int, P(OrGlass), C.c_int, C.c_int, C.c_int,
-                                      C.c_int, C.c_int64] + [C.c_void_p] * 6 + [C.c_void_p]
+                                      C.c_int, C.c_int, C.c_int64] + [C.c_void_p] * 6 + [C.c_void_p]
                                      + [C.c_void_p] * 7 + [C.c_void_p] * 4 + [C.c_int])
         L.or_trace_batch.restype = C.c_int64
+        L.or_forward_plane_z.argtypes = [P(OrSurface), C.c_int]
+        L.or_forward_plane_z.restype = C.c_double
         L.or_glass_index.argtypes = [P(OrGlass), C.c_int, C.c_int, C.c_double]
         L.or_glass_index.restype = C.c_double
         _lib = L
@@ -99,13 +101,18 @@ def _ptr(a):
     return a.ctypes.data_as(C.c_void_p) if a is not None else None
 
 
-def trace(lens, rays: dict, path=(0, 0, 0), nthreads: int = 0, diag: bool = False) -> dict:
+def trace(lens, rays: dict, path=(0, 0, 0), nthreads: int = 0, diag: bool = False,
+          forward: bool = False) -> dict:
     """Trace sensor-side FP32 rays through ``lens`` along ``path`` = (kind, j, i).
 
     kind 0 = transmit, kind 1 = two-reflection ghost with 1-based refracting
     surface indices j < i.  Returns FP64 arrays: mask, x, y, z (= 0, the output
     plane), dx, dy, dz, throughput; with ``diag`` also edge/TIR/grazing margins
     and the failure kind.  nthreads = 0 uses OpenMP's default.
+
+    forward: the rays start on the forward input plane (``forward_plane_z``)
+    travelling toward the image and follow the path's interactions in reverse
+    order (forward light tracing, Sec. 3); the outputs lie on the sensor plane.
     """
     L = lib()
     S, ns, G, ng = _pack(lens)
@@ -120,7 +127,7 @@ def trace(lens, rays: dict, path=(0, 0, 0), nthreads: int = 0, diag: bool = Fals
         for k in ("edge_margin", "tir_margin", "graze_margin"):
             dg[k] = np.empty(n, np.float64)
         dg["fail_kind"] = np.empty(n, np.int32)
-    nv = L.or_trace_batch(S, ns, G, ng, int(path[0]), int(path[1]), int(path[2]), n,
+    nv = L.or_trace_batch(S, ns, G, ng, int(path[0]), int(path[1]), int(path[2]), int(bool(forward)), n,
                           _ptr(f["x"]), _ptr(f["y"]), _ptr(f["dx"]), _ptr(f["dy"]),
                           _ptr(f["dz"]), _ptr(f["lambda_nm"]), _ptr(out["mask"]),
                           _ptr(out["x"]), _ptr(out["y"]), _ptr(out["z"]), _ptr(out["dx"]),
@@ -133,6 +140,13 @@ def trace(lens, rays: dict, path=(0, 0, 0), nthreads: int = 0, diag: bool = Fals
     out.update(dg)
     out["n_valid"] = int(nv)
     return out
+
+
+def forward_plane_z(lens) -> float:
+    """z of the forward input plane (1 mm in front of the first surface's
+    foremost point within its clear aperture)."""
+    S, ns, _, _ = _pack(lens)
+    return float(lib().or_forward_plane_z(S, ns))
 
 
 def build_sequence(lens, kind: int, j: int = 0, i: int = 0):

@@ -300,12 +300,33 @@ static double sensor_plane_z(const or_surface *s, int ns)
     return z;
 }
 
-/* Batch entry: sensor-side FP32 rays (x, y on the sensor plane, direction,
- * wavelength in nm) traced along path (kind, j, i); FP64 outputs.
- * Diagnostics arrays may be NULL.  Returns the number of valid rays, or -1 on
- * a bad path. */
+/* Forward input plane: 1 mm in front of the foremost point of surface 1
+ * within its clear aperture.  The surface point at height h lies at
+ * z = R - sgn(R) sqrt(R^2 - h^2) (vertex frame); it is foremost at the rim
+ * when that is negative, else at the vertex. */
+double or_forward_plane_z(const or_surface *s, int ns)
+{
+    if (ns <= 0)
+        return -1.0;
+    double zf = 0.0;
+    if (s[0].radius != 0.0) {
+        const double R = s[0].radius, h = s[0].sd;
+        const double z_rim = R - copysign(sqrt(R * R - h * h), R);
+        if (z_rim < zf)
+            zf = z_rim;
+    }
+    return zf - 1.0;
+}
+
+/* Batch entry.  Sensor-side (forward = 0): FP32 rays with x, y on the sensor
+ * plane, direction toward the object and wavelength in nm, traced along path
+ * (kind, j, i) to the front vertex plane z = 0.  Forward light tracing
+ * (forward = 1): rays with x, y on the forward input plane travelling toward
+ * the image follow the same interactions in reverse order and direction and
+ * are reported on the sensor plane.  FP64 outputs.  Diagnostics arrays may be
+ * NULL.  Returns the number of valid rays, or -1 on a bad path. */
 int64_t or_trace_batch(const or_surface *s, int ns, const or_glass *g, int ng,
-                       int kind, int j, int i, int64_t n,
+                       int kind, int j, int i, int forward, int64_t n,
                        const float *x, const float *y, const float *dx, const float *dy,
                        const float *dz, const float *lam,
                        uint8_t *mask, double *ox, double *oy, double *oz,
@@ -318,6 +339,20 @@ int64_t or_trace_batch(const or_surface *s, int ns, const or_glass *g, int ng,
     if (nsteps < 0)
         return -1;
     double zs = sensor_plane_z(s, ns);
+    if (forward) {
+        for (int a = 0, b = nsteps - 1; a < b; ++a, --b) {
+            or_step tmp = seq[a];
+            seq[a] = seq[b];
+            seq[b] = tmp;
+        }
+        /* a reflection keeps its side (its incoming and outgoing segments
+           swap); transmissions and stop crossings are walked the other way */
+        for (int k = 0; k < nsteps; ++k)
+            if (seq[k].type != 1)
+                seq[k].dir = -seq[k].dir;
+    }
+    const double z_start = forward ? or_forward_plane_z(s, ns) : zs, z_end = forward ? zs : 0.0;
+    const int exit_dir = forward ? 1 : -1;
     int64_t nvalid = 0;
 #ifdef _OPENMP
     if (nthreads > 0)
@@ -325,12 +360,12 @@ int64_t or_trace_batch(const or_surface *s, int ns, const or_glass *g, int ng,
 #pragma omp parallel for schedule(static) reduction(+ : nvalid) if (nthreads != 1)
 #endif
     for (int64_t r = 0; r < n; ++r) {
-        double o[3] = {(double)x[r], (double)y[r], zs};
+        double o[3] = {(double)x[r], (double)y[r], z_start};
         double d[3] = {(double)dx[r], (double)dy[r], (double)dz[r]};
         double P[3], D[3], I;
         or_diag dg;
         int ok = or_trace_sequence(s, ns, g, ng, seq, nsteps, (double)lam[r], o, d,
-                                   0.0, -1, P, D, &I, &dg);
+                                   z_end, exit_dir, P, D, &I, &dg);
         mask[r] = (uint8_t)ok;
         nvalid += ok;
         if (ox) ox[r] = P[0];

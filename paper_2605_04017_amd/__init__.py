@@ -16,6 +16,7 @@ RAY_FIELDS = ("x", "y", "dx", "dy", "dz", "lambda_nm")
 EXIT_FIELDS = ("mask", "x", "y", "dx", "dy", "dz", "throughput")
 
 LT_TRACE_PLAIN_FP32 = N.LT_TRACE_PLAIN_FP32
+LT_TRACE_FORWARD = N.LT_TRACE_FORWARD
 LT_F32, LT_BF16, LT_FP8 = N.LT_F32, N.LT_BF16, N.LT_FP8
 LT_ACT_TANH, LT_ACT_RELU = N.LT_ACT_TANH, N.LT_ACT_RELU
 MAP_FIELDS = ("logit", "mask", "x", "y", "dx", "dy", "dz", "throughput")
@@ -28,6 +29,7 @@ __all__ = ["LtError", "Lens", "lt_lens_create", "lt_lens_query", "lt_trace", "lt
            "lt_map_forward_train", "lt_map_backward", "lt_map_train_step", "lt_map_adam_state",
            "TARGET_FIELDS", "lt_path_encode", "lt_path_decode", "lt_trace_compact",
            "lt_map_quantize", "lt_rays_generate", "lt_map_eval_ex", "LT_EVAL_MASK_ONLY",
+           "lt_lens_planes", "LT_TRACE_FORWARD",
            "LT_EVAL_GATED"]
 
 TARGET_FIELDS = ("valid", "x", "y", "dx", "dy", "throughput")
@@ -133,6 +135,13 @@ def lt_lens_query(lens: Lens) -> Tuple[int, int, int]:
     return ns.value, nr.value, ng.value
 
 
+def lt_lens_planes(lens: Lens) -> Tuple[float, float]:
+    """(z of the forward input plane, z of the sensor plane) in the lens frame."""
+    a, b = C.c_double(), C.c_double()
+    N.check(N.lib().lt_lens_planes(lens.handle, C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
 def lt_ghost_index(n_refracting: int, j: int, i: int) -> int:
     return int(N.lib().lt_ghost_index(n_refracting, j, i))
 
@@ -191,7 +200,7 @@ def lt_trace(lens: Lens, path, rays: Dict, out: Optional[Dict] = None, n: Option
 
 def lt_trace_ex(lens: Lens, path, rays: Dict, out: Optional[Dict] = None,
                 n: Optional[int] = None, flags: int = 0, stream=None) -> Dict:
-    """lt_trace with option flags (LT_TRACE_PLAIN_FP32 = 1)."""
+    """lt_trace with option flags (LT_TRACE_PLAIN_FP32 = 1, LT_TRACE_FORWARD = 2)."""
     torch = _torch()
     if n is None:
         n = int(rays["x"].numel())

@@ -13,6 +13,7 @@ LT_OK, LT_ERR_ARG, LT_ERR_LENS, LT_ERR_PATH, LT_ERR_DTYPE, LT_ERR_OOM, LT_ERR_DE
 LT_MAX_SURFACES = 24
 LT_MAX_GLASSES = 24
 LT_TRACE_PLAIN_FP32 = 1
+LT_TRACE_FORWARD = 2
 
 
 class LtError(RuntimeError):
@@ -87,6 +88,7 @@ SIGNATURES = {
     "lt_lens_destroy": (C.c_int, [C.c_void_p]),
     "lt_lens_query": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                 C.POINTER(C.c_int32)]),
+    "lt_lens_planes": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "lt_ghost_index": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32]),
     "lt_ghost_path": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(lt_path)]),
     "lt_path_encode": (C.c_int, [C.c_int32, C.POINTER(lt_path), C.POINTER(C.c_uint64)]),

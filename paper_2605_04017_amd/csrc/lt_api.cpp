@@ -1,6 +1,7 @@
 // Host runtime of liblt.so: status codes, thread-local errors, lens
 // validation and storage, path bookkeeping and per-launch trace tables.
 #include <cmath>
+#include <utility>
 #include <cstring>
 #include <new>
 #include <string>
@@ -42,7 +43,25 @@ static double glass_index_host(const lt_glass &g, double lam_um)
     return 1.0;
 }
 
-lt_status build_trace_table(const Lens &L, const lt_path &p, TraceTable *t)
+// Forward input plane: 1 mm in front of the foremost point of the first
+// surface within its clear aperture (its vertex, or its rim when it is
+// concave toward the object).
+double forward_plane_z(const Lens &L)
+{
+    const lt_surface &s = L.surf[0];
+    double rim = 0.0;
+    if (s.radius_mm != 0.0) {
+        const double R = s.radius_mm, h = s.semi_diameter_mm;
+        rim = R - (R > 0.0 ? 1.0 : -1.0) * std::sqrt(R * R - h * h);
+    }
+    return (rim < 0.0 ? rim : 0.0) - 1.0;
+}
+
+// Sensor-side paths start on the sensor plane and end on the front vertex
+// plane; forward paths (Sec. 3, forward light tracing) are the same
+// interactions in reverse order and direction, from the forward input plane
+// (in air) to the sensor plane.
+lt_status build_trace_table(const Lens &L, const lt_path &p, bool forward, TraceTable *t)
 {
     // interaction list: (surface, type, travel direction)
     int surf[kMaxSteps], type[kMaxSteps], dir[kMaxSteps];
@@ -71,8 +90,21 @@ lt_status build_trace_table(const Lens &L, const lt_path &p, TraceTable *t)
     } else {
         return fail(LT_ERR_PATH, "path kind must be 0 (transmit) or 1 (ghost)");
     }
+    if (forward) {
+        for (int a = 0, b = m - 1; a < b; ++a, --b) {
+            std::swap(surf[a], surf[b]);
+            std::swap(type[a], type[b]);
+            std::swap(dir[a], dir[b]);
+        }
+        // a reflection keeps its side (its incoming and outgoing segments
+        // swap); transmissions and stop crossings are walked the other way
+        for (int k = 0; k < m; ++k)
+            if (type[k] != kStepR)
+                dir[k] = -dir[k];
+    }
     std::memset(t, 0, sizeof(*t));
     t->nsteps = m;
+    t->exit_dir = forward ? 1.0f : -1.0f;
     auto split = [](double v, float *h, float *l) {
         *h = static_cast<float>(v);
         *l = static_cast<float>(v - static_cast<double>(*h));
@@ -89,8 +121,8 @@ lt_status build_trace_table(const Lens &L, const lt_path &p, TraceTable *t)
     };
     auto medium_before = [&](int s) { return s == 0 ? -1 : L.surf[s - 1].glass_after; };
     auto medium_after = [&](int s) { return L.surf[s].glass_after; };
-    t->glass_start = code_of(medium_after(L.ns - 1));
-    double zprev = L.zs;
+    t->glass_start = forward ? kAirCode : code_of(medium_after(L.ns - 1));
+    double zprev = forward ? forward_plane_z(L) : L.zs;
     for (int k = 0; k < m; ++k) {
         const lt_surface &s = L.surf[surf[k]];
         StepGeom &g = t->geom[k];
@@ -104,7 +136,7 @@ lt_status build_trace_table(const Lens &L, const lt_path &p, TraceTable *t)
         t->code[k] = static_cast<uint32_t>(type[k]) | (code_of(far) << 4) |
                      (static_cast<uint32_t>(flags) << 12);
     }
-    split(0.0 - zprev, &t->z_exit_h, &t->z_exit_l);
+    split((forward ? L.zs : 0.0) - zprev, &t->z_exit_h, &t->z_exit_l);
     return LT_OK;
 }
 
@@ -217,6 +249,16 @@ lt_status lt_lens_query(lt_lens lens, int32_t *n_surfaces, int32_t *n_refracting
     if (n_surfaces) *n_surfaces = L->ns;
     if (n_refracting) *n_refracting = L->nr;
     if (n_ghost_paths) *n_ghost_paths = L->nr * (L->nr - 1) / 2;
+    return LT_OK;
+}
+
+lt_status lt_lens_planes(lt_lens lens, double *z_forward_in, double *z_sensor)
+{
+    Lens *L = as_lens(lens);
+    if (!L || !z_forward_in || !z_sensor)
+        return fail(LT_ERR_ARG, "NULL lens or output");
+    *z_forward_in = forward_plane_z(*L);
+    *z_sensor = L->zs;
     return LT_OK;
 }
 

@@ -59,14 +59,16 @@ struct GlassF {
 
 struct TraceTable {
     int32_t nsteps;
-    uint32_t glass_start;     // medium the sensor sits in (kAirCode = air)
+    uint32_t glass_start;     // medium of the start plane (kAirCode = air)
     float z_exit_h, z_exit_l; // output plane z in the last step's vertex frame
+    float exit_dir;           // required sign of the exit direction's z (-1 toward the object)
     GlassF glass[LT_MAX_GLASSES];
     StepGeom geom[kMaxSteps];
     uint32_t code[kMaxSteps];  // type | glass2 << 4 | flags << 12
 };
 static_assert(sizeof(TraceTable) <= 3584, "trace table must fit the kernel-argument segment");
 
-lt_status build_trace_table(const Lens &L, const lt_path &p, TraceTable *t);
+lt_status build_trace_table(const Lens &L, const lt_path &p, bool forward, TraceTable *t);
+double forward_plane_z(const Lens &L);
 
 }  // namespace lt

@@ -113,10 +113,10 @@ extern "C" lt_status lt_trace_compact(lt_lens lens, const lt_path *path, const l
         return fail(LT_ERR_ARG, "NULL lens, path, rays, out or count");
     if (n < 0)
         return fail(LT_ERR_ARG, "negative ray count");
-    if (flags & ~static_cast<uint32_t>(LT_TRACE_PLAIN_FP32))
+    if (flags & ~static_cast<uint32_t>(LT_TRACE_PLAIN_FP32 | LT_TRACE_FORWARD))
         return fail(LT_ERR_ARG, "unknown trace flag");
     TraceTable table;
-    lt_status st = build_trace_table(*L, *path, &table);
+    lt_status st = build_trace_table(*L, *path, (flags & LT_TRACE_FORWARD) != 0, &table);
     if (st != LT_OK)
         return st;
     if (n > 0) {
@@ -149,10 +149,10 @@ extern "C" lt_status lt_trace_ex(lt_lens lens, const lt_path *path, const lt_ray
         return fail(LT_ERR_ARG, "NULL lens, path, rays or out");
     if (n < 0)
         return fail(LT_ERR_ARG, "negative ray count");
-    if (flags & ~static_cast<uint32_t>(LT_TRACE_PLAIN_FP32))
+    if (flags & ~static_cast<uint32_t>(LT_TRACE_PLAIN_FP32 | LT_TRACE_FORWARD))
         return fail(LT_ERR_ARG, "unknown trace flag");
     TraceTable table;
-    lt_status st = build_trace_table(*L, *path, &table);
+    lt_status st = build_trace_table(*L, *path, (flags & LT_TRACE_FORWARD) != 0, &table);
     if (st != LT_OK)
         return st;
     if (n == 0)

@@ -230,7 +230,7 @@ __host__ __device__ __forceinline__ RayOut trace_one_ff(const TraceTable &T, flo
         // double-word accuracy; no renormalisation is needed.
     }
     // output plane, reached along the signed line
-    if (!(dz.h < 0.0f))
+    if (!(dz.h * T.exit_dir > 0.0f))
         return o;
     const ff t = ff_div(ff_sub(ff{T.z_exit_h, T.z_exit_l}, pz), dz);
     o.x = ff_to_f(ff_add(px, ff_mul(t, dx)));
@@ -357,7 +357,7 @@ __host__ __device__ __forceinline__ RayOut trace_one_fast(const TraceTable &T, f
         dy *= inv;
         dz *= inv;
     }
-    if (!(dz < 0.0f))
+    if (!(dz * T.exit_dir > 0.0f))
         return o;
     const float t = (T.z_exit_h - pz) / dz;
     o.x = fmaf(t, dx, px);

@@ -461,6 +461,35 @@ def make_rays(lens: Lens, n: int, seed: int, lam_range=(400.0, 700.0)) -> dict:
             "dz": (vz / norm).astype(f32), "lambda_nm": lam.astype(f32)}
 
 
+def make_forward_rays(lens: Lens, n: int, seed: int, half_angle_deg: float = 20.0, direction=None,
+                      aperture_scale: float = 1.1, lam_range=(400.0, 700.0)) -> dict:
+    """n scene-side rays for forward light tracing, as float32 SoA arrays.
+
+    The start point is uniform by area on a disk of aperture_scale times the
+    first surface's semi-diameter (in the forward input plane).  The direction
+    is either the given unit vector (a distant point light) or uniform in
+    solid angle within half_angle_deg of the axis, travelling toward the
+    image.  The wavelength is uniform in lam_range nm."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    r0 = aperture_scale * lens.surfaces[0].semi_diameter
+    rho = r0 * np.sqrt(rng.uniform(0.0, 1.0, n))
+    phi = 2.0 * np.pi * rng.uniform(0.0, 1.0, n)
+    if direction is None:
+        cmin = math.cos(math.radians(half_angle_deg))
+        cz = rng.uniform(cmin, 1.0, n)
+        az = 2.0 * np.pi * rng.uniform(0.0, 1.0, n)
+        sz = np.sqrt(1.0 - cz * cz)
+        d = np.stack([sz * np.cos(az), sz * np.sin(az), cz], 1)
+    else:
+        d = np.tile(np.asarray(direction, np.float64) / np.linalg.norm(direction), (n, 1))
+        rng.uniform(0.0, 1.0, 2 * n)   # keep the stream aligned with the cone case
+    lam = rng.uniform(lam_range[0], lam_range[1], n)
+    f32 = np.float32
+    return {"x": (rho * np.cos(phi)).astype(f32), "y": (rho * np.sin(phi)).astype(f32),
+            "dx": d[:, 0].astype(f32), "dy": d[:, 1].astype(f32), "dz": d[:, 2].astype(f32),
+            "lambda_nm": lam.astype(f32)}
+
+
 RAY_FIELDS = ("x", "y", "dx", "dy", "dz", "lambda_nm")
 
 # workload presets ---------------------------------------------------------
