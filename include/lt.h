@@ -204,6 +204,34 @@ typedef struct {
 lt_status lt_rays_generate(lt_lens lens, const lt_raygen *cfg, const lt_ray_buffers *out,
                            int64_t n, void *stream);
 
+/* Settings of the on-device generator of scene-side rays for forward light
+ * tracing from a point light (Sec. 3; the rendering pipeline samples p_in on
+ * the forward input plane and connects it with the light). */
+typedef struct {
+    uint64_t seed;          /* Philox key word 0 (word 1 is 0) */
+    uint64_t first;         /* counter of ray 0; ray k uses (first + k, 0, 0, 0) */
+    float light[3];         /* at_infinity = 1: direction of travel of the light
+                               (normalised on the host, light[2] > 0); 0: the
+                               light's position in the lens frame, in front of
+                               the forward input plane (light[2] < z_forward_in) */
+    int32_t at_infinity;
+    float aperture_mm;      /* radius of the disk on the forward input plane
+                               (centred on the axis) that p_in is drawn from */
+    float lambda_min_nm;    /* wavelength range, uniform */
+    float lambda_max_nm;
+} lt_raygen_forward;
+
+/* Draw n forward rays on the device: p_in uniform by area on the disk
+ * (x, y of the output; the rays start on the plane lt_lens_planes reports),
+ * direction the light's (at infinity) or normalised p_in - light (FP32),
+ * wavelength uniform.  Philox4x64-10 as in lt_rays_generate; uniforms from
+ * bits 40..63 of words 0, 1, 2 (radius, angle, wavelength).  Output feeds
+ * lt_trace_ex(..., LT_TRACE_FORWARD) or a forward map.  Errors: LT_ERR_ARG
+ * (NULL, n < 0, aperture <= 0, bad range, light not in front of the plane or
+ * direction not toward the lens), LT_ERR_DEVICE. */
+lt_status lt_rays_generate_forward(lt_lens lens, const lt_raygen_forward *cfg,
+                                   const lt_ray_buffers *out, int64_t n, void *stream);
+
 /* Exit rays on the output plane z = 0 (device, n entries each). */
 typedef struct {
     uint8_t *mask;
@@ -300,6 +328,14 @@ typedef struct {
                             Training targets are moved into the same frame; the
                             raw outputs of lt_map_forward_train are in it.
                             0: plain input. */
+    int32_t forward;     /* 1: a forward-light-tracing map (Sec. 3: scene-side
+                            rays on the forward input plane, exits on the
+                            sensor plane travelling toward it), whose decoded
+                            exit direction has dz = +sqrt(1 - dx^2 - dy^2).
+                            0: a sensor-side map, dz = -sqrt(1 - dx^2 - dy^2).
+                            Forward and sensor-side maps of one lens differ
+                            (the transport is not a bijection), so each
+                            direction has its own map. */
 } lt_map_desc;
 
 typedef struct lt_map_s *lt_map;
@@ -441,6 +477,41 @@ lt_status lt_map_train_step(lt_map map, const lt_rays *rays, const lt_targets *t
  * checkpoint and resume. */
 lt_status lt_map_adam_state(lt_map map, float *m, float *v, int64_t count, int32_t to_map,
                             void *stream);
+
+/* ---------------------------------------------------------- sensor image */
+
+/* Raster of the sensor (the CMOS-sized output rectangle of forward light
+ * tracing, Sec. 3): width x height mm centred on the optical axis in the
+ * sensor plane, nx x ny pixels.  Pixel (ix, iy) covers
+ * x in [x0 + ix / sx, x0 + (ix + 1) / sx), x0 = -width / 2, sx = nx / width,
+ * likewise in y; row iy = 0 lies at y = -height / 2. */
+typedef struct {
+    float width_mm;
+    float height_mm;
+    int32_t nx;
+    int32_t ny;
+} lt_sensor;
+
+/* Forward light tracing image formation (Sec. 3, the flare sum over valid
+ * paths; the splat step of the rendering pipeline): for every ray r < n with
+ * mask[r] != 0 (mask may be NULL: every ray), adds
+ *     w = (throughput[r] * dz[r]) * scale
+ * to images[k][iy][ix], k = r / n_per_image, with the box pixel filter h and
+ * G = dot(w_out, n_cmos) = dz for n_cmos = +z (exit directions are unit).
+ * The pixel is found in FP32 with one rounding per operation:
+ *     ix = floor((x[r] - x0) * sx),  iy = floor((y[r] - y0) * sy),
+ * where x0 = -width/2 and sx = nx / width are FP32 values; rays outside
+ * [0, nx) x [0, ny) and rays with NaN positions add nothing.  images (device,
+ * [ceil(n / n_per_image)][ny][nx] float32) are accumulated into, not cleared.
+ * Head-major map outputs (field[p * n_rays + r]) splat per path with
+ * n_per_image = n_rays, or into one image with n_per_image = n.  Additions
+ * are FP32 atomics in unspecified order, so a pixel matches the exact sum of
+ * its k terms to within the rounding of a k-term FP32 sum.
+ * Errors: LT_ERR_ARG (NULL pointer with n > 0, n < 0, n_per_image < 1,
+ * non-positive extents or pixel counts, nx * ny > 2^31), LT_ERR_DEVICE. */
+lt_status lt_splat(const float *x, const float *y, const float *dz, const float *throughput,
+                   const uint8_t *mask, int64_t n, int64_t n_per_image, const lt_sensor *sensor,
+                   float scale, float *images, void *stream);
 
 #ifdef __cplusplus
 }

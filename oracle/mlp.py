@@ -53,6 +53,7 @@ class MapDesc:
     n_heads: int = 1
     activation: int = ACT_TANH
     canonical: bool = False  # symmetry-reduced input (Sec. 4.1), see canonical_frame
+    forward: bool = False    # forward light tracing map (Sec. 3): exits travel toward the sensor, dz > 0
 
 
 @dataclasses.dataclass
@@ -206,7 +207,9 @@ def decode(o: np.ndarray, p: MapParams, rays: Dict[str, np.ndarray] = None) -> D
             raise ValueError("a canonical-input map needs the rays to decode")
         _, c, s, flip = canonical_frame(rays)
         x, y, dx, dy = to_lab_frame(x, y, dx, dy, c[None], s[None], flip[None])
-    dz = -np.sqrt(np.maximum(0.0, 1.0 - dx * dx - dy * dy))
+    # the exit direction is a unit vector; its z component points toward
+    # the object for a sensor-side map and toward the sensor for a forward one
+    dz = (1.0 if p.desc.forward else -1.0) * np.sqrt(np.maximum(0.0, 1.0 - dx * dx - dy * dy))
     res = {"logit": logit, "mask": mask.astype(np.uint8)}
     for k, v in (("x", x), ("y", y), ("dx", dx), ("dy", dy), ("dz", dz)):
         res[k] = np.where(mask, v, np.nan)

@@ -29,7 +29,7 @@ __all__ = ["LtError", "Lens", "lt_lens_create", "lt_lens_query", "lt_trace", "lt
            "lt_map_forward_train", "lt_map_backward", "lt_map_train_step", "lt_map_adam_state",
            "TARGET_FIELDS", "lt_path_encode", "lt_path_decode", "lt_trace_compact",
            "lt_map_quantize", "lt_rays_generate", "lt_map_eval_ex", "LT_EVAL_MASK_ONLY",
-           "lt_lens_planes", "LT_TRACE_FORWARD",
+           "lt_lens_planes", "LT_TRACE_FORWARD", "lt_rays_generate_forward", "lt_splat",
            "LT_EVAL_GATED"]
 
 TARGET_FIELDS = ("valid", "x", "y", "dx", "dy", "throughput")
@@ -65,11 +65,13 @@ def _dev_ptr(t, dtype, n: int, name: str) -> int:
 class Lens:
     """Owned lt_lens handle."""
 
-    def __init__(self, handle: int, n_surfaces: int, n_refracting: int, n_ghost: int):
+    def __init__(self, handle: int, n_surfaces: int, n_refracting: int, n_ghost: int,
+                 front_semi_diameter: float = 0.0):
         self._h = C.c_void_p(handle)
         self.n_surfaces = n_surfaces
         self.n_refracting = n_refracting
         self.n_ghost_paths = n_ghost
+        self.front_semi_diameter = front_semi_diameter
 
     @property
     def handle(self):
@@ -126,7 +128,7 @@ def lt_lens_create(surfaces, glasses) -> Lens:
     N.check(N.lib().lt_lens_create(S, len(srows), G, len(grows), C.byref(h)))
     ns, nr, ng = C.c_int32(), C.c_int32(), C.c_int32()
     N.check(N.lib().lt_lens_query(h, C.byref(ns), C.byref(nr), C.byref(ng)))
-    return Lens(h.value, ns.value, nr.value, ng.value)
+    return Lens(h.value, ns.value, nr.value, ng.value, float(srows[0][2]) if srows else 0.0)
 
 
 def lt_lens_query(lens: Lens) -> Tuple[int, int, int]:
@@ -236,6 +238,54 @@ def lt_rays_generate(lens: Lens, n: int, seed: int, first: int = 0, half_width: 
     return out
 
 
+def lt_rays_generate_forward(lens: Lens, n: int, seed: int, light=(0.0, 0.0, 1.0),
+                             at_infinity: bool = True, aperture: Optional[float] = None,
+                             first: int = 0, lam_range=(400.0, 700.0), out: Optional[Dict] = None,
+                             device="cuda", stream=None) -> Dict:
+    """n scene-side rays from a point light drawn on the device (p_in
+    uniform on the aperture disk of the forward input plane).  ``light``: the
+    direction of travel (at infinity) or the light's position.  ``aperture``
+    defaults to the first surface's semi-diameter."""
+    torch = _torch()
+    if aperture is None:
+        aperture = lens.front_semi_diameter
+    if out is None:
+        out = {k: torch.empty(n, dtype=torch.float32, device=device) for k in RAY_FIELDS}
+    b = N.lt_ray_buffers()
+    for k in RAY_FIELDS:
+        setattr(b, k, _dev_ptr(out[k], torch.float32, n, f"out[{k}]") if n else None)
+    cfg = N.lt_raygen_forward(int(seed) & 0xFFFFFFFFFFFFFFFF, int(first) & 0xFFFFFFFFFFFFFFFF,
+                              (C.c_float * 3)(*[float(v) for v in light]), int(bool(at_infinity)),
+                              float(aperture), float(lam_range[0]), float(lam_range[1]))
+    N.check(N.lib().lt_rays_generate_forward(lens.handle, C.byref(cfg), C.byref(b), int(n),
+                                             C.c_void_p(_stream_ptr(stream) if n else 0)))
+    return out
+
+
+def lt_splat(x, y, dz, throughput, sensor, images=None, mask=None, n: Optional[int] = None,
+             n_per_image: Optional[int] = None, scale: float = 1.0, stream=None):
+    """Add scale * throughput * dz of every (masked) exit ray to its sensor
+    pixel; ``sensor`` = (width_mm, height_mm, nx, ny).  ``images`` (float32,
+    [n_images, ny, nx], accumulated into) is allocated zeroed if None."""
+    torch = _torch()
+    if n is None:
+        n = int(x.numel())
+    per = max(1, n) if n_per_image is None else int(n_per_image)
+    w, h, nx, ny = sensor
+    n_img = max(1, -(-n // max(1, per)))
+    if images is None:
+        images = torch.zeros((n_img, int(ny), int(nx)), dtype=torch.float32, device=x.device)
+    s = N.lt_sensor(float(w), float(h), int(nx), int(ny))
+    f32 = torch.float32
+    ptrs = [_dev_ptr(t, f32, n, nm) if n else None
+            for t, nm in ((x, "x"), (y, "y"), (dz, "dz"), (throughput, "throughput"))]
+    mp = _dev_ptr(mask, torch.uint8, n, "mask") if (mask is not None and n) else None
+    ip = _dev_ptr(images, f32, n_img * int(nx) * int(ny), "images") if n else None
+    N.check(N.lib().lt_splat(*ptrs, mp, int(n), int(per), C.byref(s), float(scale), ip,
+                             C.c_void_p(_stream_ptr(stream) if n else 0)))
+    return images
+
+
 def lt_trace_compact(lens: Lens, path, rays: Dict, out: Optional[Dict] = None, idx=None,
                      count=None, n: Optional[int] = None, flags: int = 0, stream=None):
     """Trace and keep only valid rays: returns (out, idx, count) where the
@@ -291,14 +341,18 @@ class Map:
 
 
 def lt_map_create(width: int = 128, depth: int = 5, n_heads: int = 1,
-                  activation: int = N.LT_ACT_TANH, canonical: bool = False) -> Map:
+                  activation: int = N.LT_ACT_TANH, canonical: bool = False,
+                  forward: bool = False) -> Map:
     """``canonical``: symmetry-reduced input frame (rotation + mirror about
-    the optical axis), see lt_map_desc in include/lt.h."""
-    d = N.lt_map_desc(6, int(width), int(depth), int(n_heads), int(activation), int(bool(canonical)))
+    the optical axis); ``forward``: a forward-light-tracing map (exit dz > 0).
+    See lt_map_desc in include/lt.h."""
+    d = N.lt_map_desc(6, int(width), int(depth), int(n_heads), int(activation), int(bool(canonical)),
+                      int(bool(forward)))
     h = C.c_void_p()
     N.check(N.lib().lt_map_create(C.byref(d), C.byref(h)))
     m = Map(h.value, width, depth, n_heads, activation)
     m.canonical = bool(canonical)
+    m.forward = bool(forward)
     return m
 
 

@@ -50,13 +50,25 @@ class lt_raygen(C.Structure):
                 ("lambda_max_nm", C.c_float)]
 
 
+class lt_raygen_forward(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("first", C.c_uint64), ("light", C.c_float * 3),
+                ("at_infinity", C.c_int32), ("aperture_mm", C.c_float),
+                ("lambda_min_nm", C.c_float), ("lambda_max_nm", C.c_float)]
+
+
+class lt_sensor(C.Structure):
+    _fields_ = [("width_mm", C.c_float), ("height_mm", C.c_float), ("nx", C.c_int32),
+                ("ny", C.c_int32)]
+
+
 class lt_exit(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in ("mask", "x", "y", "dx", "dy", "dz", "throughput")]
 
 
 class lt_map_desc(C.Structure):
     _fields_ = [("in_dim", C.c_int32), ("width", C.c_int32), ("depth", C.c_int32),
-                ("n_heads", C.c_int32), ("activation", C.c_int32), ("canonical", C.c_int32)]
+                ("n_heads", C.c_int32), ("activation", C.c_int32), ("canonical", C.c_int32),
+                ("forward", C.c_int32)]
 
 
 class lt_map_out(C.Structure):
@@ -101,6 +113,10 @@ SIGNATURES = {
                                  C.c_int64, C.c_uint32, C.c_void_p, C.c_void_p]),
     "lt_rays_generate": (C.c_int, [C.c_void_p, C.POINTER(lt_raygen), C.POINTER(lt_ray_buffers),
                                    C.c_int64, C.c_void_p]),
+    "lt_rays_generate_forward": (C.c_int, [C.c_void_p, C.POINTER(lt_raygen_forward),
+                                           C.POINTER(lt_ray_buffers), C.c_int64, C.c_void_p]),
+    "lt_splat": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                           C.c_int64, C.POINTER(lt_sensor), C.c_float, C.c_void_p, C.c_void_p]),
     "lt_trace": (C.c_int, [C.c_void_p, C.POINTER(lt_path), C.POINTER(lt_rays),
                            C.POINTER(lt_exit), C.c_int64, C.c_void_p]),
     "lt_trace_ex": (C.c_int, [C.c_void_p, C.POINTER(lt_path), C.POINTER(lt_rays),

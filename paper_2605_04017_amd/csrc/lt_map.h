@@ -18,7 +18,7 @@ constexpr int kMaxLds = 160 * 1024;
 
 struct MapLayout {
     // sizes
-    int32_t H = 0, D = 0, P = 0, act = 0, canon = 0;
+    int32_t H = 0, D = 0, P = 0, act = 0, canon = 0, fwd = 0;
     int64_t n_params = 0;
     int32_t T = 0;    // M-tiles per hidden layer (H / 16)
     int32_t C = 0;    // K-chunks of 32 per hidden layer (H / 32)

@@ -35,6 +35,7 @@ MapLayout make_layout(const lt_map_desc &d)
     L.P = d.n_heads;
     L.act = d.activation;
     L.canon = d.canonical;
+    L.fwd = d.forward;
     L.T = L.H / 16;
     L.C = L.H / 32;
     L.TO = (L.P * kHeadSlots + 15) / 16;
@@ -463,7 +464,7 @@ __global__ __launch_bounds__((eval_waves<H, TRAIN>() * 64)) void map_eval_bf16_k
                     const float thr = fmaf(sc[4], w[5], sh[4]);
                     if (A.canonical)
                         canon_out(myfr, x, y, dx, dy);
-                    const float dz = -sqrtf(fmaxf(0.0f, 1.0f - dx * dx - dy * dy));
+                    const float dz = A.dz_sign * sqrtf(fmaxf(0.0f, 1.0f - dx * dx - dy * dy));
                     out.x[idx] = m ? x : nan;
                     out.y[idx] = m ? y : nan;
                     out.dx[idx] = m ? dx : nan;
@@ -507,7 +508,7 @@ __global__ __launch_bounds__((eval_waves<H, TRAIN>() * 64)) void map_eval_bf16_k
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt)
                     decode_store(o[nt], to, g, ray0 + nt * 16 + col, n, A.P, out_shift, out_scale, out,
-                                 A.canonical != 0, fr[nt], A.flags, A.mask_in);
+                                 A.canonical != 0, fr[nt], A.flags, A.mask_in, A.dz_sign);
             }
         }
     }
@@ -567,6 +568,7 @@ static lt_status launch_bf16_impl(const Map &M, const lt_rays &rays, const lt_ma
     A.img_bias = FP8 ? L.img8_bias : L.img_bias;
     A.img_hidden = FP8 ? L.img8_hidden : L.img_hidden;
     A.canonical = L.canon;
+    A.dz_sign = L.fwd ? 1.0f : -1.0f;
     if constexpr (!TRAIN) {
         // the staged part ends on a 1 KiB boundary; the transpose buffers
         // (16 floats per ray of a wave tile) follow it
@@ -668,6 +670,8 @@ lt_status lt_map_create(const lt_map_desc *desc, lt_map *out)
         return fail(LT_ERR_ARG, "unknown activation");
     if (d.canonical != 0 && d.canonical != 1)
         return fail(LT_ERR_ARG, "canonical must be 0 or 1");
+    if (d.forward != 0 && d.forward != 1)
+        return fail(LT_ERR_ARG, "forward must be 0 or 1");
     Map *M = new (std::nothrow) Map();
     if (!M)
         return fail(LT_ERR_OOM, "host allocation");

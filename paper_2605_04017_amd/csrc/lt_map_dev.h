@@ -153,6 +153,7 @@ struct EvalArgs {
     int64_t img_out, img_bias, img_hidden;
     int64_t xpose;        // LDS offset of the per-wave output transpose buffers (4 KiB each)
     int32_t canonical;    // symmetry-reduced input frame
+    float dz_sign;        // sign of the decoded exit dz: -1 sensor-side map, +1 forward map
     float *canon_out;     // training forward: [3][n_pad] frame (c, s, sg) per ray, or null
     uint32_t flags;       // LT_EVAL_MASK_ONLY / LT_EVAL_GATED
     const uint8_t *mask_in;  // LT_EVAL_GATED: [P][n] validity from a classifier
@@ -224,7 +225,7 @@ __device__ __forceinline__ void canon_out(const CanonFrame &F, float &x, float &
 __device__ __forceinline__ void decode_store(floatx4 v, int to, int g, int64_t r, int64_t n, int P,
                                              const float *out_shift, const float *out_scale,
                                              const lt_map_out &out, bool canon, const CanonFrame &F,
-                                             uint32_t flags, const uint8_t *mask_in)
+                                             uint32_t flags, const uint8_t *mask_in, float dz_sign)
 {
     const int head = 2 * to + (g >> 1);
     const bool even = (g & 1) == 0;
@@ -251,7 +252,7 @@ __device__ __forceinline__ void decode_store(floatx4 v, int to, int g, int64_t r
             float dy = recv;
             if (canon)
                 canon_out(F, x, y, dx, dy);
-            const float dz = -sqrtf(fmaxf(0.0f, 1.0f - dx * dx - dy * dy));
+            const float dz = dz_sign * sqrtf(fmaxf(0.0f, 1.0f - dx * dx - dy * dy));
             out.x[idx] = m ? x : nan;
             out.y[idx] = m ? y : nan;
             out.dx[idx] = m ? dx : nan;

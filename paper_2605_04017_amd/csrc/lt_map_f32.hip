@@ -105,6 +105,7 @@ struct F32Args {
     F32Layout F;
     int32_t D, P, TO;
     int32_t canonical;
+    float dz_sign;        // -1: sensor-side map, +1: forward map
     uint32_t flags;
     const uint8_t *mask_in;
     int64_t n;
@@ -298,7 +299,7 @@ __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args
 #pragma unroll
                 for (int nt = 0; nt < kF32NT; ++nt)
                     decode_store(o[nt], to, g, ray0 + nt * 16 + col, n, A.P, out_shift, out_scale, out,
-                                 A.canonical != 0, fr[nt], A.flags, A.mask_in);
+                                 A.canonical != 0, fr[nt], A.flags, A.mask_in, A.dz_sign);
             }
         }
     }
@@ -317,6 +318,7 @@ static lt_status launch_f32(const Map &M, const lt_rays &rays, const lt_map_out 
     A.P = M.lay.P;
     A.TO = M.lay.TO;
     A.canonical = M.lay.canon;
+    A.dz_sign = M.lay.fwd ? 1.0f : -1.0f;
     A.n = n;
     auto kern = map_eval_f32_kernel<H, ACT>;
     static bool attr = false;

@@ -364,7 +364,6 @@ __global__ __launch_bounds__(256) void dw_kernel(DwArgs A)
     if (group * 4 * kDwTilesPerWave >= total)
         return;
     const int d_rows = is_out ? 2 * 16 * L.TO : H;
-    const int h_rows = is_in ? 16 : H + 16;
     __bf16 *dl = reinterpret_cast<__bf16 *>(lds);
     __bf16 *hl = dl + static_cast<int64_t>(d_rows) * RS;
 

@@ -577,3 +577,33 @@ def philox_rays(lens: Lens, n: int, seed: int, first: int = 0, half_w: float = S
     l0, l1 = float(f32(lam_range[0])), float(f32(lam_range[1]))
     return {"x": sx, "y": sy, "dx": (vx / norm).astype(f32), "dy": (vy / norm).astype(f32),
             "dz": (vz / norm).astype(f32), "lambda_nm": ((l1 - l0) * u4 + l0).astype(f32)}
+
+
+def philox_forward_rays(n: int, seed: int, light=(0.0, 0.0, 1.0), at_infinity: bool = True,
+                        aperture: float = 1.0, z_plane: float = 0.0, first: int = 0,
+                        lam_range=(400.0, 700.0)) -> dict:
+    """Host twin of the device's forward generator: rays k = 0..n-1 from a
+    point light, p_in uniform by area on the aperture disk (float64 from the
+    same 24-bit uniforms, rounded to float32), direction the light's
+    (at infinity) or normalised p_in - light with p_in on the plane z_plane."""
+    ctr = np.arange(n, dtype=np.uint64) + np.uint64(first)
+    z = np.zeros(n, np.uint64)
+    o0, o1, o2, _ = philox4x64_10((ctr, z, z, z), (seed, 0))
+    s40 = np.uint64(40)
+    u0, u1, u2 = ((o >> s40).astype(np.float64) * 2.0 ** -24 for o in (o0, o1, o2))
+    f32 = np.float32
+    rho = float(f32(aperture)) * np.sqrt(u0)
+    phi = 2.0 * np.pi * u1
+    px = (rho * np.cos(phi)).astype(f32)
+    py = (rho * np.sin(phi)).astype(f32)
+    if at_infinity:
+        v = np.asarray(light, np.float32).astype(np.float64)   # the device receives FP32
+        d = np.tile(v / np.linalg.norm(v), (n, 1))
+    else:
+        lx, ly, lz = (float(f32(c)) for c in light)
+        d = np.stack([px.astype(np.float64) - lx, py.astype(np.float64) - ly,
+                      np.full(n, float(f32(z_plane)) - lz)], 1)
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+    l0, l1 = float(f32(lam_range[0])), float(f32(lam_range[1]))
+    return {"x": px, "y": py, "dx": d[:, 0].astype(f32), "dy": d[:, 1].astype(f32),
+            "dz": d[:, 2].astype(f32), "lambda_nm": ((l1 - l0) * u2 + l0).astype(f32)}

@@ -115,7 +115,8 @@ def test_trace_argument_errors_without_gpu():
 
 @pytest.mark.parametrize("desc", [(5, 128, 5, 1, 0), (6, 100, 5, 1, 0), (6, 128, 0, 1, 0),
                                   (6, 128, 9, 1, 0), (6, 128, 5, 0, 0), (6, 128, 5, 65, 0),
-                                  (6, 128, 5, 1, 7), (6, 128, 5, 1, 0, 2)])
+                                  (6, 128, 5, 1, 7), (6, 128, 5, 1, 0, 2),
+                                  (6, 128, 5, 1, 0, 0, 3)])
 def test_map_desc_validation(desc):
     """Bad shapes are rejected before any device allocation."""
     d = N.lt_map_desc(*desc)
@@ -129,3 +130,42 @@ def test_map_null_handles():
     assert L.lt_map_num_params(None) == -1
     assert L.lt_map_eval(None, 1, None, None, 0, None) == N.LT_ERR_ARG
     assert L.lt_map_destroy(None) == N.LT_OK
+
+
+def test_splat_and_forward_raygen_argument_errors_without_gpu():
+    """Argument validation of lt_splat and lt_rays_generate_forward happens
+    before any device call (n = 0 is a no-op)."""
+    L = N.lib()
+    s = N.lt_sensor(36.0, 24.0, 480, 320)
+    assert L.lt_splat(None, None, None, None, None, 0, 1, C.byref(s), 1.0, None, None) == N.LT_OK
+    assert L.lt_splat(None, None, None, None, None, 5, 5, C.byref(s), 1.0, None, None) == N.LT_ERR_ARG
+    assert L.lt_splat(None, None, None, None, None, -1, 5, C.byref(s), 1.0, None, None) == N.LT_ERR_ARG
+    assert L.lt_splat(None, None, None, None, None, 0, 0, C.byref(s), 1.0, None, None) == N.LT_ERR_ARG
+    assert L.lt_splat(None, None, None, None, None, 0, 1, None, 1.0, None, None) == N.LT_ERR_ARG
+    for bad in ((0.0, 24.0, 480, 320), (36.0, 24.0, 0, 320), (36.0, float("inf"), 480, 320),
+                (36.0, 24.0, 1 << 16, 1 << 16), (36.0, 24.0, 480, -3)):
+        sb = N.lt_sensor(*bad)
+        assert L.lt_splat(None, None, None, None, None, 0, 1, C.byref(sb), 1.0, None, None) == N.LT_ERR_ARG
+    lens = synth.config_lens(2)
+    h = lt.lt_lens_create(lens.surfaces, lens.glasses)
+    b = N.lt_ray_buffers()
+
+    def gen(light, at_inf, ap=10.0, lam=(400.0, 700.0), n=0):
+        cfg = N.lt_raygen_forward(1, 0, (C.c_float * 3)(*light), at_inf, ap, *lam)
+        return L.lt_rays_generate_forward(h.handle, C.byref(cfg), C.byref(b), n, None)
+    assert gen((0.0, 0.0, 1.0), 1) == N.LT_OK
+    assert gen((0.0, 0.0, 1.0), 1, n=4) == N.LT_ERR_ARG          # NULL outputs
+    assert gen((0.0, 0.0, 1.0), 1, n=-1) == N.LT_ERR_ARG
+    assert gen((0.0, 0.0, -1.0), 1) == N.LT_ERR_ARG               # travels away from the lens
+    assert gen((0.0, 0.0, 0.0), 1) == N.LT_ERR_ARG
+    assert gen((0.0, 0.0, 3.0), 0) == N.LT_ERR_ARG                # light behind the input plane
+    assert gen((0.0, 0.0, -100.0), 0) == N.LT_OK
+    assert gen((0.0, 0.0, 1.0), 1, ap=0.0) == N.LT_ERR_ARG
+    assert gen((0.0, 0.0, 1.0), 1, lam=(700.0, 400.0)) == N.LT_ERR_ARG
+
+
+def test_splat_wrapper_empty_without_gpu():
+    import torch
+    e = torch.empty(0, dtype=torch.float32)
+    img = lt.lt_splat(e, e, e, e, (36.0, 24.0, 48, 32))
+    assert img.shape == (1, 32, 48) and float(img.abs().sum()) == 0.0
