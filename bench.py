@@ -423,6 +423,182 @@ def multi_path(lt, synth, mlp, dev, n=16777216):
     return res
 
 
+FLARE_SENSOR = (36.0, 24.0, 720, 480)
+FLARE_BANDS = ((600.0, 700.0), (500.0, 600.0), (400.0, 500.0))   # R, G, B
+
+
+def _norm_stats(a):
+    import numpy as np
+    mu, sd = a.mean(0), a.std(0)
+    sd[~(sd > 0)] = 1.0
+    return mu, sd
+
+
+def flare(lt, synth, mlp, dev, steps=10000, n_render=1 << 20, theta_deg=10.0, n_ghosts=8,
+          batch=65536, seed=6006, n_pool=1 << 22):
+    """Forward light tracing of a distant point light (Sec. 3 flare sum; the
+    forward half of the rendering pipeline, whose transmit image comes from
+    backward path tracing): per RGB channel, 1,048,576 rays from the light
+    at theta_deg off axis, p_in uniform on the first surface's clear
+    aperture in the forward input plane, wavelength uniform in the channel's
+    band, through the n_ghosts brightest two-reflection ghosts of the
+    11-surface lens, splatted into per-path 720 x 480 images of the
+    36 x 24 mm sensor.
+
+    Map: one forward map (5 x 128 tanh trunk, one head per ghost, canonical
+    input), fitted for `steps` steps on GPU forward traces of rays from
+    directions within 15 degrees of the axis (so it serves any light in that
+    cone).  Frame time: map (BF16) + splat versus forward trace + splat, on
+    the same resident rays.  Image error: relative L1 of each path's map
+    image against its traced image, at the pixel size and after 4 x 4 and
+    16 x 16 binning, next to the Monte Carlo floor (two traced renders with
+    independent rays)."""
+    import math
+    import numpy as np
+    import torch
+    lens = synth.config_lens(2)
+    h = lt.lt_lens_create(lens.surfaces, lens.glasses)
+    stream = torch.cuda.current_stream()
+    nr = lens.n_refracting
+    ghosts = [(1, j, i) for j in range(1, nr + 1) for i in range(j + 1, nr + 1)]
+    th = math.radians(theta_deg)
+    light = (math.sin(th), 0.0, math.cos(th))
+    W, H, NX, NY = FLARE_SENSOR
+    fwd = lt.LT_TRACE_FORWARD
+
+    # the brightest ghosts of this light (green band)
+    n_probe = 1 << 18
+    probe = lt.lt_rays_generate_forward(h, n_probe, seed, light, lam_range=FLARE_BANDS[1])
+    energy = []
+    for p in ghosts:
+        o = lt.lt_trace_ex(h, p, probe, None, n_probe, fwd, stream)
+        energy.append(float(lt.lt_splat(o["x"], o["y"], o["dz"], o["throughput"], FLARE_SENSOR,
+                                        mask=o["mask"], stream=stream).sum()))
+    order = np.argsort(energy)[::-1]
+    paths = [ghosts[k] for k in order[:n_ghosts]]
+    P = len(paths)
+    covered = float(np.sum(np.asarray(energy)[order[:n_ghosts]]) / max(1e-30, np.sum(energy)))
+
+    # training data: forward traces of a 15-degree cone of directions
+    t0 = time.perf_counter()
+    pool_np = synth.make_forward_rays(lens, n_pool, seed + 1, half_angle_deg=15.0, aperture_scale=1.0)
+    pool = {k: torch.from_numpy(v).to(dev) for k, v in pool_np.items()}
+    tgt = {"valid": torch.empty((P, n_pool), dtype=torch.uint8, device=dev)}
+    for f in ("x", "y", "dx", "dy", "throughput"):
+        tgt[f] = torch.empty((P, n_pool), dtype=torch.float32, device=dev)
+    ex = lt.empty_exit(n_pool, dev)
+    src, c, s, flip = mlp.canonical_frame(pool_np)
+    out_shift, out_scale = np.zeros((P, 5)), np.ones((P, 5))
+    for k, p in enumerate(paths):
+        lt.lt_trace_ex(h, p, pool, ex, n_pool, fwd, stream)
+        tgt["valid"][k].copy_(ex["mask"])
+        for f in ("x", "y", "dx", "dy", "throughput"):
+            tgt[f][k].copy_(ex[f])
+        ok = ex["mask"].bool().cpu().numpy()
+        reg = np.stack([ex[f].cpu().numpy()[ok].astype(np.float64)
+                        for f in ("x", "y", "dx", "dy", "throughput")], 1)
+        if ok.sum() > 1:
+            reg[:, 0], reg[:, 1], reg[:, 2], reg[:, 3] = mlp.to_canonical_frame(
+                reg[:, 0], reg[:, 1], reg[:, 2], reg[:, 3], c[ok], s[ok], flip[ok])
+            out_shift[k], out_scale[k] = _norm_stats(reg)
+    x = np.stack([src[f].astype(np.float64) for f in synth.RAY_FIELDS], 1)
+    in_shift, in_sd = _norm_stats(x)
+    desc = mlp.MapDesc(MAP_WIDTH, MAP_DEPTH, P, mlp.ACT_TANH, canonical=True, forward=True)
+    prm = mlp.init_params(desc, 7)
+    m = lt.lt_map_create(MAP_WIDTH, MAP_DEPTH, P, lt.LT_ACT_TANH, True, True)
+    lt.lt_map_set_params(m, torch.from_numpy(prm.flat().astype(np.float32)).to(dev))
+    lt.lt_map_set_norm(m, in_shift, 1.0 / in_sd, out_shift.reshape(-1), out_scale.reshape(-1))
+    ws = lt.workspace(m, batch)
+    del ex
+    t_data = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    loss = None
+    for k in range(1, steps + 1):
+        lo = ((k - 1) * batch) % (n_pool - batch + 1)
+        rb = {f: v[lo:lo + batch] for f, v in pool.items()}
+        tb = {f: v[:, lo:lo + batch].contiguous() for f, v in tgt.items()}
+        lr = 2e-3 * (0.5 ** (k / max(1, steps / 4)))
+        loss = lt.lt_map_train_step(m, rb, tb, {"lr": lr, "step": k, "w_bce": 1.0, "w_l2": 4.0}, ws)
+    torch.cuda.synchronize()
+    t_fit = time.perf_counter() - t0
+    del pool, tgt, ws
+
+    # one frame: three channels, every path
+    n = n_render
+    rays = [lt.lt_rays_generate_forward(h, n, seed + 10 + ch, light, lam_range=b)
+            for ch, b in enumerate(FLARE_BANDS)]
+    rays2 = [lt.lt_rays_generate_forward(h, n, seed + 20 + ch, light, lam_range=b)
+             for ch, b in enumerate(FLARE_BANDS)]
+    img_map = torch.zeros((3, P, NY, NX), dtype=torch.float32, device=dev)
+    img_tr = torch.zeros_like(img_map)
+    img_tr2 = torch.zeros_like(img_map)
+    mout = lt.empty_map_out(P, n, dev)
+    eout = lt.empty_exit(n, dev)
+    lt.lt_map_quantize(m, lt.LT_BF16, stream)
+
+    def render_map(dt=lt.LT_BF16):
+        img_map.zero_()
+        for ch in range(3):
+            lt.lt_map_eval(m, dt, rays[ch], mout, n, stream)
+            lt.lt_splat(mout["x"], mout["y"], mout["dz"], mout["throughput"], FLARE_SENSOR,
+                        images=img_map[ch], mask=mout["mask"], n=P * n, n_per_image=n,
+                        scale=1.0 / n, stream=stream)
+
+    def render_trace(rs=rays, img=img_tr):
+        img.zero_()
+        for ch in range(3):
+            for k, p in enumerate(paths):
+                lt.lt_trace_ex(h, p, rs[ch], eout, n, fwd, stream)
+                lt.lt_splat(eout["x"], eout["y"], eout["dz"], eout["throughput"], FLARE_SENSOR,
+                            images=img[ch, k], mask=eout["mask"], n=n, scale=1.0 / n, stream=stream)
+    t_map = time_kernel(render_map, stream, 5)
+    t_tr = time_kernel(render_trace, stream, 3)
+    render_trace(rays2, img_tr2)
+    t_eval = time_kernel(lambda: lt.lt_map_eval(m, lt.LT_BF16, rays[1], mout, n, stream), stream, 5)
+    t_splat = time_kernel(lambda: lt.lt_splat(mout["x"], mout["y"], mout["dz"], mout["throughput"],
+                                              FLARE_SENSOR, images=img_map[1], mask=mout["mask"],
+                                              n=P * n, n_per_image=n, scale=1.0 / n, stream=stream),
+                          stream, 10)
+    render_map()
+    torch.cuda.synchronize()
+
+    def rel_l1(a, b, binning=1):
+        if binning > 1:
+            pool = torch.nn.functional.avg_pool2d
+            a, b = (pool(t.reshape(-1, 1, NY, NX), binning) for t in (a, b))
+        return float((a - b).abs().sum() / b.abs().sum().clamp_min(1e-30))
+
+    def errs(a, b, c):
+        return {f"rel_l1_{tag}": rel_l1(a, b, bn) for tag, bn in (("px", 1), ("4x4", 4), ("16x16", 16))} | {
+            f"mc_floor_{tag}": rel_l1(c, b, bn) for tag, bn in (("px", 1), ("4x4", 4), ("16x16", 16))}
+    per_path = {}
+    for k, p in enumerate(paths):
+        per_path[f"ghost{p[1]},{p[2]}"] = {"energy_share": float(img_tr[:, k].sum() / img_tr.sum()),
+                                           **errs(img_map[:, k], img_tr[:, k], img_tr2[:, k])}
+    splat_bytes = 17 * P * n
+    res = {"lens": "11-surface double-Gauss-style lens", "light": f"point at infinity, {theta_deg} deg",
+           "rays_per_channel": n, "channels": "RGB bands 600-700 / 500-600 / 400-500 nm",
+           "sensor": {"mm": [W, H], "pixels": [NX, NY]},
+           "paths": P, "selected_ghosts_energy_share_of_all_55": covered,
+           "map": f"5 x {MAP_WIDTH} tanh, {P} heads, canonical input, forward exits, BF16 eval",
+           "fit_steps": steps, "fit_seconds": t_fit, "fit_data_seconds": t_data,
+           "fit_final_loss": [float(v) for v in loss.cpu()],
+           "frame_ms_map_bf16": t_map * 1e3, "frame_ms_trace": t_tr * 1e3,
+           "frame_speedup_map_over_trace": t_tr / t_map,
+           "ray_paths_per_s_map_G": 3 * n * P / t_map / 1e9,
+           "ray_paths_per_s_trace_G": 3 * n * P / t_tr / 1e9,
+           "map_eval_ms_per_channel": t_eval * 1e3, "splat_ms_per_channel": t_splat * 1e3,
+           "splat_roofline": {"bound": "hbm", "achieved": splat_bytes / t_splat / 1e9,
+                              "peak": MI355X_HBM_GBS, "unit": "GB/s",
+                              "frac": splat_bytes / t_splat / 1e9 / MI355X_HBM_GBS,
+                              "bytes_per_ray": 17, "rays_per_launch": P * n},
+           "flare_image": errs(img_map.sum(1), img_tr.sum(1), img_tr2.sum(1)),
+           "per_path": per_path}
+    del img_map, img_tr, img_tr2, mout, eout, rays, rays2
+    torch.cuda.empty_cache()
+    return res
+
+
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "map_f32_c2_4M_traffic.md")
 MAP_F32_SOURCES = ("paper_2605_04017_amd/csrc/lt_map_f32.hip", "paper_2605_04017_amd/csrc/lt_map_dev.h",
                    "paper_2605_04017_amd/csrc/lt_map.h")
@@ -498,6 +674,7 @@ def main():
     ap.add_argument("--no-multi-path", action="store_true")
     ap.add_argument("--no-train-epoch", action="store_true")
     ap.add_argument("--no-paper-pair", action="store_true")
+    ap.add_argument("--no-flare", action="store_true")
     ap.add_argument("--rays", type=int, default=N_RAYS)
     ap.add_argument("--traffic-probe", nargs="?", const="f32", choices=("f32", "bf16", "fp8"),
                     help="only run the short program the counter runs profile (map precision)")
@@ -630,6 +807,9 @@ def main():
     if not args.no_train_epoch:
         res["train_epoch_67M"] = train_epoch(lt, synth, mlp, dev)
         print("# training epoch done", file=sys.stderr, flush=True)
+    if not args.no_flare:
+        res["flare_forward"] = flare(lt, synth, mlp, dev)
+        print("# flare frame done", file=sys.stderr, flush=True)
     if not args.no_multi_path:
         res["multi_path_16M"] = multi_path(lt, synth, mlp, dev)
         print("# multi-path done", file=sys.stderr, flush=True)

@@ -51,7 +51,7 @@ def gpu_map(p, dev):
     import torch
     import paper_2605_04017_amd as lt
     d = p.desc
-    m = lt.lt_map_create(d.width, d.depth, d.n_heads, d.activation, d.canonical)
+    m = lt.lt_map_create(d.width, d.depth, d.n_heads, d.activation, d.canonical, d.forward)
     assert m.n_params == mlp.n_params(d)
     lt.lt_map_set_params(m, torch.from_numpy(p.flat().astype(np.float32)).to(dev))
     lt.lt_map_set_norm(m, p.in_shift, p.in_scale, p.out_shift.reshape(-1), p.out_scale.reshape(-1))
@@ -97,10 +97,10 @@ def compare(g, p, rays, mode, sel=None):
     off = g["mask"] == 0
     assert np.all(np.isnan(g["x"][off])) and np.all(g["throughput"][off] == 0)
     assert np.all(np.isnan(g["dz"][off]))
-    # dz = -sqrt(max(0, 1 - dx^2 - dy^2)), checked on the square (no sqrt
-    # amplification near grazing)
+    # dz = -+sqrt(max(0, 1 - dx^2 - dy^2)) (sensor-side / forward map),
+    # checked on the square (no sqrt amplification near grazing)
     dx64, dy64, dz64 = (g[k][both].astype(np.float64) for k in ("dx", "dy", "dz"))
-    assert np.all(dz64 <= 0)
+    assert np.all(dz64 >= 0) if p.desc.forward else np.all(dz64 <= 0)
     assert np.allclose(dz64 ** 2, np.maximum(0, 1 - dx64 ** 2 - dy64 ** 2), atol=1e-6)
     print(f"[map parity] {mode} {p.desc}: logit err median/p99/max {stl[0]:.1e}/{stl[1]:.1e}/"
           f"{stl[2]:.1e}, outputs {sto[0]:.1e}/{sto[1]:.1e}/{sto[2]:.1e}, valid {int(both.sum())}",
@@ -432,3 +432,26 @@ def test_eval_flags(dev, width, depth, heads, dtype):
     assert set(g1) == set(lt.MAP_FIELDS[2:])
     with pytest.raises(lt.LtError):
         lt.lt_map_eval_ex(m, dtype, r, flags=lt.LT_EVAL_GATED | lt.LT_EVAL_MASK_ONLY, mask_in=ones)
+
+
+@pytest.mark.parametrize("heads,dtype,canonical,n", [(1, 0, False, 20001), (9, 1, True, 50000),
+                                                     (56, 1, True, 4099), (3, 2, False, 30000)])
+def test_forward_map(dev, heads, dtype, canonical, n):
+    """Forward-light-tracing maps (scene-side inputs on the forward input
+    plane, exits toward the sensor): parity with the reference decode, whose
+    exit dz is +sqrt(1 - dx^2 - dy^2)."""
+    import paper_2605_04017_amd as lt
+    L = synth.config_lens(2)
+    rays = synth.make_forward_rays(L, n, 90 + heads)
+    desc = mlp.MapDesc(128, 5, heads, mlp.ACT_TANH, canonical=canonical, forward=True)
+    src = mlp.canonical_frame(rays)[0] if canonical else rays
+    p = make_params(desc, 80 + heads, src)
+    g = run_eval(gpu_map(p, dev), rays, dev, dtype)
+    mode = {0: "f32", 1: "bf16", 2: "fp8"}[dtype]
+    if dtype == lt.LT_F32:
+        _with_tols(*F32_TOLS, lambda: compare(g, p, rays, "f32"))
+    elif dtype == lt.LT_FP8:
+        _with_tols(1e-4, 3e-2, 3e-1, lambda: compare(g, p, rays, "fp8"))
+    else:
+        compare(g, p, rays, mode)
+    assert np.all(g["dz"][g["mask"] == 1] >= 0)

@@ -281,3 +281,24 @@ def test_cosine_loss_parameter_gradient():
         lm = mlp.loss_and_grad(q, x, valid, t, 1.0, 0.5, 1.5)[0][0]
         fd = (lp - lm) / (2 * h)
         assert abs(fd - flat[k]) <= 1e-6 * max(1.0, abs(fd)), (k, fd, flat[k])
+
+
+def test_forward_map_decode_flips_only_dz():
+    """A forward map decodes the same exit rays as a sensor-side map with the
+    same parameters except for the sign of dz (unit directions toward the
+    sensor)."""
+    import dataclasses
+    import synth
+    rays = synth.config_rays(1, 500)
+    d0 = mlp.MapDesc(32, 2, 3, mlp.ACT_TANH)
+    p0 = mlp.init_params(d0, 5)
+    p1 = dataclasses.replace(p0, desc=dataclasses.replace(d0, forward=True))
+    o = mlp.forward(p0, mlp.features(rays, p0))[0]
+    a, b = mlp.decode(o, p0, rays), mlp.decode(o, p1, rays)
+    for k in ("logit", "mask", "x", "y", "dx", "dy", "throughput"):
+        assert np.array_equal(a[k], b[k], equal_nan=True)
+    ok = a["mask"] == 1
+    assert np.array_equal(-a["dz"][ok], b["dz"][ok])
+    assert np.all(b["dz"][ok] >= 0)
+    s2 = b["dx"][ok] ** 2 + b["dy"][ok] ** 2
+    assert np.allclose(b["dz"][ok] ** 2, np.maximum(0.0, 1.0 - s2), rtol=0, atol=1e-12)
