@@ -563,20 +563,35 @@ def philox_rays(lens: Lens, n: int, seed: int, first: int = 0, half_w: float = S
     s40, s16, m24 = np.uint64(40), np.uint64(16), np.uint64(0xFFFFFF)
     u0, u1, u2, u3 = ((o >> s40).astype(np.float64) * 2.0 ** -24 for o in (o0, o1, o2, o3))
     u4 = ((o0 >> s16) & m24).astype(np.float64) * 2.0 ** -24
+    return rays_from_uniforms(lens, np.stack([u0, u1, u2, u3, u4]), half_w, half_h, lam_range)
+
+
+def rays_from_uniforms(lens: Lens, u: np.ndarray, half_w: float = SENSOR_HALF_W,
+                       half_h: float = SENSOR_HALF_H, lam_range=(400.0, 700.0),
+                       lam: np.ndarray | None = None) -> dict:
+    """Sensor-side rays of points u (5, n) of [0, 1)^5: sensor point
+    (2 u0 - 1) * half extents, target point on the rear disk at radius
+    sd * sqrt(u2) and angle 2 pi u3, wavelength lambda_min + u4 * range (or
+    the given wavelengths).  Float64 from the given values, rounded to
+    float32 (the sensor point before the direction is formed, as on the
+    device)."""
+    u = np.asarray(u, np.float64)
+    n = u.shape[1]
     f32 = np.float32
     hw, hh = float(f32(half_w)), float(f32(half_h))
-    sx = (2.0 * hw * u0 - hw).astype(f32)
-    sy = (2.0 * hh * u1 - hh).astype(f32)
+    sx = (2.0 * hw * u[0] - hw).astype(f32)
+    sy = (2.0 * hh * u[1] - hh).astype(f32)
     rear = lens.surfaces[-1]
-    rho = float(f32(rear.semi_diameter)) * np.sqrt(u2)
-    phi = 2.0 * np.pi * u3
+    rho = float(f32(rear.semi_diameter)) * np.sqrt(u[2])
+    phi = 2.0 * np.pi * u[3]
     vx = rho * np.cos(phi) - sx.astype(np.float64)
     vy = rho * np.sin(phi) - sy.astype(np.float64)
     vz = np.full(n, -float(f32(rear.thickness)))
     norm = np.sqrt(vx * vx + vy * vy + vz * vz)
     l0, l1 = float(f32(lam_range[0])), float(f32(lam_range[1]))
+    lam_out = ((l1 - l0) * u[4] + l0).astype(f32) if lam is None else np.asarray(lam, f32)
     return {"x": sx, "y": sy, "dx": (vx / norm).astype(f32), "dy": (vy / norm).astype(f32),
-            "dz": (vz / norm).astype(f32), "lambda_nm": ((l1 - l0) * u4 + l0).astype(f32)}
+            "dz": (vz / norm).astype(f32), "lambda_nm": lam_out}
 
 
 def philox_forward_rays(n: int, seed: int, light=(0.0, 0.0, 1.0), at_infinity: bool = True,
