@@ -183,14 +183,23 @@ typedef struct {
     float *lambda_nm;
 } lt_ray_buffers;
 
+/* Wavelength sampling of the generators (Sec. 5.1, data collection). */
+#define LT_LAMBDA_UNIFORM 0  /* uniform on [lambda_min, lambda_max] */
+#define LT_LAMBDA_CIE 1      /* density proportional to xbar + ybar + zbar of the CIE XYZ
+                                colour-matching functions (multi-lobe analytic fit of
+                                Wyman, Sloan and Shirley, JCGT 2013) on the range; the
+                                inverse CDF is evaluated in FP64 from a 1,025-node cubic
+                                Hermite table of the closed-form CDF (error < 1e-6 nm) */
+
 /* Settings of the on-device ray generator. */
 typedef struct {
     uint64_t seed;          /* Philox key word 0 (word 1 is 0) */
     uint64_t first;         /* counter of ray 0; ray k uses (first + k, 0, 0, 0) */
     float half_width_mm;    /* sensor frame half extents (36 x 24 mm frame: 18, 12) */
     float half_height_mm;
-    float lambda_min_nm;    /* wavelength range, uniform */
+    float lambda_min_nm;    /* wavelength range */
     float lambda_max_nm;
+    int32_t lambda_mode;    /* LT_LAMBDA_UNIFORM or LT_LAMBDA_CIE */
 } lt_raygen;
 
 /* Draw n sensor-side rays on the device (training data for Sec. 5.1 "MLP
@@ -242,6 +251,63 @@ typedef struct {
     float *dz;
     float *throughput;
 } lt_exit;
+
+/* Markov-chain sampler of valid training rays for one path (Sec. 5.1: the
+ * data generator draws samples inside the small valid region of each path
+ * with a Markov chain whose target is the binary visibility of the path,
+ * after Hachisuka and Jensen, "Robust adaptive photon tracing using photon
+ * path visibility", TOG 2011).  One chain per lane.  The state u in [0, 1)^5
+ * maps to a sensor-side ray by the recipe of lt_rays_generate (u0, u1:
+ * sensor point; u2, u3: radius and angle on the rear disk; u4: wavelength).
+ * Step s of chain c draws Philox4x64-10 with counter (s, c, 1, 0), key
+ * (seed, 0); r_sel = bits 40..63 of word 0, c0..c4 = bits 16..39 of word 0,
+ * then bits 40..63 and 16..39 of words 1 and 2 (24-bit uniforms).  A chain
+ * without a visible state, or with r_sel < p_large, proposes u' = c;
+ * otherwise u'_i = wrap(u_i + d (2 c_i - 1)), wrap(v) = v - floor(v) (0 if
+ * that rounds to 1).  The proposal is accepted iff its path is valid.  After
+ * a small step, m += 1 and d <- clamp(d + (a - target) / m, 1e-5, 0.5) with
+ * a = 1 if accepted; all of it FP32 with one rounding per operation. */
+typedef struct {
+    uint64_t seed;
+    uint64_t first_step;    /* global index of the first step of this call */
+    float half_width_mm;    /* sensor frame half extents */
+    float half_height_mm;
+    float lambda_min_nm;
+    float lambda_max_nm;
+    int32_t lambda_mode;    /* LT_LAMBDA_UNIFORM or LT_LAMBDA_CIE */
+    float p_large;          /* probability of an independent proposal, [0, 1] */
+    float target_accept;    /* small-step acceptance the step size is steered to, (0, 1) */
+} lt_mcmc_cfg;
+
+/* Chain state (device, caller-owned, kept between calls): u [5][n_chains]
+ * FP32, step [n_chains] FP32 (d), n_small [n_chains] int32 (m), visible
+ * [n_chains] uint8. */
+typedef struct {
+    float *u;
+    float *step;
+    int32_t *n_small;
+    uint8_t *visible;
+} lt_mcmc_state;
+
+/* Reset n_chains chains: u = 0, d = step0, m = 0, not visible (a kernel,
+ * usable under stream capture).  Errors: LT_ERR_ARG (NULL with n > 0,
+ * n < 0, step0 outside [1e-5, 0.5]). */
+lt_status lt_mcmc_init(const lt_mcmc_state *state, int64_t n_chains, float step0, void *stream);
+
+/* Advance n_chains chains by n_steps along path.  Step t of chain c writes
+ * rays_out[t * n_chains + c] (the ray of the chain's state after the step,
+ * or the rejected proposal while the chain has no visible state) and its
+ * exit in exit_out (the lt_trace fields; mask 0 with NaN fields for the
+ * invisible case).  counts (device, 4 x uint64, may be NULL) accumulates:
+ * independent proposals, accepted independent proposals, small steps,
+ * accepted small steps; the second over the first estimates the path's
+ * valid fraction under uniform sampling.  flags: 0 or LT_TRACE_PLAIN_FP32.
+ * Errors: LT_ERR_ARG, LT_ERR_PATH, LT_ERR_LENS (last surface not in front of
+ * the sensor), LT_ERR_DEVICE. */
+lt_status lt_mcmc_run(lt_lens lens, const lt_path *path, const lt_mcmc_cfg *cfg,
+                      const lt_mcmc_state *state, int64_t n_chains, int32_t n_steps,
+                      const lt_ray_buffers *rays_out, const lt_exit *exit_out, uint64_t *counts,
+                      uint32_t flags, void *stream);
 
 /* ------------------------------------------------------------ brute force */
 

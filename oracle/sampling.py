@@ -69,17 +69,20 @@ def cie_density(l) -> np.ndarray:
     return sum(w * _lobe(l, mu, s1, s2) for w, mu, s1, s2 in _LOBES)
 
 
-def _lobe_integral(l: float, mu: float, s1: float, s2: float) -> float:
-    """Integral of one split Gaussian from -inf to l."""
+def _lobe_integral(l, mu: float, s1: float, s2: float):
+    """Integral of one split Gaussian from -inf to l (scalar or array)."""
+    from scipy.special import erf, erfc
     c = math.sqrt(math.pi / 2.0)
-    if l < mu:
-        return s1 * c * math.erfc((mu - l) / (s1 * math.sqrt(2.0)))
-    return s1 * c + s2 * c * math.erf((l - mu) / (s2 * math.sqrt(2.0)))
+    l = np.asarray(l, np.float64)
+    left = s1 * c * erfc((mu - l) / (s1 * math.sqrt(2.0)))
+    right = s1 * c + s2 * c * erf((l - mu) / (s2 * math.sqrt(2.0)))
+    return np.where(l < mu, left, right)
 
 
-def cie_cdf(l: float) -> float:
+def cie_cdf(l):
     """Closed-form integral of cie_density from -inf to l."""
-    return sum(w * _lobe_integral(l, mu, s1, s2) for w, mu, s1, s2 in _LOBES)
+    v = sum(w * _lobe_integral(l, mu, s1, s2) for w, mu, s1, s2 in _LOBES)
+    return float(v) if np.ndim(v) == 0 else v
 
 
 def cie_inverse(u, lam_min: float = 400.0, lam_max: float = 700.0) -> np.ndarray:
@@ -88,18 +91,15 @@ def cie_inverse(u, lam_min: float = 400.0, lam_max: float = 700.0) -> np.ndarray
     by 64 bisection steps in FP64."""
     u = np.atleast_1d(np.asarray(u, np.float64))
     f0, f1 = cie_cdf(lam_min), cie_cdf(lam_max)
-    out = np.empty_like(u)
-    for k, uk in enumerate(u):
-        tgt = f0 + uk * (f1 - f0)
-        lo, hi = lam_min, lam_max
-        for _ in range(64):
-            mid = 0.5 * (lo + hi)
-            if cie_cdf(mid) < tgt:
-                lo = mid
-            else:
-                hi = mid
-        out[k] = 0.5 * (lo + hi)
-    return out
+    tgt = f0 + u * (f1 - f0)
+    lo = np.full(u.shape, float(lam_min))
+    hi = np.full(u.shape, float(lam_max))
+    for _ in range(64):
+        mid = 0.5 * (lo + hi)
+        below = cie_cdf(mid) < tgt
+        lo = np.where(below, mid, lo)
+        hi = np.where(below, hi, mid)
+    return 0.5 * (lo + hi)
 
 
 # ------------------------------------------------------------ the chain ----
@@ -130,13 +130,14 @@ def wrap(v: np.ndarray) -> np.ndarray:
 
 def run_chains(visible: Callable[[np.ndarray], np.ndarray], state: Dict[str, np.ndarray],
                seed: int, first_step: int, n_steps: int, p_large: float = 0.1,
-               target: float = 0.234):
+               target: float = 0.234, proposals: list | None = None):
     """Advance every chain by n_steps.  ``visible(u)`` maps a (5, n) FP32
     array of primary-sample points to their boolean visibility.  ``state``
     (modified in place): u (5, n) float32, d (n,) float32, m (n,) int32,
     vis (n,) bool.  Returns per-step outputs: u (n_steps, 5, n), valid
     (n_steps, n), and the counts [large proposals, large accepted, small
-    proposals, small accepted]."""
+    proposals, small accepted].  If ``proposals`` is a list, each step's
+    proposals (5, n) are appended to it."""
     f32 = np.float32
     u, d, m, vis = state["u"], state["d"], state["m"], state["vis"]
     n = u.shape[1]
@@ -150,6 +151,8 @@ def run_chains(visible: Callable[[np.ndarray], np.ndarray], state: Dict[str, np.
         large = ~vis | (r_sel < pl)
         small_prop = wrap(u + d[None, :] * (f32(2.0) * c - f32(1.0)))
         prop = np.where(large[None, :], c, small_prop).astype(f32)
+        if proposals is not None:
+            proposals.append(prop.copy())
         acc = visible(prop)
         counts += [large.sum(), (large & acc).sum(), (~large).sum(), (~large & acc).sum()]
         sm = ~large

@@ -17,6 +17,7 @@ EXIT_FIELDS = ("mask", "x", "y", "dx", "dy", "dz", "throughput")
 
 LT_TRACE_PLAIN_FP32 = N.LT_TRACE_PLAIN_FP32
 LT_TRACE_FORWARD = N.LT_TRACE_FORWARD
+LT_LAMBDA_UNIFORM, LT_LAMBDA_CIE = N.LT_LAMBDA_UNIFORM, N.LT_LAMBDA_CIE
 LT_F32, LT_BF16, LT_FP8 = N.LT_F32, N.LT_BF16, N.LT_FP8
 LT_ACT_TANH, LT_ACT_RELU = N.LT_ACT_TANH, N.LT_ACT_RELU
 MAP_FIELDS = ("logit", "mask", "x", "y", "dx", "dy", "dz", "throughput")
@@ -30,6 +31,7 @@ __all__ = ["LtError", "Lens", "lt_lens_create", "lt_lens_query", "lt_trace", "lt
            "TARGET_FIELDS", "lt_path_encode", "lt_path_decode", "lt_trace_compact",
            "lt_map_quantize", "lt_rays_generate", "lt_map_eval_ex", "LT_EVAL_MASK_ONLY",
            "lt_lens_planes", "LT_TRACE_FORWARD", "lt_rays_generate_forward", "lt_splat",
+           "LT_LAMBDA_UNIFORM", "LT_LAMBDA_CIE", "mcmc_state", "lt_mcmc_init", "lt_mcmc_run",
            "LT_EVAL_GATED"]
 
 TARGET_FIELDS = ("valid", "x", "y", "dx", "dy", "throughput")
@@ -221,7 +223,7 @@ def lt_trace_ex(lens: Lens, path, rays: Dict, out: Optional[Dict] = None,
 
 def lt_rays_generate(lens: Lens, n: int, seed: int, first: int = 0, half_width: float = 18.0,
                      half_height: float = 12.0, lam_range=(400.0, 700.0), out: Optional[Dict] = None,
-                     device="cuda", stream=None) -> Dict:
+                     device="cuda", stream=None, lambda_mode: int = N.LT_LAMBDA_UNIFORM) -> Dict:
     """n sensor-side rays drawn on the device (Philox4x64-10, ray k from
     counter first + k); returns a dict of float32 tensors."""
     torch = _torch()
@@ -232,7 +234,7 @@ def lt_rays_generate(lens: Lens, n: int, seed: int, first: int = 0, half_width: 
         setattr(b, k, _dev_ptr(out[k], torch.float32, n, f"out[{k}]") if n else None)
     cfg = N.lt_raygen(int(seed) & 0xFFFFFFFFFFFFFFFF, int(first) & 0xFFFFFFFFFFFFFFFF,
                       float(half_width), float(half_height), float(lam_range[0]),
-                      float(lam_range[1]))
+                      float(lam_range[1]), int(lambda_mode))
     N.check(N.lib().lt_rays_generate(lens.handle, C.byref(cfg), C.byref(b), int(n),
                                      C.c_void_p(_stream_ptr(stream) if n else 0)))
     return out
@@ -260,6 +262,73 @@ def lt_rays_generate_forward(lens: Lens, n: int, seed: int, light=(0.0, 0.0, 1.0
     N.check(N.lib().lt_rays_generate_forward(lens.handle, C.byref(cfg), C.byref(b), int(n),
                                              C.c_void_p(_stream_ptr(stream) if n else 0)))
     return out
+
+
+def mcmc_state(n_chains: int, device="cuda") -> Dict:
+    """Device buffers of n_chains Markov chains (u [5][n], step, n_small,
+    visible); call lt_mcmc_init before the first run."""
+    torch = _torch()
+    return {"u": torch.empty((5, n_chains), dtype=torch.float32, device=device),
+            "step": torch.empty(n_chains, dtype=torch.float32, device=device),
+            "n_small": torch.empty(n_chains, dtype=torch.int32, device=device),
+            "visible": torch.empty(n_chains, dtype=torch.uint8, device=device)}
+
+
+def _mcmc_struct(state) -> "N.lt_mcmc_state":
+    torch = _torch()
+    n = int(state["step"].numel())
+    s = N.lt_mcmc_state()
+    if n:
+        s.u = _dev_ptr(state["u"], torch.float32, 5 * n, "state[u]")
+        s.step = _dev_ptr(state["step"], torch.float32, n, "state[step]")
+        s.n_small = _dev_ptr(state["n_small"], torch.int32, n, "state[n_small]")
+        s.visible = _dev_ptr(state["visible"], torch.uint8, n, "state[visible]")
+    return s
+
+
+def lt_mcmc_init(state: Dict, step0: float = 0.05, stream=None):
+    n = int(state["step"].numel())
+    N.check(N.lib().lt_mcmc_init(C.byref(_mcmc_struct(state)), n, float(step0),
+                                 C.c_void_p(_stream_ptr(stream) if n else 0)))
+    return state
+
+
+def lt_mcmc_run(lens: Lens, path, state: Dict, n_steps: int, seed: int, first_step: int = 0,
+                p_large: float = 0.1, target_accept: float = 0.234, half_width: float = 18.0,
+                half_height: float = 12.0, lam_range=(400.0, 700.0),
+                lambda_mode: int = N.LT_LAMBDA_UNIFORM, rays_out: Optional[Dict] = None,
+                exit_out: Optional[Dict] = None, counts=None, flags: int = 0, stream=None):
+    """Advance the chains by n_steps along ``path``; returns (rays, exits,
+    counts): rays / exits are dicts of [n_steps, n_chains] tensors (step-major),
+    counts a device uint64[4] (independent proposals, accepted, small steps,
+    accepted), accumulated into if given."""
+    torch = _torch()
+    n = int(state["step"].numel())
+    dev = state["step"].device
+    m = n * int(n_steps)
+    if rays_out is None:
+        rays_out = {k: torch.empty((n_steps, n), dtype=torch.float32, device=dev) for k in RAY_FIELDS}
+    if exit_out is None:
+        exit_out = empty_exit(m, dev)
+        exit_out = {k: v.view(n_steps, n) for k, v in exit_out.items()}
+    if counts is None:
+        counts = torch.zeros(4, dtype=torch.int64, device=dev)
+    rb = N.lt_ray_buffers()
+    eb = N.lt_exit()
+    for k in RAY_FIELDS:
+        setattr(rb, k, _dev_ptr(rays_out[k], torch.float32, m, f"rays_out[{k}]") if m else None)
+    for k in EXIT_FIELDS:
+        dt = torch.uint8 if k == "mask" else torch.float32
+        setattr(eb, k, _dev_ptr(exit_out[k], dt, m, f"exit_out[{k}]") if m else None)
+    cfg = N.lt_mcmc_cfg(int(seed) & 0xFFFFFFFFFFFFFFFF, int(first_step) & 0xFFFFFFFFFFFFFFFF,
+                        float(half_width), float(half_height), float(lam_range[0]),
+                        float(lam_range[1]), int(lambda_mode), float(p_large), float(target_accept))
+    cp = _dev_ptr(counts, torch.int64, 4, "counts") if n else None
+    N.check(N.lib().lt_mcmc_run(lens.handle, C.byref(_path(path)), C.byref(cfg),
+                                C.byref(_mcmc_struct(state)), n, int(n_steps), C.byref(rb),
+                                C.byref(eb), cp, int(flags),
+                                C.c_void_p(_stream_ptr(stream) if n else 0)))
+    return rays_out, exit_out, counts
 
 
 def lt_splat(x, y, dz, throughput, sensor, images=None, mask=None, n: Optional[int] = None,

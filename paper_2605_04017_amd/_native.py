@@ -14,6 +14,7 @@ LT_MAX_SURFACES = 24
 LT_MAX_GLASSES = 24
 LT_TRACE_PLAIN_FP32 = 1
 LT_TRACE_FORWARD = 2
+LT_LAMBDA_UNIFORM, LT_LAMBDA_CIE = 0, 1
 
 
 class LtError(RuntimeError):
@@ -47,7 +48,18 @@ class lt_ray_buffers(C.Structure):
 class lt_raygen(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("first", C.c_uint64), ("half_width_mm", C.c_float),
                 ("half_height_mm", C.c_float), ("lambda_min_nm", C.c_float),
-                ("lambda_max_nm", C.c_float)]
+                ("lambda_max_nm", C.c_float), ("lambda_mode", C.c_int32)]
+
+
+class lt_mcmc_cfg(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("first_step", C.c_uint64), ("half_width_mm", C.c_float),
+                ("half_height_mm", C.c_float), ("lambda_min_nm", C.c_float),
+                ("lambda_max_nm", C.c_float), ("lambda_mode", C.c_int32), ("p_large", C.c_float),
+                ("target_accept", C.c_float)]
+
+
+class lt_mcmc_state(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("u", "step", "n_small", "visible")]
 
 
 class lt_raygen_forward(C.Structure):
@@ -115,6 +127,11 @@ SIGNATURES = {
                                    C.c_int64, C.c_void_p]),
     "lt_rays_generate_forward": (C.c_int, [C.c_void_p, C.POINTER(lt_raygen_forward),
                                            C.POINTER(lt_ray_buffers), C.c_int64, C.c_void_p]),
+    "lt_mcmc_init": (C.c_int, [C.POINTER(lt_mcmc_state), C.c_int64, C.c_float, C.c_void_p]),
+    "lt_mcmc_run": (C.c_int, [C.c_void_p, C.POINTER(lt_path), C.POINTER(lt_mcmc_cfg),
+                              C.POINTER(lt_mcmc_state), C.c_int64, C.c_int32,
+                              C.POINTER(lt_ray_buffers), C.POINTER(lt_exit), C.c_void_p, C.c_uint32,
+                              C.c_void_p]),
     "lt_splat": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                            C.c_int64, C.POINTER(lt_sensor), C.c_float, C.c_void_p, C.c_void_p]),
     "lt_trace": (C.c_int, [C.c_void_p, C.POINTER(lt_path), C.POINTER(lt_rays),

@@ -18,43 +18,14 @@
 #include <cmath>
 
 #include "lt_internal.h"
+#include "lt_rng.h"
 
 namespace lt {
 
-struct U64x4 {
-    uint64_t v[4];
-};
-
-__device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
-                                              uint64_t k0, uint64_t k1)
-{
-    constexpr uint64_t kM0 = 0xD2E7470EE14C6C93ull, kM1 = 0xCA5A826395121157ull;
-    constexpr uint64_t kW0 = 0x9E3779B97F4A7C15ull, kW1 = 0xBB67AE8584CAA73Bull;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t lo0 = kM0 * c0, hi0 = __umul64hi(kM0, c0);
-        const uint64_t lo1 = kM1 * c2, hi1 = __umul64hi(kM1, c2);
-        const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-        c0 = n0;
-        c1 = lo1;
-        c2 = n2;
-        c3 = lo0;
-        k0 += kW0;
-        k1 += kW1;
-    }
-    return U64x4{{c0, c1, c2, c3}};
-}
-
-// 24-bit uniform in [0, 1) from bits [shift, shift + 24) of a word
-__device__ __forceinline__ float u24(uint64_t w, int shift)
-{
-    return static_cast<float>(static_cast<uint32_t>((w >> shift) & 0xFFFFFFull)) * 0x1.0p-24f;
-}
-
 struct RaygenArgs {
     uint64_t seed, first;
-    float hw, hh, lam0, lam1;
-    float sd, dist;   // last surface: semi-diameter, sensor-to-vertex distance
+    SensorRayGen G;   // sensor frame, last surface: semi-diameter, sensor-to-vertex distance
+    LambdaSampler S;
     int64_t n;
 };
 
@@ -69,19 +40,13 @@ __global__ __launch_bounds__(256) void raygen_kernel(RaygenArgs A, float *__rest
     const U64x4 o = philox4x64_10(A.first + static_cast<uint64_t>(k), 0, 0, 0, A.seed, 0);
     const float u0 = u24(o.v[0], 40), u1 = u24(o.v[1], 40), u2 = u24(o.v[2], 40);
     const float u3 = u24(o.v[3], 40), u4 = u24(o.v[0], 16);
-    const float sx = fmaf(2.0f * A.hw, u0, -A.hw);
-    const float sy = fmaf(2.0f * A.hh, u1, -A.hh);
-    const float rho = A.sd * sqrtf(u2);
-    float sphi, cphi;
-    sincospif(2.0f * u3, &sphi, &cphi);
-    const float vx = rho * cphi - sx, vy = rho * sphi - sy, vz = -A.dist;
-    const float inv = 1.0f / sqrtf(vx * vx + vy * vy + vz * vz);
-    x[k] = sx;
-    y[k] = sy;
-    dx[k] = vx * inv;
-    dy[k] = vy * inv;
-    dz[k] = vz * inv;
-    lam[k] = fmaf(A.lam1 - A.lam0, u4, A.lam0);
+    const RayF r = sensor_ray(A.G, u0, u1, u2, u3, sample_lambda(A.S, u4));
+    x[k] = r.x;
+    y[k] = r.y;
+    dx[k] = r.dx;
+    dy[k] = r.dy;
+    dz[k] = r.dz;
+    lam[k] = r.lam;
 }
 
 struct RaygenFwdArgs {
@@ -193,6 +158,10 @@ extern "C" lt_status lt_rays_generate(lt_lens lens, const lt_raygen *cfg, const 
     if (!(cfg->half_width_mm > 0.0f) || !(cfg->half_height_mm > 0.0f) ||
         !(cfg->lambda_min_nm > 0.0f) || !(cfg->lambda_max_nm >= cfg->lambda_min_nm))
         return fail(LT_ERR_ARG, "invalid sensor extent or wavelength range");
+    if (cfg->lambda_mode != LT_LAMBDA_UNIFORM && cfg->lambda_mode != LT_LAMBDA_CIE)
+        return fail(LT_ERR_ARG, "unknown wavelength mode");
+    if (cfg->lambda_mode == LT_LAMBDA_CIE && !(cfg->lambda_max_nm > cfg->lambda_min_nm))
+        return fail(LT_ERR_ARG, "CIE sampling needs lambda_max > lambda_min");
     if (n == 0)
         return LT_OK;
     if (!out->x || !out->y || !out->dx || !out->dy || !out->dz || !out->lambda_nm)
@@ -203,12 +172,18 @@ extern "C" lt_status lt_rays_generate(lt_lens lens, const lt_raygen *cfg, const 
     RaygenArgs A;
     A.seed = cfg->seed;
     A.first = cfg->first;
-    A.hw = cfg->half_width_mm;
-    A.hh = cfg->half_height_mm;
-    A.lam0 = cfg->lambda_min_nm;
-    A.lam1 = cfg->lambda_max_nm;
-    A.sd = static_cast<float>(last.semi_diameter_mm);
-    A.dist = static_cast<float>(last.thickness_mm);
+    A.G.hw = cfg->half_width_mm;
+    A.G.hh = cfg->half_height_mm;
+    A.G.sd = static_cast<float>(last.semi_diameter_mm);
+    A.G.dist = static_cast<float>(last.thickness_mm);
+    A.S.lam0 = cfg->lambda_min_nm;
+    A.S.lam1 = cfg->lambda_max_nm;
+    A.S.mode = cfg->lambda_mode;
+    if (cfg->lambda_mode == LT_LAMBDA_CIE) {
+        const lt_status st = cie_table(cfg->lambda_min_nm, cfg->lambda_max_nm, &A.S);
+        if (st != LT_OK)
+            return st;
+    }
     A.n = n;
     const int64_t blocks = (n + 255) / 256;
     if (blocks > 0x7fffffffLL)

@@ -169,3 +169,38 @@ def test_splat_wrapper_empty_without_gpu():
     e = torch.empty(0, dtype=torch.float32)
     img = lt.lt_splat(e, e, e, e, (36.0, 24.0, 48, 32))
     assert img.shape == (1, 32, 48) and float(img.abs().sum()) == 0.0
+
+
+def test_mcmc_argument_errors_without_gpu():
+    L = N.lib()
+    lens = synth.config_lens(2)
+    h = lt.lt_lens_create(lens.surfaces, lens.glasses)
+    st = N.lt_mcmc_state()
+    p = N.lt_path(1, 2, 10)
+
+    def cfg(**kw):
+        a = dict(seed=1, first_step=0, half_width_mm=18.0, half_height_mm=12.0, lambda_min_nm=400.0,
+                 lambda_max_nm=700.0, lambda_mode=0, p_large=0.1, target_accept=0.234)
+        a.update(kw)
+        return N.lt_mcmc_cfg(*a.values())
+
+    def run(c, n=0, steps=4, path=p):
+        return L.lt_mcmc_run(h.handle, C.byref(path), C.byref(c), C.byref(st), n, steps, None, None,
+                             None, 0, None)
+    assert run(cfg()) == N.LT_OK                                   # no chains: no-op
+    assert run(cfg(), n=8) == N.LT_ERR_ARG                         # NULL state fields
+    assert run(cfg(), n=-1) == N.LT_ERR_ARG
+    assert run(cfg(p_large=1.5)) == N.LT_ERR_ARG
+    assert run(cfg(target_accept=0.0)) == N.LT_ERR_ARG
+    assert run(cfg(lambda_mode=3)) == N.LT_ERR_ARG
+    assert run(cfg(lambda_mode=1, lambda_max_nm=400.0)) == N.LT_ERR_ARG
+    assert run(cfg(half_width_mm=0.0)) == N.LT_ERR_ARG
+    assert run(cfg(), path=N.lt_path(1, 3, 3)) == N.LT_ERR_PATH
+    assert L.lt_mcmc_run(h.handle, C.byref(p), C.byref(cfg()), C.byref(st), 0, 1, None, None, None, 8,
+                         None) == N.LT_ERR_ARG                      # unknown flag
+    assert L.lt_mcmc_init(C.byref(st), 0, C.c_float(0.05), None) == N.LT_OK
+    assert L.lt_mcmc_init(C.byref(st), 4, C.c_float(0.05), None) == N.LT_ERR_ARG
+    assert L.lt_mcmc_init(C.byref(st), 0, C.c_float(0.9), None) == N.LT_ERR_ARG
+    rg = N.lt_raygen(1, 0, 18.0, 12.0, 400.0, 700.0, 2)
+    b = N.lt_ray_buffers()
+    assert L.lt_rays_generate(h.handle, C.byref(rg), C.byref(b), 0, None) == N.LT_ERR_ARG
