@@ -599,6 +599,71 @@ def flare(lt, synth, mlp, dev, steps=10000, n_render=1 << 20, theta_deg=10.0, n_
     return res
 
 
+def sampler_yield(lt, synth, dev, path=(1, 2, 10), n_chains=1 << 20, steps=32, burn_in=256,
+                  n_uniform=1 << 24, seed=7007):
+    """Training-data generation for one ghost path of the 11-surface lens
+    with a small valid region (Sec. 5.1: a Markov chain with a binary
+    visibility target raises the valid-sample yield): valid labelled rays
+    per second from the device chains (1,048,576 chains, 32 timed steps after
+    a 256-step burn-in) against rejection sampling (16,777,216 uniform rays
+    traced with compacted output).  The chains' outputs repeat a state when
+    a proposal is rejected, so the rate of distinct valid samples (accepted
+    proposals) is reported too."""
+    import numpy as np
+    import torch
+    lens = synth.config_lens(2)
+    h = lt.lt_lens_create(lens.surfaces, lens.glasses)
+    stream = torch.cuda.current_stream()
+    uni = lt.lt_rays_generate(h, n_uniform, seed)
+    cout = {k: torch.empty(n_uniform, dtype=torch.float32, device=dev) for k in lt.EXIT_FIELDS[1:]}
+    cidx = torch.empty(n_uniform, dtype=torch.int64, device=dev)
+    cnt = torch.empty(1, dtype=torch.int64, device=dev)
+
+    def rejection():
+        lt.lt_rays_generate(h, n_uniform, seed, out=uni, stream=stream)
+        lt.lt_trace_compact(h, path, uni, cout, cidx, cnt, n_uniform, 0, stream)
+    t_rej = time_kernel(rejection, stream, 3)
+    n_valid = int(cnt.item())
+    del uni, cout, cidx
+    st = lt.lt_mcmc_init(lt.mcmc_state(n_chains, dev), 0.05)
+    rays = {k: torch.empty((steps, n_chains), dtype=torch.float32, device=dev) for k in lt.RAY_FIELDS}
+    ex = {k: v.view(steps, n_chains) for k, v in lt.empty_exit(steps * n_chains, dev).items()}
+    counts = torch.zeros(4, dtype=torch.int64, device=dev)
+    first = 0
+    for _ in range(burn_in // steps):
+        lt.lt_mcmc_run(h, path, st, steps, seed, first, rays_out=rays, exit_out=ex, counts=counts,
+                       stream=stream)
+        first += steps
+    torch.cuda.synchronize()
+    c0 = counts.cpu().numpy().copy()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    lt.lt_mcmc_run(h, path, st, steps, seed, first, rays_out=rays, exit_out=ex, counts=counts, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_mc = e0.elapsed_time(e1) * 1e-3
+    c1 = counts.cpu().numpy()
+    d = (c1 - c0).astype(np.float64)
+    valid_out = float(ex["mask"].float().sum())
+    res = {"path": list(path), "lens": "11-surface double-Gauss-style lens",
+           "uniform_valid_fraction": n_valid / n_uniform,
+           "rejection_valid_rays_per_s_M": n_valid / t_rej / 1e6,
+           "rejection_ms": t_rej * 1e3, "rejection_rays": n_uniform,
+           "chains": n_chains, "steps_timed": steps, "burn_in_steps": burn_in,
+           "mcmc_ms": t_mc * 1e3,
+           "mcmc_valid_outputs_fraction": valid_out / (steps * n_chains),
+           "mcmc_valid_rays_per_s_M": valid_out / t_mc / 1e6,
+           "mcmc_distinct_valid_rays_per_s_M": (d[1] + d[3]) / t_mc / 1e6,
+           "small_step_acceptance": d[3] / max(1.0, d[2]),
+           "uniform_fraction_estimate_from_chains": c1[1] / max(1, c1[0]),
+           "valid_rays_per_traced_ray": {"rejection": n_valid / n_uniform,
+                                         "mcmc_outputs": valid_out / (steps * n_chains),
+                                         "mcmc_distinct": (d[1] + d[3]) / (steps * n_chains)}}
+    del rays, ex, st
+    torch.cuda.empty_cache()
+    return res
+
+
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "map_f32_c2_4M_traffic.md")
 MAP_F32_SOURCES = ("paper_2605_04017_amd/csrc/lt_map_f32.hip", "paper_2605_04017_amd/csrc/lt_map_dev.h",
                    "paper_2605_04017_amd/csrc/lt_map.h")
@@ -675,6 +740,7 @@ def main():
     ap.add_argument("--no-train-epoch", action="store_true")
     ap.add_argument("--no-paper-pair", action="store_true")
     ap.add_argument("--no-flare", action="store_true")
+    ap.add_argument("--no-sampler", action="store_true")
     ap.add_argument("--rays", type=int, default=N_RAYS)
     ap.add_argument("--traffic-probe", nargs="?", const="f32", choices=("f32", "bf16", "fp8"),
                     help="only run the short program the counter runs profile (map precision)")
@@ -810,6 +876,9 @@ def main():
     if not args.no_flare:
         res["flare_forward"] = flare(lt, synth, mlp, dev)
         print("# flare frame done", file=sys.stderr, flush=True)
+    if not args.no_sampler:
+        res["sampler_yield_ghost"] = sampler_yield(lt, synth, dev)
+        print("# sampler yield done", file=sys.stderr, flush=True)
     if not args.no_multi_path:
         res["multi_path_16M"] = multi_path(lt, synth, mlp, dev)
         print("# multi-path done", file=sys.stderr, flush=True)
