@@ -171,6 +171,9 @@ def exit_error(g, o, n_sample):
     import numpy as np
     gm, om = g["mask"].astype(bool), o["mask"].astype(bool)
     both = gm & om
+    if not both.any():   # a barely fitted classifier may accept nothing
+        return {"mask_agreement": float(np.mean(gm == om)), "false_valid": float(np.mean(gm & ~om)),
+                "false_invalid": float(np.mean(~gm & om)), "rays": n_sample, "valid_in_both": 0}
     pos = np.hypot(g["x"][both] - o["x"][both], g["y"][both] - o["y"][both])
     u = np.stack([g["dx"][both], g["dy"][both], g["dz"][both]], 1).astype(np.float64)
     v = np.stack([o["dx"][both], o["dy"][both], o["dz"][both]], 1)
