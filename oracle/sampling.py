@@ -130,18 +130,21 @@ def wrap(v: np.ndarray) -> np.ndarray:
 
 def run_chains(visible: Callable[[np.ndarray], np.ndarray], state: Dict[str, np.ndarray],
                seed: int, first_step: int, n_steps: int, p_large: float = 0.1,
-               target: float = 0.234, proposals: list | None = None):
+               target: float = 0.234, proposals: list | None = None,
+               chain_ids: np.ndarray | None = None):
     """Advance every chain by n_steps.  ``visible(u)`` maps a (5, n) FP32
     array of primary-sample points to their boolean visibility.  ``state``
     (modified in place): u (5, n) float32, d (n,) float32, m (n,) int32,
     vis (n,) bool.  Returns per-step outputs: u (n_steps, 5, n), valid
     (n_steps, n), and the counts [large proposals, large accepted, small
     proposals, small accepted].  If ``proposals`` is a list, each step's
-    proposals (5, n) are appended to it."""
+    proposals (5, n) are appended to it.  ``chain_ids`` gives the chains'
+    indices in the counter (default 0..n-1), so any subset of a large run
+    can be followed on its own."""
     f32 = np.float32
     u, d, m, vis = state["u"], state["d"], state["m"], state["vis"]
     n = u.shape[1]
-    chains = np.arange(n)
+    chains = np.arange(n) if chain_ids is None else np.asarray(chain_ids, np.int64)
     out_u = np.empty((n_steps, 5, n), np.float32)
     out_ok = np.empty((n_steps, n), bool)
     counts = np.zeros(4, np.int64)

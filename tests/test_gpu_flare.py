@@ -164,8 +164,8 @@ def test_splat_empty(dev):
     assert float(img.abs().sum()) == 0.0
 
 
-@pytest.mark.parametrize("theta_deg", [0.0, 12.0])
-def test_forward_pipeline_image(dev, theta_deg):
+@pytest.mark.parametrize("theta_deg,n", [(0.0, 1 << 18), (12.0, 1 << 18), (10.0, 1 << 20)])
+def test_forward_pipeline_image(dev, theta_deg, n):
     """Device rays from a distant point light -> forward trace -> splat, for
     the transmit path and ghosts of the 11-surface lens, against the oracle
     tracing the same rays and forming the same images.  Rays whose oracle
@@ -175,7 +175,6 @@ def test_forward_pipeline_image(dev, theta_deg):
     import paper_2605_04017_amd as lt
     L = synth.config_lens(2)
     h = lt.lt_lens_create(L.surfaces, L.glasses)
-    n = 1 << 18
     th = math.radians(theta_deg)
     sensor = (36.0, 24.0, 360, 240)
     rays = lt.lt_rays_generate_forward(h, n, 77, (math.sin(th), 0.0, math.cos(th)))

@@ -158,3 +158,31 @@ def test_mcmc_yield_and_normalisation(dev):
     small_acc = cnt[3] / cnt[2]
     print(f"[mcmc] yield: uniform valid fraction {f_uni:.4f}, estimate {p_hat:.4f}, small-step "
           f"acceptance {small_acc:.3f}, valid outputs after 192 steps {valid_after:.4f}", flush=True)
+
+
+def test_mcmc_full_size_sampled(dev):
+    """The benchmark configuration (1,048,576 chains on ghost (1, 2, 10)),
+    64 steps from the initial state; 3,000 chains picked at random are
+    followed by the oracle on their own counters."""
+    import torch
+    import paper_2605_04017_amd as lt
+    L = synth.config_lens(2)
+    h = lt.lt_lens_create(L.surfaces, L.glasses)
+    path, n, steps, seed = (1, 2, 10), 1 << 20, 64, 7007
+    st = lt.lt_mcmc_init(lt.mcmc_state(n, dev), 0.05)
+    rays, ex, _ = lt.lt_mcmc_run(h, path, st, steps, seed)
+    ids = np.sort(np.random.default_rng(1).choice(n, 3000, replace=False))
+    idx = torch.from_numpy(ids).to(dev)
+    g_x = rays["x"][:, idx].cpu().numpy()
+    g_m = ex["mask"][:, idx].cpu().numpy()
+    g_u = st["u"][:, idx].cpu().numpy()
+    g_d = st["step"][idx].cpu().numpy()
+    torch.cuda.synchronize()
+    ost = S.new_state(ids.size, 0.05)
+    o_u, o_ok, _ = S.run_chains(S.lens_visibility(L, path, HW, HH), ost, seed, 0, steps, chain_ids=ids)
+    o_x = np.stack([synth.rays_from_uniforms(L, o_u[t], HW, HH)["x"] for t in range(steps)])
+    ident = ((g_x == o_x) & (g_m == o_ok)).all(0)
+    assert ident.mean() > 0.98, ident.mean()
+    assert np.array_equal(g_u[:, ident], ost["u"][:, ident])
+    assert np.array_equal(g_d[ident], ost["d"][ident])
+    print(f"[mcmc] full size: {ident.mean():.4f} of 3,000 sampled chains identical", flush=True)
