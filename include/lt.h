@@ -189,7 +189,10 @@ typedef struct {
                                 colour-matching functions (multi-lobe analytic fit of
                                 Wyman, Sloan and Shirley, JCGT 2013) on the range; the
                                 inverse CDF is evaluated in FP64 from a 1,025-node cubic
-                                Hermite table of the closed-form CDF (error < 1e-6 nm) */
+                                Hermite table of the closed-form CDF (error < 1e-6 nm).
+                                The first call per device and range builds the 16 KiB
+                                table (hipMalloc + synchronous copy, kept until the
+                                process ends), so make that call outside stream capture */
 
 /* Settings of the on-device ray generator. */
 typedef struct {
