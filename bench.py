@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 N_RAYS = 4194304
 MI355X_FP32_VECTOR_TFLOPS = 157.3
+MI355X_FP64_VECTOR_TFLOPS = 78.6
 MI355X_FP32_MFMA_TFLOPS = 157.3
 MI355X_BF16_MFMA_TFLOPS = 2500.0
 MI355X_FP8_MFMA_TFLOPS = 5000.0
@@ -810,6 +811,8 @@ def main():
     fast = lt.empty_exit(n, dev)
     t_fast = time_kernel(lambda: lt.lt_trace_ex(h, (0, 0, 0), rays, fast, n, lt.LT_TRACE_PLAIN_FP32,
                                                 stream), stream, reps)
+    t_f64 = time_kernel(lambda: lt.lt_trace_ex(h, (0, 0, 0), rays, fast, n, lt.LT_TRACE_FP64,
+                                               stream), stream, reps)
     errors = {name: map_error(lt, oracle, lens, m, dt, rays_np, rays)
               for name, dt in (("f32", lt.LT_F32), ("bf16", lt.LT_BF16), ("fp8", lt.LT_FP8))}
     # the symmetry-reduced input frame, fitted with the same budget
@@ -847,8 +850,10 @@ def main():
         "map_fp8_mrays_s": n / t_fp8 / 1e6,
         "trace_mrays_s": n / t_trace / 1e6,
         "trace_plain_fp32_mrays_s": n / t_fast / 1e6,
+        "trace_fp64_option_mrays_s": n / t_f64 / 1e6,
         "map_over_trace": {"f32": t_trace / t_map, "bf16": t_trace / t_bf16, "fp8": t_trace / t_fp8},
         "kernel_ms": {"trace": t_trace * 1e3, "trace_plain_fp32": t_fast * 1e3,
+                      "trace_fp64_option": t_f64 * 1e3,
                       "map_f32": t_map * 1e3, "map_bf16": t_bf16 * 1e3, "map_fp8": t_fp8 * 1e3,
                       "map_f32_canonical_input": t_map_c * 1e3},
         "map_error_vs_fp64_oracle": errors,
@@ -867,7 +872,12 @@ def main():
                         "frac": fpr * n / t_fp8 / 1e12 / MI355X_FP8_MFMA_TFLOPS},
             "trace": {"bound": "alu", "achieved": trace_tf, "peak": MI355X_FP32_VECTOR_TFLOPS,
                       "unit": "TFLOP/s", "frac": trace_tf / MI355X_FP32_VECTOR_TFLOPS,
-                      "flops_per_ray": trace_flops_per_ray(lens)}},
+                      "flops_per_ray": trace_flops_per_ray(lens)},
+            "trace_fp64_option": {"bound": "alu",
+                                  "achieved": trace_flops_per_ray(lens) * n / t_f64 / 1e12,
+                                  "peak": MI355X_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": trace_flops_per_ray(lens) * n / t_f64 / 1e12
+                                  / MI355X_FP64_VECTOR_TFLOPS}},
     }
     if not args.no_paper_pair:
         res["paper_pair_2x32_5x32"] = paper_pair(lt, synth, mlp, oracle, lens, dev, args.fit_steps,

@@ -304,7 +304,8 @@ lt_status lt_mcmc_init(const lt_mcmc_state *state, int64_t n_chains, float step0
  * invisible case).  counts (device, 4 x uint64, may be NULL) accumulates:
  * independent proposals, accepted independent proposals, small steps,
  * accepted small steps; the second over the first estimates the path's
- * valid fraction under uniform sampling.  flags: 0 or LT_TRACE_PLAIN_FP32.
+ * valid fraction under uniform sampling.  flags: 0, LT_TRACE_PLAIN_FP32 or
+ * LT_TRACE_FP64 (the tracer variant that decides validity).
  * Errors: LT_ERR_ARG, LT_ERR_PATH, LT_ERR_LENS (last surface not in front of
  * the sensor), LT_ERR_DEVICE. */
 lt_status lt_mcmc_run(lt_lens lens, const lt_path *path, const lt_mcmc_cfg *cfg,
@@ -333,6 +334,13 @@ lt_status lt_trace(lt_lens lens, const lt_path *path, const lt_rays *rays,
                                    the transmitted cosine near grazing.  Faster, but
                                    exit-position errors reach a few 1e-5 mm on long
                                    ghost paths. */
+
+#define LT_TRACE_FP64 4u       /* the same operators in FP64 arithmetic, outside the FP32
+                                   form of the tracer: outputs are the FP32 roundings of
+                                   FP64 results (within one FP32 ulp of the exact trace),
+                                   at about twice the default's speed on gfx950, whose
+                                   FP64 vector rate is half its FP32 rate.  Not combinable
+                                   with LT_TRACE_PLAIN_FP32 */
 
 #define LT_TRACE_FORWARD 2u    /* forward light tracing (Sec. 3, the flare equation): rays start
                                    on the forward input plane (lt_lens_planes) in air,

@@ -17,6 +17,7 @@ EXIT_FIELDS = ("mask", "x", "y", "dx", "dy", "dz", "throughput")
 
 LT_TRACE_PLAIN_FP32 = N.LT_TRACE_PLAIN_FP32
 LT_TRACE_FORWARD = N.LT_TRACE_FORWARD
+LT_TRACE_FP64 = N.LT_TRACE_FP64
 LT_LAMBDA_UNIFORM, LT_LAMBDA_CIE = N.LT_LAMBDA_UNIFORM, N.LT_LAMBDA_CIE
 LT_F32, LT_BF16, LT_FP8 = N.LT_F32, N.LT_BF16, N.LT_FP8
 LT_ACT_TANH, LT_ACT_RELU = N.LT_ACT_TANH, N.LT_ACT_RELU
@@ -30,7 +31,7 @@ __all__ = ["LtError", "Lens", "lt_lens_create", "lt_lens_query", "lt_trace", "lt
            "lt_map_forward_train", "lt_map_backward", "lt_map_train_step", "lt_map_adam_state",
            "TARGET_FIELDS", "lt_path_encode", "lt_path_decode", "lt_trace_compact",
            "lt_map_quantize", "lt_rays_generate", "lt_map_eval_ex", "LT_EVAL_MASK_ONLY",
-           "lt_lens_planes", "LT_TRACE_FORWARD", "lt_rays_generate_forward", "lt_splat",
+           "lt_lens_planes", "LT_TRACE_FORWARD", "LT_TRACE_FP64", "lt_rays_generate_forward", "lt_splat",
            "LT_LAMBDA_UNIFORM", "LT_LAMBDA_CIE", "mcmc_state", "lt_mcmc_init", "lt_mcmc_run",
            "LT_EVAL_GATED"]
 
@@ -204,7 +205,8 @@ def lt_trace(lens: Lens, path, rays: Dict, out: Optional[Dict] = None, n: Option
 
 def lt_trace_ex(lens: Lens, path, rays: Dict, out: Optional[Dict] = None,
                 n: Optional[int] = None, flags: int = 0, stream=None) -> Dict:
-    """lt_trace with option flags (LT_TRACE_PLAIN_FP32 = 1, LT_TRACE_FORWARD = 2)."""
+    """lt_trace with option flags (LT_TRACE_PLAIN_FP32 = 1, LT_TRACE_FORWARD = 2,
+    LT_TRACE_FP64 = 4)."""
     torch = _torch()
     if n is None:
         n = int(rays["x"].numel())

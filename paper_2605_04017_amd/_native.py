@@ -14,6 +14,7 @@ LT_MAX_SURFACES = 24
 LT_MAX_GLASSES = 24
 LT_TRACE_PLAIN_FP32 = 1
 LT_TRACE_FORWARD = 2
+LT_TRACE_FP64 = 4
 LT_LAMBDA_UNIFORM, LT_LAMBDA_CIE = 0, 1
 
 

@@ -142,7 +142,7 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
     return v;
 }
 
-template <bool kFast>
+template <int kMode>
 __global__ __launch_bounds__(kChainBlock) void mcmc_kernel(TraceTable T, McmcArgs A, float *__restrict__ su,
                                                            float *__restrict__ sd,
                                                            int32_t *__restrict__ sm,
@@ -199,8 +199,7 @@ __global__ __launch_bounds__(kChainBlock) void mcmc_kernel(TraceTable T, McmcArg
             }
         }
         const RayF r = sensor_ray(A.G, p[0], p[1], p[2], p[3], sample_lambda(A.S, p[4]));
-        const RayOut o = kFast ? trace_one_fast(T, r.x, r.y, r.dx, r.dy, r.dz, r.lam)
-                               : trace_one_ff(T, r.x, r.y, r.dx, r.dy, r.dz, r.lam);
+        const RayOut o = trace_one<kMode>(T, r.x, r.y, r.dx, r.dy, r.dz, r.lam);
         if (t < 0) {
             cur = r;
             co = o;
@@ -317,8 +316,8 @@ extern "C" lt_status lt_mcmc_run(lt_lens lens, const lt_path *path, const lt_mcm
         return fail(LT_ERR_ARG, "NULL lens, path, config or state");
     if (n_chains < 0 || n_steps < 0)
         return fail(LT_ERR_ARG, "negative chain or step count");
-    if (flags & ~static_cast<uint32_t>(LT_TRACE_PLAIN_FP32))
-        return fail(LT_ERR_ARG, "unknown flag");
+    if ((flags & ~static_cast<uint32_t>(LT_TRACE_PLAIN_FP32 | LT_TRACE_FP64)) || trace_mode(flags) < 0)
+        return fail(LT_ERR_ARG, "unknown or contradictory flags");
     if (!(cfg->half_width_mm > 0.0f) || !(cfg->half_height_mm > 0.0f) ||
         !(cfg->lambda_min_nm > 0.0f) || !(cfg->lambda_max_nm >= cfg->lambda_min_nm))
         return fail(LT_ERR_ARG, "invalid sensor extent or wavelength range");
@@ -374,7 +373,10 @@ extern "C" lt_status lt_mcmc_run(lt_lens lens, const lt_path *path, const lt_mcm
     const int64_t blocks = (n_chains + kChainBlock - 1) / kChainBlock;
     if (blocks > 0x7fffffffLL)
         return fail(LT_ERR_ARG, "too many chains for one launch");
-    auto kern = (flags & LT_TRACE_PLAIN_FP32) ? mcmc_kernel<true> : mcmc_kernel<false>;
+    const int mode = trace_mode(flags);
+    auto kern = mode == kTracePlain ? mcmc_kernel<kTracePlain>
+              : mode == kTraceF64   ? mcmc_kernel<kTraceF64>
+                                    : mcmc_kernel<kTraceFF>;
     hipLaunchKernelGGL(kern, dim3(static_cast<uint32_t>(blocks)), dim3(kChainBlock), 0,
                        reinterpret_cast<hipStream_t>(stream), table, A, st->u, st->step, st->n_small,
                        st->visible, O, reinterpret_cast<unsigned long long *>(counts));

@@ -16,7 +16,7 @@ namespace lt {
 
 constexpr int kTraceBlock = 256;
 
-template <bool kFast>
+template <int kMode>
 __global__ __launch_bounds__(kTraceBlock) void trace_kernel(
     TraceTable T, const float *__restrict__ x, const float *__restrict__ y,
     const float *__restrict__ dx, const float *__restrict__ dy, const float *__restrict__ dz,
@@ -27,8 +27,7 @@ __global__ __launch_bounds__(kTraceBlock) void trace_kernel(
     const int64_t r = static_cast<int64_t>(blockIdx.x) * kTraceBlock + threadIdx.x;
     if (r >= n)
         return;
-    const RayOut o = kFast ? trace_one_fast(T, x[r], y[r], dx[r], dy[r], dz[r], lam[r])
-                           : trace_one_ff(T, x[r], y[r], dx[r], dy[r], dz[r], lam[r]);
+    const RayOut o = trace_one<kMode>(T, x[r], y[r], dx[r], dy[r], dz[r], lam[r]);
     const float nan = __builtin_nanf("");
     mask[r] = o.valid ? 1 : 0;
     ox[r] = o.valid ? o.x : nan;
@@ -44,7 +43,7 @@ __global__ __launch_bounds__(kTraceBlock) void trace_kernel(
 // with one atomic add on the global counter and writes its rays in input
 // order inside that range; the order of the ranges follows the order in
 // which workgroups reach the atomic.
-template <bool kFast>
+template <int kMode>
 __global__ __launch_bounds__(kTraceBlock) void trace_compact_kernel(
     TraceTable T, const float *__restrict__ x, const float *__restrict__ y,
     const float *__restrict__ dx, const float *__restrict__ dy, const float *__restrict__ dz,
@@ -59,8 +58,7 @@ __global__ __launch_bounds__(kTraceBlock) void trace_compact_kernel(
     RayOut o{};
     bool valid = false;
     if (r < n) {
-        o = kFast ? trace_one_fast(T, x[r], y[r], dx[r], dy[r], dz[r], lam[r])
-                  : trace_one_ff(T, x[r], y[r], dx[r], dy[r], dz[r], lam[r]);
+        o = trace_one<kMode>(T, x[r], y[r], dx[r], dy[r], dz[r], lam[r]);
         valid = o.valid;
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -113,8 +111,9 @@ extern "C" lt_status lt_trace_compact(lt_lens lens, const lt_path *path, const l
         return fail(LT_ERR_ARG, "NULL lens, path, rays, out or count");
     if (n < 0)
         return fail(LT_ERR_ARG, "negative ray count");
-    if (flags & ~static_cast<uint32_t>(LT_TRACE_PLAIN_FP32 | LT_TRACE_FORWARD))
-        return fail(LT_ERR_ARG, "unknown trace flag");
+    if ((flags & ~static_cast<uint32_t>(LT_TRACE_PLAIN_FP32 | LT_TRACE_FORWARD | LT_TRACE_FP64)) ||
+        trace_mode(flags) < 0)
+        return fail(LT_ERR_ARG, "unknown or contradictory trace flags");
     TraceTable table;
     lt_status st = build_trace_table(*L, *path, (flags & LT_TRACE_FORWARD) != 0, &table);
     if (st != LT_OK)
@@ -134,7 +133,10 @@ extern "C" lt_status lt_trace_compact(lt_lens lens, const lt_path *path, const l
     st = check_hip(hipGetLastError(), "zero_count_kernel launch");
     if (st != LT_OK || n == 0)
         return st;
-    auto kern = (flags & LT_TRACE_PLAIN_FP32) ? trace_compact_kernel<true> : trace_compact_kernel<false>;
+    const int mode = trace_mode(flags);
+    auto kern = mode == kTracePlain ? trace_compact_kernel<kTracePlain>
+              : mode == kTraceF64   ? trace_compact_kernel<kTraceF64>
+                                    : trace_compact_kernel<kTraceFF>;
     hipLaunchKernelGGL(kern, dim3(static_cast<uint32_t>(blocks)), dim3(kTraceBlock), 0, s, table,
                        rays->x, rays->y, rays->dx, rays->dy, rays->dz, rays->lambda_nm, out->x, out->y,
                        out->dx, out->dy, out->dz, out->throughput, idx_out, count, n);
@@ -149,8 +151,9 @@ extern "C" lt_status lt_trace_ex(lt_lens lens, const lt_path *path, const lt_ray
         return fail(LT_ERR_ARG, "NULL lens, path, rays or out");
     if (n < 0)
         return fail(LT_ERR_ARG, "negative ray count");
-    if (flags & ~static_cast<uint32_t>(LT_TRACE_PLAIN_FP32 | LT_TRACE_FORWARD))
-        return fail(LT_ERR_ARG, "unknown trace flag");
+    if ((flags & ~static_cast<uint32_t>(LT_TRACE_PLAIN_FP32 | LT_TRACE_FORWARD | LT_TRACE_FP64)) ||
+        trace_mode(flags) < 0)
+        return fail(LT_ERR_ARG, "unknown or contradictory trace flags");
     TraceTable table;
     lt_status st = build_trace_table(*L, *path, (flags & LT_TRACE_FORWARD) != 0, &table);
     if (st != LT_OK)
@@ -165,7 +168,10 @@ extern "C" lt_status lt_trace_ex(lt_lens lens, const lt_path *path, const lt_ray
     if (blocks > 0x7fffffffLL)
         return fail(LT_ERR_ARG, "too many rays for one launch");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    auto kern = (flags & LT_TRACE_PLAIN_FP32) ? trace_kernel<true> : trace_kernel<false>;
+    const int mode = trace_mode(flags);
+    auto kern = mode == kTracePlain ? trace_kernel<kTracePlain>
+              : mode == kTraceF64   ? trace_kernel<kTraceF64>
+                                    : trace_kernel<kTraceFF>;
     hipLaunchKernelGGL(kern, dim3(static_cast<uint32_t>(blocks)), dim3(kTraceBlock), 0, s, table,
                        rays->x, rays->y, rays->dx, rays->dy, rays->dz, rays->lambda_nm, out->mask,
                        out->x, out->y, out->dx, out->dy, out->dz, out->throughput, n);

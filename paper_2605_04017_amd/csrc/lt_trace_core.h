@@ -3,20 +3,26 @@
 // __host__ __device__ functions so the arithmetic can be inspected on the CPU;
 // the product runs them only inside the HIP kernels of lt_trace.hip.
 //
-// Two variants:
-//   trace_one_ff   -- the library's tracer.  Geometry (positions, directions,
-//                     normals, refractive indices, cosines) is carried as
-//                     float pairs (lt_ff.h), so the FP32 instruction stream
-//                     keeps about 44 bits; each hit is refined by one Newton
-//                     step on the sphere equation.  Fresnel factors are plain
-//                     FP32.  Sensor-side rays leave a camera lens nearly
-//                     collimated, so exit positions are about EFL-times more
-//                     sensitive to direction errors near the sensor; plain
-//                     FP32 rounding there already costs ~1e-5 mm.
+// Three variants:
+//   trace_one_ff   -- the library's tracer, FP32 instructions only.  Geometry
+//                     (positions, directions, normals, refractive indices,
+//                     cosines) is carried as float pairs (lt_ff.h), so the
+//                     instruction stream keeps about 44 bits; each hit is
+//                     refined by one Newton step on the sphere equation.
+//                     Fresnel factors are plain FP32.  Sensor-side rays leave
+//                     a camera lens nearly collimated, so exit positions are
+//                     about EFL-times more sensitive to direction errors near
+//                     the sensor; plain FP32 rounding there already costs
+//                     ~1e-5 mm.
 //   trace_one_fast -- the same operators in plain FP32 (one rounding per
 //                     operation), with FP64 only for the discriminant of
 //                     near-flat surfaces and the transmitted cosine near
 //                     grazing incidence.
+//   trace_one_f64  -- the same operators in FP64, an option outside the
+//                     FP32 form of the tracer: gfx950 runs FP64 vector
+//                     arithmetic at half its FP32 rate, so this takes about
+//                     half the float-pair variant's time and returns the
+//                     FP32 roundings of FP64 results.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -368,6 +374,182 @@ __host__ __device__ __forceinline__ RayOut trace_one_fast(const TraceTable &T, f
     o.I = I;
     o.valid = true;
     return o;
+}
+
+// ----------------------------------------------------------------- FP64 --
+
+__host__ __device__ __forceinline__ double glass_n_d(const GlassF &g, double l2, double il2)
+{
+    auto k = [&](int m) { return static_cast<double>(g.k[2 * m]) + static_cast<double>(g.k[2 * m + 1]); };
+    if (g.kind == 1)
+        return k(0) + il2 * (k(1) + il2 * k(2));
+    if (g.kind == 2) {
+        double s = 1.0;
+        s += k(0) * l2 / (l2 - k(3));
+        s += k(1) * l2 / (l2 - k(4));
+        s += k(2) * l2 / (l2 - k(5));
+        return sqrt(s);
+    }
+    return 1.0;
+}
+
+// smallest admissible root of the sphere equation (vertex hemisphere,
+// t0 + t > 0), as sphere_root but in FP64 (the second root is qd / c: the
+// table's FP32 radius would cost 24 bits here)
+__host__ __device__ __forceinline__ double sphere_root_d(double B, double E, double c, double pz,
+                                                       double dz, double t0)
+{
+    const double disc = B * B - c * E;
+    if (!(disc >= 0.0))
+        return INFINITY;
+    const double sq = sqrt(disc);
+    const double qd = -B - (B >= 0.0 ? sq : -sq);
+    double t = INFINITY;
+    if (qd != 0.0) {
+        const double ta = E / qd;
+        if (t0 + ta > 0.0 && c * (pz + ta * dz) < 1.0)
+            t = ta;
+    }
+    if (c != 0.0) {
+        const double tb = qd / c;
+        if (t0 + tb > 0.0 && tb < t && c * (pz + tb * dz) < 1.0)
+            t = tb;
+    }
+    return t;
+}
+
+__host__ __device__ __forceinline__ RayOut trace_one_f64(const TraceTable &T, float x, float y,
+                                                         float dx0, float dy0, float dz0,
+                                                         float lam_nm)
+{
+    RayOut o;
+    o.valid = false;
+    double dx = dx0, dy = dy0, dz = dz0;
+    {
+        const double inv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+        dx *= inv;
+        dy *= inv;
+        dz *= inv;
+    }
+    const double lum = static_cast<double>(lam_nm) / 1000.0;
+    const double l2 = lum * lum;
+    const double il2 = 1.0 / l2;
+    double ncur = T.glass_start == kAirCode ? 1.0 : glass_n_d(T.glass[T.glass_start], l2, il2);
+    double px = x, py = y, pz = 0.0;
+    double I = 1.0;
+    const int nsteps = T.nsteps;
+    for (int s = 0; s < nsteps; ++s) {
+        const StepGeom G = T.geom[s];
+        const uint32_t code = T.code[s];
+        const int type = code & 0xF;
+        const uint32_t g2 = (code >> 4) & 0xFF;
+        pz += static_cast<double>(G.zs_h) + static_cast<double>(G.zs_l);
+        const double c = static_cast<double>(G.c_h) + static_cast<double>(G.c_l);
+        // slide the point along the ray to the vertex tangent plane first, so
+        // the long transfer does not enter the root
+        double t0 = 0.0;
+        if (fabs(dz) > 1.0e-3) {
+            t0 = -pz / dz;
+            px += t0 * dx;
+            py += t0 * dy;
+            pz += t0 * dz;
+        }
+        const double od = px * dx + py * dy + pz * dz;
+        const double oo = px * px + py * py + pz * pz;
+        const double B = c * od - dz;
+        const double E = c * oo - 2.0 * pz;
+        const double t = sphere_root_d(B, E, c, pz, dz, t0);
+        if (!(t < INFINITY))
+            return o;
+        const double qx = px + t * dx, qy = py + t * dy, qz = pz + t * dz;
+        const double sd2 = static_cast<double>(G.sd2_h) + static_cast<double>(G.sd2_l);
+        if (!(qx * qx + qy * qy <= sd2))  // also rejects NaN
+            return o;
+        px = qx;
+        py = qy;
+        pz = qz;
+        if (type == kStepStop)
+            continue;
+        double nx = c * qx, ny = c * qy, nz = c * qz - 1.0;
+        double dn = nx * dx + ny * dy + nz * dz;
+        if (dn > 0.0) {
+            nx = -nx;
+            ny = -ny;
+            nz = -nz;
+            dn = -dn;
+        }
+        const double ci = -dn;
+        const double n2 = g2 == kAirCode ? 1.0 : glass_n_d(T.glass[g2], l2, il2);
+        const double n1 = ncur;
+        const double eta = n1 / n2;
+        const double k = 1.0 - eta * eta * (1.0 - ci) * (1.0 + ci);
+        const bool tir = k < 0.0;
+        const double ct = tir ? 0.0 : sqrt(k);
+        const double a1 = n1 * ci, b2 = n2 * ct;
+        const double a2 = n2 * ci, b1 = n1 * ct;
+        if (type == kStepT) {
+            if (tir)
+                return o;
+            const double a = eta * ci - ct;
+            dx = eta * dx + a * nx;
+            dy = eta * dy + a * ny;
+            dz = eta * dz + a * nz;
+            const double ss = a1 + b2, pp = a2 + b1;
+            I *= 2.0 * (a1 * b2 / (ss * ss) + a2 * b1 / (pp * pp));
+            ncur = n2;
+        } else {
+            const double a = 2.0 * ci;
+            dx += a * nx;
+            dy += a * ny;
+            dz += a * nz;
+            double R = 1.0;
+            if (!tir) {
+                const double rs = (a1 - b2) / (a1 + b2);
+                const double rp = (a2 - b1) / (a2 + b1);
+                R = 0.5 * (rs * rs + rp * rp);
+            }
+            I *= R;
+        }
+        const double inv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+        dx *= inv;
+        dy *= inv;
+        dz *= inv;
+    }
+    if (!(dz * T.exit_dir > 0.0))
+        return o;
+    const double ze = static_cast<double>(T.z_exit_h) + static_cast<double>(T.z_exit_l);
+    const double t = (ze - pz) / dz;
+    o.x = static_cast<float>(px + t * dx);
+    o.y = static_cast<float>(py + t * dy);
+    o.dx = static_cast<float>(dx);
+    o.dy = static_cast<float>(dy);
+    o.dz = static_cast<float>(dz);
+    o.I = static_cast<float>(I);
+    o.valid = true;
+    return o;
+}
+
+// ------------------------------------------------------------- dispatch --
+
+constexpr int kTraceFF = 0, kTracePlain = 1, kTraceF64 = 2;
+
+template <int kMode>
+__host__ __device__ __forceinline__ RayOut trace_one(const TraceTable &T, float x, float y, float dx,
+                                                     float dy, float dz, float lam_nm)
+{
+    if constexpr (kMode == kTracePlain)
+        return trace_one_fast(T, x, y, dx, dy, dz, lam_nm);
+    else if constexpr (kMode == kTraceF64)
+        return trace_one_f64(T, x, y, dx, dy, dz, lam_nm);
+    else
+        return trace_one_ff(T, x, y, dx, dy, dz, lam_nm);
+}
+
+// arithmetic variant selected by the LT_TRACE_* flags (-1 if contradictory)
+inline int trace_mode(uint32_t flags)
+{
+    const bool plain = (flags & LT_TRACE_PLAIN_FP32) != 0, f64 = (flags & LT_TRACE_FP64) != 0;
+    return plain && f64 ? -1 : f64 ? kTraceF64 : plain ? kTracePlain : kTraceFF;
 }
 
 }  // namespace lt

@@ -204,3 +204,14 @@ def test_mcmc_argument_errors_without_gpu():
     rg = N.lt_raygen(1, 0, 18.0, 12.0, 400.0, 700.0, 2)
     b = N.lt_ray_buffers()
     assert L.lt_rays_generate(h.handle, C.byref(rg), C.byref(b), 0, None) == N.LT_ERR_ARG
+
+
+def test_contradictory_trace_flags_rejected_without_gpu():
+    L = N.lib()
+    lens = synth.config_lens(1)
+    h = lt.lt_lens_create(lens.surfaces, lens.glasses)
+    p = N.lt_path(0, 0, 0)
+    rays, ex = N.lt_rays(), N.lt_exit()
+    both = N.LT_TRACE_FP64 | N.LT_TRACE_PLAIN_FP32
+    assert L.lt_trace_ex(h.handle, C.byref(p), C.byref(rays), C.byref(ex), 0, both, None) == N.LT_ERR_ARG
+    assert L.lt_trace_ex(h.handle, C.byref(p), C.byref(rays), C.byref(ex), 0, N.LT_TRACE_FP64, None) == N.LT_OK
