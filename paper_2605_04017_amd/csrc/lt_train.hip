@@ -3,7 +3,7 @@
 // and its regressor with a regression loss on valid samples, Sec. 5.1 "MLP
 // Training"; Adam per Kingma and Ba).
 //
-// A step runs five kernels on one stream:
+// A step runs six kernels on one stream:
 //   forward (lt_map.hip, TRAIN variant): stores normalised inputs, every
 //       hidden layer's BF16 activations as MFMA B fragments, raw outputs;
 //   loss_kernel: BCE on the logit + masked squared error on the normalised
@@ -12,9 +12,11 @@
 //       kept in registers (the same K permutation as the forward makes the
 //       FP32 result of one layer the BF16 B operand of the next), W^T images
 //       staged in LDS; stores the BF16 gradients as fragments;
-//   dw_kernel: weight gradients sum_r delta_r h_r^T over a slice of the
-//       batch, transposing fragments through LDS; the bias gradient comes from
-//       an extra all-ones column; one partial per slice (deterministic);
+//   dw_hidden_kernel / dw_kernel: weight gradients sum_r delta_r h_r^T over
+//       a slice of the batch (hidden layers of width 64 and 128 / the input
+//       and output layers and width 32), the fragments transposed into LDS
+//       rows by selector MFMAs; the bias gradient comes from an extra all-ones
+//       column; one partial per slice (deterministic, 128 slices);
 //   reduce_adam_kernel: sums the slice partials and applies Adam to the FP32
 //       master parameters.
 #include <hip/hip_runtime.h>
@@ -34,10 +36,12 @@ struct WsLayout {
     int64_t xhat = 0, hfrag = 0, dfrag = 0, o = 0, dout = 0, partial = 0, loss = 0, canon = 0, bytes = 0;
 };
 
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
 constexpr int kDwChunk = 64;     // rays per LDS chunk in dw_kernel
 constexpr int kDwPad = 8;        // bf16 padding per LDS row (bank skew)
 constexpr int kDwTilesPerWave = 16;
-constexpr int kMaxSlices = 64;
+constexpr int kMaxSlices = 128;
 constexpr int kLossBlock = 256;
 
 static int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
@@ -358,6 +362,11 @@ __global__ __launch_bounds__(256) void dw_kernel(DwArgs A)
     const int group = blockIdx.y;
     const int slice = blockIdx.z;
     const bool is_out = layer == L.D, is_in = layer == 0;
+    if constexpr (H >= 64) {
+        // hidden layers go to dw_hidden_kernel
+        if (!is_out && !is_in)
+            return;
+    }
     const int m_tiles = is_out ? L.TO : T;
     const int n_tiles = is_in ? 1 : T + 1;
     const int total = m_tiles * n_tiles;
@@ -377,6 +386,32 @@ __global__ __launch_bounds__(256) void dw_kernel(DwArgs A)
     const int64_t tiles16 = A.n_pad / 16;
     const bf16x8 *hf = reinterpret_cast<const bf16x8 *>(A.hfrag);
     const bf16x8 *df = reinterpret_cast<const bf16x8 *>(A.dfrag);
+    // fragments (16 rays x 32 features) of one chunk into rows[feature][ray]
+    // by two selector MFMAs each (see dw_hidden_kernel); wave w takes
+    // fragments w, w + 4, ...
+    bf16x8 sel[2];
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj)
+            sel[s2][jj] = to_bf16(perm32(8 * g + jj) == 16 * s2 + col ? 1.0f : 0.0f);
+    auto transpose_frags = [&](const bf16x8 *src, int src_layer, int64_t ray0, __bf16 *rows) {
+        const floatx4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            const int fidx = wave + 4 * q;
+            const int c = fidx % C, t16 = fidx / C;
+            const bf16x8 v = src[((static_cast<int64_t>(src_layer) * tiles16 + ray0 / 16 + t16) * C + c) * 64 + lane];
+#pragma unroll
+            for (int s2 = 0; s2 < 2; ++s2) {
+                const floatx4 tv = mfma_bf16(v, sel[s2], zero);
+                const floatx2 p01 = {tv[0], tv[1]}, p23 = {tv[2], tv[3]};
+                const bf16x2 a0 = __builtin_convertvector(p01, bf16x2), a1 = __builtin_convertvector(p23, bf16x2);
+                *reinterpret_cast<bf16x4 *>(rows + (32 * c + 16 * s2 + col) * RS + t16 * 16 + 4 * g) =
+                    bf16x4{a0[0], a0[1], a1[0], a1[1]};
+            }
+        }
+    };
 
     const int64_t c0 = slice * A.chunks_per_slice;
     int64_t c1 = c0 + A.chunks_per_slice;
@@ -400,15 +435,7 @@ __global__ __launch_bounds__(256) void dw_kernel(DwArgs A)
             }
         } else {
             // delta_{layer+1} fragments
-            for (int e = threadIdx.x; e < 4 * C * 64; e += blockDim.x) {
-                const int ln = e & 63, c = (e >> 6) % C, t16 = (e >> 6) / C;
-                const int64_t fi = ((static_cast<int64_t>(layer) * tiles16 + ray0 / 16 + t16) * C + c) * 64 + ln;
-                const bf16x8 v = df[fi];
-                const int gg = ln >> 4, rr = t16 * 16 + (ln & 15);
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    dl[(32 * c + perm32(8 * gg + j)) * RS + rr] = v[j];
-            }
+            transpose_frags(df, layer, ray0, dl);
         }
         // --- inputs of the layer into hl[col][ray], plus the all-ones column
         if (is_in) {
@@ -426,15 +453,7 @@ __global__ __launch_bounds__(256) void dw_kernel(DwArgs A)
                 hl[k * RS + rr] = to_bf16(v);
             }
         } else {
-            for (int e = threadIdx.x; e < 4 * C * 64; e += blockDim.x) {
-                const int ln = e & 63, c = (e >> 6) % C, t16 = (e >> 6) / C;
-                const int64_t fi = ((static_cast<int64_t>(layer - 1) * tiles16 + ray0 / 16 + t16) * C + c) * 64 + ln;
-                const bf16x8 v = hf[fi];
-                const int gg = ln >> 4, rr = t16 * 16 + (ln & 15);
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    hl[(32 * c + perm32(8 * gg + j)) * RS + rr] = v[j];
-            }
+            transpose_frags(hf, layer - 1, ray0, hl);
             for (int e = threadIdx.x; e < 16 * kDwChunk; e += blockDim.x) {
                 const int k = e / kDwChunk, rr = e % kDwChunk;
                 hl[(H + k) * RS + rr] = to_bf16(k == 0 ? 1.0f : 0.0f);
@@ -592,6 +611,124 @@ static lt_status launch_bwd(const BwdArgs &A, hipStream_t s)
     return check_hip(hipGetLastError(), "bwd_kernel launch");
 }
 
+// Weight gradients of the hidden layers (width 64 or 128): a workgroup of
+// four waves takes one layer and one slice of the batch; wave w owns M-tiles
+// [w T/4, (w + 1) T/4) against all T + 1 N-tiles (the last N-tile carries
+// the bias column), so per K step each operand is read from LDS once.  Each
+// wave owns C of a 64-ray chunk's 4C fragments (16 rays x 32 features) of
+// the deltas and of the activations, loaded one chunk ahead; a fragment is
+// transposed by two MFMAs against 0/1 selector operands: as the A operand
+// (rows = rays, K = its permuted features) times the selector of features
+// 16s..16s+15, it yields in each lane 4 consecutive rays of one feature,
+// stored with one 8-byte LDS write (exact: one nonzero product per output,
+// BF16 values round-trip through FP32).
+template <int H>
+__global__ __launch_bounds__(256) void dw_hidden_kernel(DwArgs A)
+{
+    constexpr int T = H / 16, C = H / 32, MT = T / 4;
+    constexpr int RS = kDwChunk + kDwPad;
+    static_assert(MT >= 1, "four waves share the M-tiles");
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    const MapLayout &L = A.L;
+    const int layer = blockIdx.x + 1;
+    const int slice = blockIdx.y;
+    __bf16 *dl = reinterpret_cast<__bf16 *>(lds);
+    __bf16 *hl = dl + static_cast<int64_t>(H) * RS;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, col = lane & 15;
+    const int64_t tiles16 = A.n_pad / 16;
+    const bf16x8 *hf = reinterpret_cast<const bf16x8 *>(A.hfrag);
+    const bf16x8 *df = reinterpret_cast<const bf16x8 *>(A.dfrag);
+    floatx4 acc[MT][T + 1];
+#pragma unroll
+    for (int mi = 0; mi < MT; ++mi)
+#pragma unroll
+        for (int nn = 0; nn <= T; ++nn)
+            acc[mi][nn] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int64_t c0 = slice * A.chunks_per_slice;
+    int64_t c1 = c0 + A.chunks_per_slice;
+    if (c1 > A.n_chunks)
+        c1 = A.n_chunks;
+    bf16x8 dv[C], hv[C];
+    auto load_frags = [&](int64_t ray0) {
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            const int fidx = wave + 4 * q;   // fragment (t16, c) of the chunk
+            const int c = fidx % C, t16 = fidx / C;
+            const int64_t base = (ray0 / 16 + t16) * C + c;
+            dv[q] = df[((static_cast<int64_t>(layer) * tiles16) * C + base) * 64 + lane];
+            hv[q] = hf[((static_cast<int64_t>(layer - 1) * tiles16) * C + base) * 64 + lane];
+        }
+    };
+    bf16x8 sel[2];
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj)
+            sel[s2][jj] = to_bf16(perm32(8 * g + jj) == 16 * s2 + col ? 1.0f : 0.0f);
+    // the all-ones column (bias gradient) and its zero padding never change
+    for (int e = threadIdx.x; e < 16 * kDwChunk; e += blockDim.x) {
+        const int k = e / kDwChunk, rr = e % kDwChunk;
+        hl[(H + k) * RS + rr] = to_bf16(k == 0 ? 1.0f : 0.0f);
+    }
+    if (c0 < c1)
+        load_frags(c0 * kDwChunk);
+    const floatx4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int64_t ch = c0; ch < c1; ++ch) {
+        const int64_t ray0 = ch * kDwChunk;
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            const int fidx = wave + 4 * q;
+            const int c = fidx % C, t16 = fidx / C;
+#pragma unroll
+            for (int s2 = 0; s2 < 2; ++s2) {
+                const floatx4 td = mfma_bf16(dv[q], sel[s2], zero);
+                const floatx4 th = mfma_bf16(hv[q], sel[s2], zero);
+                const int off = (32 * c + 16 * s2 + col) * RS + t16 * 16 + 4 * g;
+                const floatx2 d01 = {td[0], td[1]}, d23 = {td[2], td[3]};
+                const floatx2 h01 = {th[0], th[1]}, h23 = {th[2], th[3]};
+                const bf16x2 a0 = __builtin_convertvector(d01, bf16x2), a1 = __builtin_convertvector(d23, bf16x2);
+                const bf16x2 b0 = __builtin_convertvector(h01, bf16x2), b1 = __builtin_convertvector(h23, bf16x2);
+                *reinterpret_cast<bf16x4 *>(dl + off) = bf16x4{a0[0], a0[1], a1[0], a1[1]};
+                *reinterpret_cast<bf16x4 *>(hl + off) = bf16x4{b0[0], b0[1], b1[0], b1[1]};
+            }
+        }
+        __syncthreads();
+        if (ch + 1 < c1)
+            load_frags(ray0 + kDwChunk);
+#pragma unroll
+        for (int ks = 0; ks < kDwChunk / 32; ++ks) {
+            bf16x8 av[MT];
+#pragma unroll
+            for (int mi = 0; mi < MT; ++mi)
+                av[mi] = *reinterpret_cast<const bf16x8 *>(dl + ((wave * MT + mi) * 16 + col) * RS + ks * 32 + 8 * g);
+#pragma unroll
+            for (int nn = 0; nn <= T; ++nn) {
+                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(hl + (nn * 16 + col) * RS + ks * 32 + 8 * g);
+#pragma unroll
+                for (int mi = 0; mi < MT; ++mi)
+                    acc[mi][nn] = mfma_bf16(av[mi], bv, acc[mi][nn]);
+            }
+        }
+        __syncthreads();
+    }
+    float *out = A.partial + static_cast<int64_t>(slice) * L.n_params;
+#pragma unroll
+    for (int mi = 0; mi < MT; ++mi)
+#pragma unroll
+        for (int nn = 0; nn <= T; ++nn) {
+            const int n = nn * 16 + col;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int m = (wave * MT + mi) * 16 + 4 * g + i;
+                if (n < H)
+                    out[L.w_off[layer] + static_cast<int64_t>(m) * H + n] = acc[mi][nn][i];
+                else if (n == H)
+                    out[L.b_off[layer] + m] = acc[mi][nn][i];
+            }
+        }
+}
+
 template <int H>
 static lt_status launch_dw(const DwArgs &A, const WsLayout &w, hipStream_t s)
 {
@@ -621,7 +758,16 @@ static lt_status launch_dw(const DwArgs &A, const WsLayout &w, hipStream_t s)
         return fail(LT_ERR_ARG, "too many heads for the weight-gradient kernel");
     hipLaunchKernelGGL(kern, dim3(L.D + 1, max_groups, static_cast<uint32_t>(w.slices)), dim3(256),
                        lds, s, A);
-    return check_hip(hipGetLastError(), "dw_kernel launch");
+    lt_status st = check_hip(hipGetLastError(), "dw_kernel launch");
+    if constexpr (H >= 64) {
+        if (st == LT_OK && L.D > 1) {
+            const size_t lds_h = static_cast<size_t>(2 * H + 16) * (kDwChunk + kDwPad) * 2;
+            hipLaunchKernelGGL(dw_hidden_kernel<H>, dim3(L.D - 1, static_cast<uint32_t>(w.slices)), dim3(256),
+                               lds_h, s, A);
+            st = check_hip(hipGetLastError(), "dw_hidden_kernel launch");
+        }
+    }
+    return st;
 }
 
 static lt_status ensure_packed_wt(Map &M, hipStream_t s)
