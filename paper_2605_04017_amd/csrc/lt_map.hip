@@ -2,8 +2,9 @@
 // network evaluated with MFMA (Sec. 4.2 of the paper; the paper fuses its
 // MLPs into the rendering kernels, Sec. 5.1 "Inference").
 //
-// Data layout.  Rays are the N dimension of every MFMA tile: a wave holds 64
-// rays as four 16-ray tiles, and a layer's weights are the A operand.  The
+// Data layout.  Rays are the N dimension of every MFMA tile: a wave holds its
+// rays as 16-ray tiles (two for evaluation at width 128, four otherwise), and
+// a layer's weights are the A operand.  The
 // output D of v_mfma_f32_16x16x32_bf16 leaves lane l with rows 4*(l/16)+i of
 // its M-tile for ray l%16; two M-tiles give exactly the eight values that
 // lane must supply as the B operand of the next layer if the next layer's K
@@ -12,7 +13,7 @@
 // into the packed weights, so activations never leave registers.  All packed
 // weights, biases and normalisation constants are staged once per workgroup
 // in LDS (147 KiB for 5 x 128 with one head) and each A fragment read from
-// LDS feeds four MFMAs (one per ray tile).
+// LDS feeds one MFMA per ray tile.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
