@@ -590,6 +590,74 @@ lt_status lt_splat(const float *x, const float *y, const float *dz, const float 
                    const uint8_t *mask, int64_t n, int64_t n_per_image, const lt_sensor *sensor,
                    float scale, float *images, void *stream);
 
+/* ------------------------------------------------------------ serving */
+
+/* Continuous batching of ray queries against resident lenses and maps (the
+ * paper's inference at request scale, Sec. 5.1: many independent ray
+ * batches per frame).  A server owns n_streams HIP streams (default
+ * priority).  Requests are admitted in submission order while the bytes they
+ * account for (n * bytes_per_ray each) fit mem_budget; an admitted request
+ * is split into chunks of `chunk` rays, and each poll launches chunks on free
+ * streams, round-robin over the admitted requests that still have chunks, so
+ * requests that arrive while others run overlap with them on the device and
+ * short requests do not wait behind long ones.  Each ray is evaluated by the
+ * same kernel as a direct lt_map_eval / lt_trace call, so a result does not
+ * depend on what else is in flight.
+ * The server has no thread of its own: the caller drives it with
+ * lt_server_poll, from one thread.  Inputs and outputs are the caller's
+ * device buffers; they must stay valid, and maps and lenses unchanged, until
+ * the request is reported done. */
+typedef struct lt_server_s *lt_server;
+
+typedef struct {
+    int32_t n_streams;      /* concurrent launches, 1..16 */
+    int64_t chunk;          /* rays per launch, >= 1 (requests on multi-head maps run whole:
+                               their head-major outputs keep the request's own stride) */
+    int64_t mem_budget;     /* bytes of admitted, unfinished requests, >= 1 */
+    int64_t bytes_per_ray;  /* bytes accounted per ray of a request, >= 0 */
+} lt_server_cfg;
+
+/* A finished request. */
+typedef struct {
+    int64_t tag;            /* the tag given at submission */
+    double done_s;          /* device completion time of its last chunk, seconds after the
+                               server's start event (recorded and waited for by
+                               lt_server_create); 0 for n = 0 */
+    int32_t status;         /* LT_OK, or the first error of one of its launches */
+} lt_server_done;
+
+/* Create a server on the current device.  Errors: LT_ERR_ARG (NULL, n_streams
+ * outside 1..16, chunk or mem_budget < 1, bytes_per_ray < 0), LT_ERR_OOM,
+ * LT_ERR_DEVICE. */
+lt_status lt_server_create(const lt_server_cfg *cfg, lt_server *out);
+/* Wait for launched chunks, then free the streams and events; requests not
+ * yet finished are dropped.  NULL is a no-op. */
+lt_status lt_server_destroy(lt_server server);
+/* Queue an evaluation of map in dtype on n rays, written to out as
+ * lt_map_eval writes it.  The packed weights for dtype must be current
+ * (lt_map_quantize after the last parameter change), since the chunks of
+ * one map run on several streams.  Errors: LT_ERR_ARG (NULL, n < 0, n *
+ * bytes_per_ray above mem_budget: never admitted), LT_ERR_DTYPE,
+ * LT_ERR_STATE (packed weights not current), LT_ERR_OOM. */
+lt_status lt_server_submit_map(lt_server server, lt_map map, int32_t dtype, const lt_rays *rays,
+                               const lt_map_out *out, int64_t n, int64_t tag);
+/* Queue a trace of n rays along path (as lt_trace).  Errors: LT_ERR_ARG,
+ * LT_ERR_PATH, LT_ERR_OOM. */
+lt_status lt_server_submit_trace(lt_server server, lt_lens lens, const lt_path *path,
+                                 const lt_rays *rays, const lt_exit *out, int64_t n, int64_t tag);
+/* Progress without blocking: reap finished chunks (event queries), admit
+ * waiting requests, launch chunks on free streams.  Up to cap finished
+ * requests go to done (more stay queued for the next call); *n_done is their
+ * number and *n_open (may be NULL) the submitted requests not yet reported.
+ * A failed launch is reported in its request's status; the error return is
+ * for runtime failures of the loop itself.  Errors: LT_ERR_ARG (NULL server
+ * or n_done, cap < 0, NULL done with cap > 0), LT_ERR_DEVICE. */
+lt_status lt_server_poll(lt_server server, lt_server_done *done, int32_t cap, int32_t *n_done,
+                         int64_t *n_open);
+/* Largest accounted in-flight memory seen and the number of launches so far
+ * (either pointer may be NULL).  Errors: LT_ERR_ARG (NULL server). */
+lt_status lt_server_stats(lt_server server, int64_t *max_in_use_bytes, int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,6 +22,7 @@ LT_LAMBDA_UNIFORM, LT_LAMBDA_CIE = N.LT_LAMBDA_UNIFORM, N.LT_LAMBDA_CIE
 LT_F32, LT_BF16, LT_FP8 = N.LT_F32, N.LT_BF16, N.LT_FP8
 LT_ACT_TANH, LT_ACT_RELU = N.LT_ACT_TANH, N.LT_ACT_RELU
 MAP_FIELDS = ("logit", "mask", "x", "y", "dx", "dy", "dz", "throughput")
+LT_ERR_ARG, LT_ERR_STATE = N.LT_ERR_ARG, N.LT_ERR_STATE
 
 __all__ = ["LtError", "Lens", "lt_lens_create", "lt_lens_query", "lt_trace", "lt_trace_ex",
            "lt_ghost_index", "lt_ghost_path", "empty_exit", "RAY_FIELDS", "EXIT_FIELDS",
@@ -33,7 +34,7 @@ __all__ = ["LtError", "Lens", "lt_lens_create", "lt_lens_query", "lt_trace", "lt
            "lt_map_quantize", "lt_rays_generate", "lt_map_eval_ex", "LT_EVAL_MASK_ONLY",
            "lt_lens_planes", "LT_TRACE_FORWARD", "LT_TRACE_FP64", "lt_rays_generate_forward", "lt_splat",
            "LT_LAMBDA_UNIFORM", "LT_LAMBDA_CIE", "mcmc_state", "lt_mcmc_init", "lt_mcmc_run",
-           "LT_EVAL_GATED"]
+           "LT_EVAL_GATED", "Server", "LT_ERR_ARG", "LT_ERR_STATE"]
 
 TARGET_FIELDS = ("valid", "x", "y", "dx", "dy", "throughput")
 
@@ -477,6 +478,86 @@ def lt_map_eval(m: Map, dtype: int, rays: Dict, out: Optional[Dict] = None,
                 n: Optional[int] = None, stream=None) -> Dict:
     """Evaluate the map for ``n`` rays; outputs are (n_heads, n) tensors."""
     return lt_map_eval_ex(m, dtype, rays, out, n, 0, None, stream)
+
+
+# --------------------------------------------------------------- serving --
+
+class Server:
+    """Owned lt_server handle: the native continuous-batching request loop
+    (lt_server_* in include/lt.h).  Requests keep their tensors alive here
+    until they are reported done."""
+
+    def __init__(self, n_streams: int = 4, chunk: int = 262144, mem_budget: int = 4 << 30,
+                 bytes_per_ray: int = 64):
+        cfg = N.lt_server_cfg(int(n_streams), int(chunk), int(mem_budget), int(bytes_per_ray))
+        h = C.c_void_p()
+        N.check(N.lib().lt_server_create(C.byref(cfg), C.byref(h)))
+        self._h = h
+        self._keep = {}
+        self._done = (N.lt_server_done * 256)()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def submit_map(self, m: Map, dtype: int, rays: Dict, out: Dict, n: int, tag: int) -> None:
+        """Queue lt_map_eval(m, dtype) of n rays into ``out`` (an
+        empty_map_out(m.n_heads, n) dict); run lt_map_quantize(m, dtype) first."""
+        torch = _torch()
+        o = N.lt_map_out()
+        for k in MAP_FIELDS:
+            dt = torch.uint8 if k == "mask" else torch.float32
+            setattr(o, k, _dev_ptr(out[k], dt, m.n_heads * n, f"out[{k}]") if n else None)
+        N.check(N.lib().lt_server_submit_map(self._h, m.handle, int(dtype),
+                                             C.byref(_rays_struct(rays, n)), C.byref(o), int(n),
+                                             int(tag)))
+        self._keep[int(tag)] = (rays, out)
+
+    def submit_trace(self, lens: Lens, path, rays: Dict, out: Dict, n: int, tag: int) -> None:
+        """Queue lt_trace(lens, path) of n rays into ``out`` (an empty_exit(n) dict)."""
+        torch = _torch()
+        e = N.lt_exit()
+        for k in EXIT_FIELDS:
+            dt = torch.uint8 if k == "mask" else torch.float32
+            setattr(e, k, _dev_ptr(out[k], dt, n, f"out[{k}]") if n else None)
+        p = _path(path)
+        N.check(N.lib().lt_server_submit_trace(self._h, lens.handle, C.byref(p),
+                                               C.byref(_rays_struct(rays, n)), C.byref(e), int(n),
+                                               int(tag)))
+        self._keep[int(tag)] = (rays, out)
+
+    def poll(self):
+        """Advance the loop; returns ([(tag, done_s, status), ...], n_open)."""
+        res = []
+        n_open = C.c_int64()
+        while True:
+            k = C.c_int32()
+            N.check(N.lib().lt_server_poll(self._h, self._done, len(self._done), C.byref(k),
+                                           C.byref(n_open)))
+            for i in range(k.value):
+                d = self._done[i]
+                self._keep.pop(int(d.tag), None)
+                res.append((int(d.tag), float(d.done_s), int(d.status)))
+            if k.value < len(self._done):
+                return res, int(n_open.value)
+
+    def stats(self):
+        """(largest accounted in-flight bytes, launches so far)."""
+        a, b = C.c_int64(), C.c_int64()
+        N.check(N.lib().lt_server_stats(self._h, C.byref(a), C.byref(b)))
+        return int(a.value), int(b.value)
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            N.lib().lt_server_destroy(self._h)
+        self._h = None
+        self._keep = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 LT_EVAL_MASK_ONLY, LT_EVAL_GATED = 1, 2

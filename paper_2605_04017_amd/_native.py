@@ -98,6 +98,15 @@ class lt_train_cfg(C.Structure):
                 ("step", C.c_int64), ("w_bce", C.c_float), ("w_l2", C.c_float), ("w_cos", C.c_float)]
 
 
+class lt_server_cfg(C.Structure):
+    _fields_ = [("n_streams", C.c_int32), ("chunk", C.c_int64), ("mem_budget", C.c_int64),
+                ("bytes_per_ray", C.c_int64)]
+
+
+class lt_server_done(C.Structure):
+    _fields_ = [("tag", C.c_int64), ("done_s", C.c_double), ("status", C.c_int32)]
+
+
 LT_F32, LT_BF16, LT_FP8 = 0, 1, 2
 LT_ACT_TANH, LT_ACT_RELU = 0, 1
 
@@ -135,6 +144,16 @@ SIGNATURES = {
                               C.c_void_p]),
     "lt_splat": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                            C.c_int64, C.POINTER(lt_sensor), C.c_float, C.c_void_p, C.c_void_p]),
+    "lt_server_create": (C.c_int, [C.POINTER(lt_server_cfg), C.POINTER(C.c_void_p)]),
+    "lt_server_destroy": (C.c_int, [C.c_void_p]),
+    "lt_server_submit_map": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(lt_rays),
+                                       C.POINTER(lt_map_out), C.c_int64, C.c_int64]),
+    "lt_server_submit_trace": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(lt_path),
+                                         C.POINTER(lt_rays), C.POINTER(lt_exit), C.c_int64,
+                                         C.c_int64]),
+    "lt_server_poll": (C.c_int, [C.c_void_p, C.POINTER(lt_server_done), C.c_int32,
+                                 C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
+    "lt_server_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "lt_trace": (C.c_int, [C.c_void_p, C.POINTER(lt_path), C.POINTER(lt_rays),
                            C.POINTER(lt_exit), C.c_int64, C.c_void_p]),
     "lt_trace_ex": (C.c_int, [C.c_void_p, C.POINTER(lt_path), C.POINTER(lt_rays),

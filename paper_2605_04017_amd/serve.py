@@ -14,10 +14,13 @@ request larger than the whole budget is rejected); admitted requests feed
 chunks to free slots round-robin, so a long request does not block short
 ones behind it.
 
-The scheduler is independent of the GPU: it drives an executor with three
-operations (launch a chunk on a slot, ask whether a slot's work is done,
-read completion times).  `GpuExecutor` runs lt_map_eval / lt_trace on HIP
-streams; tests use a simulated executor.
+Two implementations share this policy.  `NativeScheduler` drives the
+native loop of liblt.so (lt_server_*: admission, chunking, stream slots and
+completion events in C++); it is what serving uses.  `Scheduler` is the same
+policy in Python over an executor with three operations (launch a chunk on a
+slot, ask whether a slot's work is done, read completion times):
+`GpuExecutor` runs lt_map_eval / lt_trace on HIP streams, and the policy
+tests use a simulated executor.
 """
 from __future__ import annotations
 
@@ -115,6 +118,56 @@ class Scheduler:
     @property
     def idle(self) -> bool:
         return not self.waiting and not self.active
+
+
+class NativeScheduler:
+    """The native request loop (lt_server_*) behind the interface run_trace
+    uses.  ``r.payload`` holds (rays, out): the request's device ray tensors
+    and its preallocated outputs (empty_map_out(1, n) or empty_exit(n)).
+    Completion times are device times after the server's start event, so the
+    clock to replay arrivals against is ``clock`` (host seconds since the
+    server was created)."""
+
+    def __init__(self, server, lenses, maps, mode: str = "map", dtype: int = 1,
+                 path=(0, 0, 0)):
+        self.server = server
+        self.t0 = time.perf_counter()
+        self.lenses, self.maps, self.mode, self.dtype, self.path = lenses, maps, mode, dtype, path
+        self.reqs: Dict[int, Request] = {}
+        self.finished: List[Request] = []
+        self.rejected: List[Request] = []
+
+    def clock(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def submit(self, r: Request):
+        import paper_2605_04017_amd as lt
+        rays, out = r.payload
+        try:
+            if self.mode == "map":
+                self.server.submit_map(self.maps[r.lens], self.dtype, rays, out, r.n, r.rid)
+            else:
+                self.server.submit_trace(self.lenses[r.lens], self.path, rays, out, r.n, r.rid)
+        except lt.LtError as e:
+            if e.status != lt.LT_ERR_ARG:
+                raise
+            r.rejected = True
+            self.rejected.append(r)
+            return
+        self.reqs[r.rid] = r
+
+    def step(self, now: float):
+        done, _ = self.server.poll()
+        for tag, done_s, status in done:
+            r = self.reqs.pop(tag)
+            if status != 0:
+                raise RuntimeError(f"request {tag} failed with status {status}")
+            r.done = done_s
+            self.finished.append(r)
+
+    @property
+    def idle(self) -> bool:
+        return not self.reqs
 
 
 def run_trace(sched: Scheduler, requests: List[Request], clock: Callable[[], float],

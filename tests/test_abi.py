@@ -215,3 +215,22 @@ def test_contradictory_trace_flags_rejected_without_gpu():
     both = N.LT_TRACE_FP64 | N.LT_TRACE_PLAIN_FP32
     assert L.lt_trace_ex(h.handle, C.byref(p), C.byref(rays), C.byref(ex), 0, both, None) == N.LT_ERR_ARG
     assert L.lt_trace_ex(h.handle, C.byref(p), C.byref(rays), C.byref(ex), 0, N.LT_TRACE_FP64, None) == N.LT_OK
+
+
+def test_server_argument_errors_without_gpu():
+    """The serving loop validates its configuration and handles before any
+    HIP call (no device here)."""
+    L = N.lib()
+    h = C.c_void_p()
+    for bad in ((0, 1, 1, 0), (17, 1, 1, 0), (4, 0, 1, 0), (4, 1, 0, 0), (4, 1, 1, -1)):
+        assert L.lt_server_create(C.byref(N.lt_server_cfg(*bad)), C.byref(h)) == N.LT_ERR_ARG
+        assert "LT_ERR_ARG" in L.lt_last_error().decode()
+    assert L.lt_server_create(None, C.byref(h)) == N.LT_ERR_ARG
+    assert L.lt_server_destroy(None) == N.LT_OK
+    k, n_open = C.c_int32(), C.c_int64()
+    assert L.lt_server_poll(None, None, 0, C.byref(k), C.byref(n_open)) == N.LT_ERR_ARG
+    assert L.lt_server_stats(None, None, None) == N.LT_ERR_ARG
+    rays, mo, ex, p = N.lt_rays(), N.lt_map_out(), N.lt_exit(), N.lt_path(0, 0, 0)
+    assert L.lt_server_submit_map(None, None, 1, C.byref(rays), C.byref(mo), 0, 0) == N.LT_ERR_ARG
+    assert L.lt_server_submit_trace(None, None, C.byref(p), C.byref(rays), C.byref(ex), 0,
+                                    0) == N.LT_ERR_ARG
