@@ -730,7 +730,8 @@ def traffic_probe(n=N_RAYS, dtype_name="f32"):
     """Short program for the counter runs: one plain copy of COPY_PROBE_BYTES
     (a negate kernel: reads and writes that many bytes), then three map
     launches in the given precision on the benchmark workload (random
-    weights: the kernels have no data-dependent control flow)."""
+    weights: the kernels have no data-dependent control flow), or with
+    "trace" three launches of each tracer variant on its transmit path."""
     import numpy as np
     import torch
     import paper_2605_04017_amd as lt
@@ -743,6 +744,17 @@ def traffic_probe(n=N_RAYS, dtype_name="f32"):
     torch.neg(src, out=dst)
     torch.cuda.synchronize()
     rays = {k: torch.from_numpy(v).to(dev) for k, v in synth.config_rays(2, n).items()}
+    if dtype_name == "trace":
+        # the three tracer variants on the transmit path, three launches each
+        h = lt.lt_lens_create(synth.config_lens(2).surfaces, synth.config_lens(2).glasses)
+        ex = lt.empty_exit(n, dev)
+        for flags in (0, lt.LT_TRACE_PLAIN_FP32, lt.LT_TRACE_FP64):
+            for _ in range(3):
+                lt.lt_trace_ex(h, (0, 0, 0), rays, ex, n, flags)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": "traffic", "kernel": "trace", "copy_bytes": COPY_PROBE_BYTES,
+                          "rays": n}), flush=True)
+        return
     p = mlp.init_params(mlp.MapDesc(MAP_WIDTH, MAP_DEPTH, 1, mlp.ACT_TANH), 5)
     m = lt.lt_map_create(MAP_WIDTH, MAP_DEPTH, 1, lt.LT_ACT_TANH)
     lt.lt_map_set_params(m, torch.from_numpy(p.flat().astype(np.float32)).to(dev))
@@ -770,7 +782,7 @@ def main():
     ap.add_argument("--no-flare", action="store_true")
     ap.add_argument("--no-sampler", action="store_true")
     ap.add_argument("--rays", type=int, default=N_RAYS)
-    ap.add_argument("--traffic-probe", nargs="?", const="f32", choices=("f32", "bf16", "fp8"),
+    ap.add_argument("--traffic-probe", nargs="?", const="f32", choices=("f32", "bf16", "fp8", "trace"),
                     help="only run the short program the counter runs profile (map precision)")
     args = ap.parse_args()
     if args.gpus != 1:
