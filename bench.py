@@ -893,6 +893,12 @@ def main():
                       "map_f32": t_map * 1e3, "map_bf16": t_bf16 * 1e3, "map_fp8": t_fp8 * 1e3,
                       "map_f32_canonical_input": t_map_c * 1e3},
         "map_error_vs_fp64_oracle": errors,
+        "paper_context": {
+            "reported": "rendering about 12-15x faster with the maps than with the ray-traced lens "
+                        "(depth-of-field path tracing in LuisaRender, per-path 32-wide tanh MLPs)",
+            "hardware_and_precision": "not stated in the paper",
+            "comparable_here": "multi_path_16M map_over_trace (all 56 paths, one trunk with 56 heads) "
+                               "and flare_forward frame_speedup_map_over_trace"},
         "fit": {"steps": args.fit_steps, "batch": 65536, "final_loss": fit_loss, "seconds": t_fit},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": MI355X_FP32_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / MI355X_FP32_MFMA_TFLOPS,
