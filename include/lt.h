@@ -636,13 +636,14 @@ lt_status lt_server_destroy(lt_server server);
 /* Queue an evaluation of map in dtype on n rays, written to out as
  * lt_map_eval writes it.  The packed weights for dtype must be current
  * (lt_map_quantize after the last parameter change), since the chunks of
- * one map run on several streams.  Errors: LT_ERR_ARG (NULL, n < 0, n *
- * bytes_per_ray above mem_budget: never admitted), LT_ERR_DTYPE,
+ * one map run on several streams.  Errors: LT_ERR_ARG (NULL handle or
+ * struct, a NULL ray or output field with n > 0, n < 0, n * bytes_per_ray
+ * above mem_budget: never admitted), LT_ERR_DTYPE,
  * LT_ERR_STATE (packed weights not current), LT_ERR_OOM. */
 lt_status lt_server_submit_map(lt_server server, lt_map map, int32_t dtype, const lt_rays *rays,
                                const lt_map_out *out, int64_t n, int64_t tag);
-/* Queue a trace of n rays along path (as lt_trace).  Errors: LT_ERR_ARG,
- * LT_ERR_PATH, LT_ERR_OOM. */
+/* Queue a trace of n rays along path (as lt_trace).  Errors: LT_ERR_ARG (as
+ * for lt_server_submit_map), LT_ERR_PATH, LT_ERR_OOM. */
 lt_status lt_server_submit_trace(lt_server server, lt_lens lens, const lt_path *path,
                                  const lt_rays *rays, const lt_exit *out, int64_t n, int64_t tag);
 /* Progress without blocking: reap finished chunks (event queries), admit

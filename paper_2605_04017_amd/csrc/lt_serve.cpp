@@ -66,6 +66,11 @@ T *at(T *p, int64_t k)
     return p ? p + k : p;
 }
 
+bool rays_set(const lt_rays &r)
+{
+    return r.x && r.y && r.dx && r.dy && r.dz && r.lambda_nm;
+}
+
 bool packed_current(const Map &M, int32_t dtype)
 {
     if (dtype == LT_F32)
@@ -255,6 +260,9 @@ lt_status lt_server_submit_map(lt_server server, lt_map map, int32_t dtype, cons
         return fail(LT_ERR_ARG, "negative ray count");
     if (dtype != LT_BF16 && dtype != LT_FP8 && dtype != LT_F32)
         return fail(LT_ERR_DTYPE, "precision not available (LT_F32, LT_BF16, LT_FP8)");
+    if (n > 0 && (!rays_set(*rays) || !out->logit || !out->mask || !out->x || !out->y || !out->dx ||
+                  !out->dy || !out->dz || !out->throughput))
+        return fail(LT_ERR_ARG, "NULL ray or output field");
     if (n > 0 && !packed_current(*M, dtype))
         return fail(LT_ERR_STATE, "run lt_map_quantize for this precision before submitting");
     Request *r = new (std::nothrow) Request;
@@ -282,6 +290,9 @@ lt_status lt_server_submit_trace(lt_server server, lt_lens lens, const lt_path *
         return fail(LT_ERR_ARG, "NULL server, lens, path, rays or out");
     if (n < 0)
         return fail(LT_ERR_ARG, "negative ray count");
+    if (n > 0 && (!rays_set(*rays) || !out->mask || !out->x || !out->y || !out->dx || !out->dy ||
+                  !out->dz || !out->throughput))
+        return fail(LT_ERR_ARG, "NULL ray or output field");
     TraceTable table;
     lt_status st = build_trace_table(*L, *path, false, &table);
     if (st != LT_OK)

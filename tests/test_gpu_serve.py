@@ -180,3 +180,25 @@ def test_native_multi_head_map_and_stale_weights():
         srv.submit_map(m, lt.LT_BF16, rays, out, reqs[1].n, 7)
     assert e.value.status == lt.LT_ERR_STATE
     srv.close()
+
+
+def test_native_submit_rejects_missing_fields():
+    """Submission checks ray and output pointers on the host (LT_ERR_ARG),
+    so a bad request never reaches a launch."""
+    import torch
+    import paper_2605_04017_amd as lt
+    from paper_2605_04017_amd import _native as N
+    import ctypes as C
+    dev = torch.device("cuda:0")
+    L = synth.serve_lenses()[0]
+    h = lt.lt_lens_create(L.surfaces, L.glasses)
+    srv = lt.Server(1, chunk=1024, mem_budget=1 << 20, bytes_per_ray=1)
+    rays, ex, p = N.lt_rays(), N.lt_exit(), N.lt_path(0, 0, 0)
+    st = N.lib().lt_server_submit_trace(srv.handle, h.handle, C.byref(p), C.byref(rays), C.byref(ex), 16, 1)
+    assert st == N.LT_ERR_ARG
+    assert N.lib().lt_server_submit_trace(srv.handle, h.handle, C.byref(p), C.byref(rays), C.byref(ex), 0,
+                                          2) == N.LT_OK
+    done, n_open = srv.poll()
+    assert [d[0] for d in done] == [2] and n_open == 0
+    srv.close()
+    torch.cuda.synchronize()
