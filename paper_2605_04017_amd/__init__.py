@@ -500,31 +500,46 @@ class Server:
     def handle(self):
         return self._h
 
-    def submit_map(self, m: Map, dtype: int, rays: Dict, out: Dict, n: int, tag: int) -> None:
-        """Queue lt_map_eval(m, dtype) of n rays into ``out`` (an
-        empty_map_out(m.n_heads, n) dict); run lt_map_quantize(m, dtype) first."""
+    @staticmethod
+    def prepare_map(m: Map, dtype: int, rays: Dict, out: Dict, n: int):
+        """Marshal a map request once (the arguments of lt_server_submit_map);
+        ``out`` is an empty_map_out(m.n_heads, n) dict."""
         torch = _torch()
         o = N.lt_map_out()
         for k in MAP_FIELDS:
             dt = torch.uint8 if k == "mask" else torch.float32
             setattr(o, k, _dev_ptr(out[k], dt, m.n_heads * n, f"out[{k}]") if n else None)
-        N.check(N.lib().lt_server_submit_map(self._h, m.handle, int(dtype),
-                                             C.byref(_rays_struct(rays, n)), C.byref(o), int(n),
-                                             int(tag)))
-        self._keep[int(tag)] = (rays, out)
+        return ("map", m.handle, int(dtype), _rays_struct(rays, n), o, int(n), (m, rays, out))
 
-    def submit_trace(self, lens: Lens, path, rays: Dict, out: Dict, n: int, tag: int) -> None:
-        """Queue lt_trace(lens, path) of n rays into ``out`` (an empty_exit(n) dict)."""
+    @staticmethod
+    def prepare_trace(lens: Lens, path, rays: Dict, out: Dict, n: int):
+        """Marshal a trace request once; ``out`` is an empty_exit(n) dict."""
         torch = _torch()
         e = N.lt_exit()
         for k in EXIT_FIELDS:
             dt = torch.uint8 if k == "mask" else torch.float32
             setattr(e, k, _dev_ptr(out[k], dt, n, f"out[{k}]") if n else None)
-        p = _path(path)
-        N.check(N.lib().lt_server_submit_trace(self._h, lens.handle, C.byref(p),
-                                               C.byref(_rays_struct(rays, n)), C.byref(e), int(n),
-                                               int(tag)))
-        self._keep[int(tag)] = (rays, out)
+        return ("trace", lens.handle, _path(path), _rays_struct(rays, n), e, int(n), (lens, rays, out))
+
+    def submit(self, prepared, tag: int) -> None:
+        """Queue a request marshalled by prepare_map / prepare_trace."""
+        kind, h, arg, r, o, n, keep = prepared
+        L = N.lib()
+        if kind == "map":
+            N.check(L.lt_server_submit_map(self._h, h, arg, C.byref(r), C.byref(o), n, int(tag)))
+        else:
+            N.check(L.lt_server_submit_trace(self._h, h, C.byref(arg), C.byref(r), C.byref(o), n,
+                                             int(tag)))
+        self._keep[int(tag)] = keep
+
+    def submit_map(self, m: Map, dtype: int, rays: Dict, out: Dict, n: int, tag: int) -> None:
+        """Queue lt_map_eval(m, dtype) of n rays into ``out`` (an
+        empty_map_out(m.n_heads, n) dict); run lt_map_quantize(m, dtype) first."""
+        self.submit(self.prepare_map(m, dtype, rays, out, n), tag)
+
+    def submit_trace(self, lens: Lens, path, rays: Dict, out: Dict, n: int, tag: int) -> None:
+        """Queue lt_trace(lens, path) of n rays into ``out`` (an empty_exit(n) dict)."""
+        self.submit(self.prepare_trace(lens, path, rays, out, n), tag)
 
     def poll(self):
         """Advance the loop; returns ([(tag, done_s, status), ...], n_open)."""

@@ -38,6 +38,7 @@ class Request:
     n: int
     arrival: float                 # seconds, on the scheduler's clock
     payload: object = None         # executor-specific (e.g. device ray tensors)
+    prepared: object = None        # marshalled launch arguments (native loop)
     # filled by the scheduler
     admitted: float = -1.0
     done: float = -1.0
@@ -140,14 +141,22 @@ class NativeScheduler:
     def clock(self) -> float:
         return time.perf_counter() - self.t0
 
-    def submit(self, r: Request):
+    def prepare(self, r: Request):
+        """Marshal the request's launch arguments ahead of its arrival (what
+        a client library does when it builds a request)."""
         import paper_2605_04017_amd as lt
         rays, out = r.payload
+        if self.mode == "map":
+            r.prepared = lt.Server.prepare_map(self.maps[r.lens], self.dtype, rays, out, r.n)
+        else:
+            r.prepared = lt.Server.prepare_trace(self.lenses[r.lens], self.path, rays, out, r.n)
+
+    def submit(self, r: Request):
+        import paper_2605_04017_amd as lt
+        if getattr(r, "prepared", None) is None:
+            self.prepare(r)
         try:
-            if self.mode == "map":
-                self.server.submit_map(self.maps[r.lens], self.dtype, rays, out, r.n, r.rid)
-            else:
-                self.server.submit_trace(self.lenses[r.lens], self.path, rays, out, r.n, r.rid)
+            self.server.submit(r.prepared, r.rid)
         except lt.LtError as e:
             if e.status != lt.LT_ERR_ARG:
                 raise
@@ -177,9 +186,13 @@ def run_trace(sched: Scheduler, requests: List[Request], clock: Callable[[], flo
     i = 0
     while i < len(pending) or not sched.idle:
         now = clock()
+        k = 0
         while i < len(pending) and pending[i].arrival <= now:
             sched.submit(pending[i])
             i += 1
+            k += 1
+            if k % 16 == 0:   # keep the device fed while a burst is being queued
+                sched.step(now)
         sched.step(now)
         if wait is not None:
             nxt = pending[i].arrival if i < len(pending) else None
