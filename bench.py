@@ -11,10 +11,12 @@ tanh hidden layers, mask logit + 4-D exit ray + throughput head).
 One step = one pass of the hot path over the batch: lt_trace (transmit
 path) and lt_map_eval (FP32).  `value` is the map's rays/s; the tracer's
 rays/s, their ratio, the BF16 and FP8 map rates, the map's exit-ray error
-against the FP64 oracle after a short fit on GPU-traced rays, and a serving
-run (mixed-size requests for eight lenses, p50/p99 latency) are reported in
-the same JSON line.  Kernel times come from HIP events on the stream the
-kernels run on.
+after a short fit on GPU-traced rays (against the GPU tracer, which the
+parity tests pin to the FP64 oracle within 1e-5 mm), and a serving run
+(mixed-size requests for eight lenses, p50/p99 latency) are reported in the
+same JSON line.  Kernel times come from HIP events on the stream the
+kernels run on.  The oracle runs only in the CPU-baseline leg, which times
+it on the host cores.
 """
 from __future__ import annotations
 
@@ -23,6 +25,8 @@ import json
 import os
 import sys
 import time
+
+from paper_2605_04017_amd import fit as F
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -60,9 +64,15 @@ def trace_flops_per_ray(lens, path=(0, 0, 0)):
     return 20 + 78 * n_t + 56 * n_r + 28 * n_s + 10
 
 
-def cpu_baseline_map(params, rays_np, budget_s=10.0):
-    """Time the FP64 reference network (numpy) on a bounded sample."""
+def cpu_baseline_map(flat, norms, rays_np, budget_s=10.0):
+    """Time the FP64 reference network (numpy) of the fitted map (its flat
+    parameters and normalisation) on a bounded sample."""
+    import numpy as np
     from oracle import mlp
+    params = mlp.init_params(mlp.MapDesc(MAP_WIDTH, MAP_DEPTH, 1, mlp.ACT_TANH), 0)
+    params.set_flat(np.asarray(flat, np.float64))
+    params.in_shift, params.in_scale = norms[0], norms[1]
+    params.out_shift, params.out_scale = norms[2], norms[3]
     threads = os.cpu_count() or 1
     n = 16384
     while True:
@@ -109,12 +119,12 @@ def time_kernel(fn, stream, reps):
     return e0.elapsed_time(e1) / reps * 1e-3
 
 
-def fit_map(lt, synth, mlp, lens, dev, steps, batch=65536, seed=3002, canonical=False):
+def fit_map(lt, synth, lens, dev, steps, batch=65536, seed=3002, canonical=False):
     """Fit the 5 x 128 tanh map on rays the GPU tracer labels (a fresh
     65,536-ray batch per step drawn from a 4M-ray pool that does not overlap
     the benchmark rays).  canonical: symmetry-reduced input frame (the
     normalisation statistics are then taken in that frame).  Returns (map,
-    params as MapParams, final loss)."""
+    (flat parameters, normalisation), final loss)."""
     import numpy as np
     import torch
     pool_np = synth.make_rays(lens, 4194304, seed)
@@ -123,22 +133,10 @@ def fit_map(lt, synth, mlp, lens, dev, steps, batch=65536, seed=3002, canonical=
     ex = lt.lt_trace(h, (0, 0, 0), pool)
     ok = ex["mask"].bool()
     reg = torch.stack([ex[k][ok] for k in ("x", "y", "dx", "dy", "throughput")], 1).double().cpu().numpy()
-    src = pool_np
-    if canonical:
-        src, c, s, flip = mlp.canonical_frame(pool_np)
-        okn = ok.cpu().numpy()
-        reg[:, 0], reg[:, 1], reg[:, 2], reg[:, 3] = mlp.to_canonical_frame(
-            reg[:, 0], reg[:, 1], reg[:, 2], reg[:, 3], c[okn], s[okn], flip[okn])
-    x = np.stack([src[k].astype(np.float64) for k in synth.RAY_FIELDS], 1)
-    sd = x.std(0)
-    sd[sd == 0] = 1.0
-    p = mlp.init_params(mlp.MapDesc(MAP_WIDTH, MAP_DEPTH, 1, mlp.ACT_TANH, canonical), 5)
-    p.in_shift, p.in_scale = x.mean(0), 1.0 / sd
-    p.out_shift = reg.mean(0)[None]
-    p.out_scale = reg.std(0)[None]
+    norms = F.map_norms(pool_np, [(ok.cpu().numpy(), reg)], canonical)
     m = lt.lt_map_create(MAP_WIDTH, MAP_DEPTH, 1, lt.LT_ACT_TANH, canonical)
-    lt.lt_map_set_params(m, torch.from_numpy(p.flat().astype(np.float32)).to(dev))
-    lt.lt_map_set_norm(m, p.in_shift, p.in_scale, p.out_shift.reshape(-1), p.out_scale.reshape(-1))
+    lt.lt_map_set_params(m, torch.from_numpy(F.init_params(MAP_WIDTH, MAP_DEPTH, 1, 5)).to(dev))
+    lt.lt_map_set_norm(m, norms[0], norms[1], norms[2].reshape(-1), norms[3].reshape(-1))
     ws = lt.workspace(m, batch)
     n_pool = pool_np["x"].shape[0]
     loss = None
@@ -151,24 +149,27 @@ def fit_map(lt, synth, mlp, lens, dev, steps, batch=65536, seed=3002, canonical=
         lr = 2e-3 * (0.5 ** (k / max(1, steps / 4)))
         loss = lt.lt_map_train_step(m, rb, tb, {"lr": lr, "step": k, "w_bce": 1.0, "w_l2": 4.0}, ws)
     torch.cuda.synchronize()
-    p.set_flat(lt.lt_map_get_params(m).cpu().numpy().astype(np.float64))
-    return m, p, [float(v) for v in loss.cpu()]
+    return m, (lt.lt_map_get_params(m).cpu().numpy(), norms), [float(v) for v in loss.cpu()]
 
 
-def map_error(lt, oracle, lens, m, dtype, rays_np, rays_dev, n_sample=65536):
-    """Exit-ray error of the map against the FP64 oracle on the first
-    n_sample benchmark rays."""
-    import torch
-    sub_dev = {k: v[:n_sample] for k, v in rays_dev.items()}
-    sub_np = {k: v[:n_sample] for k, v in rays_np.items()}
-    g = {k: v[0].cpu().numpy() for k, v in lt.lt_map_eval(m, dtype, sub_dev).items()}
-    torch.cuda.synchronize()
-    return exit_error(g, oracle.trace(lens, sub_np), n_sample)
+def map_error(lt, h, m, dtype, rays_dev, n_sample=65536):
+    """Exit-ray error of the map on the first n_sample benchmark rays against
+    the FP32 GPU tracer, which matches the FP64 oracle to within 1e-5 mm and
+    1e-6 rad (the GPU parity tests; a separate test checks that a fitted
+    map's error against both agrees to that bound)."""
+    sub = {k: v[:n_sample] for k, v in rays_dev.items()}
+    return exit_error(eval_host(lt.lt_map_eval(m, dtype, sub)),
+                      {k: v.cpu().numpy() for k, v in lt.lt_trace(h, (0, 0, 0), sub).items()}, n_sample)
+
+
+def eval_host(out):
+    """First head of map outputs as host arrays."""
+    return {k: v[0].cpu().numpy() for k, v in out.items()}
 
 
 def exit_error(g, o, n_sample):
     """Mask agreement and exit-ray errors of map outputs g (one head, host
-    arrays) against oracle traces o."""
+    arrays) against traced exits o."""
     import numpy as np
     gm, om = g["mask"].astype(bool), o["mask"].astype(bool)
     both = gm & om
@@ -187,7 +188,7 @@ def exit_error(g, o, n_sample):
             "throughput_abs_p99": float(np.quantile(thr, 0.99)), "rays": n_sample}
 
 
-def paper_pair(lt, synth, mlp, oracle, lens, dev, steps, rays_np, rays, batch=65536, seed=3003,
+def paper_pair(lt, synth, lens, dev, steps, rays, batch=65536, seed=3003,
                w_cos=200.0):
     """The paper's factorised form at its own size: a classifier of 2 x 32
     tanh (BCE) and a regressor of 5 x 32 tanh (squared error on position and
@@ -202,15 +203,12 @@ def paper_pair(lt, synth, mlp, oracle, lens, dev, steps, rays_np, rays, batch=65
     ex = lt.lt_trace(h, (0, 0, 0), pool)
     ok = ex["mask"].bool()
     reg_t = torch.stack([ex[k][ok] for k in ("x", "y", "dx", "dy", "throughput")], 1).double().cpu().numpy()
-    x = np.stack([pool_np[k].astype(np.float64) for k in synth.RAY_FIELDS], 1)
+    norms = F.map_norms(pool_np, [(ok.cpu().numpy(), reg_t)])
     nets = {}
     for name, depth in (("classifier", 2), ("regressor", 5)):
-        p = mlp.init_params(mlp.MapDesc(32, depth, 1, mlp.ACT_TANH), 11 + depth)
-        p.in_shift, p.in_scale = x.mean(0), 1.0 / x.std(0)
-        p.out_shift, p.out_scale = reg_t.mean(0)[None], reg_t.std(0)[None]
         m = lt.lt_map_create(32, depth, 1, lt.LT_ACT_TANH)
-        lt.lt_map_set_params(m, torch.from_numpy(p.flat().astype(np.float32)).to(dev))
-        lt.lt_map_set_norm(m, p.in_shift, p.in_scale, p.out_shift.reshape(-1), p.out_scale.reshape(-1))
+        lt.lt_map_set_params(m, torch.from_numpy(F.init_params(32, depth, 1, 11 + depth)).to(dev))
+        lt.lt_map_set_norm(m, norms[0], norms[1], norms[2].reshape(-1), norms[3].reshape(-1))
         nets[name] = (m, lt.workspace(m, batch))
     n_pool = pool_np["x"].shape[0]
     t0 = time.perf_counter()
@@ -246,13 +244,13 @@ def paper_pair(lt, synth, mlp, oracle, lens, dev, steps, rays_np, rays, batch=65
         res[f"{name}_ms"] = t * 1e3
         res[f"{name}_mrays_s"] = n / t / 1e6
         k = 65536
-        g = {f: v[0].cpu().numpy() for f, v in pair(dt, k).items()}
-        torch.cuda.synchronize()
-        res[f"{name}_error_vs_fp64_oracle"] = exit_error(g, oracle.trace(lens, {f: v[:k] for f, v in rays_np.items()}), k)
+        g = eval_host(pair(dt, k))
+        o = {f: v.cpu().numpy() for f, v in lt.lt_trace(h, (0, 0, 0), {f: v[:k] for f, v in rays.items()}).items()}
+        res[f"{name}_error_vs_gpu_tracer"] = exit_error(g, o, k)
     return res
 
 
-def serving(lt, synth, mlp, dev, n_req=600, loads=(0.5, 0.8), seed=5005):
+def serving(lt, synth, dev, n_req=600, loads=(0.5, 0.8), seed=5005):
     """Serving run: 8 lenses (4..22 surfaces) with resident maps; Poisson
     arrivals of 1k..1M-ray requests (log-uniform); memory-admitted
     continuous batching on 4 streams by the native request loop
@@ -269,9 +267,8 @@ def serving(lt, synth, mlp, dev, n_req=600, loads=(0.5, 0.8), seed=5005):
     for i, L in enumerate(lenses):
         hl.append(lt.lt_lens_create(L.surfaces, L.glasses))
         pools.append({k: torch.from_numpy(v).to(dev) for k, v in synth.make_rays(L, 1000000, 7000 + i).items()})
-        p = mlp.init_params(mlp.MapDesc(MAP_WIDTH, MAP_DEPTH, 1), 80 + i)
         mm = lt.lt_map_create(MAP_WIDTH, MAP_DEPTH, 1)
-        lt.lt_map_set_params(mm, torch.from_numpy(p.flat().astype(np.float32)).to(dev))
+        lt.lt_map_set_params(mm, torch.from_numpy(F.init_params(MAP_WIDTH, MAP_DEPTH, 1, 80 + i)).to(dev))
         maps.append(mm)
     res = {}
 
@@ -329,7 +326,7 @@ def serving(lt, synth, mlp, dev, n_req=600, loads=(0.5, 0.8), seed=5005):
     return res
 
 
-def train_epoch(lt, synth, mlp, dev, n_total=67108864, batch=65536, seed=4004):
+def train_epoch(lt, synth, dev, n_total=67108864, batch=65536, seed=4004):
     """One training epoch of the 5 x 128 map on the training workload: the
     67,108,864 rays are drawn on the device (lt_rays_generate), labelled by
     the FP32 tracer (transmit path), and consumed in 1,024 steps of 65,536
@@ -354,16 +351,13 @@ def train_epoch(lt, synth, mlp, dev, n_total=67108864, batch=65536, seed=4004):
     for f in ("x", "y", "dx", "dy", "throughput"):
         tgt[f] = ex[f].reshape(1, -1)
     # normalisation from the first batch (inputs) and its valid rays (outputs)
-    p = mlp.init_params(mlp.MapDesc(MAP_WIDTH, MAP_DEPTH, 1, mlp.ACT_TANH), 6)
-    x0 = np.stack([rays[k][:batch].double().cpu().numpy() for k in synth.RAY_FIELDS], 1)
+    first = {k: rays[k][:batch].cpu().numpy() for k in synth.RAY_FIELDS}
     ok = ex["mask"][:batch].bool()
     reg = torch.stack([ex[k][:batch][ok] for k in ("x", "y", "dx", "dy", "throughput")], 1).double()
-    p.in_shift, p.in_scale = x0.mean(0), 1.0 / x0.std(0)
-    p.out_shift = reg.mean(0).cpu().numpy()[None]
-    p.out_scale = reg.std(0).cpu().numpy()[None]
+    norms = F.map_norms(first, [(ok.cpu().numpy(), reg.cpu().numpy())])
     m = lt.lt_map_create(MAP_WIDTH, MAP_DEPTH, 1, lt.LT_ACT_TANH)
-    lt.lt_map_set_params(m, torch.from_numpy(p.flat().astype(np.float32)).to(dev))
-    lt.lt_map_set_norm(m, p.in_shift, p.in_scale, p.out_shift.reshape(-1), p.out_scale.reshape(-1))
+    lt.lt_map_set_params(m, torch.from_numpy(F.init_params(MAP_WIDTH, MAP_DEPTH, 1, 6)).to(dev))
+    lt.lt_map_set_norm(m, norms[0], norms[1], norms[2].reshape(-1), norms[3].reshape(-1))
     ws = lt.workspace(m, batch)
     loss = torch.zeros(3, dtype=torch.float32, device=dev)
     steps = n_total // batch
@@ -400,7 +394,7 @@ def train_epoch(lt, synth, mlp, dev, n_total=67108864, batch=65536, seed=4004):
             "loss_last_step": [float(v) for v in loss.cpu()]}
 
 
-def multi_path(lt, synth, mlp, dev, n=16777216):
+def multi_path(lt, synth, dev, n=16777216):
     """The 16,777,216-ray configuration: transmit + all 55 two-reflection
     ghosts of the 11-surface lens.  Tracer: one launch per path (56).  Map:
     one 5 x 128 trunk with 56 heads in one launch, FP32 / BF16 / FP8.  Both
@@ -438,9 +432,8 @@ def multi_path(lt, synth, mlp, dev, n=16777216):
            "valid_fraction_ghost_mean": float(valid[1:].mean()) / n}
     del cout, cidx
     P = len(paths)
-    p = mlp.init_params(mlp.MapDesc(MAP_WIDTH, MAP_DEPTH, P, mlp.ACT_TANH), 9)
     m = lt.lt_map_create(MAP_WIDTH, MAP_DEPTH, P, lt.LT_ACT_TANH)
-    lt.lt_map_set_params(m, torch.from_numpy(p.flat().astype(np.float32)).to(dev))
+    lt.lt_map_set_params(m, torch.from_numpy(F.init_params(MAP_WIDTH, MAP_DEPTH, P, 9)).to(dev))
     mout = lt.empty_map_out(P, n, dev)
     fpr = map_flops_per_ray(heads=P)
     for name, dt in (("f32", lt.LT_F32), ("bf16", lt.LT_BF16), ("fp8", lt.LT_FP8)):
@@ -459,14 +452,7 @@ FLARE_SENSOR = (36.0, 24.0, 720, 480)
 FLARE_BANDS = ((600.0, 700.0), (500.0, 600.0), (400.0, 500.0))   # R, G, B
 
 
-def _norm_stats(a):
-    import numpy as np
-    mu, sd = a.mean(0), a.std(0)
-    sd[~(sd > 0)] = 1.0
-    return mu, sd
-
-
-def flare(lt, synth, mlp, dev, steps=10000, n_render=1 << 20, theta_deg=10.0, n_ghosts=8,
+def flare(lt, synth, dev, steps=10000, n_render=1 << 20, theta_deg=10.0, n_ghosts=8,
           batch=65536, seed=6006, n_pool=1 << 22):
     """Forward light tracing of a distant point light (Sec. 3 flare sum; the
     forward half of the rendering pipeline, whose transmit image comes from
@@ -519,27 +505,19 @@ def flare(lt, synth, mlp, dev, steps=10000, n_render=1 << 20, theta_deg=10.0, n_
     for f in ("x", "y", "dx", "dy", "throughput"):
         tgt[f] = torch.empty((P, n_pool), dtype=torch.float32, device=dev)
     ex = lt.empty_exit(n_pool, dev)
-    src, c, s, flip = mlp.canonical_frame(pool_np)
-    out_shift, out_scale = np.zeros((P, 5)), np.ones((P, 5))
+    targets = []
     for k, p in enumerate(paths):
         lt.lt_trace_ex(h, p, pool, ex, n_pool, fwd, stream)
         tgt["valid"][k].copy_(ex["mask"])
         for f in ("x", "y", "dx", "dy", "throughput"):
             tgt[f][k].copy_(ex[f])
         ok = ex["mask"].bool().cpu().numpy()
-        reg = np.stack([ex[f].cpu().numpy()[ok].astype(np.float64)
-                        for f in ("x", "y", "dx", "dy", "throughput")], 1)
-        if ok.sum() > 1:
-            reg[:, 0], reg[:, 1], reg[:, 2], reg[:, 3] = mlp.to_canonical_frame(
-                reg[:, 0], reg[:, 1], reg[:, 2], reg[:, 3], c[ok], s[ok], flip[ok])
-            out_shift[k], out_scale[k] = _norm_stats(reg)
-    x = np.stack([src[f].astype(np.float64) for f in synth.RAY_FIELDS], 1)
-    in_shift, in_sd = _norm_stats(x)
-    desc = mlp.MapDesc(MAP_WIDTH, MAP_DEPTH, P, mlp.ACT_TANH, canonical=True, forward=True)
-    prm = mlp.init_params(desc, 7)
+        targets.append((ok, np.stack([ex[f].cpu().numpy()[ok].astype(np.float64)
+                                      for f in ("x", "y", "dx", "dy", "throughput")], 1)))
+    norms = F.map_norms(pool_np, targets, canonical=True)
     m = lt.lt_map_create(MAP_WIDTH, MAP_DEPTH, P, lt.LT_ACT_TANH, True, True)
-    lt.lt_map_set_params(m, torch.from_numpy(prm.flat().astype(np.float32)).to(dev))
-    lt.lt_map_set_norm(m, in_shift, 1.0 / in_sd, out_shift.reshape(-1), out_scale.reshape(-1))
+    lt.lt_map_set_params(m, torch.from_numpy(F.init_params(MAP_WIDTH, MAP_DEPTH, P, 7)).to(dev))
+    lt.lt_map_set_norm(m, norms[0], norms[1], norms[2].reshape(-1), norms[3].reshape(-1))
     ws = lt.workspace(m, batch)
     del ex
     t_data = time.perf_counter() - t0
@@ -740,7 +718,6 @@ def traffic_probe(n=N_RAYS, dtype_name="f32"):
     import torch
     import paper_2605_04017_amd as lt
     import synth
-    from oracle import mlp  # parameter initialiser only
     dev = torch.device("cuda:0")
     src = torch.ones(COPY_PROBE_BYTES // 4, device=dev)
     dst = torch.empty_like(src)
@@ -759,9 +736,8 @@ def traffic_probe(n=N_RAYS, dtype_name="f32"):
         print(json.dumps({"probe": "traffic", "kernel": "trace", "copy_bytes": COPY_PROBE_BYTES,
                           "rays": n}), flush=True)
         return
-    p = mlp.init_params(mlp.MapDesc(MAP_WIDTH, MAP_DEPTH, 1, mlp.ACT_TANH), 5)
     m = lt.lt_map_create(MAP_WIDTH, MAP_DEPTH, 1, lt.LT_ACT_TANH)
-    lt.lt_map_set_params(m, torch.from_numpy(p.flat().astype(np.float32)).to(dev))
+    lt.lt_map_set_params(m, torch.from_numpy(F.init_params(MAP_WIDTH, MAP_DEPTH, 1, 5)).to(dev))
     out = lt.empty_map_out(1, n, dev)
     torch.cuda.synchronize()
     dt = {"f32": lt.LT_F32, "bf16": lt.LT_BF16, "fp8": lt.LT_FP8}[dtype_name]
@@ -800,10 +776,8 @@ def main():
     import numpy as np
     import torch
 
-    import oracle
     import paper_2605_04017_amd as lt
     import synth
-    from oracle import mlp
 
     dev = torch.device("cuda:0")
     lens = synth.config_lens(2)
@@ -816,7 +790,7 @@ def main():
 
     # map of the workload's architecture, fitted on GPU-traced rays
     t_fit = time.perf_counter()
-    m, params, fit_loss = fit_map(lt, synth, mlp, lens, dev, args.fit_steps)
+    m, fitted, fit_loss = fit_map(lt, synth, lens, dev, args.fit_steps)
     t_fit = time.perf_counter() - t_fit
     mout = lt.empty_map_out(1, n, dev)
     print(f"# fitted map in {t_fit:.1f} s, loss {fit_loss}", file=sys.stderr, flush=True)
@@ -853,13 +827,13 @@ def main():
                                                 stream), stream, reps)
     t_f64 = time_kernel(lambda: lt.lt_trace_ex(h, (0, 0, 0), rays, fast, n, lt.LT_TRACE_FP64,
                                                stream), stream, reps)
-    errors = {name: map_error(lt, oracle, lens, m, dt, rays_np, rays)
+    errors = {name: map_error(lt, h, m, dt, rays)
               for name, dt in (("f32", lt.LT_F32), ("bf16", lt.LT_BF16), ("fp8", lt.LT_FP8))}
     # the symmetry-reduced input frame, fitted with the same budget
     t_c = time.perf_counter()
-    mc, _, fit_loss_c = fit_map(lt, synth, mlp, lens, dev, args.fit_steps, canonical=True)
+    mc, _, fit_loss_c = fit_map(lt, synth, lens, dev, args.fit_steps, canonical=True)
     t_c = time.perf_counter() - t_c
-    errors["f32_canonical_input"] = map_error(lt, oracle, lens, mc, lt.LT_F32, rays_np, rays)
+    errors["f32_canonical_input"] = map_error(lt, h, mc, lt.LT_F32, rays)
     errors["f32_canonical_input"]["fit_final_loss"] = fit_loss_c
     t_map_c = time_kernel(lambda: lt.lt_map_eval(mc, lt.LT_F32, rays, mout, n, stream), stream, 3)
     del mc
@@ -896,7 +870,11 @@ def main():
                       "trace_fp64_option": t_f64 * 1e3,
                       "map_f32": t_map * 1e3, "map_bf16": t_bf16 * 1e3, "map_fp8": t_fp8 * 1e3,
                       "map_f32_canonical_input": t_map_c * 1e3},
-        "map_error_vs_fp64_oracle": errors,
+        "map_error_vs_gpu_tracer": errors,
+        "map_error_reference": "exit rays of the FP32 GPU tracer on the same rays; the GPU parity "
+                               "tests pin it to the FP64 oracle within 1e-5 mm / 1e-6 rad, and "
+                               "tests/test_gpu_map_error.py checks a fitted map's error against "
+                               "both agrees to that bound",
         "paper_context": {
             "reported": "rendering about 12-15x faster with the maps than with the ray-traced lens "
                         "(depth-of-field path tracing in LuisaRender, per-path 32-wide tanh MLPs)",
@@ -926,26 +904,25 @@ def main():
                                   / MI355X_FP64_VECTOR_TFLOPS}},
     }
     if not args.no_paper_pair:
-        res["paper_pair_2x32_5x32"] = paper_pair(lt, synth, mlp, oracle, lens, dev, args.fit_steps,
-                                                 rays_np, rays)
+        res["paper_pair_2x32_5x32"] = paper_pair(lt, synth, lens, dev, args.fit_steps, rays)
         print("# paper-size pair done", file=sys.stderr, flush=True)
     if not args.no_train_epoch:
-        res["train_epoch_67M"] = train_epoch(lt, synth, mlp, dev)
+        res["train_epoch_67M"] = train_epoch(lt, synth, dev)
         print("# training epoch done", file=sys.stderr, flush=True)
     if not args.no_flare:
-        res["flare_forward"] = flare(lt, synth, mlp, dev)
+        res["flare_forward"] = flare(lt, synth, dev)
         print("# flare frame done", file=sys.stderr, flush=True)
     if not args.no_sampler:
         res["sampler_yield_ghost"] = sampler_yield(lt, synth, dev)
         print("# sampler yield done", file=sys.stderr, flush=True)
     if not args.no_multi_path:
-        res["multi_path_16M"] = multi_path(lt, synth, mlp, dev)
+        res["multi_path_16M"] = multi_path(lt, synth, dev)
         print("# multi-path done", file=sys.stderr, flush=True)
     if not args.no_serving:
-        res["serving"] = serving(lt, synth, mlp, dev)
+        res["serving"] = serving(lt, synth, dev)
         print("# serving done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline_map(params, rays_np)
+        res["cpu_baseline"] = cpu_baseline_map(fitted[0], fitted[1], rays_np)
         res["cpu_baseline_trace"] = cpu_baseline_trace(lens, rays_np)
     print(json.dumps(res), flush=True)
 
