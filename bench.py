@@ -394,12 +394,79 @@ def train_epoch(lt, synth, dev, n_total=67108864, batch=65536, seed=4004):
             "loss_last_step": [float(v) for v in loss.cpu()]}
 
 
-def multi_path(lt, synth, dev, n=16777216):
+def fit_multi_head(lt, synth, lens, h, paths, dev, steps, n_pool=1 << 21, batch=65536, seed=3004):
+    """One 5 x 128 trunk with a head per path (canonical input), fitted for
+    `steps` steps on GPU traces of every path."""
+    import numpy as np
+    import torch
+    P = len(paths)
+    pool_np = synth.make_rays(lens, n_pool, seed)
+    pool = {k: torch.from_numpy(v).to(dev) for k, v in pool_np.items()}
+    tgt = {"valid": torch.empty((P, n_pool), dtype=torch.uint8, device=dev)}
+    for f in ("x", "y", "dx", "dy", "throughput"):
+        tgt[f] = torch.empty((P, n_pool), dtype=torch.float32, device=dev)
+    ex = lt.empty_exit(n_pool, dev)
+    targets = []
+    for k, p in enumerate(paths):
+        lt.lt_trace(h, p, pool, ex, n_pool)
+        tgt["valid"][k].copy_(ex["mask"])
+        for f in ("x", "y", "dx", "dy", "throughput"):
+            tgt[f][k].copy_(ex[f])
+        ok = ex["mask"].bool()
+        targets.append((ok.cpu().numpy(), torch.stack([ex[f][ok] for f in ("x", "y", "dx", "dy", "throughput")],
+                                                       1).double().cpu().numpy()))
+    norms = F.map_norms(pool_np, targets, canonical=True)
+    m = lt.lt_map_create(MAP_WIDTH, MAP_DEPTH, P, lt.LT_ACT_TANH, True)
+    lt.lt_map_set_params(m, torch.from_numpy(F.init_params(MAP_WIDTH, MAP_DEPTH, P, 9)).to(dev))
+    lt.lt_map_set_norm(m, norms[0], norms[1], norms[2].reshape(-1), norms[3].reshape(-1))
+    ws = lt.workspace(m, batch)
+    t0 = time.perf_counter()
+    loss = None
+    for k in range(1, steps + 1):
+        lo = ((k - 1) * batch) % (n_pool - batch + 1)
+        rb = {f: v[lo:lo + batch] for f, v in pool.items()}
+        tb = {f: v[:, lo:lo + batch].contiguous() for f, v in tgt.items()}
+        lr = 2e-3 * (0.5 ** (k / max(1, steps / 4)))
+        loss = lt.lt_map_train_step(m, rb, tb, {"lr": lr, "step": k, "w_bce": 1.0, "w_l2": 4.0}, ws)
+    torch.cuda.synchronize()
+    return m, time.perf_counter() - t0, [float(v) for v in loss.cpu()]
+
+
+def multi_path_error(lt, h, m, paths, dtype, rays, n_sample=65536):
+    """Map error over every (path, ray) pair of the first n_sample rays
+    against the GPU tracer: mask agreement over all pairs, exit positions
+    over the pairs valid in both; the transmit head on its own beside it."""
+    import numpy as np
+    sub = {k: v[:n_sample] for k, v in rays.items()}
+    g = {k: v.cpu().numpy() for k, v in lt.lt_map_eval(m, dtype, sub).items()}
+    agree, pos, ghost_p50, transmit = [], [], [], None
+    for i, p in enumerate(paths):
+        o = {k: v.cpu().numpy() for k, v in lt.lt_trace(h, p, sub).items()}
+        gi = {k: v[i] for k, v in g.items()}
+        e = exit_error(gi, o, n_sample)
+        if i == 0:
+            transmit = e
+        elif "pos_mm_p50" in e:
+            ghost_p50.append(e["pos_mm_p50"])
+        both = gi["mask"].astype(bool) & o["mask"].astype(bool)
+        agree.append(gi["mask"].astype(bool) == o["mask"].astype(bool))
+        pos.append(np.hypot(gi["x"][both] - o["x"][both], gi["y"][both] - o["y"][both]))
+    pos = np.concatenate(pos)
+    return {"pairs": len(paths) * n_sample, "valid_pairs_in_both": int(pos.size),
+            "mask_agreement": float(np.mean(np.concatenate(agree))),
+            "pos_mm_p50": float(np.median(pos)), "pos_mm_p99": float(np.quantile(pos, 0.99)),
+            "transmit": transmit,
+            "ghost_pos_mm_p50_median_over_paths": float(np.median(ghost_p50)) if ghost_p50 else None}
+
+
+def multi_path(lt, synth, dev, n=16777216, fit_steps=3000):
     """The 16,777,216-ray configuration: transmit + all 55 two-reflection
     ghosts of the 11-surface lens.  Tracer: one launch per path (56).  Map:
-    one 5 x 128 trunk with 56 heads in one launch, FP32 / BF16 / FP8.  Both
-    write every path's exit rays (the tracer reuses one output set per path
-    launch; the map writes [56][n] fields)."""
+    one 5 x 128 trunk with 56 heads (canonical input) in one launch, FP32 /
+    BF16 / FP8, fitted for fit_steps steps on GPU traces of all 56 paths; its
+    error against the GPU tracer is stated per precision.  Both write every
+    path's exit rays (the tracer reuses one output set per path launch; the
+    map writes [56][n] fields)."""
     import numpy as np
     import torch
     lens = synth.config_lens(3)
@@ -432,8 +499,13 @@ def multi_path(lt, synth, dev, n=16777216):
            "valid_fraction_ghost_mean": float(valid[1:].mean()) / n}
     del cout, cidx
     P = len(paths)
-    m = lt.lt_map_create(MAP_WIDTH, MAP_DEPTH, P, lt.LT_ACT_TANH)
-    lt.lt_map_set_params(m, torch.from_numpy(F.init_params(MAP_WIDTH, MAP_DEPTH, P, 9)).to(dev))
+    m, t_fit, fit_loss = fit_multi_head(lt, synth, lens, h, paths, dev, fit_steps)
+    res["fit"] = {"steps": fit_steps, "batch": 65536, "seconds": t_fit, "final_loss": fit_loss,
+                  "map": "5 x 128 tanh, 56 heads, canonical input"}
+    res["map_error_vs_gpu_tracer"] = {name: multi_path_error(lt, h, m, paths, dt, rays)
+                                      for name, dt in (("f32", lt.LT_F32), ("bf16", lt.LT_BF16),
+                                                       ("fp8", lt.LT_FP8))}
+    torch.cuda.empty_cache()
     mout = lt.empty_map_out(P, n, dev)
     fpr = map_flops_per_ray(heads=P)
     for name, dt in (("f32", lt.LT_F32), ("bf16", lt.LT_BF16), ("fp8", lt.LT_FP8)):
