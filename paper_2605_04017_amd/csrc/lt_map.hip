@@ -242,7 +242,7 @@ __global__ __launch_bounds__((eval_waves<H, TRAIN>() * 64)) void map_eval_bf16_k
     const uint8_t *out_frag = A.out_from_lds ? lds + A.img_out : A.img + A.img_out;
     const int64_t n = A.n;
     const int64_t n_tiles = TRAIN ? A.n_pad / RPW : (n + RPW - 1) / RPW;
-    // Phase offset (BF16 evaluation with the output layer resident in LDS):
+    // Phase offset (BF16 evaluation at width 128 with the output layer resident in LDS):
     // the two waves of a SIMD alternate between a layer's MFMAs and the other
     // wave's tanh epilogue, kept one phase apart by a workgroup barrier after
     // every phase.  Every wave of the workgroup passes the same number of
@@ -250,9 +250,9 @@ __global__ __launch_bounds__((eval_waves<H, TRAIN>() * 64)) void map_eval_bf16_k
     // over the workgroup; waves whose tile is past the end compute on masked
     // rays and store nothing), plus one before the loop for the lagging half
     // and one after it for the leading half.  Measured on 4,194,304 rays,
-    // one head: 7 % faster; FP8 and the streamed output layer are slower
-    // with it and keep the free-running schedule.
-    constexpr bool kPP = !TRAIN && !FP8 && !BIG && kWaves == 8;
+    // one head: 7 % faster; FP8, the streamed output layer and narrower
+    // maps (the 32-wide pair: 20 % slower) keep the free-running schedule.
+    constexpr bool kPP = H == 128 && !TRAIN && !FP8 && !BIG && kWaves == 8;
     const bool lag = wave >= kWaves / 2;
     if (kPP && lag)
         __builtin_amdgcn_s_barrier();
