@@ -358,15 +358,12 @@ __global__ __launch_bounds__(256) void dw_kernel(DwArgs A)
     constexpr int RS = kDwChunk + kDwPad;  // bf16 per LDS row
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     const MapLayout &L = A.L;
-    const int layer = blockIdx.x;
+    // with H >= 64 the hidden layers go to dw_hidden_kernel and the grid
+    // covers the input (x = 0) and output (x = 1) layers only
+    const int layer = H >= 64 ? (blockIdx.x == 0 ? 0 : L.D) : static_cast<int>(blockIdx.x);
     const int group = blockIdx.y;
     const int slice = blockIdx.z;
     const bool is_out = layer == L.D, is_in = layer == 0;
-    if constexpr (H >= 64) {
-        // hidden layers go to dw_hidden_kernel
-        if (!is_out && !is_in)
-            return;
-    }
     const int m_tiles = is_out ? L.TO : T;
     const int n_tiles = is_in ? 1 : T + 1;
     const int total = m_tiles * n_tiles;
@@ -382,7 +379,8 @@ __global__ __launch_bounds__(256) void dw_kernel(DwArgs A)
 #pragma unroll
     for (int k = 0; k < kDwTilesPerWave; ++k)
         acc[k] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-    const int tile_base = group * 4 * kDwTilesPerWave + wave * kDwTilesPerWave;
+    // tile group * 4 * kDwTilesPerWave + 4 k + wave: small layers use every wave
+    const int tile_base = group * 4 * kDwTilesPerWave + wave;
     const int64_t tiles16 = A.n_pad / 16;
     const bf16x8 *hf = reinterpret_cast<const bf16x8 *>(A.hfrag);
     const bf16x8 *df = reinterpret_cast<const bf16x8 *>(A.dfrag);
@@ -463,7 +461,7 @@ __global__ __launch_bounds__(256) void dw_kernel(DwArgs A)
         // --- MFMA: acc[tile] += sum over the chunk's rays of d[m][r] h[n][r]
 #pragma unroll
         for (int k = 0; k < kDwTilesPerWave; ++k) {
-            const int tau = tile_base + k;
+            const int tau = tile_base + 4 * k;
             if (tau >= total)
                 break;
             const int mt = tau / n_tiles, ntl = tau % n_tiles;
@@ -485,7 +483,7 @@ __global__ __launch_bounds__(256) void dw_kernel(DwArgs A)
     float *out = A.partial + static_cast<int64_t>(slice) * L.n_params;
 #pragma unroll
     for (int k = 0; k < kDwTilesPerWave; ++k) {
-        const int tau = tile_base + k;
+        const int tau = tile_base + 4 * k;
         if (tau >= total)
             break;
         const int mt = tau / n_tiles, ntl = tau % n_tiles;
@@ -747,6 +745,8 @@ static lt_status launch_dw(const DwArgs &A, const WsLayout &w, hipStream_t s)
     const int T = H / 16;
     int max_groups = 1;
     for (int layer = 0; layer <= L.D; ++layer) {
+        if (H >= 64 && layer != 0 && layer != L.D)
+            continue;   // hidden layers: dw_hidden_kernel
         const int tiles = (layer == L.D ? L.TO : T) * (layer == 0 ? 1 : T + 1);
         const int gr = (tiles + 4 * kDwTilesPerWave - 1) / (4 * kDwTilesPerWave);
         if (gr > max_groups)
@@ -756,7 +756,8 @@ static lt_status launch_dw(const DwArgs &A, const WsLayout &w, hipStream_t s)
     const size_t lds = static_cast<size_t>(rows_max + H + 16) * (kDwChunk + kDwPad) * 2;
     if (lds > static_cast<size_t>(kMaxLds))
         return fail(LT_ERR_ARG, "too many heads for the weight-gradient kernel");
-    hipLaunchKernelGGL(kern, dim3(L.D + 1, max_groups, static_cast<uint32_t>(w.slices)), dim3(256),
+    const uint32_t layers = H >= 64 ? 2u : static_cast<uint32_t>(L.D + 1);
+    hipLaunchKernelGGL(kern, dim3(layers, max_groups, static_cast<uint32_t>(w.slices)), dim3(256),
                        lds, s, A);
     lt_status st = check_hip(hipGetLastError(), "dw_kernel launch");
     if constexpr (H >= 64) {
