@@ -16,7 +16,8 @@
 //       a slice of the batch (hidden layers of width 64 and 128 / the input
 //       and output layers and width 32), the fragments transposed into LDS
 //       rows by selector MFMAs; the bias gradient comes from an extra all-ones
-//       column; one partial per slice (deterministic, 128 slices);
+//       column; one partial per slice (deterministic; 256 slices for the
+//       input and output layers, 128 for the hidden layers);
 //   reduce_adam_kernel: sums the slice partials and applies Adam to the FP32
 //       master parameters.
 #include <hip/hip_runtime.h>
@@ -32,7 +33,7 @@ namespace lt {
 // --------------------------------------------------------- workspace -------
 
 struct WsLayout {
-    int64_t n_pad = 0, tiles16 = 0, slices = 0, loss_blocks = 0;
+    int64_t n_pad = 0, tiles16 = 0, slices = 0, slices_h = 0, loss_blocks = 0;
     int64_t xhat = 0, hfrag = 0, dfrag = 0, o = 0, dout = 0, partial = 0, loss = 0, canon = 0, bytes = 0;
 };
 
@@ -41,7 +42,8 @@ typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 constexpr int kDwChunk = 64;     // rays per LDS chunk in dw_kernel
 constexpr int kDwPad = 8;        // bf16 padding per LDS row (bank skew)
 constexpr int kDwTilesPerWave = 16;
-constexpr int kMaxSlices = 128;
+constexpr int kMaxSlices = 256;       // slices of the input/output-layer gradients
+constexpr int kMaxHiddenSlices = 128; // slices of the hidden-layer gradients (dw_hidden_kernel)
 constexpr int kLossBlock = 256;
 
 static int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
@@ -54,6 +56,7 @@ WsLayout ws_layout(const MapLayout &L, int64_t n)
     w.slices = w.n_pad / kDwChunk < kMaxSlices ? w.n_pad / kDwChunk : kMaxSlices;
     if (w.slices < 1)
         w.slices = 1;
+    w.slices_h = w.slices < kMaxHiddenSlices ? w.slices : kMaxHiddenSlices;
     w.loss_blocks = (w.n_pad + kLossBlock - 1) / kLossBlock;
     int64_t off = 0;
     w.xhat = off;
@@ -349,6 +352,7 @@ struct DwArgs {
     float *partial;         // [slices][n_params]
     MapLayout L;
     int64_t n, n_pad, chunks_per_slice, n_chunks;
+    int64_t chunks_per_slice_h;   // dw_hidden_kernel's slices are fewer and longer
 };
 
 template <int H>
@@ -520,6 +524,7 @@ __global__ __launch_bounds__(256) void dw_kernel(DwArgs A)
 struct AdamArgs {
     const float *partial;
     int64_t slices, n_params;
+    int64_t slices_h, hid_lo, hid_hi;   // parameters [hid_lo, hid_hi) have slices_h partials
     float *master, *m, *v;
     float *grad_out;          // if non-null: write the gradient, no update
     float lr, beta1, beta2, eps, bc1, bc2;
@@ -529,23 +534,36 @@ struct AdamArgs {
     float loss_scale_bce, loss_scale_l2;
 };
 
+// hidden-layer parameters come from dw_hidden_kernel (width >= 64), which
+// writes slices_h partials; every other parameter has A.slices
+static void set_hidden_range(AdamArgs &A, const MapLayout &L, int64_t slices_h)
+{
+    A.slices_h = slices_h;
+    A.hid_lo = A.hid_hi = 0;
+    if (L.H >= 64 && L.D > 1) {
+        A.hid_lo = L.w_off[1];
+        A.hid_hi = L.w_off[L.D];
+    }
+}
+
 __global__ __launch_bounds__(256) void reduce_adam_kernel(AdamArgs A)
 {
     for (int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; k < A.n_params;
          k += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        // slices summed in order; eight loads in flight at a time
+        // slices summed in order; sixteen loads in flight at a time
         float gsum = 0.0f;
         int64_t s = 0;
-        for (; s + 8 <= A.slices; s += 8) {
-            float p[8];
+        const int64_t ns = (k >= A.hid_lo && k < A.hid_hi) ? A.slices_h : A.slices;
+        for (; s + 16 <= ns; s += 16) {
+            float p[16];
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
+            for (int j = 0; j < 16; ++j)
                 p[j] = A.partial[(s + j) * A.n_params + k];
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
+            for (int j = 0; j < 16; ++j)
                 gsum += p[j];
         }
-        for (; s < A.slices; ++s)
+        for (; s < ns; ++s)
             gsum += A.partial[s * A.n_params + k];
         if (A.grad_out) {
             A.grad_out[k] = gsum;
@@ -643,8 +661,8 @@ __global__ __launch_bounds__(256) void dw_hidden_kernel(DwArgs A)
 #pragma unroll
         for (int nn = 0; nn <= T; ++nn)
             acc[mi][nn] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-    const int64_t c0 = slice * A.chunks_per_slice;
-    int64_t c1 = c0 + A.chunks_per_slice;
+    const int64_t c0 = slice * A.chunks_per_slice_h;
+    int64_t c1 = c0 + A.chunks_per_slice_h;
     if (c1 > A.n_chunks)
         c1 = A.n_chunks;
     bf16x8 dv[C], hv[C];
@@ -763,7 +781,7 @@ static lt_status launch_dw(const DwArgs &A, const WsLayout &w, hipStream_t s)
     if constexpr (H >= 64) {
         if (st == LT_OK && L.D > 1) {
             const size_t lds_h = static_cast<size_t>(2 * H + 16) * (kDwChunk + kDwPad) * 2;
-            hipLaunchKernelGGL(dw_hidden_kernel<H>, dim3(L.D - 1, static_cast<uint32_t>(w.slices)), dim3(256),
+            hipLaunchKernelGGL(dw_hidden_kernel<H>, dim3(L.D - 1, static_cast<uint32_t>(w.slices_h)), dim3(256),
                                lds_h, s, A);
             st = check_hip(hipGetLastError(), "dw_hidden_kernel launch");
         }
@@ -828,6 +846,7 @@ static lt_status run_backward(Map &M, const WsLayout &w, uint8_t *ws, const floa
     D.n_pad = w.n_pad;
     D.n_chunks = w.n_pad / kDwChunk;
     D.chunks_per_slice = (D.n_chunks + w.slices - 1) / w.slices;
+    D.chunks_per_slice_h = (D.n_chunks + w.slices_h - 1) / w.slices_h;
     if (L.H == 128)
         return launch_dw<128>(D, w, s);
     if (L.H == 64)
@@ -920,6 +939,7 @@ lt_status lt_map_backward(lt_map map, const float *grad_o, void *ws, int64_t ws_
     AdamArgs A{};
     A.partial = reinterpret_cast<const float *>(wb + w.partial);
     A.slices = n > 0 ? w.slices : 0;
+    set_hidden_range(A, M->lay, n > 0 ? w.slices_h : 0);
     A.n_params = M->lay.n_params;
     A.grad_out = grad_params;
     hipLaunchKernelGGL(reduce_adam_kernel, dim3(256), dim3(256), 0, s, A);
@@ -990,6 +1010,7 @@ lt_status lt_map_train_step(lt_map map, const lt_rays *rays, const lt_targets *t
     AdamArgs AA{};
     AA.partial = reinterpret_cast<const float *>(wb + w.partial);
     AA.slices = w.slices;
+    set_hidden_range(AA, M->lay, w.slices_h);
     AA.n_params = M->lay.n_params;
     AA.master = M->master;
     AA.m = M->adam_m;
