@@ -48,9 +48,28 @@ F32Layout f32_layout(const MapLayout &L)
     return f;
 }
 
+// For tanh maps the image holds an equivalent network whose activation is
+// r = 1 / (1 + 2^u), one exp2 and one reciprocal, instead of
+// tanh z = 1 - 2 / (1 + 2^(k z)) with k = 2 log2 e:
+//   layer 0:            W' = k W,      b' = k b
+//   hidden layers l:    W' = -2 k W,   b' = k (b + sum_j W[i][j])   (input h = 1 - 2 r)
+//   output layer:       W' = -2 W,     b' = b + sum_j W[i][j]
+// so every layer computes the same pre-activation (times k) from r.  Row
+// sums are taken in FP64 when the image is built.
+constexpr float kTanhK = 2.8853900817779268f;
+
+__device__ float row_sum(const float *__restrict__ W, int n)
+{
+    double s = 0.0;
+    for (int j = 0; j < n; ++j)
+        s += static_cast<double>(W[j]);
+    return static_cast<float>(s);
+}
+
 __global__ void pack_f32_kernel(const float *__restrict__ P, const float *__restrict__ norm,
                                 MapLayout L, F32Layout F, float *__restrict__ img)
 {
+    const bool fold = L.act == LT_ACT_TANH;
     const int64_t total = F.bytes / 4;
     const int64_t bias_floats = static_cast<int64_t>(L.D) * L.H + 16LL * L.TO + 12 + 10LL * L.P;
     const int K4 = L.H / 4;
@@ -62,12 +81,19 @@ __global__ void pack_f32_kernel(const float *__restrict__ P, const float *__rest
             const int64_t b = e;
             const int64_t nb = static_cast<int64_t>(L.D) * L.H;
             if (b < nb) {
-                v = P[L.b_off[b / L.H] + b % L.H];
+                const int l = static_cast<int>(b / L.H), i = static_cast<int>(b % L.H);
+                v = P[L.b_off[l] + i];
+                if (fold)
+                    v = kTanhK * (l == 0 ? v : v + row_sum(P + L.w_off[l] + static_cast<int64_t>(i) * L.H, L.H));
             } else if (b < nb + 16LL * L.TO) {
                 const int slot = static_cast<int>(b - nb);
                 const int head = slot / kHeadSlots, q = slot % kHeadSlots;
-                if (head < L.P && q < kMapOut)
-                    v = P[L.b_off[L.D] + head * kMapOut + q];
+                if (head < L.P && q < kMapOut) {
+                    const int row = head * kMapOut + q;
+                    v = P[L.b_off[L.D] + row];
+                    if (fold)
+                        v += row_sum(P + L.w_off[L.D] + static_cast<int64_t>(row) * L.H, L.H);
+                }
             } else if (b < bias_floats) {
                 v = norm[b - nb - 16LL * L.TO];
             }
@@ -81,21 +107,21 @@ __global__ void pack_f32_kernel(const float *__restrict__ P, const float *__rest
                 const int t = static_cast<int>(f / 2), c = static_cast<int>(f % 2);
                 const int k = 4 * c + g;
                 if (k < 6)
-                    v = P[L.w_off[0] + static_cast<int64_t>(16 * t + mrow) * 6 + k];
+                    v = P[L.w_off[0] + static_cast<int64_t>(16 * t + mrow) * 6 + k] * (fold ? kTanhK : 1.0f);
             } else if (!is_out) {
                 const int per = L.T * K4;
                 const int l = static_cast<int>(f / per) + 1;
                 const int r = static_cast<int>(f % per);
                 const int t = r / K4, q = r % K4;
                 const int k = 16 * (q / 4) + 4 * g + (q % 4);
-                v = P[L.w_off[l] + static_cast<int64_t>(16 * t + mrow) * L.H + k];
+                v = P[L.w_off[l] + static_cast<int64_t>(16 * t + mrow) * L.H + k] * (fold ? -2.0f * kTanhK : 1.0f);
             } else {
                 const int to = static_cast<int>(f / K4), q = static_cast<int>(f % K4);
                 const int slot = 16 * to + mrow;
                 const int head = slot / kHeadSlots, qq = slot % kHeadSlots;
                 const int k = 16 * (q / 4) + 4 * g + (q % 4);
                 if (head < L.P && qq < kMapOut)
-                    v = P[L.w_off[L.D] + static_cast<int64_t>(head * kMapOut + qq) * L.H + k];
+                    v = P[L.w_off[L.D] + static_cast<int64_t>(head * kMapOut + qq) * L.H + k] * (fold ? -2.0f : 1.0f);
             }
         }
         img[e] = v;
@@ -118,10 +144,16 @@ __device__ __forceinline__ floatx4 mfma_f32(float a, float b, floatx4 c)
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// activation of the packed FP32 network: r = 1 / (1 + 2^u) for tanh maps
+// (the scale and the affine map to tanh live in the packed weights), ReLU
+// unchanged
 template <int ACT>
-__device__ __forceinline__ float act_f32(float z)
+__device__ __forceinline__ float act_f32(float u)
 {
-    return act<ACT>(z);
+    if constexpr (ACT == LT_ACT_TANH)
+        return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(u));
+    else
+        return act<ACT>(u);
 }
 
 // One workgroup of eight waves (32 rays each, two 16-ray N tiles) per CU:
