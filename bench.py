@@ -253,7 +253,7 @@ def paper_pair(lt, synth, lens, dev, steps, rays, batch=65536, seed=3003,
 def serving(lt, synth, dev, n_req=600, loads=(0.5, 0.8), seed=5005):
     """Serving run: 8 lenses (4..22 surfaces) with resident maps; Poisson
     arrivals of 1k..1M-ray requests (log-uniform); memory-admitted
-    continuous batching on 4 streams by the native request loop
+    continuous batching on 8 streams by the native request loop
     (lt_server_*), requests split into chunks of 262,144 rays.  Offered load
     relative to the saturated rate measured with all requests queued at
     t = 0.  The Python loop's saturated rate (the same policy in Python over
@@ -296,7 +296,7 @@ def serving(lt, synth, dev, n_req=600, loads=(0.5, 0.8), seed=5005):
                 rays, out = r.payload
                 r.prepared = (lt.Server.prepare_map(maps[r.lens], dtype, rays, out, r.n) if mode == "map"
                               else lt.Server.prepare_trace(hl[r.lens], (0, 0, 0), rays, out, r.n))
-            srv = lt.Server(4, chunk=262144, mem_budget=4 << 30, bytes_per_ray=64)
+            srv = lt.Server(8, chunk=262144, mem_budget=4 << 30, bytes_per_ray=64)
             sched = NativeScheduler(srv, hl, maps, mode, dtype)
             done = run_trace(sched, reqs, sched.clock)
             torch.cuda.synchronize()
@@ -314,7 +314,7 @@ def serving(lt, synth, dev, n_req=600, loads=(0.5, 0.8), seed=5005):
                                   "mrays_s": thr / 1e6, "requests": st["n"]}
         if key == "map_bf16":
             reqs = requests(1e9)
-            ex = GpuExecutor(4, hl, maps, mode, dtype)
+            ex = GpuExecutor(8, hl, maps, mode, dtype)
             sched = Scheduler(ex, mem_budget_bytes=4 << 30, bytes_per_ray=64, chunk=262144)
             ex.start_clock()
             done = run_trace(sched, reqs, ex.clock)
@@ -322,7 +322,7 @@ def serving(lt, synth, dev, n_req=600, loads=(0.5, 0.8), seed=5005):
             span = max(r.done for r in done) - min(r.arrival for r in done)
             out["python_loop_saturated_mrays_s"] = sum(r.n for r in done) / span / 1e6
         res[key] = out
-    res["loop"] = "native (lt_server_*), 4 streams, chunks of 262,144 rays, 4 GiB admission budget"
+    res["loop"] = "native (lt_server_*), 8 streams, chunks of 262,144 rays, 4 GiB admission budget"
     return res
 
 
