@@ -231,11 +231,16 @@ __global__ __launch_bounds__((eval_waves<H, TRAIN>() * 64)) void map_eval_bf16_k
     constexpr int NT = eval_subtiles<H, TRAIN>();  // 16-ray MFMA N tiles per wave
     constexpr int RPW = 16 * NT;                   // rays per wave tile
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
-    for (int64_t o = threadIdx.x * 16; o < A.lds_bytes; o += blockDim.x * 16)
-        *reinterpret_cast<uint4 *>(lds + o) = *reinterpret_cast<const uint4 *>(A.img + o);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // The staged part of the image (whole 1 KiB rows) goes to LDS by direct
+    // global-to-LDS loads, one row per wave instruction, all in flight at
+    // once: a copy through registers waits out one load latency per row
+    // and thread, which short launches (a few tiles per workgroup) feel.
+    for (int64_t row = wave; row * 1024 < A.lds_bytes; row += kWaves)
+        __builtin_amdgcn_global_load_lds(A.img + row * 1024 + lane * 16, lds + row * 1024, 16, 0, 0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
 
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, col = lane & 15;
     const float *bias = reinterpret_cast<const float *>(lds + A.img_bias);
     const float *nrm = bias + A.D * H + 16 * A.TO;  // in_shift[6], in_scale[6], out_shift, out_scale
@@ -585,6 +590,8 @@ static lt_status launch_bf16_impl(const Map &M, const lt_rays &rays, const lt_ma
     const MapLayout &L = M.lay;
     A.img = FP8 ? M.img_fp8 : M.img_bf16;
     A.lds_bytes = FP8 ? L.img8_lds_bytes : L.out_in_lds_bytes;
+    if (A.lds_bytes % 1024 != 0 || A.lds_bytes > kMaxLds)
+        return fail(LT_ERR_STATE, "packed image not staged in whole 1 KiB rows");
     A.D = L.D;
     A.P = L.P;
     A.TO = L.TO;
