@@ -251,10 +251,13 @@ __global__ __launch_bounds__(waves_for<H>() * 64) void bwd_kernel(BwdArgs A)
     constexpr int T = H / 16, C = H / 32;
     constexpr int kWaves = waves_for<H>();
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
-    for (int64_t o = threadIdx.x * 16; o < A.lds_bytes; o += blockDim.x * 16)
-        *reinterpret_cast<uint4 *>(lds + o) = *reinterpret_cast<const uint4 *>(A.wt + o);
-    __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // transposed weights (whole 1 KiB fragments) into LDS by direct
+    // global-to-LDS loads, all in flight before one wait
+    for (int64_t row = wave; row * 1024 < A.lds_bytes; row += kWaves)
+        __builtin_amdgcn_global_load_lds(A.wt + row * 1024 + lane * 16, lds + row * 1024, 16, 0, 0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
     const int g = lane >> 4, col = lane & 15;
     const int64_t hid_bytes = static_cast<int64_t>(A.D - 1) * T * C * kFragBytes;
     const uint8_t *wt_out = A.out_from_lds ? lds + hid_bytes : A.wt + hid_bytes;
@@ -816,6 +819,8 @@ static lt_status run_backward(Map &M, const WsLayout &w, uint8_t *ws, const floa
     const int64_t full = wt_bytes(L);
     B.out_from_lds = full <= kMaxLds;
     B.lds_bytes = B.out_from_lds ? full : wt_hidden_bytes(L);
+    if (B.lds_bytes % 1024 != 0 || B.lds_bytes > kMaxLds)
+        return fail(LT_ERR_STATE, "transposed image not staged in whole 1 KiB rows");
     B.D = L.D;
     B.P = L.P;
     B.TO = L.TO;
