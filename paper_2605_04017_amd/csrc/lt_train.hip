@@ -426,9 +426,14 @@ __global__ __launch_bounds__(256) void dw_kernel(DwArgs A)
         const int64_t ray0 = ch * kDwChunk;
         // --- gradients into dl[row][ray]
         if (is_out) {
+            // only the rows of this group's M tiles: with many heads the
+            // groups split the output layer, and each reads its own rows
             const int slots = 16 * L.TO;
-            for (int e = threadIdx.x; e < slots * kDwChunk; e += blockDim.x) {
-                const int s = e / kDwChunk, rr = e % kDwChunk;
+            const int t_lo = group * 4 * kDwTilesPerWave;
+            const int t_hi = total < t_lo + 4 * kDwTilesPerWave ? total : t_lo + 4 * kDwTilesPerWave;
+            const int s_lo = 16 * (t_lo / n_tiles), s_hi = 16 * ((t_hi - 1) / n_tiles + 1);
+            for (int e = threadIdx.x; e < (s_hi - s_lo) * kDwChunk; e += blockDim.x) {
+                const int s = s_lo + e / kDwChunk, rr = e % kDwChunk;
                 const int64_t r = ray0 + rr;
                 const int head = s / kHeadSlots, q = s % kHeadSlots;
                 const float d = (head < L.P && q < kMapOut && r < A.n)
