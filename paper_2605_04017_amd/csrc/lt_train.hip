@@ -72,7 +72,7 @@ WsLayout ws_layout(const MapLayout &L, int64_t n)
     w.partial = off;
     off = align256(off + w.slices * L.n_params * 4);
     w.loss = off;
-    off = align256(off + w.loss_blocks * 2 * 4);
+    off = align256(off + w.loss_blocks * L.P * 2 * 4);   // per (ray block, head)
     w.canon = off;   // canonical frame (c, s, sg) per ray for the loss (canonical maps)
     off = align256(off + 3 * w.n_pad * 4);
     w.bytes = off;
@@ -146,7 +146,9 @@ __global__ __launch_bounds__(kLossBlock) void loss_kernel(LossArgs A)
     const float inv = 1.0f / (static_cast<float>(A.n) * A.P);
     if (r < A.n_pad) {
         const float *sh = A.norm + 12, *sc = A.norm + 12 + 5 * A.P;
-        for (int h = 0; h < A.P; ++h) {
+        // one head per grid row, so many-head maps fill the device
+        const int h0 = static_cast<int>(blockIdx.y);
+        for (int h = h0; h < h0 + 1; ++h) {
             float *d = A.dout + static_cast<int64_t>(h * kMapOut) * A.n_pad + r;
             if (r >= A.n) {
                 for (int q = 0; q < kMapOut; ++q)
@@ -226,8 +228,9 @@ __global__ __launch_bounds__(kLossBlock) void loss_kernel(LossArgs A)
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        A.partial[2 * blockIdx.x] = red[0][0];
-        A.partial[2 * blockIdx.x + 1] = red[1][0];
+        const int64_t pi = static_cast<int64_t>(blockIdx.y) * gridDim.x + blockIdx.x;
+        A.partial[2 * pi] = red[0][0];
+        A.partial[2 * pi + 1] = red[1][0];
     }
 }
 
@@ -1009,8 +1012,9 @@ lt_status lt_map_train_step(lt_map map, const lt_rays *rays, const lt_targets *t
     LA.w_bce = cfg->w_bce;
     LA.w_l2 = cfg->w_l2;
     LA.w_cos = cfg->w_cos;
-    hipLaunchKernelGGL(loss_kernel, dim3(static_cast<uint32_t>(w.loss_blocks)), dim3(kLossBlock), 0,
-                       s, LA);
+    hipLaunchKernelGGL(loss_kernel,
+                       dim3(static_cast<uint32_t>(w.loss_blocks), static_cast<uint32_t>(M->lay.P)),
+                       dim3(kLossBlock), 0, s, LA);
     st = check_hip(hipGetLastError(), "loss_kernel launch");
     if (st != LT_OK)
         return st;
@@ -1032,7 +1036,7 @@ lt_status lt_map_train_step(lt_map map, const lt_rays *rays, const lt_targets *t
     AA.bc1 = static_cast<float>(1.0 - std::pow(static_cast<double>(cfg->beta1), static_cast<double>(cfg->step)));
     AA.bc2 = static_cast<float>(1.0 - std::pow(static_cast<double>(cfg->beta2), static_cast<double>(cfg->step)));
     AA.loss_partial = reinterpret_cast<const float *>(wb + w.loss);
-    AA.loss_blocks = w.loss_blocks;
+    AA.loss_blocks = w.loss_blocks * M->lay.P;
     AA.loss_out = loss_out;
     const double np = static_cast<double>(n) * M->lay.P;
     AA.loss_scale_bce = static_cast<float>(cfg->w_bce / np);
