@@ -435,16 +435,33 @@ __global__ __launch_bounds__(256) void dw_kernel(DwArgs A)
             const int t_lo = group * 4 * kDwTilesPerWave;
             const int t_hi = total < t_lo + 4 * kDwTilesPerWave ? total : t_lo + 4 * kDwTilesPerWave;
             const int s_lo = 16 * (t_lo / n_tiles), s_hi = 16 * ((t_hi - 1) / n_tiles + 1);
-            for (int e = threadIdx.x; e < (s_hi - s_lo) * kDwChunk; e += blockDim.x) {
-                const int s = s_lo + e / kDwChunk, rr = e % kDwChunk;
-                const int64_t r = ray0 + rr;
-                const int head = s / kHeadSlots, q = s % kHeadSlots;
-                const float d = (head < L.P && q < kMapOut && r < A.n)
-                                    ? A.dout[static_cast<int64_t>(head * kMapOut + q) * A.dout_stride + r]
-                                    : 0.0f;
-                const __bf16 hi = to_bf16(d);
-                dl[s * RS + rr] = hi;
-                dl[(slots + s) * RS + rr] = to_bf16(d - static_cast<float>(hi));
+            // eight loads in flight per thread before their LDS writes: with
+            // many heads one workgroup fills a CU's LDS, so load latency is
+            // not hidden by other waves
+            constexpr int kU = 8;
+            const int cnt = (s_hi - s_lo) * kDwChunk;
+            for (int e0 = threadIdx.x; e0 < cnt; e0 += kU * blockDim.x) {
+                float dv[kU];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int e = e0 + u * static_cast<int>(blockDim.x);
+                    const int s = s_lo + e / kDwChunk, rr = e % kDwChunk;
+                    const int64_t r = ray0 + rr;
+                    const int head = s / kHeadSlots, q = s % kHeadSlots;
+                    dv[u] = (e < cnt && head < L.P && q < kMapOut && r < A.n)
+                                ? A.dout[static_cast<int64_t>(head * kMapOut + q) * A.dout_stride + r]
+                                : 0.0f;
+                }
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int e = e0 + u * static_cast<int>(blockDim.x);
+                    if (e >= cnt)
+                        break;
+                    const int s = s_lo + e / kDwChunk, rr = e % kDwChunk;
+                    const __bf16 hi = to_bf16(dv[u]);
+                    dl[s * RS + rr] = hi;
+                    dl[(slots + s) * RS + rr] = to_bf16(dv[u] - static_cast<float>(hi));
+                }
             }
         } else {
             // delta_{layer+1} fragments
