@@ -114,10 +114,28 @@ typedef struct lt_lens_s *lt_lens;
 lt_status lt_lens_create(const lt_surface *surfaces, int32_t n_surfaces,
                          const lt_glass *glasses, int32_t n_glasses, lt_lens *out);
 lt_status lt_lens_destroy(lt_lens lens);
+/* Wavelength of the helium d line, where lt_lens_query reports focal lengths. */
+#define LT_LAMBDA_D_NM 587.5618
+
 /* Counts of a stored lens: all surfaces, refracting surfaces (not the stop),
- * and two-reflection ghost paths = C(n_refracting, 2). */
+ * and two-reflection ghost paths = C(n_refracting, 2) (Sec. 4.2, "Path
+ * Decomposition": paths with at most two reflections); and its paraxial
+ * effective focal length and back focal distance (last vertex to the rear
+ * focal point) in mm at LT_LAMBDA_D_NM, as lt_lens_paraxial gives them.
+ * Any output pointer may be NULL.  Host-only.  Errors: LT_ERR_ARG (NULL
+ * lens). */
 lt_status lt_lens_query(lt_lens lens, int32_t *n_surfaces, int32_t *n_refracting,
-                        int32_t *n_ghost_paths);
+                        int32_t *n_ghost_paths, double *efl_mm, double *bfl_mm);
+
+/* First-order optics of a stored lens at lambda_nm (for tests and lens
+ * set-up; the tracer itself is exact, Sec. 3): a ray parallel to the axis
+ * entering from the object side is traced paraxially (heights y, reduced
+ * slopes nu = n u; nu' = nu - y (n' - n) / R at each surface, y += t nu' / n'
+ * between vertices); efl = -1 / nu'_N for unit entry height, bfl = -y_N n'_N /
+ * nu'_N.  An afocal lens reports +infinity for both.  Either output may be
+ * NULL.  Host-only.  Errors: LT_ERR_ARG (NULL lens, wavelength outside
+ * 380..780 nm). */
+lt_status lt_lens_paraxial(lt_lens lens, double lambda_nm, double *efl_mm, double *bfl_mm);
 
 /* ------------------------------------------------------------------ paths */
 
@@ -417,6 +435,19 @@ typedef struct {
 
 typedef struct lt_map_s *lt_map;
 
+/* The symmetry-reduced frame of a canonical-input map (Sec. 4.1, geometric
+ * simplification), computed by the same device function the map kernels
+ * use, for taking a canonical map's normalisation statistics: rays_out (may
+ * be NULL) receives (r, 0, dx', dy', dz, lambda) per ray as described at
+ * lt_map_desc.canonical; if exits is not NULL, its x, y, dx, dy fields,
+ * head-major [n_heads][n] exit rays of these rays in the lens frame, are
+ * moved in place into each ray's frame (x' = c x + s y, y' = sg (c y - s x),
+ * likewise the direction; FP32, one rounding per operation; NaN stays NaN;
+ * its other fields are not used).  Errors: LT_ERR_ARG (NULL rays, a NULL
+ * field that is used, both outputs NULL, n or n_heads negative), LT_ERR_DEVICE. */
+lt_status lt_canonical_frame(const lt_rays *rays, const lt_ray_buffers *rays_out,
+                             const lt_exit *exits, int32_t n_heads, int64_t n, void *stream);
+
 /* Per-head outputs, head-major: field[p * n + r] (device). */
 typedef struct {
     float *logit;
@@ -437,7 +468,8 @@ lt_status lt_map_destroy(lt_map map);
 /* Number of FP32 parameters. */
 int64_t lt_map_num_params(lt_map map);
 /* Copy count (= lt_map_num_params) FP32 parameters from / to device memory,
- * stream-ordered.  Setting parameters invalidates the packed BF16/FP8 copies;
+ * stream-ordered (the trained weights of the per-path networks, Sec. 5.1
+ * "MLP Training"; also checkpoint and resume of a fit).  Setting parameters invalidates the packed BF16/FP8 copies;
  * they are rebuilt on the stream by the next evaluation.  Getting them before
  * any were set: LT_ERR_STATE. */
 lt_status lt_map_set_params(lt_map map, const float *params, int64_t count, void *stream);
@@ -449,7 +481,9 @@ lt_status lt_map_set_norm(lt_map map, const float *in_shift, const float *in_sca
                           const float *out_shift, const float *out_scale);
 
 /* Build the packed copy of the parameters that lt_map_eval uses for dtype
- * now, on the stream (otherwise the first evaluation after
+ * now, on the stream (Sec. 5.1 "Inference": the trained network is evaluated
+ * inside the renderer at reduced cost; here the reduced-precision copies are
+ * made once per parameter change) (otherwise the first evaluation after
  * lt_map_set_params / a training step does it).  Evaluations that may run
  * concurrently on several streams should be preceded by this call, since
  * the lazy repack is not serialised between streams.  Errors: LT_ERR_ARG,
@@ -521,19 +555,25 @@ typedef struct {
     float w_cos;
 } lt_train_cfg;
 
-/* Bytes of device workspace a training call on n rays needs (-1 on error).
+/* Bytes of device workspace a training call on n rays needs (-1 on error):
+ * the activations a hand-written backward keeps between the forward and the
+ * backward pass of the Sec. 5.1 "MLP Training" loss, and per-slice gradient
+ * partials.
  * The workspace must be 256-byte aligned; its content between calls is only
  * meaningful from lt_map_forward_train to lt_map_backward. */
 int64_t lt_map_workspace_bytes(lt_map map, int64_t n);
 
-/* Training forward (BF16, as lt_map_eval): writes the raw network outputs
+/* Training forward (Sec. 5.1 "MLP Training"; BF16, as lt_map_eval): writes
+ * the raw network outputs
  * o_raw[6 * n_heads][n] (row 6p + q: logit, then the normalised x, y, dx, dy,
  * throughput of head p) and keeps the activations in the workspace for
  * lt_map_backward.  Allocates nothing. */
 lt_status lt_map_forward_train(lt_map map, const lt_rays *rays, float *o_raw, void *workspace,
                                int64_t workspace_bytes, int64_t n, void *stream);
 
-/* Hand-written backward pass of the last lt_map_forward_train on the same
+/* Hand-written backward pass (the gradient of the Sec. 5.1 "MLP Training"
+ * losses with respect to the parameters, by the chain rule through the
+ * network of Sec. 4.2) of the last lt_map_forward_train on the same
  * workspace: given dL/do_raw (same layout as o_raw), writes dL/dparams
  * (lt_map_num_params floats, parameter order).  BF16 MFMA with FP32
  * accumulation: gradients of hidden layers are rounded to BF16 before the
@@ -542,9 +582,14 @@ lt_status lt_map_forward_train(lt_map map, const lt_rays *rays, float *o_raw, vo
 lt_status lt_map_backward(lt_map map, const float *grad_o, void *workspace,
                           int64_t workspace_bytes, float *grad_params, int64_t n, void *stream);
 
-/* One fused training step on a batch of n rays: forward, loss, backward and
- * Adam on the map's FP32 master parameters and moments.  loss_out (device,
- * 3 floats, may be NULL): total, BCE part, L2 part.  Allocates nothing. */
+/* One fused training step on a batch of n rays (Sec. 5.1 "MLP Training":
+ * binary cross-entropy for the classifier, a regression loss for the
+ * regressor, Adam): forward, loss, backward and Adam on the map's FP32 master
+ * parameters and moments.  loss_out (device, 3 floats, may be NULL): total,
+ * BCE part, L2 part.  Allocates nothing.
+ * Training (this call, lt_map_forward_train, lt_map_backward) supports at
+ * most 62 heads at width 128 (any head count at widths 32 and 64); more is
+ * LT_ERR_ARG before anything is enqueued. */
 lt_status lt_map_train_step(lt_map map, const lt_rays *rays, const lt_targets *targets, int64_t n,
                             const lt_train_cfg *cfg, void *workspace, int64_t workspace_bytes,
                             float *loss_out, void *stream);

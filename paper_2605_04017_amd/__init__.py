@@ -24,7 +24,7 @@ LT_ACT_TANH, LT_ACT_RELU = N.LT_ACT_TANH, N.LT_ACT_RELU
 MAP_FIELDS = ("logit", "mask", "x", "y", "dx", "dy", "dz", "throughput")
 LT_ERR_ARG, LT_ERR_STATE = N.LT_ERR_ARG, N.LT_ERR_STATE
 
-__all__ = ["LtError", "Lens", "lt_lens_create", "lt_lens_query", "lt_trace", "lt_trace_ex",
+__all__ = ["LtError", "Lens", "lt_lens_create", "lt_lens_query", "lt_lens_paraxial", "lt_canonical_frame", "lt_trace", "lt_trace_ex",
            "lt_ghost_index", "lt_ghost_path", "empty_exit", "RAY_FIELDS", "EXIT_FIELDS",
            "LT_TRACE_PLAIN_FP32", "LT_F32", "LT_BF16", "LT_FP8", "LT_ACT_TANH", "LT_ACT_RELU",
            "Map", "lt_map_create", "lt_map_set_params", "lt_map_get_params", "lt_map_set_norm",
@@ -131,14 +131,25 @@ def lt_lens_create(surfaces, glasses) -> Lens:
     h = C.c_void_p()
     N.check(N.lib().lt_lens_create(S, len(srows), G, len(grows), C.byref(h)))
     ns, nr, ng = C.c_int32(), C.c_int32(), C.c_int32()
-    N.check(N.lib().lt_lens_query(h, C.byref(ns), C.byref(nr), C.byref(ng)))
+    N.check(N.lib().lt_lens_query(h, C.byref(ns), C.byref(nr), C.byref(ng), None, None))
     return Lens(h.value, ns.value, nr.value, ng.value, float(srows[0][2]) if srows else 0.0)
 
 
-def lt_lens_query(lens: Lens) -> Tuple[int, int, int]:
+def lt_lens_query(lens: Lens) -> Tuple[int, int, int, float, float]:
+    """(surfaces, refracting surfaces, ghost paths, paraxial EFL, back focal
+    distance) with the focal lengths in mm at the d line (587.5618 nm)."""
     ns, nr, ng = C.c_int32(), C.c_int32(), C.c_int32()
-    N.check(N.lib().lt_lens_query(lens.handle, C.byref(ns), C.byref(nr), C.byref(ng)))
-    return ns.value, nr.value, ng.value
+    efl, bfl = C.c_double(), C.c_double()
+    N.check(N.lib().lt_lens_query(lens.handle, C.byref(ns), C.byref(nr), C.byref(ng),
+                                  C.byref(efl), C.byref(bfl)))
+    return ns.value, nr.value, ng.value, efl.value, bfl.value
+
+
+def lt_lens_paraxial(lens: Lens, lambda_nm: float) -> Tuple[float, float]:
+    """Paraxial (EFL, back focal distance) in mm at ``lambda_nm``."""
+    efl, bfl = C.c_double(), C.c_double()
+    N.check(N.lib().lt_lens_paraxial(lens.handle, float(lambda_nm), C.byref(efl), C.byref(bfl)))
+    return efl.value, bfl.value
 
 
 def lt_lens_planes(lens: Lens) -> Tuple[float, float]:
@@ -241,6 +252,37 @@ def lt_rays_generate(lens: Lens, n: int, seed: int, first: int = 0, half_width: 
     N.check(N.lib().lt_rays_generate(lens.handle, C.byref(cfg), C.byref(b), int(n),
                                      C.c_void_p(_stream_ptr(stream) if n else 0)))
     return out
+
+
+def lt_canonical_frame(rays: Dict, exits: Optional[Dict] = None, n_heads: int = 1,
+                       out: Optional[Dict] = None, want_rays: bool = True,
+                       n: Optional[int] = None, stream=None) -> Optional[Dict]:
+    """Symmetry-reduced frame of a canonical-input map (the map kernels' own
+    transform): returns the canonical rays (dict of float32 tensors) unless
+    ``want_rays`` is False; ``exits`` (dict with x, y, dx, dy float32 tensors of
+    n_heads * n entries, head-major) is moved into each ray's frame in place."""
+    torch = _torch()
+    if n is None:
+        n = int(rays["x"].numel())
+    ro = None
+    if want_rays:
+        if out is None:
+            out = {k: torch.empty(n, dtype=torch.float32, device=rays["x"].device)
+                   for k in RAY_FIELDS}
+        ro = N.lt_ray_buffers()
+        for k in RAY_FIELDS:
+            setattr(ro, k, _dev_ptr(out[k], torch.float32, n, f"out[{k}]") if n else None)
+    ex = None
+    if exits is not None:
+        ex = N.lt_exit()
+        for k in ("x", "y", "dx", "dy"):
+            setattr(ex, k, _dev_ptr(exits[k], torch.float32, n_heads * n, f"exits[{k}]") if n else None)
+    N.check(N.lib().lt_canonical_frame(C.byref(_rays_struct(rays, n)),
+                                       C.byref(ro) if ro is not None else None,
+                                       C.byref(ex) if ex is not None else None,
+                                       int(n_heads if exits is not None else 0), int(n),
+                                       C.c_void_p(_stream_ptr(stream) if n else 0)))
+    return out if want_rays else None
 
 
 def lt_rays_generate_forward(lens: Lens, n: int, seed: int, light=(0.0, 0.0, 1.0),

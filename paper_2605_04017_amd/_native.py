@@ -121,7 +121,11 @@ SIGNATURES = {
                                  C.c_int32, C.POINTER(C.c_void_p)]),
     "lt_lens_destroy": (C.c_int, [C.c_void_p]),
     "lt_lens_query": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
-                                C.POINTER(C.c_int32)]),
+                                C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "lt_lens_paraxial": (C.c_int, [C.c_void_p, C.c_double, C.POINTER(C.c_double),
+                                   C.POINTER(C.c_double)]),
+    "lt_canonical_frame": (C.c_int, [C.POINTER(lt_rays), C.POINTER(lt_ray_buffers), C.POINTER(lt_exit),
+                                     C.c_int32, C.c_int64, C.c_void_p]),
     "lt_lens_planes": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "lt_ghost_index": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32]),
     "lt_ghost_path": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(lt_path)]),

@@ -240,8 +240,32 @@ lt_status lt_lens_destroy(lt_lens lens)
     return LT_OK;
 }
 
+// First-order (paraxial) trace of a ray parallel to the axis entering from
+// the object side: heights y and reduced slopes nu = n u, refraction
+// nu' = nu - y (n' - n) c at each surface, transfer y += t nu' / n' to the
+// next vertex.  The effective focal length is -y_1 / nu'_N, the back focal
+// distance (last vertex to the focal point) -y_N n'_N / nu'_N.
+static bool paraxial_focal(const Lens &L, double lam_um, double *efl, double *bfl)
+{
+    double y = 1.0, nu = 0.0, n = 1.0;
+    for (int k = 0; k < L.ns; ++k) {
+        const lt_surface &s = L.surf[k];
+        const double n2 = glass_index_host(L.glass[s.glass_after], lam_um);
+        const double c = s.radius_mm == 0.0 ? 0.0 : 1.0 / s.radius_mm;
+        nu -= y * (n2 - n) * c;
+        n = n2;
+        if (k + 1 < L.ns)
+            y += s.thickness_mm * nu / n;
+    }
+    if (nu == 0.0)
+        return false;   // afocal
+    *efl = -1.0 / nu;
+    *bfl = -y * n / nu;
+    return true;
+}
+
 lt_status lt_lens_query(lt_lens lens, int32_t *n_surfaces, int32_t *n_refracting,
-                        int32_t *n_ghost_paths)
+                        int32_t *n_ghost_paths, double *efl_mm, double *bfl_mm)
 {
     Lens *L = as_lens(lens);
     if (!L)
@@ -249,6 +273,24 @@ lt_status lt_lens_query(lt_lens lens, int32_t *n_surfaces, int32_t *n_refracting
     if (n_surfaces) *n_surfaces = L->ns;
     if (n_refracting) *n_refracting = L->nr;
     if (n_ghost_paths) *n_ghost_paths = L->nr * (L->nr - 1) / 2;
+    if (efl_mm || bfl_mm)
+        return lt_lens_paraxial(lens, LT_LAMBDA_D_NM, efl_mm, bfl_mm);
+    return LT_OK;
+}
+
+lt_status lt_lens_paraxial(lt_lens lens, double lambda_nm, double *efl_mm, double *bfl_mm)
+{
+    Lens *L = as_lens(lens);
+    if (!L)
+        return fail(LT_ERR_ARG, "NULL lens");
+    if (!(lambda_nm >= 380.0 && lambda_nm <= 780.0))
+        return fail(LT_ERR_ARG, "wavelength outside 380..780 nm");
+    double efl = 0.0, bfl = 0.0;
+    if (!paraxial_focal(*L, lambda_nm / 1000.0, &efl, &bfl)) {
+        efl = bfl = INFINITY;
+    }
+    if (efl_mm) *efl_mm = efl;
+    if (bfl_mm) *bfl_mm = bfl;
     return LT_OK;
 }
 

@@ -773,6 +773,24 @@ __global__ __launch_bounds__(256) void dw_hidden_kernel(DwArgs A)
         }
 }
 
+// LDS of dw_kernel: the staged output-gradient rows of one group (two
+// 16-row fragments per output tile) or the layer's own rows, the activation
+// rows and the selector, each a padded chunk of BF16.
+static size_t dw_lds_bytes(const MapLayout &L)
+{
+    const int rows_max = 2 * 16 * L.TO > L.H ? 2 * 16 * L.TO : L.H;
+    return static_cast<size_t>(rows_max + L.H + 16) * (kDwChunk + kDwPad) * 2;
+}
+
+// Checked by every training call before it enqueues anything: at width 128
+// the output-gradient staging of more than 62 heads exceeds a CU's LDS.
+static lt_status check_train_shape(const MapLayout &L)
+{
+    if (dw_lds_bytes(L) > static_cast<size_t>(kMaxLds))
+        return fail(LT_ERR_ARG, "too many heads to train at this width (at most 62 at width 128)");
+    return LT_OK;
+}
+
 template <int H>
 static lt_status launch_dw(const DwArgs &A, const WsLayout &w, hipStream_t s)
 {
@@ -798,8 +816,7 @@ static lt_status launch_dw(const DwArgs &A, const WsLayout &w, hipStream_t s)
         if (gr > max_groups)
             max_groups = gr;
     }
-    const int rows_max = 2 * 16 * L.TO > H ? 2 * 16 * L.TO : H;
-    const size_t lds = static_cast<size_t>(rows_max + H + 16) * (kDwChunk + kDwPad) * 2;
+    const size_t lds = dw_lds_bytes(L);
     if (lds > static_cast<size_t>(kMaxLds))
         return fail(LT_ERR_ARG, "too many heads for the weight-gradient kernel");
     const uint32_t layers = H >= 64 ? 2u : static_cast<uint32_t>(L.D + 1);
@@ -928,7 +945,10 @@ lt_status lt_map_forward_train(lt_map map, const lt_rays *rays, float *o_raw, vo
     if (!rays_ok(rays))
         return fail(LT_ERR_ARG, "NULL ray field");
     WsLayout w;
-    lt_status st = check_ws(M, ws, ws_bytes, n, &w);
+    lt_status st = check_train_shape(M->lay);
+    if (st != LT_OK)
+        return st;
+    st = check_ws(M, ws, ws_bytes, n, &w);
     if (st != LT_OK)
         return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -956,7 +976,10 @@ lt_status lt_map_backward(lt_map map, const float *grad_o, void *ws, int64_t ws_
     if (!M->has_params)
         return fail(LT_ERR_STATE, "parameters were never set");
     WsLayout w;
-    lt_status st = check_ws(M, ws, ws_bytes, n, &w);
+    lt_status st = check_train_shape(M->lay);
+    if (st != LT_OK)
+        return st;
+    st = check_ws(M, ws, ws_bytes, n, &w);
     if (st != LT_OK)
         return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -995,7 +1018,10 @@ lt_status lt_map_train_step(lt_map map, const lt_rays *rays, const lt_targets *t
         !(cfg->w_cos >= 0.0f && cfg->w_cos < 1e30f))
         return fail(LT_ERR_ARG, "bad optimiser settings (step must be >= 1)");
     WsLayout w;
-    lt_status st = check_ws(M, ws, ws_bytes, n, &w);
+    lt_status st = check_train_shape(M->lay);
+    if (st != LT_OK)
+        return st;
+    st = check_ws(M, ws, ws_bytes, n, &w);
     if (st != LT_OK)
         return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);

@@ -1,9 +1,10 @@
 """Host-side set-up for fitting maps with the library: seeded initial
-parameters in the library's flat layout, normalisation statistics of inputs
-and traced targets, and the symmetry-reduced frame those statistics are taken
-in for canonical-input maps (Sec. 4.1, geometric simplification).  None of
-this runs per ray on the hot path; the training step itself is
-lt_map_train_step."""
+parameters in the library's flat layout and normalisation statistics of
+inputs and traced targets.  For canonical-input maps the statistics are taken
+in the symmetry-reduced frame (Sec. 4.1, geometric simplification), which the
+library computes on the device (lt_canonical_frame, the map kernels' own
+transform).  None of this runs per ray on the hot path; the training step
+itself is lt_map_train_step."""
 from __future__ import annotations
 
 from typing import Dict, List, Tuple
@@ -39,40 +40,25 @@ def norm_stats(a: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
     return mu, sd
 
 
-def canonical_rotation(x: np.ndarray, y: np.ndarray, dx: np.ndarray, dy: np.ndarray):
-    """Rotation (c, s) taking the sensor point onto the +x half line and the
-    mirror flag making the rotated direction's y component non-negative (the
-    identity rotation for a point on the axis)."""
-    x, y, dx, dy = (np.asarray(v, np.float64) for v in (x, y, dx, dy))
-    r = np.hypot(x, y)
-    on_axis = r == 0
-    rr = np.where(on_axis, 1.0, r)
-    c = np.where(on_axis, 1.0, x / rr)
-    s = np.where(on_axis, 0.0, y / rr)
-    flip = (c * dy - s * dx) < 0
-    return c, s, flip
-
-
-def canonical_inputs(rays: Dict[str, np.ndarray]) -> Dict[str, np.ndarray]:
-    """Sensor-side rays in their symmetry-reduced frame (float64): r, 0,
-    rotated (and mirrored) direction, dz and wavelength unchanged."""
-    c, s, flip = canonical_rotation(rays["x"], rays["y"], rays["dx"], rays["dy"])
-    x, y, dx, dy = (np.asarray(rays[k], np.float64) for k in ("x", "y", "dx", "dy"))
-    m = np.where(flip, -1.0, 1.0)
-    return {"x": c * x + s * y, "y": np.zeros_like(x), "dx": c * dx + s * dy,
-            "dy": m * (c * dy - s * dx), "dz": np.asarray(rays["dz"], np.float64),
-            "lambda_nm": np.asarray(rays["lambda_nm"], np.float64)}
-
-
-def canonical_outputs(rays: Dict[str, np.ndarray], out: np.ndarray) -> np.ndarray:
-    """Exit (x, y, dx, dy, ...) columns of `out` (rows = the given rays) moved
-    into each ray's symmetry-reduced frame; further columns unchanged."""
-    c, s, flip = canonical_rotation(rays["x"], rays["y"], rays["dx"], rays["dy"])
-    m = np.where(flip, -1.0, 1.0)
-    o = np.array(out, np.float64, copy=True)
-    x, y, dx, dy = o[:, 0].copy(), o[:, 1].copy(), o[:, 2].copy(), o[:, 3].copy()
-    o[:, 0], o[:, 1] = c * x + s * y, m * (c * y - s * x)
-    o[:, 2], o[:, 3] = c * dx + s * dy, m * (c * dy - s * dx)
+def _canonical(rays: Dict[str, np.ndarray], reg: np.ndarray = None):
+    """Rays (and optionally exit rows reg[:, :4] of the same rays) in the
+    symmetry-reduced frame, computed on the device by lt_canonical_frame."""
+    import torch
+    from . import lt_canonical_frame
+    dev = torch.device("cuda")
+    r = {k: torch.from_numpy(np.ascontiguousarray(rays[k], np.float32)).to(dev)
+         for k in ("x", "y", "dx", "dy", "dz", "lambda_nm")}
+    ex = None
+    if reg is not None:
+        ex = {k: torch.from_numpy(np.ascontiguousarray(reg[:, i], np.float32)).to(dev)
+              for i, k in enumerate(("x", "y", "dx", "dy"))}
+    out = lt_canonical_frame(r, ex, 1, want_rays=reg is None)
+    torch.cuda.synchronize()
+    if reg is None:
+        return {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
+    o = np.array(reg, np.float64, copy=True)
+    for i, k in enumerate(("x", "y", "dx", "dy")):
+        o[:, i] = ex[k].cpu().numpy()
     return o
 
 
@@ -81,9 +67,10 @@ def map_norms(rays: Dict[str, np.ndarray], targets: List[Tuple[np.ndarray, np.nd
     """(in_shift, in_scale, out_shift [P, 5], out_scale [P, 5]) for a map:
     input statistics over `rays`, and per head the statistics of the traced
     exit (x, y, dx, dy, throughput) over its valid rays.  `targets` holds per
-    head (valid mask, [n, 5] exit values); with `canonical` both are taken in
+    head (valid mask, [n_valid, 5] exit values of the valid rays); with
+    `canonical` both are taken in
     the symmetry-reduced frame."""
-    src = canonical_inputs(rays) if canonical else rays
+    src = _canonical(rays) if canonical else rays
     x = np.stack([np.asarray(src[k], np.float64) for k in ("x", "y", "dx", "dy", "dz", "lambda_nm")], 1)
     in_shift, in_sd = norm_stats(x)
     P = len(targets)
@@ -94,7 +81,7 @@ def map_norms(rays: Dict[str, np.ndarray], targets: List[Tuple[np.ndarray, np.nd
             continue
         reg = np.asarray(reg, np.float64)
         if canonical:
-            sub = {f: np.asarray(rays[f])[ok] for f in ("x", "y", "dx", "dy")}
-            reg = canonical_outputs(sub, reg)
+            sub = {f: np.asarray(rays[f])[ok] for f in ("x", "y", "dx", "dy", "dz", "lambda_nm")}
+            reg = _canonical(sub, reg)
         out_shift[k], out_scale[k] = norm_stats(reg)
     return in_shift, 1.0 / in_sd, out_shift, out_scale

@@ -47,8 +47,46 @@ def test_lens_create_and_query():
     lens = synth.config_lens(2)
     h = lt.lt_lens_create(lens.surfaces, lens.glasses)
     assert (h.n_surfaces, h.n_refracting, h.n_ghost_paths) == (12, 11, 55)
-    assert lt.lt_lens_query(h) == (12, 11, 55)
+    assert lt.lt_lens_query(h)[:3] == (12, 11, 55)
     h.close()
+
+
+def _abcd_reduced(lens, lam_nm):
+    """System matrix (heights, reduced angles) from the front vertex to the
+    last vertex: refraction [[1, 0], [-P, 1]] with P = (n' - n) / R, transfer
+    [[1, t / n'], [0, 1]] (a product of matrices; the library traces y-nu)."""
+    import numpy as np
+    import oracle
+    ns = [1.0] + [oracle.glass_index(lens, s.glass_after, lam_nm) for s in lens.surfaces]
+    M = np.eye(2)
+    for k, s in enumerate(lens.surfaces):
+        P = 0.0 if s.radius == 0 else (ns[k + 1] - ns[k]) / s.radius
+        M = np.array([[1.0, 0.0], [-P, 1.0]]) @ M
+        if k < len(lens.surfaces) - 1:
+            M = np.array([[1.0, s.thickness / ns[k + 1]], [0.0, 1.0]]) @ M
+    return M, ns[-1]
+
+
+@pytest.mark.parametrize("config", [1, 2, 5])
+def test_lens_paraxial_focal_lengths(config):
+    """lt_lens_query / lt_lens_paraxial EFL and back focal distance against
+    the ABCD matrix of the prescription (EFL = -1/C, BFD = -n' A/C), which the
+    oracle pins tie to finite-height traces of the exact tracer; and the
+    synthetic lenses put the sensor at the d-line paraxial focus."""
+    lenses = [synth.config_lens(config)] if config != 5 else synth.serve_lenses()
+    for lens in lenses:
+        h = lt.lt_lens_create(lens.surfaces, lens.glasses)
+        for lam in (587.5618, 450.0, 650.0):
+            M, n_img = _abcd_reduced(lens, lam)
+            efl, bfl = lt.lt_lens_paraxial(h, lam)
+            assert abs(efl - (-1.0 / M[1, 0])) <= 1e-12 * abs(efl)
+            assert abs(bfl - (-n_img * M[0, 0] / M[1, 0])) <= 1e-12 * abs(bfl)
+        ns_, nr, ng, efl_d, bfl_d = lt.lt_lens_query(h)
+        assert (efl_d, bfl_d) == lt.lt_lens_paraxial(h, 587.5618)
+        assert abs(bfl_d - lens.surfaces[-1].thickness) < 1e-6 * abs(bfl_d)
+        with pytest.raises(lt.LtError):
+            lt.lt_lens_paraxial(h, 200.0)
+        h.close()
 
 
 @pytest.mark.parametrize("mutate,msg", [

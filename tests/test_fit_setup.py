@@ -27,23 +27,6 @@ def test_param_layout_matches_the_library_order():
         assert np.array_equal(v, F.init_params(width, depth, heads, 1))
 
 
-def test_canonical_inputs_agree_with_the_oracle_frame():
-    rays = synth.config_rays(2, 20000)
-    a = F.canonical_inputs(rays)
-    b, c, s, flip = mlp.canonical_frame(rays)
-    for k in ("x", "dx", "dy", "dz", "lambda_nm"):
-        assert np.allclose(a[k], b[k], atol=2e-6), k
-    assert np.all(a["y"] == 0) and np.all(a["dy"] >= 0) and np.all(a["x"] >= 0)
-    # outputs: the oracle's transform of lab-frame exits
-    rng = np.random.default_rng(0)
-    out = rng.normal(size=(20000, 5))
-    got = F.canonical_outputs(rays, out)
-    ref = mlp.to_canonical_frame(out[:, 0], out[:, 1], out[:, 2], out[:, 3], c, s, flip)
-    for i in range(4):
-        assert np.allclose(got[:, i], ref[i], atol=1e-5)
-    assert np.array_equal(got[:, 4], out[:, 4])
-
-
 def test_map_norms_are_standardising():
     rays = synth.config_rays(2, 10000)
     ok = np.arange(10000) % 3 == 0

@@ -21,6 +21,8 @@ from oracle import mlp
 pytestmark = pytest.mark.gpu
 
 MED_TOL, P99_TOL, MAX_TOL = 1e-5, 2e-3, 2e-2
+# FP8 hidden layers: 3 mantissa bits, so a flip is 16 times a BF16 one
+FP8_TOLS = (1e-4, 3e-2, 3e-1)
 
 
 @pytest.fixture(scope="module")
@@ -158,9 +160,11 @@ def test_streamed_output_layer(dev, width, heads, n, dtype):
         MED_TOL, P99_TOL, MAX_TOL = saved
 
 
-def test_multi_head_full_size_sampled(dev):
-    """The 56-head map on 16,777,216 rays (the launch the benchmark times),
-    every 1024th ray checked for every head."""
+@pytest.mark.parametrize("dtype", [1, 2, 0])
+def test_multi_head_full_size_sampled(dev, dtype):
+    """The 56-head map on 16,777,216 rays (the launches the benchmark times:
+    every workgroup loops over many ray tiles), every 1024th ray checked for
+    every head, in BF16, FP8 and FP32."""
     import torch
     import paper_2605_04017_amd as lt
     n = 16777216
@@ -169,13 +173,19 @@ def test_multi_head_full_size_sampled(dev):
     p = make_params(desc, 45, {k: v[:65536] for k, v in rays.items()})
     m = gpu_map(p, dev)
     r = {k: torch.from_numpy(v).to(dev) for k, v in rays.items()}
-    out = lt.lt_map_eval(m, lt.LT_BF16, r)
+    out = lt.lt_map_eval(m, dtype, r)
     torch.cuda.synchronize()
     sel = np.arange(0, n, 1024)
     g = {k: v[:, ::1024].cpu().numpy() for k, v in out.items()}
     del out, r
     torch.cuda.empty_cache()
-    compare(g, p, {k: v[sel] for k, v in rays.items()}, "bf16")
+    sub = {k: v[sel] for k, v in rays.items()}
+    if dtype == lt.LT_F32:
+        _with_tols(*F32_TOLS, lambda: compare(g, p, sub, "f32"))
+    elif dtype == lt.LT_FP8:
+        _with_tols(*FP8_TOLS, lambda: compare(g, p, sub, "fp8"))
+    else:
+        compare(g, p, sub, "bf16")
 
 
 @pytest.mark.parametrize("width,heads", [(32, 3), (64, 2)])
@@ -455,3 +465,36 @@ def test_forward_map(dev, heads, dtype, canonical, n):
     else:
         compare(g, p, rays, mode)
     assert np.all(g["dz"][g["mask"] == 1] >= 0)
+
+
+def test_canonical_frame_call(dev):
+    """lt_canonical_frame (the set-up's source of canonical statistics) gives
+    the oracle's FP32 canonical inputs bit for bit and its exit transform to
+    FP32 rounding; NaN exits stay NaN."""
+    import torch
+    import paper_2605_04017_amd as lt
+    n, H = 30001, 3
+    rays = synth.config_rays(2, n)
+    rays["x"][:5] = 0.0
+    rays["y"][:5] = 0.0   # on-axis sensor points keep the identity frame
+    r = {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in rays.items()}
+    rng = np.random.default_rng(3)
+    ex_np = {k: rng.normal(0, 5, (H, n)).astype(np.float32) for k in ("x", "y", "dx", "dy")}
+    ex_np["x"][1, 7] = np.nan
+    ex = {k: torch.from_numpy(v.reshape(-1).copy()).to(dev) for k, v in ex_np.items()}
+    out = lt.lt_canonical_frame(r, ex, H)
+    torch.cuda.synchronize()
+    ref, c, s, flip = mlp.canonical_frame(rays)
+    for k in synth.RAY_FIELDS:
+        assert np.array_equal(out[k].cpu().numpy(), ref[k]), k
+    got = {k: v.cpu().numpy().reshape(H, n) for k, v in ex.items()}
+    want = mlp.to_canonical_frame(*(ex_np[k].astype(np.float64) for k in ("x", "y", "dx", "dy")),
+                                  c[None], s[None], flip[None])
+    for i, k in enumerate(("x", "y", "dx", "dy")):
+        a, b = got[k], want[i]
+        fin = np.isfinite(b)
+        assert np.array_equal(np.isnan(a), ~fin), k
+        assert np.all(np.abs(a[fin] - b[fin]) <= 4e-7 * (np.abs(ex_np["x"]) + np.abs(ex_np["y"])
+                                                         + np.abs(ex_np["dx"]) + np.abs(ex_np["dy"]))[fin]), k
+    with pytest.raises(lt.LtError):
+        lt.lt_canonical_frame(r, None, 1, want_rays=False)

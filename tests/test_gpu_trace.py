@@ -204,24 +204,27 @@ def test_trace_compact_empty_and_errors(dev):
         lt.lt_trace_compact(h, (1, 2, 2), r)
 
 
+@pytest.mark.parametrize("variant", ["float_pair", "fp64"])
 @pytest.mark.parametrize("cfg,n", [(1, 65536), (2, 262144)])
-def test_forward_tracing_all_paths(dev, cfg, n):
+def test_forward_tracing_all_paths(dev, cfg, n, variant):
     """LT_TRACE_FORWARD: scene-side rays from the forward input plane to the
     sensor, transmit and every two-reflection ghost, against the FP64
-    oracle's forward trace (same tolerances as the sensor-side tracer).
-    Exit positions are compared for rays landing within twice the 36 x 24 mm
-    frame's half-extent; grazing rays far off the sensor are compared in mask,
-    direction and throughput only."""
+    oracle's forward trace (same tolerances as the sensor-side tracer), for
+    the default float-pair tracer (the one the flare frame runs) and the
+    FP64 variant.  Exit positions are compared for rays landing within twice
+    the 36 x 24 mm frame's half-extent; grazing rays far off the sensor are
+    compared in mask, direction and throughput only."""
     import paper_2605_04017_amd as lt
     L = synth.config_lens(cfg)
     rays = synth.make_forward_rays(L, n, 6000 + cfg)
     nr = L.n_refracting
     paths = [(0, 0, 0)] + [(1, j, i) for j in range(1, nr + 1) for i in range(j + 1, nr + 1)]
-    if cfg == 2:
+    if cfg == 2 and variant == "fp64":
         paths = paths[::5]
+    flags = lt.LT_TRACE_FORWARD | (lt.LT_TRACE_FP64 if variant == "fp64" else 0)
     worst = 0.0
     for path in paths:
-        g = _gpu_trace(L, rays, dev, path, flags=lt.LT_TRACE_FP64 | lt.LT_TRACE_FORWARD)
+        g = _gpu_trace(L, rays, dev, path, flags=flags)
         o = oracle.trace(L, rays, path, diag=True, forward=True)
         st = compare_trace(g, o, pos_window=(2 * synth.SENSOR_HALF_W, 2 * synth.SENSOR_HALF_H))
         worst = max(worst, st.get("pos_max", 0.0))
@@ -229,7 +232,7 @@ def test_forward_tracing_all_paths(dev, cfg, n):
             assert st["pos_compared"] > n // 20
             assert st["valid"] > n // 20
             assert np.all(g["dz"][g["mask"] == 1] > 0)
-    _report(f"forward C{cfg} {len(paths)} paths", {"worst_pos": worst})
+    _report(f"forward {variant} C{cfg} {len(paths)} paths", {"worst_pos": worst})
 
 
 def test_forward_compact_matches(dev):

@@ -313,3 +313,156 @@ def test_cosine_direction_loss_train_step(dev):
     assert np.mean(np.abs(step[big] - expect[big]) < 1e-6) > 0.99
     with pytest.raises(lt.LtError):
         lt.lt_map_train_step(m, r, t, {"lr": 1e-3, "step": 2, "w_cos": -1.0}, ws)
+
+
+# ------------------------------------------- element-wise step parity ----
+
+def _trace_targets(lens, rays_np, dev, heads):
+    """Traced targets of the first `heads` paths (transmit, then the ghosts
+    in lt_ghost_index order) from the GPU tracer, head-major [heads][n]."""
+    import torch
+    import paper_2605_04017_amd as lt
+    h = lt.lt_lens_create(lens.surfaces, lens.glasses)
+    r = to_dev(rays_np, dev)
+    nr = lens.n_refracting
+    paths = [(0, 0, 0)] + [(1, j, i) for j in range(1, nr + 1) for i in range(j + 1, nr + 1)]
+    n = rays_np["x"].shape[0]
+    t = {"valid": torch.empty((heads, n), dtype=torch.uint8, device=dev)}
+    for k in ("x", "y", "dx", "dy", "throughput"):
+        t[k] = torch.empty((heads, n), dtype=torch.float32, device=dev)
+    for p_i, path in enumerate(paths[:heads]):
+        ex = lt.lt_trace(h, path, r)
+        t["valid"][p_i] = ex["mask"]
+        for k in ("x", "y", "dx", "dy", "throughput"):
+            t[k][p_i] = ex[k]
+    torch.cuda.synchronize()
+    return r, t
+
+
+def _fit_norm(p, t):
+    """Per-head output normalisation from the valid traced targets."""
+    tv = {k: v.cpu().numpy() for k, v in t.items()}
+    for hd in range(p.desc.n_heads):
+        ok = tv["valid"][hd] == 1
+        if ok.sum() < 2:
+            continue
+        reg = np.stack([tv[k][hd][ok] for k in ("x", "y", "dx", "dy", "throughput")], 1)
+        sd = reg.std(0)
+        sd[sd == 0] = 1.0
+        p.out_shift[hd] = reg.mean(0).astype(np.float32)
+        p.out_scale[hd] = sd.astype(np.float32)
+    return tv
+
+
+# Element-wise bound of a GPU gradient g against the reference g_ref of one
+# layer: |g - g_ref| <= GRAD_A |g_ref| + GRAD_B max|g_ref|.  Every gradient
+# element is a sum over the batch; the two sides differ by FP32 accumulation
+# (relative ~ sqrt(K) 2^-24 per product sum, far below GRAD_A) and by the
+# BF16 roundings that FP32 noise moves across a rounding boundary.  Such a
+# flip changes one rounded activation or hidden gradient by one BF16 ulp
+# (2^-8 of it); it hits a fraction f of the batch's terms (f ~ FP32 error /
+# BF16 ulp ~ 1e-3) with random sign, so it moves an element by about
+# 2^-8 sqrt(f n) |term|, while the largest element of a layer is a coherent
+# sum of ~0.1 n |term|: at n = 65,536 the ratio is ~1e-5, and GRAD_B = 1e-4
+# leaves a factor of ten.
+GRAD_A, GRAD_B = 2.0 ** -8, 1e-4
+
+
+def _elementwise(p, g_gpu, g_ref, what):
+    worst = 0.0
+    for li, ((gW, gb), (rW, rb)) in enumerate(zip(split_layers(p, g_gpu), g_ref)):
+        for a, r, nm in ((gW, rW, "W"), (gb, rb, "b")):
+            scale = np.abs(r).max()
+            bound = GRAD_A * np.abs(r) + GRAD_B * scale
+            ex = np.abs(a - r) / np.maximum(bound, 1e-300)
+            worst = max(worst, float(ex.max()))
+            assert np.all(np.abs(a - r) <= bound), (
+                f"{what} layer {li} {nm}: {int((np.abs(a - r) > bound).sum())} of {r.size} elements "
+                f"outside the bound, worst |g - g_ref| / max|g_ref| = "
+                f"{float(np.abs(a - r).max() / scale):.3e}")
+    return worst
+
+
+@pytest.mark.parametrize("width,depth,heads,n,steps", [(128, 5, 1, 65536, 10), (128, 5, 56, 65536, 4),
+                                                       (64, 3, 1, 16384, 3)])
+def test_train_step_elementwise(dev, width, depth, heads, n, steps):
+    """The fused lt_map_train_step at the training configuration's shape
+    (5 x 128 trunk, batch 65,536; one head and the 56-path map) over several
+    Adam steps.  Per step: the loss components against the reference loss
+    of the same parameters (1e-3 relative); the step's gradient, read back
+    from the Adam moments as g = (m_new - beta1 m_old) / (1 - beta1), element
+    by element against the reference gradient with the kernels' BF16
+    rounding; and the second moment and the parameters against the oracle's
+    Adam step driven by that gradient."""
+    import torch
+    import paper_2605_04017_amd as lt
+    L = synth.config_lens(2)
+    rays = synth.config_rays(2, n)
+    desc = mlp.MapDesc(width, depth, heads, mlp.ACT_TANH)
+    p = make_params(desc, 300 + heads, rays)
+    r, t = _trace_targets(L, rays, dev, heads)
+    tv = _fit_norm(p, t)
+    m = gpu_map(p, dev)
+    ws = lt.workspace(m, n)
+    valid = tv["valid"].astype(np.int64)
+    tnorm = mlp.normalise_targets({k: tv[k] for k in ("x", "y", "dx", "dy", "throughput")}, p)
+    b1, b2, eps, lr = 0.9, 0.999, 1e-8, 2e-3
+    P = m.n_params
+    theta = lt.lt_map_get_params(m).cpu().numpy().astype(np.float64)
+    mv = np.zeros(2 * P)
+    worst = 0.0
+    for k in range(1, steps + 1):
+        cfg = {"lr": lr, "beta1": b1, "beta2": b2, "eps": eps, "step": k, "w_bce": 1.0, "w_l2": 1.0}
+        loss = lt.lt_map_train_step(m, r, t, cfg, ws).cpu().numpy().astype(np.float64)
+        theta_new = lt.lt_map_get_params(m).cpu().numpy().astype(np.float64)
+        mv_new = lt.lt_map_adam_state(m).cpu().numpy().astype(np.float64).reshape(-1)
+        q = p.copy()
+        q.set_flat(theta)
+        (lref, bref, l2ref), gref = mlp.loss_and_grad_quantized(q, mlp.features(rays, q), valid, tnorm)
+        for got, ref, nm in ((loss[0], lref, "total"), (loss[1], bref, "bce"), (loss[2], l2ref, "l2")):
+            assert abs(got - ref) <= 1e-3 * abs(ref), f"step {k} {nm} loss {got} vs {ref}"
+        g = (mv_new[:P] - b1 * mv[:P]) / (1.0 - b1)
+        worst = max(worst, _elementwise(q, g, gref, f"step {k}"))
+        st = mlp.AdamState(mv[:P].copy(), mv[P:].copy(), k - 1)
+        mlp.adam_step(q, g, st, lr, b1, b2, eps)
+        # FP32 on the device: v to a few ulps; the update to a few ulps of
+        # lr * |m_hat / sqrt(v_hat)| plus the rounding of the parameter
+        assert np.all(np.abs(mv_new[P:] - st.v) <= 1e-5 * st.v + 1e-30), f"step {k}: second moment"
+        upd = lr * np.abs(st.m / (1 - b1 ** k)) / (np.sqrt(st.v / (1 - b2 ** k)) + eps)
+        tol = 1e-5 * upd + 2.0 ** -23 * np.abs(theta_new)
+        bad = np.abs(theta_new - q.flat()) > tol
+        assert not bad.any(), f"step {k}: {int(bad.sum())} parameters off the Adam update"
+        theta, mv = theta_new, mv_new
+    print(f"[train step] {desc} n={n}: {steps} steps, worst element error / bound {worst:.3f}",
+          flush=True)
+
+
+def test_train_rejects_too_many_heads_up_front(dev):
+    """At width 128 more than 62 heads do not fit the weight-gradient
+    kernel's LDS: every training call refuses before enqueuing anything
+    (parameters and moments untouched); 62 heads train."""
+    import torch
+    import paper_2605_04017_amd as lt
+    n = 512
+    rays = synth.config_rays(2, n)
+    for heads, ok in ((63, False), (62, True)):
+        p = make_params(mlp.MapDesc(128, 2, heads, mlp.ACT_TANH), 500 + heads, rays)
+        m = gpu_map(p, dev)
+        r = to_dev(rays, dev)
+        t = {"valid": torch.zeros((heads, n), dtype=torch.uint8, device=dev)}
+        for k in ("x", "y", "dx", "dy", "throughput"):
+            t[k] = torch.zeros((heads, n), dtype=torch.float32, device=dev)
+        ws = lt.workspace(m, n)
+        before = lt.lt_map_get_params(m).clone()
+        if ok:
+            lt.lt_map_train_step(m, r, t, {"lr": 1e-3, "step": 1}, ws)
+            torch.cuda.synchronize()
+            assert not torch.equal(before, lt.lt_map_get_params(m))
+            continue
+        with pytest.raises(lt.LtError) as e:
+            lt.lt_map_train_step(m, r, t, {"lr": 1e-3, "step": 1}, ws)
+        assert e.value.status == lt.LT_ERR_ARG and "62" in str(e.value)
+        with pytest.raises(lt.LtError):
+            lt.lt_map_forward_train(m, r)
+        torch.cuda.synchronize()
+        assert torch.equal(before, lt.lt_map_get_params(m))
