@@ -281,35 +281,73 @@ def fp8_layer_scales(p: MapParams):
     return ws, hs
 
 
+# The quantised network as the BF16 / FP8 kernels evaluate it, one rounding
+# step per function.  The paper does not state the precision its networks
+# run at; these rounding points are those of the reduced-precision kernels.
+# A value passes through FP32 registers before it is rounded, so round_bf16
+# rounds the FP32 value of its argument.
+
+def input_layer_split(xhat: np.ndarray, W0: np.ndarray, b0: np.ndarray):
+    """Input layer with inputs and weights split into BF16 hi + lo parts:
+    z = x_hi W_hi + x_lo W_hi + x_hi W_lo + b (the x_lo W_lo term, below
+    2^-16 of each product, is dropped).  Returns (z, (x_hi, x_lo))."""
+    x_hi, x_lo = split_bf16(xhat)
+    W_hi, W_lo = split_bf16(W0)
+    return x_hi @ W_hi.T + x_lo @ W_hi.T + x_hi @ W_lo.T + b0, (x_hi, x_lo)
+
+
+def output_layer_split(h: np.ndarray, Wo: np.ndarray, bo: np.ndarray) -> np.ndarray:
+    """Output layer on BF16 activations with weights split into hi + lo:
+    o = h W_hi + h W_lo + b."""
+    W_hi, W_lo = split_bf16(Wo)
+    return h @ W_hi.T + h @ W_lo.T + bo
+
+
+def hidden_layer_bf16(h: np.ndarray, W: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Pre-activation of a hidden layer: BF16 activations times BF16 weights,
+    exact sums (the kernels accumulate in FP32)."""
+    return h @ round_bf16(W).T + b
+
+
+def transpose_weights_bf16(W: np.ndarray) -> np.ndarray:
+    """The weights of the backward's transpose products (BF16)."""
+    return round_bf16(W)
+
+
+def activation_bf16(z: np.ndarray, kind: int) -> np.ndarray:
+    """An activation rounded once to BF16."""
+    return round_bf16(act(z, kind))
+
+
+def hidden_layer_fp8(z_prev: np.ndarray, W: np.ndarray, b: np.ndarray, sw: float, sh: float,
+                     kind: int) -> np.ndarray:
+    """FP8 hidden layer: activations of the previous pre-activation rounded
+    once to E4M3 after scaling by sh, weights rounded to E4M3 after scaling by
+    sw, products summed exactly and divided by sw sh."""
+    hq = round_fp8_e4m3(act(z_prev, kind) * sh)
+    Wq = round_fp8_e4m3(W * sw)
+    return (hq @ Wq.T) / (sw * sh) + b
+
+
 def forward_quantized(p: MapParams, xhat: np.ndarray, mode: str):
     """Forward pass with the kernels' rounding.  mode: "bf16" or "fp8".
 
-    bf16: input layer with split hi/lo BF16 inputs and weights, hidden
-    layers with BF16 weights and BF16-rounded activations, output layer with
-    split hi/lo BF16 weights.  fp8: the same input and output layers; every
-    hidden layer multiplies FP8 weights round_fp8(s_w W) by FP8 activations
-    round_fp8(s_h tanh(z)) (one rounding from the exact activation) and
-    divides by s_w s_h; the last hidden activation is rounded to BF16."""
+    bf16: split input layer, hidden layers with BF16 weights and BF16-rounded
+    activations, split output layer.  fp8: the same input and output layers;
+    every hidden layer is hidden_layer_fp8 (one FP8 rounding of each scaled
+    activation); the last hidden activation is rounded to BF16."""
     L = len(p.W)
-    x_hi, x_lo = split_bf16(xhat)
-    W0_hi, W0_lo = split_bf16(p.W[0])
-    z = x_hi @ W0_hi.T + x_lo @ W0_hi.T + x_hi @ W0_lo.T + p.b[0]
+    z, _ = input_layer_split(xhat, p.W[0], p.b[0])
     if mode == "fp8":
         ws, hsc = fp8_layer_scales(p)
         for li in range(1, L - 1):
-            sw, sh = ws[li - 1], hsc[li - 1]
-            hq = round_fp8_e4m3(act(z, p.desc.activation) * sh)
-            Wq = round_fp8_e4m3(p.W[li] * sw)
-            z = (hq @ Wq.T) / (sw * sh) + p.b[li]
-        h = round_bf16(act(z, p.desc.activation))
+            z = hidden_layer_fp8(z, p.W[li], p.b[li], ws[li - 1], hsc[li - 1], p.desc.activation)
+        h = activation_bf16(z, p.desc.activation)
     else:
-        h = round_bf16(act(z, p.desc.activation))
+        h = activation_bf16(z, p.desc.activation)
         for li in range(1, L - 1):
-            z = h @ round_bf16(p.W[li]).T + p.b[li]
-            h = round_bf16(act(z, p.desc.activation))
-    Wo_hi, Wo_lo = split_bf16(p.W[L - 1])
-    o = h @ Wo_hi.T + h @ Wo_lo.T + p.b[L - 1]
-    return o
+            h = activation_bf16(hidden_layer_bf16(h, p.W[li], p.b[li]), p.desc.activation)
+    return output_layer_split(h, p.W[L - 1], p.b[L - 1])
 
 
 # ------------------------------------------------------------ training ----
@@ -372,44 +410,50 @@ def forward_quantized_cache(p: MapParams, xhat: np.ndarray):
     """BF16 forward of the training kernels, keeping what the backward uses:
     (o, (x_hi, x_lo, [h_1 .. h_depth]))."""
     L = len(p.W)
-    x_hi, x_lo = split_bf16(xhat)
-    W0_hi, W0_lo = split_bf16(p.W[0])
-    z = x_hi @ W0_hi.T + x_lo @ W0_hi.T + x_hi @ W0_lo.T + p.b[0]
-    hs = [round_bf16(act(z, p.desc.activation))]
+    z, (x_hi, x_lo) = input_layer_split(xhat, p.W[0], p.b[0])
+    hs = [activation_bf16(z, p.desc.activation)]
     for li in range(1, L - 1):
-        z = hs[-1] @ round_bf16(p.W[li]).T + p.b[li]
-        hs.append(round_bf16(act(z, p.desc.activation)))
-    Wo_hi, Wo_lo = split_bf16(p.W[L - 1])
-    o = hs[-1] @ Wo_hi.T + hs[-1] @ Wo_lo.T + p.b[L - 1]
+        hs.append(activation_bf16(hidden_layer_bf16(hs[-1], p.W[li], p.b[li]), p.desc.activation))
+    o = output_layer_split(hs[-1], p.W[L - 1], p.b[L - 1])
     return o, (x_hi, x_lo, hs)
+
+
+def output_grad_split(d_out: np.ndarray) -> np.ndarray:
+    """The output gradient as the backward kernels carry it: BF16 hi + lo."""
+    d_hi, d_lo = split_bf16(d_out)
+    return d_hi + d_lo
+
+
+def hidden_grad_bf16(delta: np.ndarray, h: np.ndarray, kind: int) -> np.ndarray:
+    """Gradient of a hidden pre-activation: the incoming gradient times the
+    activation derivative taken from the stored BF16 activation (1 - h^2 for
+    tanh, [h > 0] for ReLU), rounded once to BF16."""
+    dphi = 1.0 - h * h if kind == ACT_TANH else (h > 0).astype(np.float64)
+    return round_bf16(delta * dphi)
 
 
 def backward_quantized(p: MapParams, cache, d_out: np.ndarray):
     """Parameter gradient for a given output gradient d_out (n, 6H), with the
     training kernels' rounding: the output gradient enters split into BF16
     hi + lo (against BF16 output weights for the transpose product); every
-    hidden-layer gradient is multiplied by the activation derivative (1 - h^2
-    for tanh, [h > 0] for ReLU, from the stored BF16 activation) and rounded
-    to BF16, then used in BF16 for its weight gradient (against the stored
-    BF16 activations, or the split inputs for the first layer), for its bias
-    gradient (sum over rays) and for the next transpose product (against BF16
-    weights).  Sums are exact here (FP64); the kernels accumulate in FP32."""
+    hidden-layer gradient is hidden_grad_bf16, then used in BF16 for its
+    weight gradient (against the stored BF16 activations, or the split
+    inputs for the first layer), for its bias gradient (sum over rays) and
+    for the next transpose product (against BF16 weights).  Sums are exact
+    here (FP64); the kernels accumulate in FP32."""
     x_hi, x_lo, hs = cache
     L = len(p.W)
-    d_hi, d_lo = split_bf16(d_out)
-    d = d_hi + d_lo
+    d = output_grad_split(d_out)
     grads = [None] * L
     grads[L - 1] = (d.T @ hs[-1], d.sum(0))
-    delta = d @ round_bf16(p.W[L - 1])
+    delta = d @ transpose_weights_bf16(p.W[L - 1])
     for li in range(L - 2, -1, -1):
-        h = hs[li]
-        dphi = 1.0 - h * h if p.desc.activation == ACT_TANH else (h > 0).astype(np.float64)
-        delta_b = round_bf16(delta * dphi)
+        delta_b = hidden_grad_bf16(delta, hs[li], p.desc.activation)
         if li == 0:
             grads[0] = (delta_b.T @ (x_hi + x_lo), delta_b.sum(0))
         else:
             grads[li] = (delta_b.T @ hs[li - 1], delta_b.sum(0))
-            delta = delta_b @ round_bf16(p.W[li])
+            delta = delta_b @ transpose_weights_bf16(p.W[li])
     return grads
 
 
