@@ -406,7 +406,10 @@ def test_train_step_elementwise(dev, width, depth, heads, n, steps):
     ws = lt.workspace(m, n)
     valid = tv["valid"].astype(np.int64)
     tnorm = mlp.normalise_targets({k: tv[k] for k in ("x", "y", "dx", "dy", "throughput")}, p)
-    b1, b2, eps, lr = 0.9, 0.999, 1e-8, 2e-3
+    # the ABI passes the optimiser settings as FP32 (lt_train_cfg), so the
+    # reference step runs on exactly those values: 1 - beta2 differs from
+    # 1e-3 by 1.3e-5 relative in FP32
+    b1, b2, eps, lr = (float(np.float32(v)) for v in (0.9, 0.999, 1e-8, 2e-3))
     P = m.n_params
     theta = lt.lt_map_get_params(m).cpu().numpy().astype(np.float64)
     mv = np.zeros(2 * P)
