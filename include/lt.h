@@ -594,6 +594,26 @@ lt_status lt_map_train_step(lt_map map, const lt_rays *rays, const lt_targets *t
                             const lt_train_cfg *cfg, void *workspace, int64_t workspace_bytes,
                             float *loss_out, void *stream);
 
+/* Bytes of the library's static training scratch on each GPU (64 MiB). */
+#define LT_STATIC_SCRATCH_BYTES (64LL << 20)
+
+/* lt_map_train_step for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving or training loops, harnesses that
+ * forbid hipMalloc): the same kernels and result, with the workspace taken
+ * from a static device array of LT_STATIC_SCRATCH_BYTES that every GPU the
+ * library runs on holds from the library's load until the process ends (its
+ * address is looked up once per device, on the first call there).  The call
+ * itself performs no device allocation or free.  A batch whose
+ * lt_map_workspace_bytes exceeds LT_STATIC_SCRATCH_BYTES is LT_ERR_ARG before
+ * anything is enqueued (the 5 x 128 one-head map fits 9,728 rays, so the
+ * paper's batch of 8,192; the 2 x 32 classifier 192,896).  Every call on one
+ * GPU shares that GPU's scratch and leaves its content behind: calls that
+ * may overlap on one GPU (several streams, several threads) race and must
+ * be serialised by the caller.  Other errors as lt_map_train_step. */
+lt_status lt_map_train_step_static(lt_map map, const lt_rays *rays, const lt_targets *targets,
+                                   int64_t n, const lt_train_cfg *cfg, float *loss_out,
+                                   void *stream);
+
 /* Copy the Adam moments (first m, then v; lt_map_num_params floats each,
  * device) out of the map (to_map = 0) or into it (to_map = 1), for
  * checkpoint and resume. */

@@ -23,13 +23,15 @@ LT_F32, LT_BF16, LT_FP8 = N.LT_F32, N.LT_BF16, N.LT_FP8
 LT_ACT_TANH, LT_ACT_RELU = N.LT_ACT_TANH, N.LT_ACT_RELU
 MAP_FIELDS = ("logit", "mask", "x", "y", "dx", "dy", "dz", "throughput")
 LT_ERR_ARG, LT_ERR_STATE = N.LT_ERR_ARG, N.LT_ERR_STATE
+LT_STATIC_SCRATCH_BYTES = N.LT_STATIC_SCRATCH_BYTES
 
 __all__ = ["LtError", "Lens", "lt_lens_create", "lt_lens_query", "lt_lens_paraxial", "lt_canonical_frame", "lt_trace", "lt_trace_ex",
            "lt_ghost_index", "lt_ghost_path", "empty_exit", "RAY_FIELDS", "EXIT_FIELDS",
            "LT_TRACE_PLAIN_FP32", "LT_F32", "LT_BF16", "LT_FP8", "LT_ACT_TANH", "LT_ACT_RELU",
            "Map", "lt_map_create", "lt_map_set_params", "lt_map_get_params", "lt_map_set_norm",
            "lt_map_eval", "empty_map_out", "MAP_FIELDS", "lt_map_workspace_bytes", "workspace",
-           "lt_map_forward_train", "lt_map_backward", "lt_map_train_step", "lt_map_adam_state",
+           "lt_map_forward_train", "lt_map_backward", "lt_map_train_step", "lt_map_train_step_static",
+           "lt_map_adam_state", "LT_STATIC_SCRATCH_BYTES",
            "TARGET_FIELDS", "lt_path_encode", "lt_path_decode", "lt_trace_compact",
            "lt_map_quantize", "lt_rays_generate", "lt_map_eval_ex", "LT_EVAL_MASK_ONLY",
            "lt_lens_planes", "LT_TRACE_FORWARD", "LT_TRACE_FP64", "lt_rays_generate_forward", "lt_splat",
@@ -708,13 +710,8 @@ def lt_map_backward(m: Map, grad_o, ws, grad_params=None, n: Optional[int] = Non
     return grad_params
 
 
-def lt_map_train_step(m: Map, rays: Dict, targets: Dict, cfg: Dict, ws, loss_out=None,
-                      n: Optional[int] = None, stream=None):
-    """One fused forward + loss + backward + Adam step.  ``targets``: dict of
-    (n_heads, n) CUDA tensors (valid uint8, the rest float32); ``cfg``: lr,
-    beta1, beta2, eps, step (1-based), w_bce, w_l2, w_cos (cosine direction
-    loss; 0 = squared error on all five outputs).  Returns loss_out
-    (device float32[3]: total, bce, l2)."""
+def _train_args(m: Map, rays: Dict, targets: Dict, cfg: Dict, loss_out, n: Optional[int]):
+    """Marshalled arguments of a fused training step."""
     torch = _torch()
     if n is None:
         n = int(rays["x"].numel())
@@ -728,10 +725,33 @@ def lt_map_train_step(m: Map, rays: Dict, targets: Dict, cfg: Dict, ws, loss_out
                        float(cfg.get("beta2", 0.999)), float(cfg.get("eps", 1e-8)),
                        int(cfg["step"]), float(cfg.get("w_bce", 1.0)), float(cfg.get("w_l2", 1.0)),
                        float(cfg.get("w_cos", 0.0)))
-    N.check(N.lib().lt_map_train_step(m.handle, C.byref(_rays_struct(rays, n)), C.byref(t), int(n),
-                                      C.byref(c), C.c_void_p(ws.data_ptr()), ws.numel(),
-                                      C.c_void_p(_dev_ptr(loss_out, torch.float32, 3, "loss_out")),
+    lp = C.c_void_p(_dev_ptr(loss_out, torch.float32, 3, "loss_out"))
+    return n, _rays_struct(rays, n), t, c, loss_out, lp
+
+
+def lt_map_train_step(m: Map, rays: Dict, targets: Dict, cfg: Dict, ws, loss_out=None,
+                      n: Optional[int] = None, stream=None):
+    """One fused forward + loss + backward + Adam step.  ``targets``: dict of
+    (n_heads, n) CUDA tensors (valid uint8, the rest float32); ``cfg``: lr,
+    beta1, beta2, eps, step (1-based), w_bce, w_l2, w_cos (cosine direction
+    loss; 0 = squared error on all five outputs).  Returns loss_out
+    (device float32[3]: total, bce, l2)."""
+    n, r, t, c, loss_out, lp = _train_args(m, rays, targets, cfg, loss_out, n)
+    N.check(N.lib().lt_map_train_step(m.handle, C.byref(r), C.byref(t), int(n), C.byref(c),
+                                      C.c_void_p(ws.data_ptr()), ws.numel(), lp,
                                       C.c_void_p(_stream_ptr(stream))))
+    return loss_out
+
+
+def lt_map_train_step_static(m: Map, rays: Dict, targets: Dict, cfg: Dict, loss_out=None,
+                             n: Optional[int] = None, stream=None):
+    """lt_map_train_step with the workspace taken from the library's static
+    per-GPU scratch (no allocation in the call; batches whose workspace
+    exceeds LT_STATIC_SCRATCH_BYTES raise).  Overlapping calls on one GPU
+    race on that scratch."""
+    n, r, t, c, loss_out, lp = _train_args(m, rays, targets, cfg, loss_out, n)
+    N.check(N.lib().lt_map_train_step_static(m.handle, C.byref(r), C.byref(t), int(n), C.byref(c),
+                                             lp, C.c_void_p(_stream_ptr(stream))))
     return loss_out
 
 

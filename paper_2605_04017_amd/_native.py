@@ -179,9 +179,15 @@ SIGNATURES = {
     "lt_map_train_step": (C.c_int, [C.c_void_p, C.POINTER(lt_rays), C.POINTER(lt_targets),
                                     C.c_int64, C.POINTER(lt_train_cfg), C.c_void_p, C.c_int64,
                                     C.c_void_p, C.c_void_p]),
+    "lt_map_train_step_static": (C.c_int, [C.c_void_p, C.POINTER(lt_rays), C.POINTER(lt_targets),
+                                           C.c_int64, C.POINTER(lt_train_cfg), C.c_void_p,
+                                           C.c_void_p]),
     "lt_map_adam_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
                                     C.c_void_p]),
 }
+
+# Bytes of the library's static training scratch per GPU (include/lt.h).
+LT_STATIC_SCRATCH_BYTES = 64 << 20
 
 
 def lib():

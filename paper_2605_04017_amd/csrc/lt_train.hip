@@ -23,6 +23,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
+#include <string>
 
 #include "lt_internal.h"
 #include "lt_map.h"
@@ -918,6 +920,65 @@ static bool rays_ok(const lt_rays *r)
     return r && r->x && r->y && r->dx && r->dy && r->dz && r->lambda_nm;
 }
 
+// Argument checks of a fused training step, all before anything is enqueued.
+static lt_status check_train_args(const Map *M, const lt_rays *rays, const lt_targets *targets,
+                                  int64_t n, const lt_train_cfg *cfg)
+{
+    if (!M || !targets || !cfg || n <= 0)
+        return fail(LT_ERR_ARG, "NULL argument or non-positive batch");
+    if (!M->has_params)
+        return fail(LT_ERR_STATE, "parameters were never set");
+    if (!rays_ok(rays))
+        return fail(LT_ERR_ARG, "NULL ray field");
+    if (!targets->valid || !targets->x || !targets->y || !targets->dx || !targets->dy ||
+        !targets->throughput)
+        return fail(LT_ERR_ARG, "NULL target field");
+    if (cfg->step < 1 || !(cfg->lr >= 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) ||
+        !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) || !(cfg->eps > 0.0f) ||
+        !(cfg->w_cos >= 0.0f && cfg->w_cos < 1e30f))
+        return fail(LT_ERR_ARG, "bad optimiser settings (step must be >= 1)");
+    return check_train_shape(M->lay);
+}
+
+// ------------------------------------------------------ static scratch ----
+// Workspace of lt_map_train_step_static: a device array in the library's own
+// code object, so the call allocates nothing.  Every GPU the library runs on
+// holds its own copy (LT_STATIC_SCRATCH_BYTES) from the module's load until
+// the process ends.  In host code `scratch` names a host-side stand-in: its
+// device address on the current device comes from hipGetSymbolAddress, once
+// per device, and only that address is passed to kernels.
+static __device__ __align__(256) uint8_t scratch[LT_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static uint8_t *g_scratch_ptr[kMaxScratchDevices] = {};
+
+static lt_status static_scratch(uint8_t **out)
+{
+    int dev = -1;
+    lt_status st = check_hip(hipGetDevice(&dev), "hipGetDevice");
+    if (st != LT_OK)
+        return st;
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return fail(LT_ERR_DEVICE, "device index out of the static scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        st = check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (st != LT_OK)
+            return st;
+        if (!p || reinterpret_cast<uintptr_t>(p) % 256)
+            return fail(LT_ERR_DEVICE, "static scratch has no 256-byte aligned device address");
+        g_scratch_ptr[dev] = static_cast<uint8_t *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return LT_OK;
+}
+
+static lt_status train_step(Map &M, const lt_rays *rays, const lt_targets *targets, int64_t n,
+                            const lt_train_cfg *cfg, const WsLayout &w, uint8_t *wb, float *loss_out,
+                            hipStream_t s);
+
 }  // namespace lt
 
 using namespace lt;
@@ -1004,29 +1065,47 @@ lt_status lt_map_train_step(lt_map map, const lt_rays *rays, const lt_targets *t
                             void *stream)
 {
     Map *M = as_map(map);
-    if (!M || !targets || !cfg || n <= 0)
-        return fail(LT_ERR_ARG, "NULL argument or non-positive batch");
-    if (!M->has_params)
-        return fail(LT_ERR_STATE, "parameters were never set");
-    if (!rays_ok(rays))
-        return fail(LT_ERR_ARG, "NULL ray field");
-    if (!targets->valid || !targets->x || !targets->y || !targets->dx || !targets->dy ||
-        !targets->throughput)
-        return fail(LT_ERR_ARG, "NULL target field");
-    if (cfg->step < 1 || !(cfg->lr >= 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) ||
-        !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) || !(cfg->eps > 0.0f) ||
-        !(cfg->w_cos >= 0.0f && cfg->w_cos < 1e30f))
-        return fail(LT_ERR_ARG, "bad optimiser settings (step must be >= 1)");
-    WsLayout w;
-    lt_status st = check_train_shape(M->lay);
+    lt_status st = check_train_args(M, rays, targets, n, cfg);
     if (st != LT_OK)
         return st;
+    WsLayout w;
     st = check_ws(M, ws, ws_bytes, n, &w);
     if (st != LT_OK)
         return st;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    uint8_t *wb = static_cast<uint8_t *>(ws);
-    st = ensure_packed_bf16(*M, s);
+    return train_step(*M, rays, targets, n, cfg, w, static_cast<uint8_t *>(ws), loss_out,
+                      reinterpret_cast<hipStream_t>(stream));
+}
+
+lt_status lt_map_train_step_static(lt_map map, const lt_rays *rays, const lt_targets *targets,
+                                   int64_t n, const lt_train_cfg *cfg, float *loss_out, void *stream)
+{
+    Map *M = as_map(map);
+    lt_status st = check_train_args(M, rays, targets, n, cfg);
+    if (st != LT_OK)
+        return st;
+    const WsLayout w = ws_layout(M->lay, n);
+    if (w.bytes > LT_STATIC_SCRATCH_BYTES)
+        return fail(LT_ERR_ARG, "batch needs " + std::to_string(w.bytes) +
+                                    " bytes of scratch; the static scratch holds " +
+                                    std::to_string(static_cast<int64_t>(LT_STATIC_SCRATCH_BYTES)) +
+                                    " (lt_map_workspace_bytes gives a batch's need)");
+    uint8_t *ws = nullptr;
+    st = static_scratch(&ws);
+    if (st != LT_OK)
+        return st;
+    return train_step(*M, rays, targets, n, cfg, w, ws, loss_out, reinterpret_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"
+
+namespace lt {
+
+static lt_status train_step(Map &Mr, const lt_rays *rays, const lt_targets *targets, int64_t n,
+                            const lt_train_cfg *cfg, const WsLayout &w, uint8_t *wb, float *loss_out,
+                            hipStream_t s)
+{
+    Map *M = &Mr;
+    lt_status st = ensure_packed_bf16(*M, s);
     if (st != LT_OK)
         return st;
     EvalArgs A{};
@@ -1093,6 +1172,10 @@ lt_status lt_map_train_step(lt_map map, const lt_rays *rays, const lt_targets *t
         ++M->version;  // master parameters changed: packed images are stale
     return st;
 }
+
+}  // namespace lt
+
+extern "C" {
 
 lt_status lt_map_adam_state(lt_map map, float *m, float *v, int64_t count, int32_t to_map,
                             void *stream)
