@@ -1,20 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark of the lens transport hot path on one MI355X.
 
-Workload: the 11-surface double-Gauss-style lens (seeded prescription and
-Cauchy glasses) with 4,194,304 sensor-side rays (sensor point uniform on
-the 36 x 24 mm frame, direction uniform toward the rear element, wavelength
-uniform in 400..700 nm), inputs resident in HBM.  The comparison it is
-quoted on: FP32 GPU brute-force trace versus FP32 map (6-D input, 5 x 128
-tanh hidden layers, mask logit + 4-D exit ray + throughput head).
+Workload (the headline): the 11-surface double-Gauss-style lens (seeded
+prescription and Cauchy glasses) with 16,777,216 sensor-side rays (sensor
+point uniform on the 36 x 24 mm frame, direction uniform toward the rear
+element, wavelength uniform in 400..700 nm) and every light path with at
+most two reflections: the transmit path and the 55 two-reflection ghosts,
+56 paths.  Inputs are resident in HBM.
 
-One step = one pass of the hot path over the batch: lt_trace (transmit
-path) and lt_map_eval (FP32).  `value` is the map's rays/s; the tracer's
-rays/s, their ratio, the BF16 and FP8 map rates, the map's exit-ray error
-after a short fit on GPU-traced rays (against the GPU tracer, which the
-parity tests pin to the FP64 oracle within 1e-5 mm), and a serving run
-(mixed-size requests for eight lenses, p50/p99 latency) are reported in the
-same JSON line.  Kernel times come from HIP events on the stream the
+One step = one pass of the hot path over the batch: the brute-force tracer
+on all 56 paths (one compacted launch per path: valid rays only) and the map
+(one 5 x 128 tanh trunk with a head per path, canonical input, fitted on
+GPU-traced rays of all 56 paths) in FP32 with compacted output (mask bitmap
++ valid rays, Sec. 4.2).  `value` is the map's ray-path evaluations per
+second; the tracer's rate, their ratios (against each tracer variant that
+meets the tolerance), BF16 and FP8 map rates, the uncompacted rates, the
+map's error against the GPU tracer, rooflines, and the other workloads (the
+4,194,304-ray transmit-only case, the paper-size pair, training, forward
+flare tracing, the sampler, serving with p50/p99 latency) are reported in
+the same JSON line.  Kernel times come from HIP events on the stream the
 kernels run on.  The oracle runs only in the CPU-baseline leg, which times
 it on the host cores.
 """
@@ -31,7 +35,8 @@ from paper_2605_04017_amd import fit as F
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-N_RAYS = 4194304
+N_RAYS = 4194304          # the transmit-only case
+N_RAYS_ALL_PATHS = 16777216  # the headline: 56 paths
 MI355X_FP32_VECTOR_TFLOPS = 157.3
 MI355X_FP64_VECTOR_TFLOPS = 78.6
 MI355X_FP32_MFMA_TFLOPS = 157.3
@@ -64,47 +69,55 @@ def trace_flops_per_ray(lens, path=(0, 0, 0)):
     return 20 + 78 * n_t + 56 * n_r + 28 * n_s + 10
 
 
-def cpu_baseline_map(flat, norms, rays_np, budget_s=10.0):
-    """Time the FP64 reference network (numpy) of the fitted map (its flat
-    parameters and normalisation) on a bounded sample."""
+def cpu_baseline_map(flat, norms, rays_np, heads=1, canonical=False, budget_s=10.0):
+    """Time the FP64 reference network (numpy) of a fitted map (its flat
+    parameters and normalisation) on a bounded sample; the rate counts
+    ray-path evaluations (rays x heads)."""
     import numpy as np
     from oracle import mlp
-    params = mlp.init_params(mlp.MapDesc(MAP_WIDTH, MAP_DEPTH, 1, mlp.ACT_TANH), 0)
+    params = mlp.init_params(mlp.MapDesc(MAP_WIDTH, MAP_DEPTH, heads, mlp.ACT_TANH, canonical=canonical), 0)
     params.set_flat(np.asarray(flat, np.float64))
     params.in_shift, params.in_scale = norms[0], norms[1]
     params.out_shift, params.out_scale = norms[2], norms[3]
     threads = os.cpu_count() or 1
-    n = 16384
+    n = 4096
     while True:
         sample = {k: v[:n] for k, v in rays_np.items()}
         t0 = time.perf_counter()
         o, _ = mlp.forward(params, mlp.features(sample, params))
-        mlp.decode(o, params)
+        mlp.decode(o, params, sample)
         dt = time.perf_counter() - t0
         if dt > budget_s / 4 or n * 4 > rays_np["x"].shape[0]:
             break
         n *= 4
-    return {"value": n / dt / 1e6, "unit": "Mrays/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n} rays of the workload, FP64 numpy forward of the 5 x 128 tanh "
-                      f"map (BLAS threads = host cores)"}
+    unit = "Mray-paths/s" if heads > 1 else "Mrays/s"
+    return {"value": n * heads / dt / 1e6, "unit": unit, "cores": threads, "kind": "oracle",
+            "sample": f"first {n} rays of the workload x {heads} heads, FP64 numpy forward and decode "
+                      f"of the 5 x 128 tanh map (BLAS threads = host cores)"}
 
 
-def cpu_baseline_trace(lens, rays_np, budget_s=10.0):
-    """Time the FP64 oracle tracer on the host cores on a bounded sample."""
+def cpu_baseline_trace(lens, rays_np, paths=((0, 0, 0),), budget_s=10.0):
+    """Time the FP64 oracle tracer on the host cores on a bounded sample of
+    rays, each traced along every path in `paths`; the rate counts
+    ray-path traces."""
     import oracle
     n_all = rays_np["x"].shape[0]
     threads = os.cpu_count() or 1
-    probe = {k: v[:65536] for k, v in rays_np.items()}
+    probe = {k: v[:8192] for k, v in rays_np.items()}
     t0 = time.perf_counter()
-    oracle.trace(lens, probe, nthreads=threads)
+    for p in paths:
+        oracle.trace(lens, probe, p, nthreads=threads)
     dt = time.perf_counter() - t0
-    n = int(min(n_all, max(65536, 65536 * budget_s / max(dt, 1e-6))))
+    n = int(min(n_all, max(8192, 8192 * budget_s / max(dt, 1e-6))))
     sample = {k: v[:n] for k, v in rays_np.items()}
     t0 = time.perf_counter()
-    oracle.trace(lens, sample, nthreads=threads)
+    for p in paths:
+        oracle.trace(lens, sample, p, nthreads=threads)
     dt = time.perf_counter() - t0
-    return {"value": n / dt / 1e6, "unit": "Mrays/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n} of the {n_all} rays, transmit path, FP64 C oracle, OpenMP"}
+    what = "transmit path" if len(paths) == 1 else f"all {len(paths)} paths"
+    unit = "Mrays/s" if len(paths) == 1 else "Mray-paths/s"
+    return {"value": n * len(paths) / dt / 1e6, "unit": unit, "cores": threads, "kind": "oracle",
+            "sample": f"first {n} of the {n_all} rays, {what}, FP64 C oracle, OpenMP"}
 
 
 def time_kernel(fn, stream, reps):
@@ -429,7 +442,7 @@ def fit_multi_head(lt, synth, lens, h, paths, dev, steps, n_pool=1 << 21, batch=
         lr = 2e-3 * (0.5 ** (k / max(1, steps / 4)))
         loss = lt.lt_map_train_step(m, rb, tb, {"lr": lr, "step": k, "w_bce": 1.0, "w_l2": 4.0}, ws)
     torch.cuda.synchronize()
-    return m, time.perf_counter() - t0, [float(v) for v in loss.cpu()]
+    return m, time.perf_counter() - t0, [float(v) for v in loss.cpu()], norms
 
 
 def multi_path_error(lt, h, m, paths, dtype, rays, n_sample=65536):
@@ -459,63 +472,145 @@ def multi_path_error(lt, h, m, paths, dtype, rays, n_sample=65536):
             "ghost_pos_mm_p50_median_over_paths": float(np.median(ghost_p50)) if ghost_p50 else None}
 
 
-def multi_path(lt, synth, dev, n=16777216, fit_steps=3000):
-    """The 16,777,216-ray configuration: transmit + all 55 two-reflection
-    ghosts of the 11-surface lens.  Tracer: one launch per path (56).  Map:
-    one 5 x 128 trunk with 56 heads (canonical input) in one launch, FP32 /
-    BF16 / FP8, fitted for fit_steps steps on GPU traces of all 56 paths; its
-    error against the GPU tracer is stated per precision.  Both write every
-    path's exit rays (the tracer reuses one output set per path launch; the
-    map writes [56][n] fields)."""
+def all_paths_paths(lens):
+    nr = lens.n_refracting
+    return [(0, 0, 0)] + [(1, j, i) for j in range(1, nr + 1) for i in range(j + 1, nr + 1)]
+
+
+def map_compact_bytes(n, heads, counts, with_dz=True):
+    """Algorithmic HBM bytes of one compacted map launch: 24 B of input per
+    ray, the mask bitmap (one bit per ray and head, in 32-bit words) and 24 B
+    (28 with dz) per valid ray-path: index, x, y, dx, dy, (dz), throughput."""
+    return 24 * n + 4 * heads * ((n + 31) // 32) + (28 if with_dz else 24) * int(sum(counts))
+
+
+def all_paths(lt, synth, dev, args):
+    """The headline workload: 16,777,216 rays of the 11-surface lens, every
+    path with at most two reflections (transmit + 55 ghosts).  Tracer: one
+    launch per path.  Map: one 5 x 128 trunk with 56 heads (canonical
+    input), fitted on GPU traces of all 56 paths.  The timed step runs the
+    compacted tracer over all paths and the compacted FP32 map; the other
+    precisions, uncompacted outputs and tracer variants are timed beside it."""
     import numpy as np
     import torch
+    n = args.rays_all
     lens = synth.config_lens(3)
     rays_np = synth.config_rays(3, n)
     rays = {k: torch.from_numpy(v).to(dev) for k, v in rays_np.items()}
-    del rays_np
     h = lt.lt_lens_create(lens.surfaces, lens.glasses)
-    nr = lens.n_refracting
-    paths = [(0, 0, 0)] + [(1, j, i) for j in range(1, nr + 1) for i in range(j + 1, nr + 1)]
-    out = lt.empty_exit(n, dev)
+    paths = all_paths_paths(lens)
+    P = len(paths)
     stream = torch.cuda.current_stream()
 
-    def trace_all():
-        for p in paths:
-            lt.lt_trace(h, p, rays, out, n, stream)
-    t_trace = time_kernel(trace_all, stream, 2)
+    # tracer outputs: compacted, one buffer set reused by every path launch
     cout = {k: torch.empty(n, dtype=torch.float32, device=dev) for k in lt.EXIT_FIELDS[1:]}
     cidx = torch.empty(n, dtype=torch.int64, device=dev)
-    counts = torch.empty(len(paths), dtype=torch.int64, device=dev)
+    tcounts = torch.empty(P, dtype=torch.int64, device=dev)
 
-    def trace_all_compact():
+    def trace_all_compact(flags=0):
         for k, p in enumerate(paths):
-            lt.lt_trace_compact(h, p, rays, cout, cidx, counts[k:k + 1], n, 0, stream)
-    t_compact = time_kernel(trace_all_compact, stream, 2)
-    valid = counts.cpu().numpy()
-    res = {"paths": len(paths), "rays": n, "trace_all_paths_ms": t_trace * 1e3,
-           "trace_ray_paths_per_s_M": n * len(paths) / t_trace / 1e6,
-           "trace_all_paths_compact_ms": t_compact * 1e3,
-           "valid_fraction_transmit": float(valid[0]) / n,
-           "valid_fraction_ghost_mean": float(valid[1:].mean()) / n}
-    del cout, cidx
-    P = len(paths)
-    m, t_fit, fit_loss = fit_multi_head(lt, synth, lens, h, paths, dev, fit_steps)
-    res["fit"] = {"steps": fit_steps, "batch": 65536, "seconds": t_fit, "final_loss": fit_loss,
-                  "map": "5 x 128 tanh, 56 heads, canonical input"}
-    res["map_error_vs_gpu_tracer"] = {name: multi_path_error(lt, h, m, paths, dt, rays)
-                                      for name, dt in (("f32", lt.LT_F32), ("bf16", lt.LT_BF16),
-                                                       ("fp8", lt.LT_FP8))}
+            lt.lt_trace_compact(h, p, rays, cout, cidx, tcounts[k:k + 1], n, flags, stream)
+
+    # the map, fitted on GPU traces of every path
+    m, t_fit, fit_loss, norms = fit_multi_head(lt, synth, lens, h, paths, dev, args.fit_steps)
+    flat = lt.lt_map_get_params(m).cpu().numpy()
+    for dt in (lt.LT_F32, lt.LT_BF16, lt.LT_FP8):
+        lt.lt_map_quantize(m, dt)
+    # compacted map outputs: capacity = the largest head count, with margin
+    probe = lt.lt_map_eval_compact(m, lt.LT_F32, rays, capacity=n // 4, with_bits=False)
+    cap = int(probe["count"].max()) * 9 // 8 + 1024
+    del probe
     torch.cuda.empty_cache()
+    cmp = lt.lt_map_eval_compact(m, lt.LT_F32, rays, capacity=cap)
+    torch.cuda.synchronize()
+    print(f"# all paths: map fitted in {t_fit:.1f} s, compacted capacity {cap}", file=sys.stderr, flush=True)
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        trace_all_compact()
+        if ev is not None:
+            ev[1].record(stream)
+        lt.lt_map_eval_compact(m, lt.LT_F32, rays, capacity=cap, out=cmp, n=n, stream=stream)
+        if ev is not None:
+            ev[2].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t_trace = float(np.mean([e[0].elapsed_time(e[1]) for e in evs])) * 1e-3
+    t_map = float(np.mean([e[1].elapsed_time(e[2]) for e in evs])) * 1e-3
+    counts_f32 = cmp["count"].cpu().numpy()
+    assert counts_f32.max() <= cap, "compacted map output overflowed its capacity"
+    tvalid = tcounts.cpu().numpy()
+    print(f"# all paths: timed {args.steps} steps", file=sys.stderr, flush=True)
+
+    # other precisions and uncompacted outputs of the map
+    reps = 3
+    t_cmp, cnt = {"f32": t_map}, {"f32": counts_f32}
+    for name, dt in (("bf16", lt.LT_BF16), ("fp8", lt.LT_FP8)):
+        t_cmp[name] = time_kernel(lambda: lt.lt_map_eval_compact(m, dt, rays, capacity=cap, out=cmp, n=n,
+                                                                  stream=stream), stream, reps)
+        cnt[name] = cmp["count"].cpu().numpy()
+        assert cnt[name].max() <= cap, "compacted map output overflowed its capacity"
     mout = lt.empty_map_out(P, n, dev)
-    fpr = map_flops_per_ray(heads=P)
+    t_full = {}
     for name, dt in (("f32", lt.LT_F32), ("bf16", lt.LT_BF16), ("fp8", lt.LT_FP8)):
-        t = time_kernel(lambda: lt.lt_map_eval(m, dt, rays, mout, n, stream), stream, 2)
-        res[f"map_{name}_ms"] = t * 1e3
-        res[f"map_{name}_over_trace"] = t_trace / t
-        res[f"map_{name}_over_trace_compact"] = t_compact / t
-        res[f"map_{name}_tflops"] = fpr * n / t / 1e12
-    res["map_output_gb"] = P * n * 29 / 1e9
-    del mout, out, rays
+        t_full[name] = time_kernel(lambda: lt.lt_map_eval(m, dt, rays, mout, n, stream), stream, 2)
+    del mout
+    torch.cuda.empty_cache()
+    # tracer variants: uncompacted default, compacted FP64 option, compacted plain FP32
+    out = lt.empty_exit(n, dev)
+
+    def trace_all(flags=0):
+        for p in paths:
+            lt.lt_trace_ex(h, p, rays, out, n, flags, stream)
+    t_trace_full = time_kernel(trace_all, stream, 1)
+    t_trace_f64 = time_kernel(lambda: trace_all_compact(lt.LT_TRACE_FP64), stream, 1)
+    t_trace_plain = time_kernel(lambda: trace_all_compact(lt.LT_TRACE_PLAIN_FP32), stream, 1)
+    del out
+    print("# all paths: variants timed", file=sys.stderr, flush=True)
+
+    errors = {name: multi_path_error(lt, h, m, paths, dt, rays)
+              for name, dt in (("f32", lt.LT_F32), ("bf16", lt.LT_BF16), ("fp8", lt.LT_FP8))}
+    fpr = map_flops_per_ray(heads=P)
+    tracers = {"float_pair_compact": t_trace, "float_pair": t_trace_full, "fp64_option_compact": t_trace_f64}
+    res = {"paths": P, "rays": n, "ray_paths": P * n,
+           "trace_ms": {"float_pair_compact": t_trace * 1e3, "float_pair": t_trace_full * 1e3,
+                        "fp64_option_compact": t_trace_f64 * 1e3,
+                        "plain_fp32_compact_outside_tolerance": t_trace_plain * 1e3},
+           "trace_mray_paths_s": {k: P * n / v / 1e6 for k, v in tracers.items()},
+           "valid_fraction_transmit": float(tvalid[0]) / n,
+           "valid_fraction_ghost_mean": float(tvalid[1:].mean()) / n,
+           "map_compact_ms": {k: v * 1e3 for k, v in t_cmp.items()},
+           "map_uncompacted_ms": {k: v * 1e3 for k, v in t_full.items()},
+           "map_compact_mray_paths_s": {k: P * n / v / 1e6 for k, v in t_cmp.items()},
+           "map_over_trace": {k: {tn: tt / v for tn, tt in tracers.items()} for k, v in t_cmp.items()},
+           "map_valid_fraction": {k: float(v.sum()) / (P * n) for k, v in cnt.items()},
+           "compact_capacity_per_head": cap,
+           "fit": {"steps": args.fit_steps, "batch": 65536, "seconds": t_fit, "final_loss": fit_loss,
+                   "map": "5 x 128 tanh, 56 heads, canonical input"},
+           "map_error_vs_gpu_tracer": errors}
+    rl = {}
+    for name, peak in (("f32", MI355X_FP32_MFMA_TFLOPS), ("bf16", MI355X_BF16_MFMA_TFLOPS),
+                       ("fp8", MI355X_FP8_MFMA_TFLOPS)):
+        tf = fpr * n / t_cmp[name] / 1e12
+        byt = map_compact_bytes(n, P, cnt[name])
+        gbs = byt / t_cmp[name] / 1e9
+        rl[name] = {"bound": "mfma", "achieved": tf, "peak": peak, "unit": "TFLOP/s", "frac": tf / peak,
+                    "flops_per_ray": fpr, "algorithmic_bytes": byt, "hbm_gbs": gbs,
+                    "hbm_frac": gbs / MI355X_HBM_GBS}
+    res["roofline_by_dtype"] = rl
+    res["wall_s_timed"] = wall
+    res["_cpu"] = (flat, norms, rays_np, lens, paths)
+    res["_t"] = (t_trace, t_map, wall)
+    del rays, cout, cidx, cmp
     torch.cuda.empty_cache()
     return res
 
@@ -747,27 +842,29 @@ def sampler_yield(lt, synth, dev, path=(1, 2, 10), n_chains=1 << 20, steps=32, b
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "map_f32_c2_4M_traffic.md")
+TRAFFIC_ALL_SUMMARY = os.path.join(ROOT, "profiles", "map_compact_56heads_16M_traffic.md")
 MAP_F32_SOURCES = ("paper_2605_04017_amd/csrc/lt_map_f32.hip", "paper_2605_04017_amd/csrc/lt_map_dev.h",
                    "paper_2605_04017_amd/csrc/lt_map.h")
+MAP_BF16_SOURCES = ("paper_2605_04017_amd/csrc/lt_map.hip",)
 COPY_PROBE_BYTES = 512 << 20
 
 
-def map_f32_source_hash():
+def source_hash(sources):
     import hashlib
     h = hashlib.sha256()
-    for f in MAP_F32_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the FP32 map kernel from the committed
-    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by the
-    counter's reading for a plain copy of known size), or None when the
-    kernel sources changed since the counters were taken."""
+def measured_traffic(summary, sources):
+    """HBM bytes per launch of a map kernel from a committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by the counter's
+    reading for a plain copy of known size), or None when the kernel sources
+    changed since the counters were taken."""
     try:
-        text = open(TRAFFIC_SUMMARY).read()
+        text = open(summary).read()
     except OSError:
         return None
     blk = text.split("```json", 1)[-1].split("```", 1)[0] if "```json" in text else ""
@@ -775,30 +872,58 @@ def measured_traffic():
         d = json.loads(blk)
     except ValueError:
         return None
-    if d.get("source_hash") != map_f32_source_hash():
+    if d.get("source_hash") != source_hash(sources):
         return None
     return d
 
 
-def traffic_probe(n=N_RAYS, dtype_name="f32"):
+def traffic_probe(args):
     """Short program for the counter runs: one plain copy of COPY_PROBE_BYTES
-    (a negate kernel: reads and writes that many bytes), then three map
-    launches in the given precision on the benchmark workload (random
-    weights: the kernels have no data-dependent control flow), or with
-    "trace" three launches of each tracer variant on its transmit path."""
-    import numpy as np
+    (a negate kernel: reads and writes that many bytes), then three launches
+    of the kernel under study.  f32 / bf16 / fp8: the one-head map on the
+    4,194,304-ray transmit-only workload (random weights: no data-dependent
+    control flow).  trace: three launches of each tracer variant on that
+    workload's transmit path.  all_f32 / all_bf16 / all_fp8: the compacted
+    56-head map of the headline (16,777,216 rays), fitted exactly as the
+    benchmark fits it, so that its valid fraction and output bytes are the
+    benchmark's."""
     import torch
     import paper_2605_04017_amd as lt
     import synth
+    kind = args.traffic_probe
     dev = torch.device("cuda:0")
     src = torch.ones(COPY_PROBE_BYTES // 4, device=dev)
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
     torch.neg(src, out=dst)
     torch.cuda.synchronize()
+    del src, dst
+    if kind.startswith("all_"):
+        n = args.rays_all
+        lens = synth.config_lens(3)
+        rays = {k: torch.from_numpy(v).to(dev) for k, v in synth.config_rays(3, n).items()}
+        h = lt.lt_lens_create(lens.surfaces, lens.glasses)
+        paths = all_paths_paths(lens)
+        m, _, _, _ = fit_multi_head(lt, synth, lens, h, paths, dev, args.fit_steps)
+        dt = {"all_f32": lt.LT_F32, "all_bf16": lt.LT_BF16, "all_fp8": lt.LT_FP8}[kind]
+        probe = lt.lt_map_eval_compact(m, lt.LT_F32, rays, capacity=n // 4, with_bits=False)
+        cap = int(probe["count"].max()) * 9 // 8 + 1024
+        del probe
+        torch.cuda.empty_cache()
+        cmp = lt.lt_map_eval_compact(m, dt, rays, capacity=cap)
+        for _ in range(3):
+            lt.lt_map_eval_compact(m, dt, rays, capacity=cap, out=cmp, n=n)
+        torch.cuda.synchronize()
+        counts = cmp["count"].cpu().tolist()
+        print(json.dumps({"probe": "traffic", "kernel": "map compacted, 56 heads", "dtype": kind[4:],
+                          "copy_bytes": COPY_PROBE_BYTES, "rays": n, "heads": len(paths),
+                          "valid_ray_paths": int(sum(counts)),
+                          "algorithmic_bytes": map_compact_bytes(n, len(paths), counts),
+                          "source_hash": source_hash(MAP_F32_SOURCES + MAP_BF16_SOURCES)}), flush=True)
+        return
+    n = args.rays
     rays = {k: torch.from_numpy(v).to(dev) for k, v in synth.config_rays(2, n).items()}
-    if dtype_name == "trace":
-        # the three tracer variants on the transmit path, three launches each
+    if kind == "trace":
         h = lt.lt_lens_create(synth.config_lens(2).surfaces, synth.config_lens(2).glasses)
         ex = lt.empty_exit(n, dev)
         for flags in (0, lt.LT_TRACE_PLAIN_FP32, lt.LT_TRACE_FP64):
@@ -812,12 +937,89 @@ def traffic_probe(n=N_RAYS, dtype_name="f32"):
     lt.lt_map_set_params(m, torch.from_numpy(F.init_params(MAP_WIDTH, MAP_DEPTH, 1, 5)).to(dev))
     out = lt.empty_map_out(1, n, dev)
     torch.cuda.synchronize()
-    dt = {"f32": lt.LT_F32, "bf16": lt.LT_BF16, "fp8": lt.LT_FP8}[dtype_name]
+    dt = {"f32": lt.LT_F32, "bf16": lt.LT_BF16, "fp8": lt.LT_FP8}[kind]
     for _ in range(3):
         lt.lt_map_eval(m, dt, rays, out, n)
     torch.cuda.synchronize()
-    print(json.dumps({"probe": "traffic", "dtype": dtype_name, "copy_bytes": COPY_PROBE_BYTES,
-                      "rays": n, "source_hash": map_f32_source_hash()}), flush=True)
+    print(json.dumps({"probe": "traffic", "dtype": kind, "copy_bytes": COPY_PROBE_BYTES,
+                      "rays": n, "source_hash": source_hash(MAP_F32_SOURCES)}), flush=True)
+
+
+def transmit_only(lt, synth, dev, args):
+    """The 4,194,304-ray transmit-only case: FP32 tracer variants against the
+    one-head 5 x 128 map in each precision, map errors, the canonical input."""
+    import numpy as np
+    import torch
+    lens = synth.config_lens(2)
+    rays_np = synth.config_rays(2, args.rays)
+    n = args.rays
+    rays = {k: torch.from_numpy(v).to(dev) for k, v in rays_np.items()}
+    h = lt.lt_lens_create(lens.surfaces, lens.glasses)
+    out = lt.empty_exit(n, dev)
+    stream = torch.cuda.current_stream()
+    t_fit = time.perf_counter()
+    m, fitted, fit_loss = fit_map(lt, synth, lens, dev, args.fit_steps)
+    t_fit = time.perf_counter() - t_fit
+    mout = lt.empty_map_out(1, n, dev)
+    reps = 10
+    t_trace = time_kernel(lambda: lt.lt_trace(h, (0, 0, 0), rays, out, n, stream), stream, reps)
+    t_map = time_kernel(lambda: lt.lt_map_eval(m, lt.LT_F32, rays, mout, n, stream), stream, reps)
+    t_bf16 = time_kernel(lambda: lt.lt_map_eval(m, lt.LT_BF16, rays, mout, n, stream), stream, reps)
+    t_fp8 = time_kernel(lambda: lt.lt_map_eval(m, lt.LT_FP8, rays, mout, n, stream), stream, reps)
+    fast = lt.empty_exit(n, dev)
+    t_fast = time_kernel(lambda: lt.lt_trace_ex(h, (0, 0, 0), rays, fast, n, lt.LT_TRACE_PLAIN_FP32,
+                                                stream), stream, reps)
+    t_f64 = time_kernel(lambda: lt.lt_trace_ex(h, (0, 0, 0), rays, fast, n, lt.LT_TRACE_FP64,
+                                               stream), stream, reps)
+    errors = {name: map_error(lt, h, m, dt, rays)
+              for name, dt in (("f32", lt.LT_F32), ("bf16", lt.LT_BF16), ("fp8", lt.LT_FP8))}
+    mc, _, fit_loss_c = fit_map(lt, synth, lens, dev, args.fit_steps, canonical=True)
+    errors["f32_canonical_input"] = map_error(lt, h, mc, lt.LT_F32, rays)
+    errors["f32_canonical_input"]["fit_final_loss"] = fit_loss_c
+    t_map_c = time_kernel(lambda: lt.lt_map_eval(mc, lt.LT_F32, rays, mout, n, stream), stream, 3)
+    del mc
+    fpr = map_flops_per_ray()
+    tfl = trace_flops_per_ray(lens)
+    tr = measured_traffic(TRAFFIC_SUMMARY, MAP_F32_SOURCES)
+    traffic = None
+    if tr is not None and tr.get("rays") == n:
+        traffic = tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]
+    res = {
+        "workload": "11-surface lens + stop, 4,194,304 sensor-side rays, transmit path; map 5 x 128 tanh, "
+                    "1 head (mask logit + x, y, dx, dy, throughput)",
+        "rays": n,
+        "map_mrays_s": {"f32": n / t_map / 1e6, "bf16": n / t_bf16 / 1e6, "fp8": n / t_fp8 / 1e6},
+        "trace_mrays_s": {"float_pair": n / t_trace / 1e6, "fp64_option": n / t_f64 / 1e6,
+                          "plain_fp32_outside_tolerance": n / t_fast / 1e6},
+        "map_over_trace": {k: {"float_pair": t_trace / t, "fp64_option": t_f64 / t}
+                           for k, t in (("f32", t_map), ("bf16", t_bf16), ("fp8", t_fp8))},
+        "kernel_ms": {"trace": t_trace * 1e3, "trace_plain_fp32": t_fast * 1e3,
+                      "trace_fp64_option": t_f64 * 1e3,
+                      "map_f32": t_map * 1e3, "map_bf16": t_bf16 * 1e3, "map_fp8": t_fp8 * 1e3,
+                      "map_f32_canonical_input": t_map_c * 1e3},
+        "map_error_vs_gpu_tracer": errors,
+        "fit": {"steps": args.fit_steps, "batch": 65536, "final_loss": fit_loss, "seconds": t_fit},
+        "roofline": {
+            "map_f32": {"bound": "mfma", "achieved": fpr * n / t_map / 1e12, "peak": MI355X_FP32_MFMA_TFLOPS,
+                        "unit": "TFLOP/s", "frac": fpr * n / t_map / 1e12 / MI355X_FP32_MFMA_TFLOPS,
+                        "traffic": traffic, "kernel": "map_eval_f32_kernel<128, tanh>",
+                        "flops_per_ray": fpr, "algorithmic_bytes": 53 * n, "traffic_detail": tr},
+            "map_bf16": {"bound": "mfma", "achieved": fpr * n / t_bf16 / 1e12,
+                         "peak": MI355X_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
+                         "frac": fpr * n / t_bf16 / 1e12 / MI355X_BF16_MFMA_TFLOPS},
+            "map_fp8": {"bound": "mfma", "achieved": fpr * n / t_fp8 / 1e12,
+                        "peak": MI355X_FP8_MFMA_TFLOPS, "unit": "TFLOP/s",
+                        "frac": fpr * n / t_fp8 / 1e12 / MI355X_FP8_MFMA_TFLOPS},
+            "trace": {"bound": "alu", "achieved": tfl * n / t_trace / 1e12, "peak": MI355X_FP32_VECTOR_TFLOPS,
+                      "unit": "TFLOP/s", "frac": tfl * n / t_trace / 1e12 / MI355X_FP32_VECTOR_TFLOPS,
+                      "flops_per_ray": tfl},
+            "trace_fp64_option": {"bound": "alu", "achieved": tfl * n / t_f64 / 1e12,
+                                  "peak": MI355X_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": tfl * n / t_f64 / 1e12 / MI355X_FP64_VECTOR_TFLOPS}},
+    }
+    del rays, out, fast, mout
+    torch.cuda.empty_cache()
+    return res, lens
 
 
 def main():
@@ -828,155 +1030,84 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fit-steps", type=int, default=3000)
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--no-multi-path", action="store_true")
+    ap.add_argument("--no-transmit-only", action="store_true")
     ap.add_argument("--no-train-epoch", action="store_true")
     ap.add_argument("--no-paper-pair", action="store_true")
     ap.add_argument("--no-flare", action="store_true")
     ap.add_argument("--no-sampler", action="store_true")
-    ap.add_argument("--rays", type=int, default=N_RAYS)
-    ap.add_argument("--traffic-probe", nargs="?", const="f32", choices=("f32", "bf16", "fp8", "trace"),
-                    help="only run the short program the counter runs profile (map precision)")
+    ap.add_argument("--rays", type=int, default=N_RAYS, help="rays of the transmit-only case")
+    ap.add_argument("--rays-all", type=int, default=N_RAYS_ALL_PATHS, help="rays of the 56-path headline")
+    ap.add_argument("--traffic-probe", nargs="?", const="f32",
+                    choices=("f32", "bf16", "fp8", "trace", "all_f32", "all_bf16", "all_fp8"),
+                    help="only run the short program the counter runs profile")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: every box in this setup has one MI355X; "
               "multi-GPU sharding is described in DESIGN.md, not run.", file=sys.stderr)
         sys.exit(2)
     if args.traffic_probe:
-        traffic_probe(args.rays, args.traffic_probe)
+        traffic_probe(args)
         return
 
-    import numpy as np
     import torch
 
     import paper_2605_04017_amd as lt
     import synth
 
     dev = torch.device("cuda:0")
-    lens = synth.config_lens(2)
-    rays_np = synth.config_rays(2, args.rays)
-    n = args.rays
-    rays = {k: torch.from_numpy(v).to(dev) for k, v in rays_np.items()}
-    h = lt.lt_lens_create(lens.surfaces, lens.glasses)
-    out = lt.empty_exit(n, dev)
-    stream = torch.cuda.current_stream()
-
-    # map of the workload's architecture, fitted on GPU-traced rays
-    t_fit = time.perf_counter()
-    m, fitted, fit_loss = fit_map(lt, synth, lens, dev, args.fit_steps)
-    t_fit = time.perf_counter() - t_fit
-    mout = lt.empty_map_out(1, n, dev)
-    print(f"# fitted map in {t_fit:.1f} s, loss {fit_loss}", file=sys.stderr, flush=True)
-
-    def step(ev=None):
-        if ev is not None:
-            ev[0].record(stream)
-        lt.lt_trace(h, (0, 0, 0), rays, out, n, stream)
-        if ev is not None:
-            ev[1].record(stream)
-        lt.lt_map_eval(m, lt.LT_F32, rays, mout, n, stream)
-        if ev is not None:
-            ev[2].record(stream)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(evs[k])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    t_trace = float(np.mean([e[0].elapsed_time(e[1]) for e in evs])) * 1e-3
-    t_map = float(np.mean([e[1].elapsed_time(e[2]) for e in evs])) * 1e-3
-    ms_per_step = wall / args.steps * 1e3
-    print(f"# timed {args.steps} steps", file=sys.stderr, flush=True)
-
-    reps = 5
-    t_bf16 = time_kernel(lambda: lt.lt_map_eval(m, lt.LT_BF16, rays, mout, n, stream), stream, reps)
-    t_fp8 = time_kernel(lambda: lt.lt_map_eval(m, lt.LT_FP8, rays, mout, n, stream), stream, reps)
-    fast = lt.empty_exit(n, dev)
-    t_fast = time_kernel(lambda: lt.lt_trace_ex(h, (0, 0, 0), rays, fast, n, lt.LT_TRACE_PLAIN_FP32,
-                                                stream), stream, reps)
-    t_f64 = time_kernel(lambda: lt.lt_trace_ex(h, (0, 0, 0), rays, fast, n, lt.LT_TRACE_FP64,
-                                               stream), stream, reps)
-    errors = {name: map_error(lt, h, m, dt, rays)
-              for name, dt in (("f32", lt.LT_F32), ("bf16", lt.LT_BF16), ("fp8", lt.LT_FP8))}
-    # the symmetry-reduced input frame, fitted with the same budget
-    t_c = time.perf_counter()
-    mc, _, fit_loss_c = fit_map(lt, synth, lens, dev, args.fit_steps, canonical=True)
-    t_c = time.perf_counter() - t_c
-    errors["f32_canonical_input"] = map_error(lt, h, mc, lt.LT_F32, rays)
-    errors["f32_canonical_input"]["fit_final_loss"] = fit_loss_c
-    t_map_c = time_kernel(lambda: lt.lt_map_eval(mc, lt.LT_F32, rays, mout, n, stream), stream, 3)
-    del mc
-    print("# map errors measured", file=sys.stderr, flush=True)
-
-    fpr = map_flops_per_ray()
-    achieved = fpr * n / t_map / 1e12
-    trace_tf = trace_flops_per_ray(lens) * n / t_trace / 1e12
-    tr = measured_traffic()
+    A = all_paths(lt, synth, dev, args)
+    flat, norms, rays_all_np, lens3, paths = A.pop("_cpu")
+    t_trace, t_map, wall = A.pop("_t")
+    n, P = args.rays_all, len(paths)
+    rl = A["roofline_by_dtype"]["f32"]
+    tr = measured_traffic(TRAFFIC_ALL_SUMMARY, MAP_F32_SOURCES + MAP_BF16_SOURCES)
     traffic = None
-    if tr is not None and tr.get("rays") == n:
+    if tr is not None and tr.get("rays") == n and tr.get("dtype") == "f32":
         traffic = tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]
     res = {
         "metric": "Mrays/s map vs GPU brute-force trace at stated exit-ray error; p99 latency",
-        "value": n / t_map / 1e6,
-        "unit": "Mrays/s",
+        "value": P * n / t_map / 1e6,
+        "unit": "Mray-paths/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": wall / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "double-Gauss-style 11-surface lens + stop, 4,194,304 sensor-side "
-                               "rays; step = FP32 brute-force trace + FP32 map, 5 x 128 tanh",
-                   "rays": n,
-                   "map": "6-D input, 5 x 128 tanh, 1 head (mask logit + x, y, dx, dy, throughput), "
-                          f"fitted for {args.fit_steps} steps of 65,536 GPU-traced rays"},
-        "map_f32_mrays_s": n / t_map / 1e6,
-        "map_bf16_mrays_s": n / t_bf16 / 1e6,
-        "map_fp8_mrays_s": n / t_fp8 / 1e6,
-        "trace_mrays_s": n / t_trace / 1e6,
-        "trace_plain_fp32_mrays_s": n / t_fast / 1e6,
-        "trace_fp64_option_mrays_s": n / t_f64 / 1e6,
-        "map_over_trace": {"f32": t_trace / t_map, "bf16": t_trace / t_bf16, "fp8": t_trace / t_fp8},
-        "kernel_ms": {"trace": t_trace * 1e3, "trace_plain_fp32": t_fast * 1e3,
-                      "trace_fp64_option": t_f64 * 1e3,
-                      "map_f32": t_map * 1e3, "map_bf16": t_bf16 * 1e3, "map_fp8": t_fp8 * 1e3,
-                      "map_f32_canonical_input": t_map_c * 1e3},
-        "map_error_vs_gpu_tracer": errors,
-        "map_error_reference": "exit rays of the FP32 GPU tracer on the same rays; the GPU parity "
-                               "tests pin it to the FP64 oracle within 1e-5 mm / 1e-6 rad, and "
-                               "tests/test_gpu_map_error.py checks a fitted map's error against "
-                               "both agrees to that bound",
+        "config": {"workload": "double-Gauss-style 11-surface lens + stop, 16,777,216 sensor-side rays, "
+                               "all 56 paths with at most two reflections (transmit + 55 ghosts); "
+                               "step = FP32 brute-force trace of every path (compacted output) + "
+                               "FP32 map, one 5 x 128 tanh trunk with 56 heads (compacted output)",
+                   "rays": n, "paths": P,
+                   "map": "6-D canonical input, 5 x 128 tanh, 56 heads (mask logit + x, y, dx, dy, "
+                          f"throughput each), fitted for {args.fit_steps} steps of 65,536 GPU-traced rays"},
+        "value_note": "map ray-path evaluations per second (rays x paths); map_over_trace compares with "
+                      "each tracer variant that holds 1e-5 mm / 1e-6 rad against the FP64 oracle",
+        "map_over_trace": A["map_over_trace"]["f32"],
+        "roofline": {"bound": "mfma", "achieved": rl["achieved"], "peak": rl["peak"], "unit": "TFLOP/s",
+                     "frac": rl["frac"], "traffic": traffic,
+                     "kernel": "map_eval_f32_kernel<128, tanh, compacted>",
+                     "flops_per_ray": rl["flops_per_ray"], "algorithmic_bytes": rl["algorithmic_bytes"],
+                     "hbm_achieved_gbs": rl["hbm_gbs"], "hbm_peak_gbs": MI355X_HBM_GBS,
+                     "hbm_frac": rl["hbm_frac"], "traffic_detail": tr},
+        "roofline_other": {"map_bf16_compact": A["roofline_by_dtype"]["bf16"],
+                           "map_fp8_compact": A["roofline_by_dtype"]["fp8"]},
+        "all_paths_16M": A,
         "paper_context": {
             "reported": "rendering about 12-15x faster with the maps than with the ray-traced lens "
                         "(depth-of-field path tracing in LuisaRender, per-path 32-wide tanh MLPs)",
             "hardware_and_precision": "not stated in the paper",
-            "comparable_here": "multi_path_16M map_over_trace (all 56 paths, one trunk with 56 heads) "
-                               "and flare_forward frame_speedup_map_over_trace"},
-        "fit": {"steps": args.fit_steps, "batch": 65536, "final_loss": fit_loss, "seconds": t_fit},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": MI355X_FP32_MFMA_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / MI355X_FP32_MFMA_TFLOPS,
-                     "traffic": traffic, "kernel": "map_eval_f32_kernel<128, tanh>",
-                     "flops_per_ray": fpr, "algorithmic_bytes": 53 * n,
-                     "traffic_detail": tr},
-        "roofline_other": {
-            "map_bf16": {"bound": "mfma", "achieved": fpr * n / t_bf16 / 1e12,
-                         "peak": MI355X_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
-                         "frac": fpr * n / t_bf16 / 1e12 / MI355X_BF16_MFMA_TFLOPS},
-            "map_fp8": {"bound": "mfma", "achieved": fpr * n / t_fp8 / 1e12,
-                        "peak": MI355X_FP8_MFMA_TFLOPS, "unit": "TFLOP/s",
-                        "frac": fpr * n / t_fp8 / 1e12 / MI355X_FP8_MFMA_TFLOPS},
-            "trace": {"bound": "alu", "achieved": trace_tf, "peak": MI355X_FP32_VECTOR_TFLOPS,
-                      "unit": "TFLOP/s", "frac": trace_tf / MI355X_FP32_VECTOR_TFLOPS,
-                      "flops_per_ray": trace_flops_per_ray(lens)},
-            "trace_fp64_option": {"bound": "alu",
-                                  "achieved": trace_flops_per_ray(lens) * n / t_f64 / 1e12,
-                                  "peak": MI355X_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                                  "frac": trace_flops_per_ray(lens) * n / t_f64 / 1e12
-                                  / MI355X_FP64_VECTOR_TFLOPS}},
+            "comparable_here": "map_over_trace (all 56 paths, one trunk with 56 heads) and "
+                               "flare_forward frame_speedup_map_over_trace"},
     }
+    print("# headline done", file=sys.stderr, flush=True)
+    lens2 = None
+    if not args.no_transmit_only:
+        res["transmit_only_4M"], lens2 = transmit_only(lt, synth, dev, args)
+        print("# transmit-only case done", file=sys.stderr, flush=True)
     if not args.no_paper_pair:
-        res["paper_pair_2x32_5x32"] = paper_pair(lt, synth, lens, dev, args.fit_steps, rays)
+        lens2 = lens2 or synth.config_lens(2)
+        rays2 = {k: torch.from_numpy(v).to(dev) for k, v in synth.config_rays(2, args.rays).items()}
+        res["paper_pair_2x32_5x32"] = paper_pair(lt, synth, lens2, dev, args.fit_steps, rays2)
+        del rays2
         print("# paper-size pair done", file=sys.stderr, flush=True)
     if not args.no_train_epoch:
         res["train_epoch_67M"] = train_epoch(lt, synth, dev)
@@ -987,15 +1118,12 @@ def main():
     if not args.no_sampler:
         res["sampler_yield_ghost"] = sampler_yield(lt, synth, dev)
         print("# sampler yield done", file=sys.stderr, flush=True)
-    if not args.no_multi_path:
-        res["multi_path_16M"] = multi_path(lt, synth, dev)
-        print("# multi-path done", file=sys.stderr, flush=True)
     if not args.no_serving:
         res["serving"] = serving(lt, synth, dev)
         print("# serving done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline_map(fitted[0], fitted[1], rays_np)
-        res["cpu_baseline_trace"] = cpu_baseline_trace(lens, rays_np)
+        res["cpu_baseline"] = cpu_baseline_map(flat, norms, rays_all_np, heads=P, canonical=True)
+        res["cpu_baseline_trace"] = cpu_baseline_trace(lens3, rays_all_np, paths)
     print(json.dumps(res), flush=True)
 
 

@@ -519,6 +519,42 @@ lt_status lt_map_eval(lt_map map, int32_t dtype, const lt_rays *rays, const lt_m
 lt_status lt_map_eval_ex(lt_map map, int32_t dtype, const lt_rays *rays, const lt_map_out *out,
                          int64_t n, uint32_t flags, const uint8_t *mask_in, void *stream);
 
+/* Compacted outputs of lt_map_eval_compact, per head p = 0 .. n_heads - 1
+ * (device buffers owned by the caller): */
+typedef struct {
+    uint32_t *mask_bits;  /* [n_heads][(n + 31) / 32] or NULL: bit r % 32 of word
+                             p * ((n + 31) / 32) + r / 32 is ray r's mask for head p
+                             (bits past n are 0) */
+    int32_t *idx;         /* [n_heads][capacity]: input ray index of each entry */
+    float *x;             /* [n_heads][capacity]: exit position, direction and */
+    float *y;             /*   throughput of the entry, exactly the values */
+    float *dx;            /*   lt_map_eval writes for that ray and head */
+    float *dy;
+    float *dz;            /* may be NULL (not written) */
+    float *throughput;
+    int64_t *count;       /* [n_heads]: valid rays per head (may exceed capacity) */
+    int64_t capacity;     /* entries per head */
+} lt_map_compact;
+
+/* Compacted evaluation (Sec. 4.2, "Neural Ray Masking": where g(x) = 0 the
+ * map outputs nothing).  Computes what lt_map_eval computes for the same
+ * dtype, bit for bit, and writes, per head, the mask bitmap and only the
+ * valid rays, densely: entry k of head p (k < min(count[p], capacity)) sits
+ * at p * capacity + k.  A head's entries from one workgroup pass (256
+ * consecutive rays at width 128, 512 otherwise) keep their input order; the
+ * order of the passes is unspecified, so sort by idx for a canonical order.
+ * count[p] is the total number of valid rays of head p; entries beyond
+ * capacity are counted but not written, so count[p] > capacity signals
+ * overflow.  The counts are cleared by a kernel on the stream (capture-safe);
+ * n = 0 writes zero counts.  Output bytes per ray and head: 1/8 for the
+ * bitmap plus 24 (28 with dz) per valid ray, against 29 for lt_map_eval.
+ * Errors: LT_ERR_ARG (NULL map, rays, out or count; n outside 0 .. 2^31 - 1;
+ * negative capacity; a NULL field that would be written; a map whose LDS
+ * image leaves no room for the 2 KiB reservation arrays), LT_ERR_DTYPE,
+ * LT_ERR_STATE (parameters never set), LT_ERR_DEVICE. */
+lt_status lt_map_eval_compact(lt_map map, int32_t dtype, const lt_rays *rays,
+                              const lt_map_compact *out, int64_t n, void *stream);
+
 /* ----------------------------------------------------------- training */
 
 /* Traced targets per head, head-major [n_heads][n] (device): validity (the

@@ -662,6 +662,47 @@ def lt_map_eval_ex(m: Map, dtype: int, rays: Dict, out: Optional[Dict] = None,
     return out
 
 
+COMPACT_FIELDS = ("x", "y", "dx", "dy", "dz", "throughput")
+
+
+def lt_map_eval_compact(m: Map, dtype: int, rays: Dict, capacity: Optional[int] = None,
+                        out: Optional[Dict] = None, n: Optional[int] = None, with_dz: bool = True,
+                        with_bits: bool = True, stream=None) -> Dict:
+    """Compacted evaluation (lt_map_eval_compact): per head the mask bitmap
+    ``bits`` (int32 view of the uint32 words, shape (n_heads, ceil(n/32))),
+    the valid rays' input indices ``idx`` and exit fields, shape
+    (n_heads, capacity), and ``count`` (n_heads,) int64.  Entries of head p
+    past count[p] (or capacity) are not written.  ``capacity`` defaults to n."""
+    torch = _torch()
+    if n is None:
+        n = int(rays["x"].numel())
+    if capacity is None:
+        capacity = n
+    dev = rays["x"].device
+    P = m.n_heads
+    words = (n + 31) // 32
+    if out is None:
+        out = {k: torch.empty((P, capacity), dtype=torch.float32, device=dev)
+               for k in COMPACT_FIELDS if k != "dz" or with_dz}
+        out["idx"] = torch.empty((P, capacity), dtype=torch.int32, device=dev)
+        out["count"] = torch.empty(P, dtype=torch.int64, device=dev)
+        if with_bits:
+            out["bits"] = torch.empty((P, words), dtype=torch.int32, device=dev)
+    o = N.lt_map_compact()
+    cap_n = P * capacity
+    for k in COMPACT_FIELDS:
+        t = out.get(k)
+        setattr(o, k, _dev_ptr(t, torch.float32, cap_n, f"out[{k}]") if (t is not None and cap_n) else None)
+    o.idx = _dev_ptr(out["idx"], torch.int32, cap_n, "out[idx]") if cap_n else None
+    o.mask_bits = (_dev_ptr(out["bits"], torch.int32, P * words, "out[bits]")
+                   if (out.get("bits") is not None and n) else None)
+    o.count = _dev_ptr(out["count"], torch.int64, P, "out[count]")
+    o.capacity = int(capacity)
+    N.check(N.lib().lt_map_eval_compact(m.handle, int(dtype), C.byref(_rays_struct(rays, n)),
+                                        C.byref(o), int(n), C.c_void_p(_stream_ptr(stream))))
+    return out
+
+
 # -------------------------------------------------------------- training --
 
 def lt_map_workspace_bytes(m: Map, n: int) -> int:

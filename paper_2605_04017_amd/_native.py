@@ -89,6 +89,11 @@ class lt_map_out(C.Structure):
                                            "throughput")]
 
 
+class lt_map_compact(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in ("mask_bits", "idx", "x", "y", "dx", "dy", "dz",
+                                           "throughput", "count")] + [("capacity", C.c_int64)]
+
+
 class lt_targets(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in ("valid", "x", "y", "dx", "dy", "throughput")]
 
@@ -137,6 +142,8 @@ SIGNATURES = {
     "lt_map_quantize": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "lt_map_eval_ex": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(lt_rays), C.POINTER(lt_map_out),
                                  C.c_int64, C.c_uint32, C.c_void_p, C.c_void_p]),
+    "lt_map_eval_compact": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(lt_rays),
+                                      C.POINTER(lt_map_compact), C.c_int64, C.c_void_p]),
     "lt_rays_generate": (C.c_int, [C.c_void_p, C.POINTER(lt_raygen), C.POINTER(lt_ray_buffers),
                                    C.c_int64, C.c_void_p]),
     "lt_rays_generate_forward": (C.c_int, [C.c_void_p, C.POINTER(lt_raygen_forward),

@@ -23,15 +23,21 @@ struct MapLayout {
     int32_t T = 0;    // M-tiles per hidden layer (H / 16)
     int32_t C = 0;    // K-chunks of 32 per hidden layer (H / 32)
     int32_t TO = 0;   // M-tiles of the output layer (ceil(P * 8 / 16))
+    int32_t LT = 0;   // M-tiles of the logit rows alone (ceil(P / 16)), for compacted evaluation
     // offsets into the flat FP32 parameter vector
     int64_t w_off[16], b_off[16];
     // BF16 fragment image (bytes)
     int64_t img_w0 = 0, img_hidden = 0, img_out = 0, img_bias = 0, img_bytes = 0;
     int64_t out_in_lds_bytes = 0;  // image bytes staged in LDS (everything, or all but the output layer)
+    // after the output fragments, never staged: the heads' logit rows alone
+    // (LT x 2C split fragments, the same values as those rows of the output
+    // layer) and their biases (16 LT floats)
+    int64_t img_logit = 0, img_logit_bias = 0;
     // FP8 image (width 128, tanh): [W0 BF16 frags][hidden FP8 16x128 frags,
     // 2 KiB each][bias + norm + per-layer scales][output BF16 frags]
     int64_t img8_hidden = 0, img8_bias = 0, img8_out = 0, img8_bytes = 0;
     int64_t img8_lds_bytes = 0;
+    int64_t img8_logit = 0, img8_logit_bias = 0;
     int32_t fp8_ok = 0;
 };
 
@@ -58,5 +64,7 @@ int64_t f32_image_bytes(const MapLayout &L);
 lt_status eval_f32(Map &M, const lt_rays &rays, const lt_map_out &out, int64_t n, uint32_t flags,
                    const uint8_t *mask_in, hipStream_t s);
 lt_status ensure_packed_f32(Map &M, hipStream_t s);
+struct MapCompact;
+lt_status eval_f32_compact(Map &M, const lt_rays &rays, const MapCompact &C, int64_t n, hipStream_t s);
 
 }  // namespace lt

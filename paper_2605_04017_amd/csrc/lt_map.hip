@@ -56,8 +56,11 @@ MapLayout make_layout(const lt_map_desc &d)
     const int64_t bias_floats = static_cast<int64_t>(L.D) * L.H + 16LL * L.TO + 12 + 10LL * L.P;
     L.img_bias = L.img_hidden + static_cast<int64_t>(L.D - 1) * L.T * L.C * kFragBytes;
     L.img_out = L.img_bias + ((bias_floats * 4 + 1023) / 1024) * 1024;
-    L.img_bytes = L.img_out + static_cast<int64_t>(L.TO) * 2 * L.C * kFragBytes;
-    L.out_in_lds_bytes = L.img_bytes <= kMaxLds ? L.img_bytes : L.img_out;
+    L.LT = (L.P + 15) / 16;
+    L.img_logit = L.img_out + static_cast<int64_t>(L.TO) * 2 * L.C * kFragBytes;
+    L.img_logit_bias = L.img_logit + static_cast<int64_t>(L.LT) * 2 * L.C * kFragBytes;
+    L.img_bytes = L.img_logit_bias + 64LL * L.LT;
+    L.out_in_lds_bytes = L.img_logit <= kMaxLds ? L.img_logit : L.img_out;
     // FP8 image: the hidden region holds one 2 KiB fragment per M-tile per
     // layer; the bias region gains two floats per hidden layer (1 / (s_w s_h)
     // and s_h)
@@ -66,8 +69,10 @@ MapLayout make_layout(const lt_map_desc &d)
     L.img8_bias = L.img8_hidden + static_cast<int64_t>(L.D - 1) * L.T * 2 * kFragBytes;
     const int64_t bias8_floats = bias_floats + 2LL * (L.D - 1);
     L.img8_out = L.img8_bias + ((bias8_floats * 4 + 1023) / 1024) * 1024;
-    L.img8_bytes = L.img8_out + static_cast<int64_t>(L.TO) * 2 * L.C * kFragBytes;
-    L.img8_lds_bytes = L.img8_bytes <= kMaxLds ? L.img8_bytes : L.img8_out;
+    L.img8_logit = L.img8_out + static_cast<int64_t>(L.TO) * 2 * L.C * kFragBytes;
+    L.img8_logit_bias = L.img8_logit + static_cast<int64_t>(L.LT) * 2 * L.C * kFragBytes;
+    L.img8_bytes = L.img8_logit_bias + 64LL * L.LT;
+    L.img8_lds_bytes = L.img8_logit <= kMaxLds ? L.img8_logit : L.img8_out;
     return L;
 }
 
@@ -88,12 +93,39 @@ __global__ void pack_bf16_kernel(const float *__restrict__ P, const float *__res
     const int64_t n_out = static_cast<int64_t>(L.TO) * 2 * L.C * 512;
     const int64_t bias_floats = static_cast<int64_t>(L.D) * L.H + 16LL * L.TO + 12 + 10LL * L.P +
                                 (fp8 ? 2LL * (L.D - 1) : 0);
+    const int64_t n_lg = static_cast<int64_t>(L.LT) * 2 * L.C * 512;
+    const int64_t n_lb = 16LL * L.LT;
     const int64_t img_out = fp8 ? L.img8_out : L.img_out;
     const int64_t img_bias = fp8 ? L.img8_bias : L.img_bias;
-    const int64_t total = n_w0 + n_hid + n_out + bias_floats;
+    const int64_t img_logit = fp8 ? L.img8_logit : L.img_logit;
+    const int64_t img_logit_bias = fp8 ? L.img8_logit_bias : L.img_logit_bias;
+    const int64_t n_frag = n_w0 + n_hid + n_out;
+    const int64_t total = n_frag + n_lg + bias_floats + n_lb;
     for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total;
          e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        if (e < n_w0 + n_hid + n_out) {
+        if (e >= n_frag && e < n_frag + n_lg) {
+            // logit fragment f, chunk cc: row mrow is the logit row of head
+            // 16 (f / 2C) + mrow, split hi / lo exactly as in the output layer
+            const int64_t loc = e - n_frag;
+            const int f = static_cast<int>(loc / 512);
+            const int within = static_cast<int>(loc % 512);
+            const int lane = within >> 3, j = within & 7;
+            const int kp = 8 * (lane >> 4) + j;
+            const int lt = f / (2 * L.C), cc = f % (2 * L.C), c = cc % L.C;
+            const int head = 16 * lt + (lane & 15);
+            float v = 0.0f;
+            if (head < L.P) {
+                const int k = 32 * c + perm32(kp);
+                const float w = P[L.w_off[L.D] + static_cast<int64_t>(head * kMapOut) * L.H + k];
+                const float hi = static_cast<float>(to_bf16(w));
+                v = cc < L.C ? hi : w - hi;
+            }
+            reinterpret_cast<__bf16 *>(img + img_logit)[loc] = to_bf16(v);
+        } else if (e >= n_frag + n_lg + bias_floats) {
+            const int head = static_cast<int>(e - (n_frag + n_lg + bias_floats));
+            reinterpret_cast<float *>(img + img_logit_bias)[head] =
+                head < L.P ? P[L.b_off[L.D] + head * kMapOut] : 0.0f;
+        } else if (e < n_frag) {
             const bool is_w0 = e < n_w0, is_hid = !is_w0 && e < n_w0 + n_hid;
             const int64_t loc = is_w0 ? e : is_hid ? e - n_w0 : e - n_w0 - n_hid;
             const int64_t base = is_w0 ? L.img_w0 : is_hid ? L.img_hidden : img_out;
@@ -137,7 +169,7 @@ __global__ void pack_bf16_kernel(const float *__restrict__ P, const float *__res
             reinterpret_cast<__bf16 *>(img + base)[loc] = to_bf16(v);
         } else {
             // biases (hidden layers, then output slots), then normalisation
-            const int64_t b = e - (n_w0 + n_hid + n_out);
+            const int64_t b = e - (n_frag + n_lg);
             float v = 0.0f;
             const int64_t nb_hidden = static_cast<int64_t>(L.D) * L.H;
             const int64_t nb_norm = nb_hidden + 16LL * L.TO + 12 + 10LL * L.P;
@@ -220,12 +252,17 @@ __global__ void pack_fp8_hidden_kernel(const float *__restrict__ P, MapLayout L,
 // BIG: the output-layer fragments do not fit in LDS (many heads); they are
 // streamed from L2 with one tile of prefetch, and each output tile is
 // transposed through LDS before decoding (evaluation only).
-template <int H, int ACT, bool TRAIN, bool FP8, bool BIG>
+// CMP: compacted evaluation (MapCompact): the heads' logit rows are computed
+// first, on their own tiles, which gives every head's mask for the wave's
+// rays; one atomic per head and workgroup reserves the output ranges; the
+// output tiles are then stored for valid rays only.
+template <int H, int ACT, bool TRAIN, bool FP8, bool BIG, bool CMP>
 __global__ __launch_bounds__((eval_waves<H, TRAIN>() * 64)) void map_eval_bf16_kernel(EvalArgs A, lt_rays rays,
                                                                                   lt_map_out out)
 {
     static_assert(!FP8 || (H == 128 && ACT == LT_ACT_TANH && !TRAIN), "FP8 path: width 128, tanh");
     static_assert(!(BIG && TRAIN), "streamed output layer: evaluation only");
+    static_assert(!(CMP && (TRAIN || BIG)), "compacted evaluation has its own store path");
     constexpr int T = H / 16, C = H / 32;
     constexpr int kWaves = eval_waves<H, TRAIN>();
     constexpr int NT = eval_subtiles<H, TRAIN>();  // 16-ray MFMA N tiles per wave
@@ -257,15 +294,19 @@ __global__ __launch_bounds__((eval_waves<H, TRAIN>() * 64)) void map_eval_bf16_k
     // and one after it for the leading half.  Measured on 4,194,304 rays,
     // one head: 7 % faster; FP8, the streamed output layer and narrower
     // maps (the 32-wide pair: 20 % slower) keep the free-running schedule.
-    constexpr bool kPP = H == 128 && !TRAIN && !FP8 && !BIG && kWaves == 8;
+    constexpr bool kPP = H == 128 && !TRAIN && !FP8 && !BIG && !CMP && kWaves == 8;
     const bool lag = wave >= kWaves / 2;
     if (kPP && lag)
         __builtin_amdgcn_s_barrier();
+    int par = 0;  // CMP: alternating reservation arrays
+    (void)par;
 
     for (int64_t tbase = static_cast<int64_t>(blockIdx.x) * kWaves; tbase < n_tiles;
          tbase += static_cast<int64_t>(gridDim.x) * kWaves) {
         const int64_t tile = tbase + wave;
-        if (!kPP && tile >= n_tiles)
+        // the phase-offset and compacted schedules keep every wave in the
+        // loop (workgroup barriers); past the end their rays are masked
+        if (!kPP && !CMP && tile >= n_tiles)
             break;
         const int64_t ray0 = tile * RPW;
         floatx4 acc[NT][T];
@@ -413,6 +454,67 @@ __global__ __launch_bounds__((eval_waves<H, TRAIN>() * 64)) void map_eval_bf16_k
         const float *bo = bias + A.D * H;
         const float *out_shift = nrm + 12;
         const float *out_scale = nrm + 12 + 5 * A.P;
+        if constexpr (CMP) {
+            // logit tiles: lane k ends with head k's mask bits for the RPW rays
+            uint64_t word = 0;
+            const float *lb = reinterpret_cast<const float *>(A.img + A.img_logit_bias);
+            const uint8_t *lf = A.img + A.img_logit;
+            for (int lt = 0; lt < A.LT; ++lt) {
+                const floatx4 bz = *reinterpret_cast<const floatx4 *>(lb + lt * 16 + 4 * g);
+                floatx4 o[NT];
+#pragma unroll
+                for (int cc = 0; cc < 2 * C; ++cc) {
+                    const bf16x8 a = *reinterpret_cast<const bf16x8 *>(
+                        lf + (static_cast<int64_t>(lt) * 2 * C + cc) * kFragBytes + lane * 16);
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+                        o[nt] = mfma_bf16(a, bop[nt][cc % C], cc == 0 ? bz : o[nt]);
+                }
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const bool live = ray0 + nt * 16 + col < n;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        mask_word_add(word, __ballot(live && o[nt][i] > 0.0f), lt, i, nt, lane);
+                }
+            }
+            store_mask_words<RPW>(A.cmp, word, A.P, lane, ray0, n);
+            const int64_t base = compact_reserve<kWaves>(word, A.P, lds + A.cmp.agg, par, A.cmp.count,
+                                                         wave, lane);
+            par ^= 1;
+            // output tiles, fragments from LDS or streamed from L2 one tile ahead
+            const bf16x8 *of = reinterpret_cast<const bf16x8 *>(out_frag) + lane;
+            bf16x8 nx[2 * C];
+#pragma unroll
+            for (int cc = 0; cc < 2 * C; ++cc)
+                nx[cc] = of[cc * 64];
+            for (int to = 0; to < A.TO; ++to) {
+                bf16x8 cur[2 * C];
+#pragma unroll
+                for (int cc = 0; cc < 2 * C; ++cc)
+                    cur[cc] = nx[cc];
+                if (to + 1 < A.TO) {
+#pragma unroll
+                    for (int cc = 0; cc < 2 * C; ++cc)
+                        nx[cc] = of[(static_cast<int64_t>(to + 1) * 2 * C + cc) * 64];
+                }
+                const floatx4 bz = *reinterpret_cast<const floatx4 *>(bo + to * 16 + 4 * g);
+                floatx4 o[NT];
+#pragma unroll
+                for (int cc = 0; cc < 2 * C; ++cc)
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+                        o[nt] = mfma_bf16(cur[cc], bop[nt][cc % C], cc == 0 ? bz : o[nt]);
+                const int hsrc = min(2 * to + (g >> 1), A.P - 1);
+                const uint64_t wd = __shfl(word, hsrc);
+                const int64_t bs = __shfl(base, hsrc);
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    compact_store(o[nt], to, g, nt, col, ray0 + nt * 16 + col, n, A.P, out_shift, out_scale,
+                                  A.cmp, A.canonical != 0, fr[nt], A.dz_sign, wd, bs);
+            }
+            continue;
+        }
         if constexpr (BIG) {
             // Output tile `to` (16 rows = slots of heads 2 to and 2 to + 1,
             // RPW rays) is written to this wave's LDS buffer as [ray][16]
@@ -484,19 +586,15 @@ __global__ __launch_bounds__((eval_waves<H, TRAIN>() * 64)) void map_eval_bf16_k
                     }
                     if (A.flags & LT_EVAL_MASK_ONLY)
                         continue;
-                    float x = fmaf(sc[0], w[1], sh[0]);
-                    float y = fmaf(sc[1], w[2], sh[1]);
-                    float dx = fmaf(sc[2], w[3], sh[2]);
-                    float dy = fmaf(sc[3], w[4], sh[3]);
+                    const float dy = fmaf(sc[3], w[4], sh[3]);
                     const float thr = fmaf(sc[4], w[5], sh[4]);
-                    if (A.canonical)
-                        canon_out(myfr, x, y, dx, dy);
-                    const float dz = A.dz_sign * sqrtf(fmaxf(0.0f, 1.0f - dx * dx - dy * dy));
-                    out.x[idx] = m ? x : nan;
-                    out.y[idx] = m ? y : nan;
-                    out.dx[idx] = m ? dx : nan;
-                    out.dy[idx] = m ? dy : nan;
-                    out.dz[idx] = m ? dz : nan;
+                    const ExitFields f = decode_fields(w[1], w[2], w[3], dy, head, out_shift, out_scale,
+                                                       A.canonical != 0, myfr, A.dz_sign);
+                    out.x[idx] = m ? f.x : nan;
+                    out.y[idx] = m ? f.y : nan;
+                    out.dx[idx] = m ? f.dx : nan;
+                    out.dy[idx] = m ? f.dy : nan;
+                    out.dz[idx] = m ? f.dz : nan;
                     out.throughput[idx] = m ? thr : 0.0f;
                 }
             }
@@ -544,6 +642,14 @@ __global__ __launch_bounds__((eval_waves<H, TRAIN>() * 64)) void map_eval_bf16_k
         __builtin_amdgcn_s_barrier();
 }
 
+// Clears the per-head counts of a compacted evaluation with an ordinary
+// kernel store (usable under stream capture).
+__global__ void zero_counts_kernel(unsigned long long *count, int P)
+{
+    if (static_cast<int>(threadIdx.x) < P)
+        count[threadIdx.x] = 0ull;
+}
+
 static int g_num_cus = 0;
 
 int num_cus()
@@ -559,11 +665,11 @@ int num_cus()
     return g_num_cus;
 }
 
-template <int H, int ACT, bool TRAIN, bool FP8, bool BIG>
+template <int H, int ACT, bool TRAIN, bool FP8, bool BIG, bool CMP = false>
 static lt_status launch_kernel(EvalArgs A, int64_t dyn_lds, const lt_rays &rays,
                                const lt_map_out &out, hipStream_t s)
 {
-    auto kern = map_eval_bf16_kernel<H, ACT, TRAIN, FP8, BIG>;
+    auto kern = map_eval_bf16_kernel<H, ACT, TRAIN, FP8, BIG, CMP>;
     static bool attr_set = false;
     if (!attr_set) {
         lt_status st = check_hip(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -583,7 +689,7 @@ static lt_status launch_kernel(EvalArgs A, int64_t dyn_lds, const lt_rays &rays,
     return check_hip(hipGetLastError(), "map_eval_bf16_kernel launch");
 }
 
-template <int H, int ACT, bool TRAIN, bool FP8 = false>
+template <int H, int ACT, bool TRAIN, bool FP8 = false, bool CMP = false>
 static lt_status launch_bf16_impl(const Map &M, const lt_rays &rays, const lt_map_out &out,
                                   EvalArgs A, hipStream_t s)
 {
@@ -595,12 +701,28 @@ static lt_status launch_bf16_impl(const Map &M, const lt_rays &rays, const lt_ma
     A.D = L.D;
     A.P = L.P;
     A.TO = L.TO;
-    A.out_from_lds = FP8 ? L.img8_lds_bytes == L.img8_bytes : L.out_in_lds_bytes == L.img_bytes;
+    A.out_from_lds = FP8 ? L.img8_lds_bytes == L.img8_logit : L.out_in_lds_bytes == L.img_logit;
+    A.LT = L.LT;
+    A.img_logit = FP8 ? L.img8_logit : L.img_logit;
+    A.img_logit_bias = FP8 ? L.img8_logit_bias : L.img_logit_bias;
     A.img_out = FP8 ? L.img8_out : L.img_out;
     A.img_bias = FP8 ? L.img8_bias : L.img_bias;
     A.img_hidden = FP8 ? L.img8_hidden : L.img_hidden;
     A.canonical = L.canon;
     A.dz_sign = L.fwd ? 1.0f : -1.0f;
+    if constexpr (CMP) {
+        // the reservation arrays follow the staged part; without room for
+        // them the output layer is read from L2 instead of LDS
+        if (A.lds_bytes + kCompactAggBytes > kMaxLds) {
+            A.lds_bytes = FP8 ? L.img8_out : L.img_out;
+            A.out_from_lds = 0;
+        }
+        if (A.lds_bytes + kCompactAggBytes > kMaxLds)
+            return fail(LT_ERR_ARG, "map too large for compacted evaluation");
+        A.cmp.agg = A.lds_bytes;
+        A.xpose = -1;
+        return launch_kernel<H, ACT, false, FP8, false, true>(A, A.lds_bytes + kCompactAggBytes, rays, out, s);
+    }
     if constexpr (!TRAIN) {
         // the staged part ends on a 1 KiB boundary; the transpose buffers
         // (16 floats per ray of a wave tile) follow it
@@ -900,6 +1022,72 @@ lt_status lt_map_eval(lt_map map, int32_t dtype, const lt_rays *rays, const lt_m
                       int64_t n, void *stream)
 {
     return lt_map_eval_ex(map, dtype, rays, out, n, 0u, nullptr, stream);
+}
+
+lt_status lt_map_eval_compact(lt_map map, int32_t dtype, const lt_rays *rays,
+                              const lt_map_compact *out, int64_t n, void *stream)
+{
+    Map *M = as_map(map);
+    if (!M || !rays || !out || !out->count)
+        return fail(LT_ERR_ARG, "NULL map, rays, out or count");
+    if (n < 0 || n > 0x7fffffffLL)
+        return fail(LT_ERR_ARG, "ray count must be in 0 .. 2^31 - 1 (32-bit input indices)");
+    if (out->capacity < 0)
+        return fail(LT_ERR_ARG, "negative capacity");
+    if (dtype != LT_BF16 && dtype != LT_FP8 && dtype != LT_F32)
+        return fail(LT_ERR_DTYPE, "precision not available (LT_F32, LT_BF16, LT_FP8)");
+    if (dtype == LT_FP8 && !M->lay.fp8_ok)
+        return fail(LT_ERR_DTYPE, "LT_FP8 needs width 128 and tanh");
+    if (n > 0) {
+        if (!rays->x || !rays->y || !rays->dx || !rays->dy || !rays->dz || !rays->lambda_nm)
+            return fail(LT_ERR_ARG, "NULL ray field");
+        if (out->capacity > 0 && (!out->idx || !out->x || !out->y || !out->dx || !out->dy ||
+                                  !out->throughput))
+            return fail(LT_ERR_ARG, "NULL output field");
+        if (!M->has_params)
+            return fail(LT_ERR_STATE, "parameters were never set");
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    unsigned long long *count = reinterpret_cast<unsigned long long *>(out->count);
+    hipLaunchKernelGGL(zero_counts_kernel, dim3(1), dim3(64), 0, s, count, M->lay.P);
+    lt_status st = check_hip(hipGetLastError(), "zero_counts_kernel launch");
+    if (st != LT_OK || n == 0)
+        return st;
+    MapCompact C{};
+    C.bits = out->mask_bits;
+    C.idx = out->idx;
+    C.x = out->x;
+    C.y = out->y;
+    C.dx = out->dx;
+    C.dy = out->dy;
+    C.dz = out->dz;
+    C.thr = out->throughput;
+    C.count = count;
+    C.cap = out->capacity;
+    C.n_words = (n + 31) / 32;
+    if (dtype == LT_F32)
+        return eval_f32_compact(*M, *rays, C, n, s);
+    EvalArgs A{};
+    A.n = n;
+    A.cmp = C;
+    const lt_map_out none{};
+    const bool relu = M->lay.act == LT_ACT_RELU;
+    const int H = M->lay.H;
+    if (dtype == LT_FP8) {
+        st = ensure_packed_fp8(*M, s);
+        return st != LT_OK ? st : launch_bf16_impl<128, LT_ACT_TANH, false, true, true>(*M, *rays, none, A, s);
+    }
+    st = ensure_packed_bf16(*M, s);
+    if (st != LT_OK)
+        return st;
+    if (H == 128)
+        return relu ? launch_bf16_impl<128, LT_ACT_RELU, false, false, true>(*M, *rays, none, A, s)
+                    : launch_bf16_impl<128, LT_ACT_TANH, false, false, true>(*M, *rays, none, A, s);
+    if (H == 64)
+        return relu ? launch_bf16_impl<64, LT_ACT_RELU, false, false, true>(*M, *rays, none, A, s)
+                    : launch_bf16_impl<64, LT_ACT_TANH, false, false, true>(*M, *rays, none, A, s);
+    return relu ? launch_bf16_impl<32, LT_ACT_RELU, false, false, true>(*M, *rays, none, A, s)
+                : launch_bf16_impl<32, LT_ACT_TANH, false, false, true>(*M, *rays, none, A, s);
 }
 
 }  // extern "C"

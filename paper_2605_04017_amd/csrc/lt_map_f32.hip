@@ -27,10 +27,11 @@ constexpr int kF32Frag = 256;   // bytes of one 16x4 FP32 A fragment (64 lanes x
 constexpr int kF32Stage = 64 * 1024;
 
 // image: [bias+norm floats, 1 KiB aligned][W0: T x 2 frags][hidden: (D-1) x T x H/4 frags]
-//        [output: TO x H/4 frags]
+//        [output: TO x H/4 frags][logit rows alone: LT x H/4 frags][logit biases: 16 LT floats]
 struct F32Layout {
     int64_t bias = 0, w0 = 0, hidden = 0, out = 0, bytes = 0;
     int64_t layer_bytes = 0, out_bytes = 0, resident = 0;
+    int64_t logit = 0, logit_bytes = 0, logit_bias = 0;
 };
 
 F32Layout f32_layout(const MapLayout &L)
@@ -43,7 +44,10 @@ F32Layout f32_layout(const MapLayout &L)
     f.layer_bytes = static_cast<int64_t>(L.T) * (L.H / 4) * kF32Frag;
     f.out = f.hidden + static_cast<int64_t>(L.D - 1) * f.layer_bytes;
     f.out_bytes = static_cast<int64_t>(L.TO) * (L.H / 4) * kF32Frag;
-    f.bytes = f.out + f.out_bytes;
+    f.logit = f.out + f.out_bytes;
+    f.logit_bytes = static_cast<int64_t>(L.LT) * (L.H / 4) * kF32Frag;
+    f.logit_bias = f.logit + f.logit_bytes;
+    f.bytes = f.logit_bias + 64LL * L.LT;
     f.resident = f.hidden;  // bias + norm + W0
     return f;
 }
@@ -77,7 +81,27 @@ __global__ void pack_f32_kernel(const float *__restrict__ P, const float *__rest
          e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const int64_t byte = e * 4;
         float v = 0.0f;
-        if (byte < F.w0) {
+        if (byte >= F.logit_bias) {
+            // logit bias of head 16 lt + row, folded like the output layer's
+            const int head = static_cast<int>((byte - F.logit_bias) / 4);
+            if (head < L.P) {
+                v = P[L.b_off[L.D] + head * kMapOut];
+                if (fold)
+                    v += row_sum(P + L.w_off[L.D] + static_cast<int64_t>(head * kMapOut) * L.H, L.H);
+            }
+        } else if (byte >= F.logit) {
+            // logit fragments: row mrow of tile lt is head 16 lt + mrow's logit row,
+            // in the output layer's K order and fold
+            const int64_t loc = (byte - F.logit) / 4;
+            const int64_t f = loc / 64;
+            const int lane = static_cast<int>(loc % 64);
+            const int g = lane >> 4, mrow = lane & 15;
+            const int lt = static_cast<int>(f / K4), q = static_cast<int>(f % K4);
+            const int head = 16 * lt + mrow;
+            const int k = 16 * (q / 4) + 4 * g + (q % 4);
+            if (head < L.P)
+                v = P[L.w_off[L.D] + static_cast<int64_t>(head * kMapOut) * L.H + k] * (fold ? -2.0f : 1.0f);
+        } else if (byte < F.w0) {
             const int64_t b = e;
             const int64_t nb = static_cast<int64_t>(L.D) * L.H;
             if (b < nb) {
@@ -131,12 +155,13 @@ __global__ void pack_f32_kernel(const float *__restrict__ P, const float *__rest
 struct F32Args {
     const uint8_t *img;
     F32Layout F;
-    int32_t D, P, TO;
+    int32_t D, P, TO, LT;
     int32_t canonical;
     float dz_sign;        // -1: sensor-side map, +1: forward map
     uint32_t flags;
     const uint8_t *mask_in;
     int64_t n;
+    MapCompact cmp;       // CMP: compacted outputs
 };
 
 __device__ __forceinline__ floatx4 mfma_f32(float a, float b, floatx4 c)
@@ -165,7 +190,11 @@ __device__ __forceinline__ float act_f32(float u)
 // the remaining gap being the per-stage barrier).
 constexpr int kF32NT = 2;
 
-template <int H, int ACT>
+// CMP: compacted evaluation.  A stage holding the heads' logit rows alone
+// runs between the hidden layers and the output groups; its signs give every
+// head's mask for the wave's rays, one atomic per head and workgroup reserves
+// the output ranges, and the output groups store valid rays only.
+template <int H, int ACT, bool CMP>
 __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args A, lt_rays rays,
                                                                       lt_map_out out)
 {
@@ -185,7 +214,8 @@ __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args
     const int64_t tile_bytes = static_cast<int64_t>(K4) * kF32Frag;
     const int per_group = static_cast<int>(kF32Stage / tile_bytes);
     const int n_groups = (A.TO + per_group - 1) / per_group;
-    const int stages = (A.D - 1) + n_groups;   // weight stages of one tile
+    const int n_pre = (A.D - 1) + (CMP ? 1 : 0);  // stages before the output groups
+    const int stages = n_pre + n_groups;          // weight stages of one tile
 
     // Stage j of a tile: hidden layer j + 1 (j < D - 1), else output group
     // j - (D - 1).  Stages stream through two LDS buffers: while the waves
@@ -197,7 +227,11 @@ __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args
             *bytes = A.F.layer_bytes;
             return A.img + A.F.hidden + static_cast<int64_t>(j) * A.F.layer_bytes;
         }
-        const int to0 = (j - (A.D - 1)) * per_group;
+        if (CMP && j == A.D - 1) {
+            *bytes = A.F.logit_bytes;
+            return A.img + A.F.logit;
+        }
+        const int to0 = (j - n_pre) * per_group;
         const int cnt = A.TO - to0 < per_group ? A.TO - to0 : per_group;
         *bytes = cnt * tile_bytes;
         return A.img + A.F.out + to0 * tile_bytes;
@@ -217,6 +251,12 @@ __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args
     int buf = 0;
     if (static_cast<int64_t>(blockIdx.x) < wg_tiles)
         prefetch(0, 0);
+    int par = 0;  // CMP: alternating reservation arrays
+    (void)par;
+    // CMP: this wave's mask words (64) and first output positions (64) per
+    // head, kept in LDS rather than registers (the kernel is at 243 VGPRs)
+    uint64_t *wave_heads = reinterpret_cast<uint64_t *>(lds + A.cmp.agg + kCompactAggBytes) + wave * 128;
+    (void)wave_heads;
 
     for (int64_t wt = blockIdx.x; wt < wg_tiles; wt += gridDim.x) {
         const bool more = wt + gridDim.x < wg_tiles;
@@ -308,8 +348,39 @@ __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args
                 }
                 continue;
             }
+            if (CMP && j == A.D - 1) {
+                const float *lb = reinterpret_cast<const float *>(A.img + A.F.logit_bias);
+                uint64_t word = 0;
+                for (int lt = 0; lt < A.LT; ++lt) {
+                    const floatx4 bz = *reinterpret_cast<const floatx4 *>(lb + lt * 16 + 4 * g);
+                    floatx4 o[kF32NT];
+#pragma unroll
+                    for (int q = 0; q < K4; ++q) {
+                        const float a = wl[(lt * K4 + q) * 64 + lane];
+#pragma unroll
+                        for (int nt = 0; nt < kF32NT; ++nt)
+                            o[nt] = mfma_f32(a, h[nt][q / 4][q % 4], q == 0 ? bz : o[nt]);
+                    }
+#pragma unroll
+                    for (int nt = 0; nt < kF32NT; ++nt) {
+                        const bool live = ray0 + nt * 16 + col < n;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            mask_word_add(word, __ballot(live && o[nt][i] > 0.0f), lt, i, nt, lane);
+                    }
+                }
+                store_mask_words<16 * kF32NT>(A.cmp, word, A.P, lane, ray0, n);
+                const int64_t base = compact_reserve<kF32Waves>(word, A.P, lds + A.cmp.agg, par, A.cmp.count,
+                                                                wave, lane);
+                par ^= 1;
+                if (lane < A.P) {
+                    wave_heads[lane] = word;
+                    wave_heads[64 + lane] = static_cast<uint64_t>(base);
+                }
+                continue;
+            }
             // output group
-            const int to0 = (j - (A.D - 1)) * per_group;
+            const int to0 = (j - n_pre) * per_group;
             const int cnt = A.TO - to0 < per_group ? A.TO - to0 : per_group;
             for (int k = 0; k < cnt; ++k) {
                 const int to = to0 + k;
@@ -322,20 +393,31 @@ __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args
                     for (int nt = 0; nt < kF32NT; ++nt)
                         o[nt] = mfma_f32(a, h[nt][q / 4][q % 4], q == 0 ? bz : o[nt]);
                 }
+                if constexpr (CMP) {
+                    const int hsrc = min(2 * to + (g >> 1), A.P - 1);
+                    const uint64_t wd = wave_heads[hsrc];
+                    const int64_t bs = static_cast<int64_t>(wave_heads[64 + hsrc]);
 #pragma unroll
-                for (int nt = 0; nt < kF32NT; ++nt)
-                    decode_store(o[nt], to, g, ray0 + nt * 16 + col, n, A.P, out_shift, out_scale, out,
-                                 A.canonical != 0, fr[nt], A.flags, A.mask_in, A.dz_sign);
+                    for (int nt = 0; nt < kF32NT; ++nt)
+                        compact_store(o[nt], to, g, nt, col, ray0 + nt * 16 + col, n, A.P, out_shift,
+                                      out_scale, A.cmp, A.canonical != 0, fr[nt], A.dz_sign, wd, bs);
+                } else {
+#pragma unroll
+                    for (int nt = 0; nt < kF32NT; ++nt)
+                        decode_store(o[nt], to, g, ray0 + nt * 16 + col, n, A.P, out_shift, out_scale, out,
+                                     A.canonical != 0, fr[nt], A.flags, A.mask_in, A.dz_sign);
+                }
             }
         }
     }
 }
 
-template <int H, int ACT>
+template <int H, int ACT, bool CMP = false>
 static lt_status launch_f32(const Map &M, const lt_rays &rays, const lt_map_out &out, int64_t n,
-                            uint32_t flags, const uint8_t *mask_in, hipStream_t s)
+                            uint32_t flags, const uint8_t *mask_in, hipStream_t s,
+                            const MapCompact *cmp = nullptr)
 {
-    F32Args A;
+    F32Args A{};
     A.flags = flags;
     A.mask_in = mask_in;
     A.img = M.img_f32;
@@ -343,12 +425,20 @@ static lt_status launch_f32(const Map &M, const lt_rays &rays, const lt_map_out 
     A.D = M.lay.D;
     A.P = M.lay.P;
     A.TO = M.lay.TO;
+    A.LT = M.lay.LT;
     A.canonical = M.lay.canon;
     A.dz_sign = M.lay.fwd ? 1.0f : -1.0f;
     A.n = n;
-    auto kern = map_eval_f32_kernel<H, ACT>;
+    auto kern = map_eval_f32_kernel<H, ACT, CMP>;
     static bool attr = false;
-    const size_t lds = static_cast<size_t>(A.F.resident + 2 * kF32Stage);
+    size_t lds = static_cast<size_t>(A.F.resident + 2 * kF32Stage);
+    if constexpr (CMP) {
+        A.cmp = *cmp;
+        A.cmp.agg = static_cast<int64_t>(lds);
+        lds += kCompactAggBytes + kF32Waves * 128 * 8;
+        if (lds > static_cast<size_t>(kMaxLds))
+            return fail(LT_ERR_ARG, "map too large for compacted evaluation");
+    }
     if (!attr) {
         lt_status st = check_hip(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                                      hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -400,6 +490,24 @@ lt_status eval_f32(Map &M, const lt_rays &rays, const lt_map_out &out, int64_t n
                     : launch_f32<64, LT_ACT_TANH>(M, rays, out, n, flags, mask_in, s);
     return relu ? launch_f32<32, LT_ACT_RELU>(M, rays, out, n, flags, mask_in, s)
                 : launch_f32<32, LT_ACT_TANH>(M, rays, out, n, flags, mask_in, s);
+}
+
+lt_status eval_f32_compact(Map &M, const lt_rays &rays, const MapCompact &C, int64_t n, hipStream_t s)
+{
+    lt_status st = ensure_packed_f32(M, s);
+    if (st != LT_OK)
+        return st;
+    const int H = M.lay.H;
+    const bool relu = M.lay.act == LT_ACT_RELU;
+    const lt_map_out none{};
+    if (H == 128)
+        return relu ? launch_f32<128, LT_ACT_RELU, true>(M, rays, none, n, 0u, nullptr, s, &C)
+                    : launch_f32<128, LT_ACT_TANH, true>(M, rays, none, n, 0u, nullptr, s, &C);
+    if (H == 64)
+        return relu ? launch_f32<64, LT_ACT_RELU, true>(M, rays, none, n, 0u, nullptr, s, &C)
+                    : launch_f32<64, LT_ACT_TANH, true>(M, rays, none, n, 0u, nullptr, s, &C);
+    return relu ? launch_f32<32, LT_ACT_RELU, true>(M, rays, none, n, 0u, nullptr, s, &C)
+                : launch_f32<32, LT_ACT_TANH, true>(M, rays, none, n, 0u, nullptr, s, &C);
 }
 
 int64_t f32_image_bytes(const MapLayout &L) { return f32_layout(L).bytes; }
