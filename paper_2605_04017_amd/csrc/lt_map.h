@@ -23,23 +23,40 @@ struct MapLayout {
     int32_t T = 0;    // M-tiles per hidden layer (H / 16)
     int32_t C = 0;    // K-chunks of 32 per hidden layer (H / 32)
     int32_t TO = 0;   // M-tiles of the output layer (ceil(P * 8 / 16))
-    int32_t LT = 0;   // M-tiles of the logit rows alone (ceil(P / 16)), for compacted evaluation
+    int32_t LT = 0;   // 16-head blocks (ceil(P / 16)) of the compacted evaluation's output tiles
     // offsets into the flat FP32 parameter vector
     int64_t w_off[16], b_off[16];
     // BF16 fragment image (bytes)
     int64_t img_w0 = 0, img_hidden = 0, img_out = 0, img_bias = 0, img_bytes = 0;
     int64_t out_in_lds_bytes = 0;  // image bytes staged in LDS (everything, or all but the output layer)
-    // after the output fragments, never staged: the heads' logit rows alone
-    // (LT x 2C split fragments, the same values as those rows of the output
-    // layer) and their biases (16 LT floats)
-    int64_t img_logit = 0, img_logit_bias = 0;
+    // after the output fragments, for compacted evaluation: the output layer
+    // again in field-major tiles (cmp_tile_row), 6 LT tiles of 2C split
+    // fragments with the same values as the output layer's rows, then their
+    // biases (16 floats per tile)
+    int64_t img_cmp = 0, img_cmp_bias = 0;
     // FP8 image (width 128, tanh): [W0 BF16 frags][hidden FP8 16x128 frags,
     // 2 KiB each][bias + norm + per-layer scales][output BF16 frags]
     int64_t img8_hidden = 0, img8_bias = 0, img8_out = 0, img8_bytes = 0;
     int64_t img8_lds_bytes = 0;
-    int64_t img8_logit = 0, img8_logit_bias = 0;
+    int64_t img8_cmp = 0, img8_cmp_bias = 0;
     int32_t fp8_ok = 0;
 };
+
+// Row r of compacted-evaluation output tile t: tiles 0 .. LT-1 hold the logit
+// of heads 16 t + r; tile LT + 5 b + f - 1 (f = 1..5: x, y, dx, dy,
+// throughput) holds output f of heads 16 b + r.  Sets the head and the output
+// index within the head (0 = logit).
+__host__ __device__ inline void cmp_tile_row(int t, int LT, int r, int *head, int *q)
+{
+    if (t < LT) {
+        *head = 16 * t + r;
+        *q = 0;
+    } else {
+        const int u = t - LT;
+        *head = 16 * (u / 5) + r;
+        *q = u % 5 + 1;
+    }
+}
 
 struct Map {
     lt_map_desc desc{};

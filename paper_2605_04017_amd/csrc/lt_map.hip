@@ -57,10 +57,10 @@ MapLayout make_layout(const lt_map_desc &d)
     L.img_bias = L.img_hidden + static_cast<int64_t>(L.D - 1) * L.T * L.C * kFragBytes;
     L.img_out = L.img_bias + ((bias_floats * 4 + 1023) / 1024) * 1024;
     L.LT = (L.P + 15) / 16;
-    L.img_logit = L.img_out + static_cast<int64_t>(L.TO) * 2 * L.C * kFragBytes;
-    L.img_logit_bias = L.img_logit + static_cast<int64_t>(L.LT) * 2 * L.C * kFragBytes;
-    L.img_bytes = L.img_logit_bias + 64LL * L.LT;
-    L.out_in_lds_bytes = L.img_logit <= kMaxLds ? L.img_logit : L.img_out;
+    L.img_cmp = L.img_out + static_cast<int64_t>(L.TO) * 2 * L.C * kFragBytes;
+    L.img_cmp_bias = L.img_cmp + 6LL * L.LT * 2 * L.C * kFragBytes;
+    L.img_bytes = L.img_cmp_bias + 6LL * 64 * L.LT;
+    L.out_in_lds_bytes = L.img_cmp <= kMaxLds ? L.img_cmp : L.img_out;
     // FP8 image: the hidden region holds one 2 KiB fragment per M-tile per
     // layer; the bias region gains two floats per hidden layer (1 / (s_w s_h)
     // and s_h)
@@ -69,10 +69,10 @@ MapLayout make_layout(const lt_map_desc &d)
     L.img8_bias = L.img8_hidden + static_cast<int64_t>(L.D - 1) * L.T * 2 * kFragBytes;
     const int64_t bias8_floats = bias_floats + 2LL * (L.D - 1);
     L.img8_out = L.img8_bias + ((bias8_floats * 4 + 1023) / 1024) * 1024;
-    L.img8_logit = L.img8_out + static_cast<int64_t>(L.TO) * 2 * L.C * kFragBytes;
-    L.img8_logit_bias = L.img8_logit + static_cast<int64_t>(L.LT) * 2 * L.C * kFragBytes;
-    L.img8_bytes = L.img8_logit_bias + 64LL * L.LT;
-    L.img8_lds_bytes = L.img8_logit <= kMaxLds ? L.img8_logit : L.img8_out;
+    L.img8_cmp = L.img8_out + static_cast<int64_t>(L.TO) * 2 * L.C * kFragBytes;
+    L.img8_cmp_bias = L.img8_cmp + 6LL * L.LT * 2 * L.C * kFragBytes;
+    L.img8_bytes = L.img8_cmp_bias + 6LL * 64 * L.LT;
+    L.img8_lds_bytes = L.img8_cmp <= kMaxLds ? L.img8_cmp : L.img8_out;
     return L;
 }
 
@@ -93,38 +93,42 @@ __global__ void pack_bf16_kernel(const float *__restrict__ P, const float *__res
     const int64_t n_out = static_cast<int64_t>(L.TO) * 2 * L.C * 512;
     const int64_t bias_floats = static_cast<int64_t>(L.D) * L.H + 16LL * L.TO + 12 + 10LL * L.P +
                                 (fp8 ? 2LL * (L.D - 1) : 0);
-    const int64_t n_lg = static_cast<int64_t>(L.LT) * 2 * L.C * 512;
-    const int64_t n_lb = 16LL * L.LT;
+    const int64_t n_lg = 6LL * L.LT * 2 * L.C * 512;
+    const int64_t n_lb = 6LL * 16 * L.LT;
     const int64_t img_out = fp8 ? L.img8_out : L.img_out;
     const int64_t img_bias = fp8 ? L.img8_bias : L.img_bias;
-    const int64_t img_logit = fp8 ? L.img8_logit : L.img_logit;
-    const int64_t img_logit_bias = fp8 ? L.img8_logit_bias : L.img_logit_bias;
+    const int64_t img_cmp = fp8 ? L.img8_cmp : L.img_cmp;
+    const int64_t img_cmp_bias = fp8 ? L.img8_cmp_bias : L.img_cmp_bias;
     const int64_t n_frag = n_w0 + n_hid + n_out;
     const int64_t total = n_frag + n_lg + bias_floats + n_lb;
     for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total;
          e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         if (e >= n_frag && e < n_frag + n_lg) {
-            // logit fragment f, chunk cc: row mrow is the logit row of head
-            // 16 (f / 2C) + mrow, split hi / lo exactly as in the output layer
+            // compacted-evaluation tile f / 2C, chunk cc: row mrow is output q
+            // of one head (cmp_tile_row), split hi / lo exactly as in the
+            // output layer
             const int64_t loc = e - n_frag;
             const int f = static_cast<int>(loc / 512);
             const int within = static_cast<int>(loc % 512);
             const int lane = within >> 3, j = within & 7;
             const int kp = 8 * (lane >> 4) + j;
-            const int lt = f / (2 * L.C), cc = f % (2 * L.C), c = cc % L.C;
-            const int head = 16 * lt + (lane & 15);
+            const int t = f / (2 * L.C), cc = f % (2 * L.C), c = cc % L.C;
+            int head = 0, q = 0;
+            cmp_tile_row(t, L.LT, lane & 15, &head, &q);
             float v = 0.0f;
             if (head < L.P) {
                 const int k = 32 * c + perm32(kp);
-                const float w = P[L.w_off[L.D] + static_cast<int64_t>(head * kMapOut) * L.H + k];
+                const float w = P[L.w_off[L.D] + static_cast<int64_t>(head * kMapOut + q) * L.H + k];
                 const float hi = static_cast<float>(to_bf16(w));
                 v = cc < L.C ? hi : w - hi;
             }
-            reinterpret_cast<__bf16 *>(img + img_logit)[loc] = to_bf16(v);
+            reinterpret_cast<__bf16 *>(img + img_cmp)[loc] = to_bf16(v);
         } else if (e >= n_frag + n_lg + bias_floats) {
-            const int head = static_cast<int>(e - (n_frag + n_lg + bias_floats));
-            reinterpret_cast<float *>(img + img_logit_bias)[head] =
-                head < L.P ? P[L.b_off[L.D] + head * kMapOut] : 0.0f;
+            const int b = static_cast<int>(e - (n_frag + n_lg + bias_floats));
+            int head = 0, q = 0;
+            cmp_tile_row(b / 16, L.LT, b % 16, &head, &q);
+            reinterpret_cast<float *>(img + img_cmp_bias)[b] =
+                head < L.P ? P[L.b_off[L.D] + head * kMapOut + q] : 0.0f;
         } else if (e < n_frag) {
             const bool is_w0 = e < n_w0, is_hid = !is_w0 && e < n_w0 + n_hid;
             const int64_t loc = is_w0 ? e : is_hid ? e - n_w0 : e - n_w0 - n_hid;
@@ -275,12 +279,27 @@ __global__ __launch_bounds__((eval_waves<H, TRAIN>() * 64)) void map_eval_bf16_k
     // and thread, which short launches (a few tiles per workgroup) feel.
     for (int64_t row = wave; row * 1024 < A.lds_bytes; row += kWaves)
         __builtin_amdgcn_global_load_lds(A.img + row * 1024 + lane * 16, lds + row * 1024, 16, 0, 0);
+    if constexpr (CMP) {
+        // the output tiles' biases and the heads' output normalisation, so
+        // that the output phase reads nothing from global memory into
+        // registers: vector memory operations complete in order, and a wait
+        // for such a load would also wait for the tile copies and stores
+        // issued before it
+        float *cl = reinterpret_cast<float *>(lds + A.cmp_consts);
+        const float *cbg = reinterpret_cast<const float *>(A.img + A.img_cmp_bias);
+        const float *ong = reinterpret_cast<const float *>(A.img + A.img_bias) + A.D * H + 16 * A.TO + 12;
+        const int ncb = 6 * 16 * A.LT;
+        for (int k = threadIdx.x; k < ncb + 10 * A.P; k += blockDim.x)
+            cl[k] = k < ncb ? cbg[k] : ong[k - ncb];
+    }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
 
     const int g = lane >> 4, col = lane & 15;
     const float *bias = reinterpret_cast<const float *>(lds + A.img_bias);
-    const float *nrm = bias + A.D * H + 16 * A.TO;  // in_shift[6], in_scale[6], out_shift, out_scale
+    // in_shift[6], in_scale[6], out_shift, out_scale: staged in LDS, except in
+    // compacted evaluation, which stages only the input and hidden layers
+    const float *nrm = (CMP ? reinterpret_cast<const float *>(A.img + A.img_bias) : bias) + A.D * H + 16 * A.TO;
     const uint8_t *out_frag = A.out_from_lds ? lds + A.img_out : A.img + A.img_out;
     const int64_t n = A.n;
     const int64_t n_tiles = TRAIN ? A.n_pad / RPW : (n + RPW - 1) / RPW;
@@ -298,8 +317,23 @@ __global__ __launch_bounds__((eval_waves<H, TRAIN>() * 64)) void map_eval_bf16_k
     const bool lag = wave >= kWaves / 2;
     if (kPP && lag)
         __builtin_amdgcn_s_barrier();
-    int par = 0;  // CMP: alternating reservation arrays
-    (void)par;
+    // CMP: the output tiles stream through two LDS buffers, one tile per
+    // stage (stage u of a workgroup pass: tile u, 2C fragments), by direct
+    // global-to-LDS copies of whole 1 KiB rows issued one stage ahead (the
+    // next pass's first tile during this pass's last stage).  Measured on
+    // the 56-head map: 9.97 ms, against 10.47 ms with half-tile stages
+    // through four buffers, copies three stages ahead.
+    constexpr int kTileBytes = 2 * C * kFragBytes;
+    auto cmp_copy = [&](int u, int buf) {
+        const uint8_t *src = A.img + A.img_cmp + static_cast<int64_t>(u) * kTileBytes;
+        uint8_t *dst = lds + A.cmp_stage + buf * kTileBytes;
+        for (int row = wave; row < kTileBytes / 1024; row += kWaves)
+            __builtin_amdgcn_global_load_lds(src + row * 1024 + lane * 16, dst + row * 1024, 16, 0, 0);
+    };
+    int stg = 0;  // CMP: stages run so far (buffer parity)
+    (void)stg;
+    if (CMP && static_cast<int64_t>(blockIdx.x) * kWaves < n_tiles)
+        cmp_copy(0, 0);
 
     for (int64_t tbase = static_cast<int64_t>(blockIdx.x) * kWaves; tbase < n_tiles;
          tbase += static_cast<int64_t>(gridDim.x) * kWaves) {
@@ -452,20 +486,47 @@ __global__ __launch_bounds__((eval_waves<H, TRAIN>() * 64)) void map_eval_bf16_k
         }
         // ---- output layer (split hi/lo weights) and decode
         const float *bo = bias + A.D * H;
-        const float *out_shift = nrm + 12;
-        const float *out_scale = nrm + 12 + 5 * A.P;
+        const float *cmp_consts = reinterpret_cast<const float *>(lds + A.cmp_consts);
+        const float *out_shift = CMP ? cmp_consts + 6 * 16 * A.LT : nrm + 12;
+        const float *out_scale = out_shift + 5 * A.P;
         if constexpr (CMP) {
-            // logit tiles: lane k ends with head k's mask bits for the RPW rays
+            // Output tiles in field-major order (cmp_tile_row): LT logit tiles,
+            // then five field tiles per 16-head block, staged through LDS once
+            // per workgroup pass (cmp_copy).  The logit tiles give lane k head
+            // k's mask bits for the wave's rays; the reservation runs on the
+            // first two field tiles' barriers; a head block's entries are
+            // stored after the next tile's barrier, so that barrier waits for
+            // no store.
+            const float *cb = cmp_consts;
+            uint8_t *agg = lds + A.cmp.agg;
+            const bool more = tbase + static_cast<int64_t>(gridDim.x) * kWaves < n_tiles;
+            const int CT = 6 * A.LT;
             uint64_t word = 0;
-            const float *lb = reinterpret_cast<const float *>(A.img + A.img_logit_bias);
-            const uint8_t *lf = A.img + A.img_logit;
-            for (int lt = 0; lt < A.LT; ++lt) {
-                const floatx4 bz = *reinterpret_cast<const floatx4 *>(lb + lt * 16 + 4 * g);
+            int64_t base = 0;
+            // lane k holds head k's bits and first position
+            auto bits_of = [&](int hs, uint64_t *wd, int64_t *bs) {
+                *wd = __shfl(word, hs);
+                *bs = __shfl(base, hs);
+            };
+            // tile t of this pass: wait for its copy, start the next one,
+            // return its buffer
+            auto stage = [&](int t) -> const uint8_t * {
+                stage_barrier();
+                const int b = stg & 1;
+                if (t + 1 < CT)
+                    cmp_copy(t + 1, b ^ 1);
+                else if (more)
+                    cmp_copy(0, b ^ 1);
+                ++stg;
+                return lds + A.cmp_stage + b * kTileBytes;
+            };
+            for (int t = 0; t < A.LT; ++t) {
+                const uint8_t *wl = stage(t);
+                const floatx4 bz = *reinterpret_cast<const floatx4 *>(cb + t * 16 + 4 * g);
                 floatx4 o[NT];
 #pragma unroll
                 for (int cc = 0; cc < 2 * C; ++cc) {
-                    const bf16x8 a = *reinterpret_cast<const bf16x8 *>(
-                        lf + (static_cast<int64_t>(lt) * 2 * C + cc) * kFragBytes + lane * 16);
+                    const bf16x8 a = *reinterpret_cast<const bf16x8 *>(wl + cc * kFragBytes + lane * 16);
 #pragma unroll
                     for (int nt = 0; nt < NT; ++nt)
                         o[nt] = mfma_bf16(a, bop[nt][cc % C], cc == 0 ? bz : o[nt]);
@@ -475,44 +536,39 @@ __global__ __launch_bounds__((eval_waves<H, TRAIN>() * 64)) void map_eval_bf16_k
                     const bool live = ray0 + nt * 16 + col < n;
 #pragma unroll
                     for (int i = 0; i < 4; ++i)
-                        mask_word_add(word, __ballot(live && o[nt][i] > 0.0f), lt, i, nt, lane);
+                        mask_word_add(word, __ballot(live && o[nt][i] > 0.0f), t, i, nt, lane);
                 }
             }
             store_mask_words<RPW>(A.cmp, word, A.P, lane, ray0, n);
-            const int64_t base = compact_reserve<kWaves>(word, A.P, lds + A.cmp.agg, par, A.cmp.count,
-                                                         wave, lane);
-            par ^= 1;
-            // output tiles, fragments from LDS or streamed from L2 one tile ahead
-            const bf16x8 *of = reinterpret_cast<const bf16x8 *>(out_frag) + lane;
-            bf16x8 nx[2 * C];
+            reserve_publish(agg, word, A.P, wave, lane);
+            floatx4 of[5][NT];
+            for (int hb = 0; hb < A.LT; ++hb) {
 #pragma unroll
-            for (int cc = 0; cc < 2 * C; ++cc)
-                nx[cc] = of[cc * 64];
-            for (int to = 0; to < A.TO; ++to) {
-                bf16x8 cur[2 * C];
+                for (int f = 0; f < 5; ++f) {
+                    const int t = A.LT + 5 * hb + f;
+                    const uint8_t *wl = stage(t);
+                    unsigned long long got = 0;
+                    if (t == A.LT)
+                        got = reserve_add<kWaves>(agg, A.cmp.count, A.P, wave, lane);
+                    if (t == A.LT + 1)
+                        base = reserve_read(agg, A.P, wave, lane);
+                    if (f == 0 && hb > 0)
+                        store_head_block<NT>(of, hb - 1, g, col, ray0, n, A.P, out_shift, out_scale, A.cmp,
+                                             A.canonical != 0, fr, A.dz_sign, bits_of);
+                    const floatx4 bz = *reinterpret_cast<const floatx4 *>(cb + t * 16 + 4 * g);
 #pragma unroll
-                for (int cc = 0; cc < 2 * C; ++cc)
-                    cur[cc] = nx[cc];
-                if (to + 1 < A.TO) {
+                    for (int cc = 0; cc < 2 * C; ++cc) {
+                        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(wl + cc * kFragBytes + lane * 16);
 #pragma unroll
-                    for (int cc = 0; cc < 2 * C; ++cc)
-                        nx[cc] = of[(static_cast<int64_t>(to + 1) * 2 * C + cc) * 64];
+                        for (int nt = 0; nt < NT; ++nt)
+                            of[f][nt] = mfma_bf16(a, bop[nt][cc % C], cc == 0 ? bz : of[f][nt]);
+                    }
+                    if (t == A.LT)
+                        reserve_store(agg, got, A.P, wave, lane);
                 }
-                const floatx4 bz = *reinterpret_cast<const floatx4 *>(bo + to * 16 + 4 * g);
-                floatx4 o[NT];
-#pragma unroll
-                for (int cc = 0; cc < 2 * C; ++cc)
-#pragma unroll
-                    for (int nt = 0; nt < NT; ++nt)
-                        o[nt] = mfma_bf16(cur[cc], bop[nt][cc % C], cc == 0 ? bz : o[nt]);
-                const int hsrc = min(2 * to + (g >> 1), A.P - 1);
-                const uint64_t wd = __shfl(word, hsrc);
-                const int64_t bs = __shfl(base, hsrc);
-#pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
-                    compact_store(o[nt], to, g, nt, col, ray0 + nt * 16 + col, n, A.P, out_shift, out_scale,
-                                  A.cmp, A.canonical != 0, fr[nt], A.dz_sign, wd, bs);
             }
+            store_head_block<NT>(of, A.LT - 1, g, col, ray0, n, A.P, out_shift, out_scale, A.cmp,
+                                 A.canonical != 0, fr, A.dz_sign, bits_of);
             continue;
         }
         if constexpr (BIG) {
@@ -701,27 +757,28 @@ static lt_status launch_bf16_impl(const Map &M, const lt_rays &rays, const lt_ma
     A.D = L.D;
     A.P = L.P;
     A.TO = L.TO;
-    A.out_from_lds = FP8 ? L.img8_lds_bytes == L.img8_logit : L.out_in_lds_bytes == L.img_logit;
+    A.out_from_lds = FP8 ? L.img8_lds_bytes == L.img8_cmp : L.out_in_lds_bytes == L.img_cmp;
     A.LT = L.LT;
-    A.img_logit = FP8 ? L.img8_logit : L.img_logit;
-    A.img_logit_bias = FP8 ? L.img8_logit_bias : L.img_logit_bias;
+    A.img_cmp = FP8 ? L.img8_cmp : L.img_cmp;
+    A.img_cmp_bias = FP8 ? L.img8_cmp_bias : L.img_cmp_bias;
     A.img_out = FP8 ? L.img8_out : L.img_out;
     A.img_bias = FP8 ? L.img8_bias : L.img_bias;
     A.img_hidden = FP8 ? L.img8_hidden : L.img_hidden;
     A.canonical = L.canon;
     A.dz_sign = L.fwd ? 1.0f : -1.0f;
     if constexpr (CMP) {
-        // the reservation arrays follow the staged part; without room for
-        // them the output layer is read from L2 instead of LDS
-        if (A.lds_bytes + kCompactAggBytes > kMaxLds) {
-            A.lds_bytes = FP8 ? L.img8_out : L.img_out;
-            A.out_from_lds = 0;
-        }
-        if (A.lds_bytes + kCompactAggBytes > kMaxLds)
+        // LDS: [input + hidden layers and their biases][two output-tile
+        // buffers][reservation arrays]
+        A.lds_bytes = A.img_bias + ((static_cast<int64_t>(L.D) * H * 4 + 1023) / 1024) * 1024;
+        A.out_from_lds = 0;
+        A.cmp_stage = A.lds_bytes;
+        A.cmp.agg = A.cmp_stage + 2LL * 2 * (H / 32) * kFragBytes;
+        A.cmp_consts = A.cmp.agg + kCompactAggBytes;
+        const int64_t dyn = A.cmp_consts + (6LL * 16 * L.LT + 10LL * L.P) * 4;
+        if (dyn > kMaxLds)
             return fail(LT_ERR_ARG, "map too large for compacted evaluation");
-        A.cmp.agg = A.lds_bytes;
         A.xpose = -1;
-        return launch_kernel<H, ACT, false, FP8, false, true>(A, A.lds_bytes + kCompactAggBytes, rays, out, s);
+        return launch_kernel<H, ACT, false, FP8, false, true>(A, dyn, rays, out, s);
     }
     if constexpr (!TRAIN) {
         // the staged part ends on a 1 KiB boundary; the transpose buffers

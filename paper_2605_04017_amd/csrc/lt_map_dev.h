@@ -156,9 +156,9 @@ struct MapCompact {
     float *x, *y, *dx, *dy, *dz, *thr;  // [P][cap]; dz may be null
     unsigned long long *count;       // [P], zeroed before the launch
     int64_t cap, n_words;
-    int64_t agg;                     // LDS offset of the reservation arrays (2 x 1 KiB)
+    int64_t agg;                     // LDS offset of the reservation arrays (1 KiB)
 };
-constexpr int kCompactAggBytes = 2048;
+constexpr int kCompactAggBytes = 1024;
 
 struct EvalArgs {
     const uint8_t *img;
@@ -178,9 +178,13 @@ struct EvalArgs {
     uint8_t *hfrag_out;   // [D][n_pad/16][C][64 lanes][16 B] BF16 activation fragments
     float *o_out;         // [6P][o_stride] raw network outputs
     int64_t n_pad, o_stride;
-    // compacted evaluation: logit tiles (LT x 2C fragments + 16 LT biases) and outputs
+    // compacted evaluation: field-major output tiles (cmp_tile_row), 6 LT of
+    // them, streamed through two LDS buffers at cmp_stage; the staged part of
+    // the image is then the input and hidden layers with their biases only
     int32_t LT;
-    int64_t img_logit, img_logit_bias;
+    int64_t img_cmp, img_cmp_bias;
+    int64_t cmp_stage;
+    int64_t cmp_consts;   // LDS offset of the tiles' biases (96 LT floats) and out_shift, out_scale
     MapCompact cmp;
 };
 
@@ -336,77 +340,109 @@ __device__ __forceinline__ void store_mask_words(const MapCompact &C, uint64_t w
         row[w0 + 1] = static_cast<uint32_t>(word >> 32);
 }
 
-// Reserves every head's output range for the workgroup's rays with one
-// atomic add per head (one atomic per wave and head serialises on the
-// counters: measured 70 ms for the 56-head 16M-ray launch, against 1.2 ms
-// per workgroup).  Lane k < P of each wave holds head k's mask word; the
-// result, in lane k, is the position of the wave's first valid ray of head
-// k.  Rays keep their order inside the workgroup (waves in order).  Every
-// wave of the workgroup calls this the same number of times; `par`
-// alternates between calls, so one call's reads never meet the next call's
-// writes.
+// Reservation of every head's output range for the workgroup's rays, one
+// atomic add per head and workgroup pass (one per wave and head serialises on
+// the counters: measured 70 ms for the 56-head 16M-ray launch, against 1.2 ms
+// per workgroup).  Three steps, separated by workgroup barriers that the
+// caller already has: (1) every wave publishes its per-head counts; (2) wave
+// 0 sums them and adds the sums to the counters; (3) every wave reads the
+// first position of its valid rays of each head.  A wave's entries follow
+// those of the waves before it, so rays keep their order inside the pass.
+// agg: 1 KiB of LDS, [8 waves][64 heads] counts (bytes) + [64] bases.  One
+// pass's step (3) reads precede the next pass's step (1) writes by at least
+// one barrier, so one set of arrays suffices.
+__device__ __forceinline__ void reserve_publish(uint8_t *agg, uint64_t word, int P, int wave, int lane)
+{
+    agg[wave * 64 + lane] = static_cast<uint8_t>(lane < P ? __popcll(word) : 0);  // at most 64 rays
+}
+
+// Step (2) in two halves: reserve_add issues wave 0's atomics and returns
+// their results; reserve_store publishes them.  Work placed between the two
+// overlaps the atomics' latency (it must not wait on vector memory).
 template <int kWaves>
-__device__ __forceinline__ int64_t compact_reserve(uint64_t word, int P, uint8_t *agg, int par,
-                                                   unsigned long long *count, int wave, int lane)
+__device__ __forceinline__ unsigned long long reserve_add(const uint8_t *agg, unsigned long long *count, int P,
+                                                          int wave, int lane)
 {
     static_assert(kWaves <= 8, "reservation arrays hold eight waves");
-    uint8_t *cnt = agg + par * 1024;  // [kWaves][64] per-wave counts (at most 64 rays)
-    unsigned long long *base = reinterpret_cast<unsigned long long *>(agg + par * 1024 + 512);
-    cnt[wave * 64 + lane] = static_cast<uint8_t>(lane < P ? __popcll(word) : 0);
-    lds_barrier();
-    if (wave == 0 && lane < P) {
-        unsigned s = 0;
+    if (wave != 0 || lane >= P)
+        return 0ull;
+    unsigned s = 0;
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w)
-            s += cnt[w * 64 + lane];
-        base[lane] = s ? atomicAdd(count + lane, static_cast<unsigned long long>(s)) : 0ull;
-    }
-    lds_barrier();
-    int64_t b = 0;
-    if (lane < P) {
-        b = static_cast<int64_t>(base[lane]);
-        for (int w = 0; w < wave; ++w)
-            b += cnt[w * 64 + lane];
-    }
+    for (int w = 0; w < kWaves; ++w)
+        s += agg[w * 64 + lane];
+    return s ? atomicAdd(count + lane, static_cast<unsigned long long>(s)) : 0ull;
+}
+
+__device__ __forceinline__ void reserve_store(uint8_t *agg, unsigned long long got, int P, int wave, int lane)
+{
+    if (wave == 0 && lane < P)
+        reinterpret_cast<unsigned long long *>(agg + 512)[lane] = got;
+}
+
+__device__ __forceinline__ int64_t reserve_read(const uint8_t *agg, int P, int wave, int lane)
+{
+    if (lane >= P)
+        return 0;
+    int64_t b = static_cast<int64_t>(reinterpret_cast<const unsigned long long *>(agg + 512)[lane]);
+    for (int w = 0; w < wave; ++w)
+        b += agg[w * 64 + lane];
     return b;
 }
 
-// Compacted counterpart of decode_store: the same tile layout and arithmetic,
-// written only for valid rays at their reserved positions.  wd and bs are the
-// mask word and first position of this lane's head (2 to + g/2) for the wave
-// tile; bit 16 nt + col is this lane's ray.  Every lane must call this.
-__device__ __forceinline__ void compact_store(floatx4 v, int to, int g, int nt, int col, int64_t r,
-                                              int64_t n, int P, const float *out_shift,
-                                              const float *out_scale, const MapCompact &C, bool canon,
-                                              const CanonFrame &F, float dz_sign, uint64_t wd, int64_t bs)
+// Stores the compacted entries of head block hb from its five field tiles:
+// of[f][nt] holds, in lane (g, col), output f (x, y, dx, dy, throughput,
+// raw) of heads 16 hb + 4g + i (element i) for ray 16 nt + col of the wave
+// tile.  head_bits(head, &wd, &bs) gives head's mask bits and first output
+// position for the wave tile (every lane calls it for every i).  The
+// arithmetic is decode_store's, so the fields are bit-identical to
+// lt_map_eval's.
+template <int NT, typename HeadBits>
+__device__ __forceinline__ void store_head_block(const floatx4 (&of)[5][NT], int hb, int g, int col, int64_t ray0,
+                                                 int64_t n, int P, const float *out_shift, const float *out_scale,
+                                                 const MapCompact &C, bool canon, const CanonFrame (&fr)[NT],
+                                                 float dz_sign, HeadBits head_bits)
 {
-    const int head = 2 * to + (g >> 1);
-    const bool even = (g & 1) == 0;
-    const bool hv = head < P;
-    const int hs = hv ? head : 0;
-    const float send = even ? v[0] : fmaf(out_scale[5 * hs + 3], v[0], out_shift[5 * hs + 3]);
-    const float recv = __shfl_xor(send, 16);
-    if (!hv || r >= n)
-        return;
-    const int bit = 16 * nt + col;
-    if (!((wd >> bit) & 1ull))
-        return;
-    const int64_t pos = bs + __popcll(wd & ((1ull << bit) - 1ull));
-    if (pos >= C.cap)
-        return;
-    const int64_t e = static_cast<int64_t>(head) * C.cap + pos;
-    if (even) {
-        const ExitFields f = decode_fields(v[1], v[2], v[3], recv, hs, out_shift, out_scale, canon, F, dz_sign);
-        C.x[e] = f.x;
-        C.y[e] = f.y;
-        C.dx[e] = f.dx;
-        C.dy[e] = f.dy;
-        if (C.dz)
-            C.dz[e] = f.dz;
-        C.idx[e] = static_cast<int32_t>(r);
-    } else {
-        C.thr[e] = fmaf(out_scale[5 * hs + 4], v[1], out_shift[5 * hs + 4]);
+    // heads one at a time (unrolled, the four decodes' temporaries exhaust the
+    // registers of the FP32 kernel)
+#pragma unroll 1
+    for (int i = 0; i < 4; ++i) {
+        const int head = 16 * hb + 4 * g + i;
+        const int hs = head < P ? head : P - 1;
+        uint64_t wd;
+        int64_t bs;
+        head_bits(hs, &wd, &bs);
+        if (head >= P)
+            continue;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int bit = 16 * nt + col;
+            const int64_t r = ray0 + bit;
+            if (r >= n || !((wd >> bit) & 1ull))
+                continue;
+            const int64_t pos = bs + __popcll(wd & ((1ull << bit) - 1ull));
+            if (pos >= C.cap)
+                continue;
+            const int64_t e = static_cast<int64_t>(head) * C.cap + pos;
+            const float dy = fmaf(out_scale[5 * head + 3], of[3][nt][i], out_shift[5 * head + 3]);
+            const ExitFields f = decode_fields(of[0][nt][i], of[1][nt][i], of[2][nt][i], dy, head, out_shift,
+                                               out_scale, canon, fr[nt], dz_sign);
+            C.x[e] = f.x;
+            C.y[e] = f.y;
+            C.dx[e] = f.dx;
+            C.dy[e] = f.dy;
+            if (C.dz)
+                C.dz[e] = f.dz;
+            C.thr[e] = fmaf(out_scale[5 * head + 4], of[4][nt][i], out_shift[5 * head + 4]);
+            C.idx[e] = static_cast<int32_t>(r);
+        }
     }
+}
+
+// Workgroup barrier after this wave's global-to-LDS copies (and every other
+// vector memory access) and LDS accesses have completed.
+__device__ __forceinline__ void stage_barrier()
+{
+    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
 lt_status ensure_packed_bf16(Map &M, hipStream_t s);

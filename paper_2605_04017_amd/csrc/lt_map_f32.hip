@@ -27,11 +27,12 @@ constexpr int kF32Frag = 256;   // bytes of one 16x4 FP32 A fragment (64 lanes x
 constexpr int kF32Stage = 64 * 1024;
 
 // image: [bias+norm floats, 1 KiB aligned][W0: T x 2 frags][hidden: (D-1) x T x H/4 frags]
-//        [output: TO x H/4 frags][logit rows alone: LT x H/4 frags][logit biases: 16 LT floats]
+//        [output: TO x H/4 frags][compacted-evaluation tiles (cmp_tile_row): 6 LT x H/4 frags]
+//        [their biases: 16 floats per tile]
 struct F32Layout {
     int64_t bias = 0, w0 = 0, hidden = 0, out = 0, bytes = 0;
     int64_t layer_bytes = 0, out_bytes = 0, resident = 0;
-    int64_t logit = 0, logit_bytes = 0, logit_bias = 0;
+    int64_t cmp = 0, cmp_tile = 0, cmp_bias = 0;
 };
 
 F32Layout f32_layout(const MapLayout &L)
@@ -44,10 +45,10 @@ F32Layout f32_layout(const MapLayout &L)
     f.layer_bytes = static_cast<int64_t>(L.T) * (L.H / 4) * kF32Frag;
     f.out = f.hidden + static_cast<int64_t>(L.D - 1) * f.layer_bytes;
     f.out_bytes = static_cast<int64_t>(L.TO) * (L.H / 4) * kF32Frag;
-    f.logit = f.out + f.out_bytes;
-    f.logit_bytes = static_cast<int64_t>(L.LT) * (L.H / 4) * kF32Frag;
-    f.logit_bias = f.logit + f.logit_bytes;
-    f.bytes = f.logit_bias + 64LL * L.LT;
+    f.cmp = f.out + f.out_bytes;
+    f.cmp_tile = static_cast<int64_t>(L.H / 4) * kF32Frag;
+    f.cmp_bias = f.cmp + 6LL * L.LT * f.cmp_tile;
+    f.bytes = f.cmp_bias + 6LL * 64 * L.LT;
     f.resident = f.hidden;  // bias + norm + W0
     return f;
 }
@@ -81,26 +82,32 @@ __global__ void pack_f32_kernel(const float *__restrict__ P, const float *__rest
          e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const int64_t byte = e * 4;
         float v = 0.0f;
-        if (byte >= F.logit_bias) {
-            // logit bias of head 16 lt + row, folded like the output layer's
-            const int head = static_cast<int>((byte - F.logit_bias) / 4);
+        if (byte >= F.cmp_bias) {
+            // compacted-evaluation bias of tile b / 16, row b % 16, folded like
+            // the output layer's
+            const int b = static_cast<int>((byte - F.cmp_bias) / 4);
+            int head = 0, qq = 0;
+            cmp_tile_row(b / 16, L.LT, b % 16, &head, &qq);
             if (head < L.P) {
-                v = P[L.b_off[L.D] + head * kMapOut];
+                const int row = head * kMapOut + qq;
+                v = P[L.b_off[L.D] + row];
                 if (fold)
-                    v += row_sum(P + L.w_off[L.D] + static_cast<int64_t>(head * kMapOut) * L.H, L.H);
+                    v += row_sum(P + L.w_off[L.D] + static_cast<int64_t>(row) * L.H, L.H);
             }
-        } else if (byte >= F.logit) {
-            // logit fragments: row mrow of tile lt is head 16 lt + mrow's logit row,
-            // in the output layer's K order and fold
-            const int64_t loc = (byte - F.logit) / 4;
+        } else if (byte >= F.cmp) {
+            // compacted-evaluation tiles: row mrow of tile t is output qq of one
+            // head (cmp_tile_row), in the output layer's K order and fold
+            const int64_t loc = (byte - F.cmp) / 4;
             const int64_t f = loc / 64;
             const int lane = static_cast<int>(loc % 64);
             const int g = lane >> 4, mrow = lane & 15;
-            const int lt = static_cast<int>(f / K4), q = static_cast<int>(f % K4);
-            const int head = 16 * lt + mrow;
+            const int t = static_cast<int>(f / K4), q = static_cast<int>(f % K4);
+            int head = 0, qq = 0;
+            cmp_tile_row(t, L.LT, mrow, &head, &qq);
             const int k = 16 * (q / 4) + 4 * g + (q % 4);
             if (head < L.P)
-                v = P[L.w_off[L.D] + static_cast<int64_t>(head * kMapOut) * L.H + k] * (fold ? -2.0f : 1.0f);
+                v = P[L.w_off[L.D] + static_cast<int64_t>(head * kMapOut + qq) * L.H + k] *
+                    (fold ? -2.0f : 1.0f);
         } else if (byte < F.w0) {
             const int64_t b = e;
             const int64_t nb = static_cast<int64_t>(L.D) * L.H;
@@ -162,6 +169,9 @@ struct F32Args {
     const uint8_t *mask_in;
     int64_t n;
     MapCompact cmp;       // CMP: compacted outputs
+    int64_t cmp_consts;   // CMP: LDS offset of the compacted-evaluation tiles' biases
+    int64_t cmp_bits;     // CMP: LDS offset of the per-wave mask bits and positions (1 KiB per wave)
+    int64_t cmp_frames;   // CMP: LDS offset of the per-wave canonical frames (32 rays x 3 floats)
 };
 
 __device__ __forceinline__ floatx4 mfma_f32(float a, float b, floatx4 c)
@@ -190,10 +200,13 @@ __device__ __forceinline__ float act_f32(float u)
 // the remaining gap being the per-stage barrier).
 constexpr int kF32NT = 2;
 
-// CMP: compacted evaluation.  A stage holding the heads' logit rows alone
-// runs between the hidden layers and the output groups; its signs give every
-// head's mask for the wave's rays, one atomic per head and workgroup reserves
-// the output ranges, and the output groups store valid rays only.
+// CMP: compacted evaluation.  After the hidden layers, the output layer runs
+// in field-major tiles (cmp_tile_row): one stage with the LT logit tiles,
+// whose signs give lane k head k's mask bits for the wave's rays, then one
+// stage per 16-head block with its five field tiles; the reservation runs on
+// the first two block stages' barriers, and a block's entries are stored
+// after the next stage's barrier, so that the barrier does not wait for the
+// stores.
 template <int H, int ACT, bool CMP>
 __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args A, lt_rays rays,
                                                                       lt_map_out out)
@@ -203,6 +216,16 @@ __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args
     uint8_t *stage0 = lds + A.F.resident;
     for (int64_t o = threadIdx.x * 16; o < A.F.resident; o += blockDim.x * 16)
         *reinterpret_cast<uint4 *>(lds + o) = *reinterpret_cast<const uint4 *>(A.img + o);
+    if constexpr (CMP) {
+        // the compacted-evaluation tiles' biases: the stages then read no
+        // global memory into registers (vector memory operations complete in
+        // order, so a wait for such a load would also wait for the stage
+        // copies and stores issued before it)
+        float *cl = reinterpret_cast<float *>(lds + A.cmp_consts);
+        const float *cbg = reinterpret_cast<const float *>(A.img + A.F.cmp_bias);
+        for (int k = threadIdx.x; k < 6 * 16 * A.LT; k += blockDim.x)
+            cl[k] = cbg[k];
+    }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, col = lane & 15;
@@ -214,8 +237,7 @@ __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args
     const int64_t tile_bytes = static_cast<int64_t>(K4) * kF32Frag;
     const int per_group = static_cast<int>(kF32Stage / tile_bytes);
     const int n_groups = (A.TO + per_group - 1) / per_group;
-    const int n_pre = (A.D - 1) + (CMP ? 1 : 0);  // stages before the output groups
-    const int stages = n_pre + n_groups;          // weight stages of one tile
+    const int stages = CMP ? A.D + A.LT : (A.D - 1) + n_groups;  // weight stages of one tile
 
     // Stage j of a tile: hidden layer j + 1 (j < D - 1), else output group
     // j - (D - 1).  Stages stream through two LDS buffers: while the waves
@@ -227,11 +249,12 @@ __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args
             *bytes = A.F.layer_bytes;
             return A.img + A.F.hidden + static_cast<int64_t>(j) * A.F.layer_bytes;
         }
-        if (CMP && j == A.D - 1) {
-            *bytes = A.F.logit_bytes;
-            return A.img + A.F.logit;
+        if (CMP) {
+            // j = D - 1: the logit tiles; j = D + b: head block b's five field tiles
+            *bytes = (j == A.D - 1 ? A.LT : 5) * A.F.cmp_tile;
+            return A.img + A.F.cmp + (j == A.D - 1 ? 0 : A.LT + 5 * (j - A.D)) * A.F.cmp_tile;
         }
-        const int to0 = (j - n_pre) * per_group;
+        const int to0 = (j - (A.D - 1)) * per_group;
         const int cnt = A.TO - to0 < per_group ? A.TO - to0 : per_group;
         *bytes = cnt * tile_bytes;
         return A.img + A.F.out + to0 * tile_bytes;
@@ -251,12 +274,10 @@ __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args
     int buf = 0;
     if (static_cast<int64_t>(blockIdx.x) < wg_tiles)
         prefetch(0, 0);
-    int par = 0;  // CMP: alternating reservation arrays
-    (void)par;
-    // CMP: this wave's mask words (64) and first output positions (64) per
-    // head, kept in LDS rather than registers (the kernel is at 243 VGPRs)
-    uint64_t *wave_heads = reinterpret_cast<uint64_t *>(lds + A.cmp.agg + kCompactAggBytes) + wave * 128;
-    (void)wave_heads;
+    // CMP: this wave's mask bits [64] and first output positions [64] per
+    // head, in LDS rather than registers (the kernel is at its register limit)
+    uint64_t *wave_bits = reinterpret_cast<uint64_t *>(lds + A.cmp_bits) + wave * 128;
+    (void)wave_bits;
 
     for (int64_t wt = blockIdx.x; wt < wg_tiles; wt += gridDim.x) {
         const bool more = wt + gridDim.x < wg_tiles;
@@ -279,6 +300,13 @@ __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args
                     f[3] = rays.dy[r];
                 }
                 fr[nt] = canon_in(f);
+                if (CMP && g == 0) {
+                    // kept in LDS until the compacted stores, not in registers
+                    float *fw = reinterpret_cast<float *>(lds + A.cmp_frames) + (wave * 32 + nt * 16 + col) * 3;
+                    fw[0] = fr[nt].c;
+                    fw[1] = fr[nt].s;
+                    fw[2] = fr[nt].sg;
+                }
                 const float fz = r < n ? rays.dz[r] : 0.0f, fl = r < n ? rays.lambda_nm[r] : 0.0f;
                 // k = g (0..3) and 4 + g (dz, lambda, pad, pad)
                 const float f0 = g == 0 ? f[0] : g == 1 ? f[1] : g == 2 ? f[2] : f[3];
@@ -313,7 +341,8 @@ __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args
         const float *out_shift = nrm + 12;
         const float *out_scale = nrm + 12 + 5 * A.P;
         float h[kF32NT][T][4];
-        for (int j = 0; j < stages; ++j) {
+        // stage j's copies are complete; the next stage's start; its buffer
+        auto begin_stage = [&](int j) -> const float * {
             stage_ready();
             if (j + 1 < stages)
                 prefetch(j + 1, buf ^ 1);
@@ -321,6 +350,12 @@ __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args
                 prefetch(0, buf ^ 1);
             const float *wl = reinterpret_cast<const float *>(stage0 + buf * kF32Stage);
             buf ^= 1;
+            return wl;
+        };
+        // CMP: the head-block stages run in a loop of their own after this one,
+        // so that their field tiles are not live across the hidden layers
+        for (int j = 0; j < (CMP ? A.D : stages); ++j) {
+            const float *wl = begin_stage(j);
             if (j <= A.D - 1) {
 #pragma unroll
                 for (int nt = 0; nt < kF32NT; ++nt)
@@ -345,14 +380,19 @@ __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args
                         for (int nt = 0; nt < kF32NT; ++nt)
                             acc[nt][t] = mfma_f32(a, h[nt][q / 4][q % 4], q == 0 ? bz : acc[nt][t]);
                     }
+                    // compacted variant: at most four K chunks of weight reads
+                    // ahead (its extra state leaves no registers for more)
+                    if (CMP && q % 4 == 3)
+                        __builtin_amdgcn_sched_barrier(0);
                 }
                 continue;
             }
-            if (CMP && j == A.D - 1) {
-                const float *lb = reinterpret_cast<const float *>(A.img + A.F.logit_bias);
+            if constexpr (CMP) {
+                // the logit tiles (j = D - 1)
+                const float *cb = reinterpret_cast<const float *>(lds + A.cmp_consts);
                 uint64_t word = 0;
                 for (int lt = 0; lt < A.LT; ++lt) {
-                    const floatx4 bz = *reinterpret_cast<const floatx4 *>(lb + lt * 16 + 4 * g);
+                    const floatx4 bz = *reinterpret_cast<const floatx4 *>(cb + lt * 16 + 4 * g);
                     floatx4 o[kF32NT];
 #pragma unroll
                     for (int q = 0; q < K4; ++q) {
@@ -370,17 +410,13 @@ __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args
                     }
                 }
                 store_mask_words<16 * kF32NT>(A.cmp, word, A.P, lane, ray0, n);
-                const int64_t base = compact_reserve<kF32Waves>(word, A.P, lds + A.cmp.agg, par, A.cmp.count,
-                                                                wave, lane);
-                par ^= 1;
-                if (lane < A.P) {
-                    wave_heads[lane] = word;
-                    wave_heads[64 + lane] = static_cast<uint64_t>(base);
-                }
+                reserve_publish(lds + A.cmp.agg, word, A.P, wave, lane);
+                if (lane < A.P)
+                    wave_bits[lane] = word;
                 continue;
             }
             // output group
-            const int to0 = (j - n_pre) * per_group;
+            const int to0 = (j - (A.D - 1)) * per_group;
             const int cnt = A.TO - to0 < per_group ? A.TO - to0 : per_group;
             for (int k = 0; k < cnt; ++k) {
                 const int to = to0 + k;
@@ -393,21 +429,75 @@ __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args
                     for (int nt = 0; nt < kF32NT; ++nt)
                         o[nt] = mfma_f32(a, h[nt][q / 4][q % 4], q == 0 ? bz : o[nt]);
                 }
-                if constexpr (CMP) {
-                    const int hsrc = min(2 * to + (g >> 1), A.P - 1);
-                    const uint64_t wd = wave_heads[hsrc];
-                    const int64_t bs = static_cast<int64_t>(wave_heads[64 + hsrc]);
 #pragma unroll
-                    for (int nt = 0; nt < kF32NT; ++nt)
-                        compact_store(o[nt], to, g, nt, col, ray0 + nt * 16 + col, n, A.P, out_shift,
-                                      out_scale, A.cmp, A.canonical != 0, fr[nt], A.dz_sign, wd, bs);
-                } else {
-#pragma unroll
-                    for (int nt = 0; nt < kF32NT; ++nt)
-                        decode_store(o[nt], to, g, ray0 + nt * 16 + col, n, A.P, out_shift, out_scale, out,
-                                     A.canonical != 0, fr[nt], A.flags, A.mask_in, A.dz_sign);
-                }
+                for (int nt = 0; nt < kF32NT; ++nt)
+                    decode_store(o[nt], to, g, ray0 + nt * 16 + col, n, A.P, out_shift, out_scale, out,
+                                 A.canonical != 0, fr[nt], A.flags, A.mask_in, A.dz_sign);
             }
+        }
+        if constexpr (CMP) {
+            const float *cb = reinterpret_cast<const float *>(lds + A.cmp_consts);
+            uint8_t *agg = lds + A.cmp.agg;
+            auto bits_of = [&](int hs, uint64_t *wd, int64_t *bs) {
+                *wd = wave_bits[hs];
+                *bs = static_cast<int64_t>(wave_bits[64 + hs]);
+            };
+            // the rays' canonical frames, from LDS (identity for plain input)
+            auto frames = [&](CanonFrame (&fl)[kF32NT]) {
+#pragma unroll
+                for (int nt = 0; nt < kF32NT; ++nt) {
+                    fl[nt] = CanonFrame{1.0f, 0.0f, 1.0f};
+                    if (A.canonical) {
+                        const float *fw =
+                            reinterpret_cast<const float *>(lds + A.cmp_frames) + (wave * 32 + nt * 16 + col) * 3;
+                        fl[nt] = CanonFrame{fw[0], fw[1], fw[2]};
+                    }
+                }
+            };
+            floatx4 of[5][kF32NT];
+            for (int hb = 0; hb < A.LT; ++hb) {
+                const float *wl = begin_stage(A.D + hb);
+                unsigned long long got = 0;
+                if (hb == 0)
+                    got = reserve_add<kF32Waves>(agg, A.cmp.count, A.P, wave, lane);
+                if (hb == 1) {
+                    const int64_t base = reserve_read(agg, A.P, wave, lane);
+                    if (lane < A.P)
+                        wave_bits[64 + lane] = static_cast<uint64_t>(base);
+                }
+                if (hb > 0) {
+                    CanonFrame fl[kF32NT];
+                    frames(fl);
+                    store_head_block<kF32NT>(of, hb - 1, g, col, ray0, n, A.P, out_shift, out_scale, A.cmp,
+                                             A.canonical != 0, fl, A.dz_sign, bits_of);
+                }
+#pragma unroll
+                for (int f = 0; f < 5; ++f) {
+                    const floatx4 bz = *reinterpret_cast<const floatx4 *>(cb + (A.LT + 5 * hb + f) * 16 + 4 * g);
+#pragma unroll
+                    for (int q = 0; q < K4; ++q) {
+                        const float a = wl[(f * K4 + q) * 64 + lane];
+#pragma unroll
+                        for (int nt = 0; nt < kF32NT; ++nt)
+                            of[f][nt] = mfma_f32(a, h[nt][q / 4][q % 4], q == 0 ? bz : of[f][nt]);
+                    }
+                    // one tile's weight reads in flight at a time (hoisting all
+                    // five tiles' reads exhausts the registers)
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                if (hb == 0)
+                    reserve_store(agg, got, A.P, wave, lane);
+            }
+            if (A.LT == 1) {  // no second block stage: its barrier, here
+                lds_barrier();
+                const int64_t base = reserve_read(agg, A.P, wave, lane);
+                if (lane < A.P)
+                    wave_bits[64 + lane] = static_cast<uint64_t>(base);
+            }
+            CanonFrame fl[kF32NT];
+            frames(fl);
+            store_head_block<kF32NT>(of, A.LT - 1, g, col, ray0, n, A.P, out_shift, out_scale, A.cmp,
+                                     A.canonical != 0, fl, A.dz_sign, bits_of);
         }
     }
 }
@@ -435,7 +525,12 @@ static lt_status launch_f32(const Map &M, const lt_rays &rays, const lt_map_out 
     if constexpr (CMP) {
         A.cmp = *cmp;
         A.cmp.agg = static_cast<int64_t>(lds);
-        lds += kCompactAggBytes + kF32Waves * 128 * 8;
+        A.cmp_consts = A.cmp.agg + kCompactAggBytes;
+        A.cmp_bits = A.cmp_consts + 6 * 16 * 4 * A.LT;
+        A.cmp_frames = A.cmp_bits + kF32Waves * 1024;
+        lds += kCompactAggBytes + 6 * 16 * 4 * A.LT + kF32Waves * 1024 + kF32Waves * 32 * 12;
+        if (A.F.cmp_tile * 5 > kF32Stage)
+            return fail(LT_ERR_ARG, "map too large for compacted evaluation");
         if (lds > static_cast<size_t>(kMaxLds))
             return fail(LT_ERR_ARG, "map too large for compacted evaluation");
     }
