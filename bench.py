@@ -263,6 +263,111 @@ def paper_pair(lt, synth, lens, dev, steps, rays, batch=65536, seed=3003,
     return res
 
 
+def paper_recipe(lt, synth, dev, path=(1, 2, 10), n_valid=81_000_000, epochs=40, batch=8192,
+                 uniform_steps=3000, n_eval=1 << 20, seed=3301, w_cos=200.0):
+    """The paper's training recipe (Sec. 5.1) against this build's default
+    for one ghost path of the 11-surface lens, at the paper's network size
+    (classifier 2 x 32, BCE; regressor 5 x 32, MSE + cosine direction loss):
+    - paper: the regressor on n_valid rays (81 M by default, the paper's
+      count per path) uniform over the path's valid region from the
+      Markov-chain sampler (CIE wavelengths), the classifier
+      on those plus as many invalid uniform rays (balanced), both for
+      `epochs` epochs of `batch` rays with lr 1e-4 x 0.95 per 10,000 batches;
+    - uniform: both on uniform rays (valid ones only count in the regression
+      loss), uniform_steps steps of 65,536 with lr 2e-3 halved every quarter.
+    Both are evaluated on n_eval uniform rays of the benchmark distribution
+    against the GPU tracer."""
+    import numpy as np
+    import torch
+    lens = synth.config_lens(2)
+    h = lt.lt_lens_create(lens.surfaces, lens.glasses)
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    data = F.sampler_dataset(h, path, n_valid, seed)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    reg_np = torch.stack([data["reg_exit"][k] for k in F.REG_FIELDS], 1).double().cpu().numpy()
+    cls_np = {k: v.cpu().numpy() for k, v in data["cls_rays"].items()}
+    reg_rays_np = {k: v.cpu().numpy() for k, v in data["reg_rays"].items()}
+    norms_cls = F.map_norms(cls_np, [(np.ones(1, bool), np.zeros((1, 5)))])
+    norms_reg = F.map_norms(reg_rays_np, [(np.ones(len(reg_np), bool), reg_np)])
+    ev = lt.lt_rays_generate(h, n_eval, seed + 7)
+    ev_t = {k: v.cpu().numpy() for k, v in lt.lt_trace(h, path, ev).items()}
+
+    def new_nets():
+        nets = {}
+        for name, depth, norms in (("classifier", 2, norms_cls), ("regressor", 5, norms_reg)):
+            m = lt.lt_map_create(32, depth, 1, lt.LT_ACT_TANH)
+            lt.lt_map_set_params(m, torch.from_numpy(F.init_params(32, depth, 1, 11 + depth)).to(dev))
+            lt.lt_map_set_norm(m, norms[0], norms[1], norms[2].reshape(-1), norms[3].reshape(-1))
+            nets[name] = m
+        return nets
+
+    def evaluate(nets):
+        o = lt.empty_map_out(1, n_eval, dev)
+        lt.lt_map_eval_ex(nets["classifier"], lt.LT_F32, ev, o, n_eval, lt.LT_EVAL_MASK_ONLY, None, stream)
+        lt.lt_map_eval_ex(nets["regressor"], lt.LT_F32, ev, o, n_eval, lt.LT_EVAL_GATED, o["mask"], stream)
+        return exit_error(eval_host(o), ev_t, n_eval)
+
+    # the paper's recipe
+    nets = new_nets()
+    zeros = torch.zeros((1, 2 * n_valid), dtype=torch.float32, device=dev)
+    t0 = time.perf_counter()
+    tc = {"valid": data["cls_valid"].reshape(1, -1)}
+    for k in F.REG_FIELDS:
+        tc[k] = zeros
+    steps_c, loss_c = F.fit_epochs(nets["classifier"], data["cls_rays"], tc, epochs, batch,
+                                   {"w_bce": 1.0, "w_l2": 0.0}, seed + 3, stream=stream)
+    tr = {"valid": torch.ones((1, n_valid), dtype=torch.uint8, device=dev)}
+    for k in F.REG_FIELDS:
+        tr[k] = data["reg_exit"][k].reshape(1, -1)
+    steps_r, loss_r = F.fit_epochs(nets["regressor"], data["reg_rays"], tr, epochs, batch,
+                                   {"w_bce": 0.0, "w_l2": 1.0, "w_cos": w_cos}, seed + 4, stream=stream)
+    torch.cuda.synchronize()
+    t_paper = time.perf_counter() - t0
+    err_paper = evaluate(nets)
+    # the default recipe: uniform rays, short schedule
+    nets_u = new_nets()
+    pool = lt.lt_rays_generate(h, 1 << 22, seed + 5)
+    pex = lt.lt_trace(h, path, pool)
+    wsc = lt.workspace(nets_u["classifier"], 65536)
+    wsr = lt.workspace(nets_u["regressor"], 65536)
+    t0 = time.perf_counter()
+    for k in range(1, uniform_steps + 1):
+        lo = ((k - 1) * 65536) % ((1 << 22) - 65536 + 1)
+        rb = {f: v[lo:lo + 65536] for f, v in pool.items()}
+        tb = {"valid": pex["mask"][lo:lo + 65536].reshape(1, -1)}
+        for f in F.REG_FIELDS:
+            tb[f] = pex[f][lo:lo + 65536].reshape(1, -1)
+        lr = 2e-3 * (0.5 ** (k / max(1, uniform_steps / 4)))
+        lt.lt_map_train_step(nets_u["classifier"], rb, tb, {"lr": lr, "step": k, "w_bce": 1.0, "w_l2": 0.0}, wsc)
+        lt.lt_map_train_step(nets_u["regressor"], rb, tb,
+                             {"lr": lr, "step": k, "w_bce": 0.0, "w_l2": 1.0, "w_cos": w_cos}, wsr)
+    torch.cuda.synchronize()
+    t_uniform = time.perf_counter() - t0
+    err_uniform = evaluate(nets_u)
+    res = {"path": list(path), "lens": "11-surface double-Gauss-style lens",
+           "uniform_valid_fraction": float(ev_t["mask"].mean()),
+           "networks": "classifier 2 x 32 tanh (BCE), regressor 5 x 32 tanh "
+                       f"(MSE on x, y, I + {w_cos:g} x (1 - cos) on direction), FP32 evaluation",
+           "paper_recipe": {"data": f"{n_valid} valid rays from the Markov-chain sampler (CIE wavelengths) "
+                                    f"for the regressor; those + {n_valid} invalid uniform rays for the "
+                                    "classifier",
+                            "schedule": f"{epochs} epochs, batch {batch}, lr 1e-4 x 0.95 per 10,000 batches",
+                            "classifier_steps": steps_c, "regressor_steps": steps_r,
+                            "data_seconds": t_data, "fit_seconds": t_paper,
+                            "chain_steps": int(data["chain_steps"]), "uniform_rays_traced": int(data["uniform_rays"]),
+                            "final_loss": {"classifier": float(loss_c[0]), "regressor": float(loss_r[0])},
+                            "error_vs_gpu_tracer": err_paper},
+           "uniform_recipe": {"data": "uniform rays (4,194,304-ray pool), labelled by the tracer",
+                              "schedule": f"{uniform_steps} steps of 65,536, lr 2e-3 halved every quarter",
+                              "fit_seconds": t_uniform, "error_vs_gpu_tracer": err_uniform},
+           "eval": f"{n_eval} uniform rays of the benchmark distribution"}
+    del data, pool, pex, ev
+    torch.cuda.empty_cache()
+    return res
+
+
 def serving(lt, synth, dev, n_req=600, loads=(0.5, 0.8), seed=5005):
     """Serving run: 8 lenses (4..22 surfaces) with resident maps; Poisson
     arrivals of 1k..1M-ray requests (log-uniform); memory-admitted
@@ -1033,6 +1138,9 @@ def main():
     ap.add_argument("--no-transmit-only", action="store_true")
     ap.add_argument("--no-train-epoch", action="store_true")
     ap.add_argument("--no-paper-pair", action="store_true")
+    ap.add_argument("--no-paper-recipe", action="store_true")
+    ap.add_argument("--paper-recipe-valid", type=int, default=81_000_000,
+                    help="valid samples of the paper-recipe fit (the paper's count per path)")
     ap.add_argument("--no-flare", action="store_true")
     ap.add_argument("--no-sampler", action="store_true")
     ap.add_argument("--rays", type=int, default=N_RAYS, help="rays of the transmit-only case")
@@ -1109,6 +1217,9 @@ def main():
         res["paper_pair_2x32_5x32"] = paper_pair(lt, synth, lens2, dev, args.fit_steps, rays2)
         del rays2
         print("# paper-size pair done", file=sys.stderr, flush=True)
+    if not args.no_paper_recipe:
+        res["paper_recipe_ghost"] = paper_recipe(lt, synth, dev, n_valid=args.paper_recipe_valid)
+        print("# paper recipe done", file=sys.stderr, flush=True)
     if not args.no_train_epoch:
         res["train_epoch_67M"] = train_epoch(lt, synth, dev)
         print("# training epoch done", file=sys.stderr, flush=True)

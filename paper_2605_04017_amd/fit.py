@@ -85,3 +85,110 @@ def map_norms(rays: Dict[str, np.ndarray], targets: List[Tuple[np.ndarray, np.nd
             reg = _canonical(sub, reg)
         out_shift[k], out_scale[k] = norm_stats(reg)
     return in_shift, 1.0 / in_sd, out_shift, out_scale
+
+
+# ------------------------------------------------- the paper's training recipe
+
+REG_FIELDS = ("x", "y", "dx", "dy", "throughput")
+
+
+def paper_lr(step: int, lr0: float = 1e-4, factor: float = 0.95, every: int = 10000) -> float:
+    """Sec. 5.1 "MLP Training": the learning rate starts at 1e-4 and decays
+    exponentially by 0.95 every 10,000 batches (read as the continuous decay
+    lr0 * factor^(step / every), step counted from 0)."""
+    return lr0 * factor ** (step / every)
+
+
+def sampler_dataset(lens, path, n_valid: int, seed: int, n_chains: int = 1 << 20, burn_in: int = 256,
+                    thin: int = 8, lambda_mode=None, stream=None) -> Dict:
+    """Training data of one path as Sec. 5.1 "Data Collection" describes it,
+    drawn and labelled on the device:
+    - regressor set: n_valid rays uniform over the path's valid region, from
+      Markov chains with a binary visibility target (lt_mcmc_run, one output
+      per chain every `thin` steps after `burn_in` steps), wavelengths
+      importance-sampled by the CIE matching functions, with their traced
+      exit rays (the chains trace every state);
+    - classifier set: those valid rays plus as many invalid ones from uniform
+      sampling (lt_rays_generate, CIE wavelengths, traced along the path), a
+      balanced set.
+    Returns {"reg_rays", "reg_exit", "cls_rays", "cls_valid", "chain_steps",
+    "uniform_rays"} (device tensors; cls_* shuffled)."""
+    import torch
+    from . import (LT_LAMBDA_CIE, RAY_FIELDS, lt_mcmc_init, lt_mcmc_run, lt_rays_generate, lt_trace,
+                   mcmc_state)
+    lam = LT_LAMBDA_CIE if lambda_mode is None else lambda_mode
+    dev = torch.device("cuda")
+    st = lt_mcmc_init(mcmc_state(n_chains, dev), 0.05, stream=stream)
+    rays_b = {k: torch.empty((thin, n_chains), dtype=torch.float32, device=dev) for k in RAY_FIELDS}
+    ex_b = None
+    first = 0
+    for _ in range(max(0, burn_in // thin)):
+        rays_b, ex_b, _ = lt_mcmc_run(lens, path, st, thin, seed, first, rays_out=rays_b, exit_out=ex_b,
+                                      lambda_mode=lam, stream=stream)
+        first += thin
+    reg_r = {k: [] for k in RAY_FIELDS}
+    reg_e = {k: [] for k in REG_FIELDS}
+    have = 0
+    while have < n_valid:
+        rays_b, ex_b, _ = lt_mcmc_run(lens, path, st, thin, seed, first, rays_out=rays_b, exit_out=ex_b,
+                                      lambda_mode=lam, stream=stream)
+        first += thin
+        ok = ex_b["mask"][thin - 1].bool()
+        for k in RAY_FIELDS:
+            reg_r[k].append(rays_b[k][thin - 1][ok])
+        for k in REG_FIELDS:
+            reg_e[k].append(ex_b[k][thin - 1][ok])
+        have += int(ok.sum())
+    reg_rays = {k: torch.cat(v)[:n_valid].contiguous() for k, v in reg_r.items()}
+    reg_exit = {k: torch.cat(v)[:n_valid].contiguous() for k, v in reg_e.items()}
+    # invalid rays of the uniform distribution
+    inv = {k: [] for k in RAY_FIELDS}
+    have, n_uniform, chunk, k0 = 0, 0, max(n_valid, 1 << 20), 0
+    while have < n_valid:
+        u = lt_rays_generate(lens, chunk, seed + 1, first=k0, lambda_mode=lam, stream=stream)
+        k0 += chunk
+        n_uniform += chunk
+        bad = lt_trace(lens, path, u, stream=stream)["mask"] == 0
+        for k in RAY_FIELDS:
+            inv[k].append(u[k][bad])
+        have += int(bad.sum())
+    inv_rays = {k: torch.cat(v)[:n_valid] for k, v in inv.items()}
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed + 2)
+    perm = torch.randperm(2 * n_valid, device=dev, generator=g)
+    cls_rays = {k: torch.cat([reg_rays[k], inv_rays[k]])[perm].contiguous() for k in RAY_FIELDS}
+    cls_valid = torch.cat([torch.ones(n_valid, dtype=torch.uint8, device=dev),
+                           torch.zeros(n_valid, dtype=torch.uint8, device=dev)])[perm].contiguous()
+    return {"reg_rays": reg_rays, "reg_exit": reg_exit, "cls_rays": cls_rays, "cls_valid": cls_valid,
+            "chain_steps": first * n_chains, "uniform_rays": n_uniform}
+
+
+def fit_epochs(m, rays: Dict, targets: Dict, epochs: int, batch: int, cfg: Dict, seed: int,
+               lr=paper_lr, stream=None):
+    """Adam over `epochs` shuffled passes of a fixed dataset (rays: dict of
+    [n] device tensors; targets: dict of [1, n] tensors as lt_map_train_step
+    takes them), `batch` rays per step, the learning rate lr(step) from step 0
+    (the paper's schedule by default).  cfg: the loss weights.  Returns
+    (steps, last loss tensor)."""
+    import torch
+    from . import lt_map_train_step, workspace
+    n = int(rays["x"].numel())
+    per_epoch = n // batch
+    ws = workspace(m, batch)
+    g = torch.Generator(device=rays["x"].device)
+    g.manual_seed(seed)
+    step, loss = 0, None
+    for _ in range(epochs):
+        perm = torch.randperm(n, device=rays["x"].device, generator=g)
+        R = {k: v[perm] for k, v in rays.items()}
+        T = {k: v[:, perm] for k, v in targets.items()}
+        for b in range(per_epoch):
+            lo = b * batch
+            rb = {k: v[lo:lo + batch] for k, v in R.items()}
+            tb = {k: v[:, lo:lo + batch] for k, v in T.items()}
+            c = dict(cfg)
+            c["lr"] = lr(step)
+            step += 1
+            c["step"] = step
+            loss = lt_map_train_step(m, rb, tb, c, ws, stream=stream)
+    return step, loss

@@ -36,3 +36,13 @@ def test_map_norms_are_standardising():
     z = (x - in_shift) * in_scale
     assert np.allclose(z.mean(0), 0, atol=1e-9) and np.allclose(z.std(0), 1, atol=1e-9)
     assert np.allclose(out_shift[0, :4], 0, atol=1e-12) and out_scale[0, 4] == 1.0
+
+
+def test_paper_lr_schedule():
+    """Sec. 5.1: 1e-4 decaying by 0.95 every 10,000 batches."""
+    from paper_2605_04017_amd import fit as F
+    assert F.paper_lr(0) == 1e-4
+    assert abs(F.paper_lr(10000) - 0.95e-4) < 1e-18
+    assert abs(F.paper_lr(20000) - 0.95 ** 2 * 1e-4) < 1e-18
+    assert abs(F.paper_lr(5000) - 0.95 ** 0.5 * 1e-4) < 1e-18
+    assert F.paper_lr(395480) < F.paper_lr(395479)
