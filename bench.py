@@ -368,14 +368,18 @@ def paper_recipe(lt, synth, dev, path=(1, 2, 10), n_valid=81_000_000, epochs=40,
     return res
 
 
-def serving(lt, synth, dev, n_req=600, loads=(0.5, 0.8), seed=5005):
+def serving(lt, synth, dev, n_req=20000, loads=(0.5, 0.8), seed=5005, ring_rays=1 << 27):
     """Serving run: 8 lenses (4..22 surfaces) with resident maps; Poisson
     arrivals of 1k..1M-ray requests (log-uniform); memory-admitted
     continuous batching on 8 streams by the native request loop
     (lt_server_*), requests split into chunks of 262,144 rays.  Offered load
     relative to the saturated rate measured with all requests queued at
     t = 0.  The Python loop's saturated rate (the same policy in Python over
-    per-chunk wrapper calls) is reported beside the native one."""
+    per-chunk wrapper calls, on the first 2,000 requests) is reported beside
+    the native one.  Request outputs are views into a ring of ring_rays rays
+    per field: admission holds at most mem_budget / bytes_per_ray = 67 M rays
+    in flight, so a ring of 134 M never hands an in-flight request's range to
+    a new one (outputs are not read here; the serving tests check them)."""
     import numpy as np
     import torch
     from paper_2605_04017_amd.serve import (GpuExecutor, NativeScheduler, Scheduler, latency_stats,
@@ -404,10 +408,16 @@ def serving(lt, synth, dev, n_req=600, loads=(0.5, 0.8), seed=5005):
                 lt.lt_map_quantize(m, dtype)
         sizes = [r.n for r in poisson_requests(n_req, 1.0, 8, seed)]
 
+        ring = lt.empty_map_out(1, ring_rays, dev) if mode == "map" else lt.empty_exit(ring_rays, dev)
+
         def run(rate):
             reqs = requests(rate)
+            pos = 0
             for r in reqs:
-                out = lt.empty_map_out(1, r.n, dev) if mode == "map" else lt.empty_exit(r.n, dev)
+                if pos + r.n > ring_rays:
+                    pos = 0
+                out = {k: (v[:, pos:pos + r.n] if v.dim() == 2 else v[pos:pos + r.n]) for k, v in ring.items()}
+                pos += r.n
                 r.payload = (r.payload, out)
             torch.cuda.synchronize()
             for r in reqs:   # marshalled up front, as a client builds its requests
@@ -430,8 +440,9 @@ def serving(lt, synth, dev, n_req=600, loads=(0.5, 0.8), seed=5005):
             st = latency_stats(done)
             out[f"load_{rho}"] = {"p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
                                   "mrays_s": thr / 1e6, "requests": st["n"]}
+        del ring
         if key == "map_bf16":
-            reqs = requests(1e9)
+            reqs = requests(1e9)[:2000]
             ex = GpuExecutor(8, hl, maps, mode, dtype)
             sched = Scheduler(ex, mem_budget_bytes=4 << 30, bytes_per_ray=64, chunk=262144)
             ex.start_clock()

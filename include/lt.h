@@ -162,7 +162,8 @@ typedef struct {
 lt_status lt_lens_planes(lt_lens lens, double *z_forward_in, double *z_sensor);
 
 /* Index of a ghost path in [0, C(N,2)) ordered by (j, i) lexicographically,
- * and its inverse.  Return -1 / LT_ERR_PATH for an invalid path. */
+ * and its inverse.  Return -1 / LT_ERR_PATH for an invalid path or index, or
+ * N outside 2..LT_MAX_SURFACES. */
 int32_t lt_ghost_index(int32_t n_refracting, int32_t j, int32_t i);
 lt_status lt_ghost_path(int32_t n_refracting, int32_t index, lt_path *out);
 

@@ -306,7 +306,7 @@ lt_status lt_lens_planes(lt_lens lens, double *z_forward_in, double *z_sensor)
 
 int32_t lt_ghost_index(int32_t n, int32_t j, int32_t i)
 {
-    if (j < 1 || i <= j || i > n)
+    if (n < 2 || n > LT_MAX_SURFACES || j < 1 || i <= j || i > n)
         return -1;
     // paths (1,2),(1,3),...,(1,n),(2,3),...: rows before j hold (n-1)+...+(n-j+1)
     const int32_t before = (j - 1) * n - (j - 1) * j / 2;
@@ -317,7 +317,7 @@ lt_status lt_ghost_path(int32_t n, int32_t index, lt_path *out)
 {
     if (!out)
         return fail(LT_ERR_ARG, "NULL output");
-    if (n < 2 || index < 0 || index >= n * (n - 1) / 2)
+    if (n < 2 || n > LT_MAX_SURFACES || index < 0 || index >= n * (n - 1) / 2)
         return fail(LT_ERR_PATH, "ghost index out of range");
     int32_t j = 1, rem = index;
     while (rem >= n - j) {
