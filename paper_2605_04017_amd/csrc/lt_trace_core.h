@@ -6,14 +6,17 @@
 // Three variants:
 //   trace_one_ff   -- the library's tracer, FP32 instructions only.  Geometry
 //                     (positions, directions, normals, refractive indices,
-//                     cosines) is carried as float pairs (lt_ff.h), so the
-//                     instruction stream keeps about 44 bits; each hit is
-//                     refined by one Newton step on the sphere equation.
-//                     Fresnel factors are plain FP32.  Sensor-side rays leave
-//                     a camera lens nearly collimated, so exit positions are
+//                     cosines) is carried as unnormalised double-words
+//                     (lt_ff.h), renormalised once per interaction; each hit
+//                     is refined by one Newton step on the sphere equation.
+//                     Fresnel factors and first guesses are plain FP32 with
+//                     approximate reciprocals.  Sensor-side rays leave a
+//                     camera lens nearly collimated, so exit positions are
 //                     about EFL-times more sensitive to direction errors near
-//                     the sensor; plain FP32 rounding there already costs
-//                     ~1e-5 mm.
+//                     the sensor: plain FP32 rounding of any one of these
+//                     groups alone costs 5e-4 to 5e-3 mm on the most
+//                     sensitive ghost paths, while the double-word form stays
+//                     at the FP32 rounding of the output.
 //   trace_one_fast -- the same operators in plain FP32 (one rounding per
 //                     operation), with FP64 only for the discriminant of
 //                     near-flat surfaces and the transmitted cosine near
@@ -63,16 +66,16 @@ __host__ __device__ __forceinline__ ff glass_n_ff(const GlassF &g, ff l2, ff il2
 {
     if (g.kind == 1) {
         const ff A{g.k[0], g.k[1]}, B{g.k[2], g.k[3]}, C{g.k[4], g.k[5]};
-        return ff_add(A, ff_mul(il2, ff_add(B, ff_mul(C, il2))));
+        return dw_add(A, dw_mul(il2, dw_add(B, dw_mul(C, il2))));
     }
     if (g.kind == 2) {
         ff s = ff_make(1.0f);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             const ff Bi{g.k[2 * i], g.k[2 * i + 1]}, Ci{g.k[6 + 2 * i], g.k[7 + 2 * i]};
-            s = ff_add(s, ff_div(ff_mul(Bi, l2), ff_sub(l2, Ci)));
+            s = dw_add(s, dw_div(dw_mul(Bi, l2), dw_sub(l2, Ci)));
         }
-        return ff_sqrt(s);
+        return dw_sqrt(s);
     }
     return ff_make(1.0f);
 }
@@ -85,16 +88,19 @@ constexpr float kGrazingK = 1.0e-2f;
 // vertex (c q_z < 1) lying ahead of the previous point (t0 + t > 0).  Both
 // roots come from the cancellation-free pair E/qd and qd/c.  Returns +inf for
 // a miss.
+// kApprox: the root and quotient from the approximate hardware instructions
+// (for a first guess that a Newton step refines).
+template <bool kApprox = false>
 __host__ __device__ __forceinline__ float sphere_root(float B, float E, float disc, float c,
                                                       float R, float pz, float dz, float t0)
 {
     if (!(disc >= 0.0f))
         return INFINITY;
-    const float sq = sqrtf(disc);
+    const float sq = kApprox ? approx_sqrt(disc) : sqrtf(disc);
     const float qd = -B - (B >= 0.0f ? sq : -sq);
     float t = INFINITY;
     if (qd != 0.0f) {
-        const float ta = E / qd;
+        const float ta = kApprox ? E * approx_rcp(qd) : E / qd;
         if (t0 + ta > 0.0f && c * fmaf(ta, dz, pz) < 1.0f)
             t = ta;
     }
@@ -112,21 +118,24 @@ __host__ __device__ __forceinline__ RayOut trace_one_ff(const TraceTable &T, flo
                                                         float dx0, float dy0, float dz0,
                                                         float lam_nm)
 {
+#pragma clang fp contract(off)
     RayOut o;
     o.valid = false;
-    // unit input direction (double-word)
+    // unit input direction
     ff dx, dy, dz;
     {
-        const ff n2 = ff_add(ff_add(two_prod(dx0, dx0), two_prod(dy0, dy0)), two_prod(dz0, dz0));
-        const ff nrm = ff_sqrt(n2);
-        dx = ff_div(ff_make(dx0), nrm);
-        dy = ff_div(ff_make(dy0), nrm);
-        dz = ff_div(ff_make(dz0), nrm);
+        const ff n2 = dw_add(dw_add(two_prod(dx0, dx0), two_prod(dy0, dy0)), two_prod(dz0, dz0));
+        const ff nrm = dw_sqrt(n2);
+        if (!(nrm.h > 0.0f))  // zero or NaN direction
+            return o;
+        dx = dw_norm(dw_div(ff_make(dx0), nrm));
+        dy = dw_norm(dw_div(ff_make(dy0), nrm));
+        dz = dw_norm(dw_div(ff_make(dz0), nrm));
     }
-    const ff lum = ff_div(ff_make(lam_nm), ff_make(1000.0f));
-    const ff l2 = ff_sqr(lum);
-    const ff il2 = ff_div(ff_make(1.0f), l2);
-    ff ncur = T.glass_start == kAirCode ? ff_make(1.0f) : glass_n_ff(T.glass[T.glass_start], l2, il2);
+    const ff lum = dw_div(ff_make(lam_nm), ff_make(1000.0f));
+    const ff l2 = dw_norm(dw_sqr(lum));
+    const ff il2 = dw_norm(dw_div(ff_make(1.0f), l2));
+    ff ncur = T.glass_start == kAirCode ? ff_make(1.0f) : dw_norm(glass_n_ff(T.glass[T.glass_start], l2, il2));
     ff px = ff_make(x), py = ff_make(y), pz = ff_make(0.0f);
     float I = 1.0f;
     const int nsteps = T.nsteps;
@@ -136,7 +145,7 @@ __host__ __device__ __forceinline__ RayOut trace_one_ff(const TraceTable &T, flo
         const int type = code & 0xF;
         const uint32_t g2 = (code >> 4) & 0xFF;
         const ff c{G.c_h, G.c_l};
-        pz = ff_add(pz, ff{G.zs_h, G.zs_l});
+        pz = dw_add(pz, ff{G.zs_h, G.zs_l});
 
         // --- positional operator: first guess in FP32 from the leading words
         const float ch = G.c_h;
@@ -145,7 +154,7 @@ __host__ __device__ __forceinline__ RayOut trace_one_ff(const TraceTable &T, flo
         if (fabsf(dz.h) > 1.0e-3f) {
             // via the vertex tangent plane: the long transfer only slides the
             // point along the ray
-            t0 = -zh / dz.h;
+            t0 = -zh * approx_rcp(dz.h);
             xh = fmaf(t0, dx.h, xh);
             yh = fmaf(t0, dy.h, yh);
             zh = fmaf(t0, dz.h, zh);
@@ -154,41 +163,40 @@ __host__ __device__ __forceinline__ RayOut trace_one_ff(const TraceTable &T, flo
         const float oo = fmaf(xh, xh, fmaf(yh, yh, zh * zh));
         const float B = fmaf(ch, od, -dz.h);
         const float E = fmaf(ch, oo, -2.0f * zh);
-        const float t1 = sphere_root(B, E, fmaf(B, B, -ch * E), ch, G.R, zh, dz.h, t0);
+        const float t1 = sphere_root<true>(B, E, fmaf(B, B, -ch * E), ch, G.R, zh, dz.h, t0);
         if (!(t1 < INFINITY))
             return o;
         const float t = t0 + t1;
         // hit point in double-word, then one Newton step on F(q) = c|q|^2 - 2 q_z
-        ff qx = ff_add(px, ff_mul_f(dx, t));
-        ff qy = ff_add(py, ff_mul_f(dy, t));
-        ff qz = ff_add(pz, ff_mul_f(dz, t));
+        ff qx = dw_add(px, dw_mul_f(dx, t));
+        ff qy = dw_add(py, dw_mul_f(dy, t));
+        ff qz = dw_add(pz, dw_mul_f(dz, t));
         {
-            const ff q2 = ff_add(ff_add(ff_sqr(qx), ff_sqr(qy)), ff_sqr(qz));
-            const ff F = ff_sub(ff_mul(c, q2), ff_add(qz, qz));
+            const ff q2 = dw_add(dw_add(dw_sqr(qx), dw_sqr(qy)), dw_sqr(qz));
+            const ff F = dw_sub(dw_mul(c, q2), ff_twice(qz));
             const float g = fmaf(ch, fmaf(qx.h, dx.h, fmaf(qy.h, dy.h, qz.h * dz.h)), -dz.h);
-            const float dt = -F.h / (2.0f * g);
             if (g != 0.0f) {
-                qx = ff_add_f(qx, dt * dx.h);
-                qy = ff_add_f(qy, dt * dy.h);
-                qz = ff_add_f(qz, dt * dz.h);
+                const float dt = -ff_to_f(F) * (0.5f * approx_rcp(g));
+                qx = dw_add_f(qx, dt * dx.h);
+                qy = dw_add_f(qy, dt * dy.h);
+                qz = dw_add_f(qz, dt * dz.h);
             }
         }
         // clear aperture (closed disk), decided in double-word
         {
-            const ff h2 = ff_add(ff_sqr(qx), ff_sqr(qy));
-            const ff m = ff_sub(h2, ff{G.sd2_h, G.sd2_l});
-            if (!(m.h <= 0.0f))  // also rejects NaN
+            const ff m = dw_sub(dw_add(dw_sqr(qx), dw_sqr(qy)), ff{G.sd2_h, G.sd2_l});
+            if (!(ff_to_f(m) <= 0.0f))  // also rejects NaN
                 return o;
         }
-        px = qx;
-        py = qy;
-        pz = qz;
+        px = dw_norm(qx);
+        py = dw_norm(qy);
+        pz = dw_norm(qz);
         if (type == kStepStop)
             continue;
 
         // --- normal of the sphere through the vertex, against the ray
-        ff nx = ff_mul(c, qx), ny = ff_mul(c, qy), nz = ff_add_f(ff_mul(c, qz), -1.0f);
-        ff dn = ff_add(ff_add(ff_mul(nx, dx), ff_mul(ny, dy)), ff_mul(nz, dz));
+        ff nx = dw_mul(c, qx), ny = dw_mul(c, qy), nz = dw_add_f(dw_mul(c, qz), -1.0f);
+        ff dn = dw_add(dw_add(dw_mul(nx, dx), dw_mul(ny, dy)), dw_mul(nz, dz));
         if (dn.h > 0.0f) {
             nx = ff_neg(nx);
             ny = ff_neg(ny);
@@ -198,11 +206,11 @@ __host__ __device__ __forceinline__ RayOut trace_one_ff(const TraceTable &T, flo
         const ff ci = ff_neg(dn);
         const ff n2 = g2 == kAirCode ? ff_make(1.0f) : glass_n_ff(T.glass[g2], l2, il2);
         const ff n1 = ncur;
-        const ff eta = ff_div(n1, n2);
-        const ff sin2 = ff_sub(ff_make(1.0f), ff_sqr(ci));
-        const ff k = ff_sub(ff_make(1.0f), ff_mul(ff_sqr(eta), sin2));
-        const bool tir = k.h < 0.0f;
-        const ff ct = tir ? ff_make(0.0f) : ff_sqrt(k);
+        const ff eta = dw_div(n1, n2);
+        const ff sin2 = dw_sub(ff_make(1.0f), dw_sqr(ci));
+        const ff k = dw_sub(ff_make(1.0f), dw_mul(dw_sqr(eta), sin2));
+        const bool tir = ff_to_f(k) < 0.0f;
+        const ff ct = tir ? ff_make(0.0f) : dw_sqrt(k);
         // Fresnel factors in FP32 from the leading words
         const float a1 = n1.h * ci.h, b2 = n2.h * ct.h;  // s-polarisation terms
         const float a2 = n2.h * ci.h, b1 = n1.h * ct.h;  // p-polarisation terms
@@ -210,37 +218,37 @@ __host__ __device__ __forceinline__ RayOut trace_one_ff(const TraceTable &T, flo
             if (tir)
                 return o;
             // --- directional operator: vector Snell
-            const ff a = ff_sub(ff_mul(eta, ci), ct);
-            dx = ff_add(ff_mul(eta, dx), ff_mul(a, nx));
-            dy = ff_add(ff_mul(eta, dy), ff_mul(a, ny));
-            dz = ff_add(ff_mul(eta, dz), ff_mul(a, nz));
+            const ff a = dw_sub(dw_mul(eta, ci), ct);
+            dx = dw_norm(dw_add(dw_mul(eta, dx), dw_mul(a, nx)));
+            dy = dw_norm(dw_add(dw_mul(eta, dy), dw_mul(a, ny)));
+            dz = dw_norm(dw_add(dw_mul(eta, dz), dw_mul(a, nz)));
             // --- Fresnel: unpolarised transmittance, 2ab/(a+b)^2 over s and p
             const float ss = a1 + b2, pp = a2 + b1;
-            I *= 2.0f * (a1 * b2 / (ss * ss) + a2 * b1 / (pp * pp));
-            ncur = n2;
+            I *= 2.0f * fmaf(a1 * b2, approx_rcp(ss * ss), a2 * b1 * approx_rcp(pp * pp));
+            ncur = dw_norm(n2);
         } else {
             // --- directional operator: mirror reflection
-            const ff a = ff_add(ci, ci);
-            dx = ff_add(dx, ff_mul(a, nx));
-            dy = ff_add(dy, ff_mul(a, ny));
-            dz = ff_add(dz, ff_mul(a, nz));
+            const ff a = ff_twice(ci);
+            dx = dw_norm(dw_add(dx, dw_mul(a, nx)));
+            dy = dw_norm(dw_add(dy, dw_mul(a, ny)));
+            dz = dw_norm(dw_add(dz, dw_mul(a, nz)));
             float R = 1.0f;
             if (!tir) {
-                const float rs = (a1 - b2) / (a1 + b2);
-                const float rp = (a2 - b1) / (a2 + b1);
+                const float rs = (a1 - b2) * approx_rcp(a1 + b2);
+                const float rp = (a2 - b1) * approx_rcp(a2 + b1);
                 R = 0.5f * fmaf(rs, rs, rp * rp);
             }
             I *= R;
         }
         // |n| = 1 on the sphere and |d| = 1, so both updates keep |d| = 1 to
-        // double-word accuracy; no renormalisation is needed.
+        // double-word accuracy; no renormalisation of the length is needed.
     }
     // output plane, reached along the signed line
     if (!(dz.h * T.exit_dir > 0.0f))
         return o;
-    const ff t = ff_div(ff_sub(ff{T.z_exit_h, T.z_exit_l}, pz), dz);
-    o.x = ff_to_f(ff_add(px, ff_mul(t, dx)));
-    o.y = ff_to_f(ff_add(py, ff_mul(t, dy)));
+    const ff t = dw_div(dw_sub(ff{T.z_exit_h, T.z_exit_l}, pz), dz);
+    o.x = ff_to_f(dw_add(px, dw_mul(t, dx)));
+    o.y = ff_to_f(dw_add(py, dw_mul(t, dy)));
     o.dx = ff_to_f(dx);
     o.dy = ff_to_f(dy);
     o.dz = ff_to_f(dz);
