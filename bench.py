@@ -317,12 +317,13 @@ def paper_recipe(lt, synth, dev, path=(1, 2, 10), n_valid=81_000_000, epochs=40,
     for k in F.REG_FIELDS:
         tc[k] = zeros
     steps_c, loss_c = F.fit_epochs(nets["classifier"], data["cls_rays"], tc, epochs, batch,
-                                   {"w_bce": 1.0, "w_l2": 0.0}, seed + 3, stream=stream)
+                                   {"w_bce": 1.0, "w_l2": 0.0}, seed + 3, stream=stream, graph_steps=512)
     tr = {"valid": torch.ones((1, n_valid), dtype=torch.uint8, device=dev)}
     for k in F.REG_FIELDS:
         tr[k] = data["reg_exit"][k].reshape(1, -1)
     steps_r, loss_r = F.fit_epochs(nets["regressor"], data["reg_rays"], tr, epochs, batch,
-                                   {"w_bce": 0.0, "w_l2": 1.0, "w_cos": w_cos}, seed + 4, stream=stream)
+                                   {"w_bce": 0.0, "w_l2": 1.0, "w_cos": w_cos}, seed + 4, stream=stream,
+                                   graph_steps=512)
     torch.cuda.synchronize()
     t_paper = time.perf_counter() - t0
     err_paper = evaluate(nets)
@@ -354,6 +355,7 @@ def paper_recipe(lt, synth, dev, path=(1, 2, 10), n_valid=81_000_000, epochs=40,
                                     f"for the regressor; those + {n_valid} invalid uniform rays for the "
                                     "classifier",
                             "schedule": f"{epochs} epochs, batch {batch}, lr 1e-4 x 0.95 per 10,000 batches",
+                            "steps_run_as": "recorded runs of 512 steps (fit.TrainGraph), the rest of each epoch eager",
                             "classifier_steps": steps_c, "regressor_steps": steps_r,
                             "data_seconds": t_data, "fit_seconds": t_paper,
                             "chain_steps": int(data["chain_steps"]), "uniform_rays_traced": int(data["uniform_rays"]),
@@ -509,13 +511,48 @@ def train_epoch(lt, synth, dev, n_total=67108864, batch=65536, seed=4004):
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     t_train = ev[2].elapsed_time(ev[3]) * 1e-3
+    # the same steps as recorded runs of 64 (fit.TrainGraph) on a twin map:
+    # per run, the run's 64 batches are copied into the graph's buffers, the
+    # 64 schedule entries written with one copy, and the graph replayed
+    g_map = lt.lt_map_create(MAP_WIDTH, MAP_DEPTH, 1, lt.LT_ACT_TANH)
+    lt.lt_map_set_params(g_map, torch.from_numpy(F.init_params(MAP_WIDTH, MAP_DEPTH, 1, 6)).to(dev))
+    lt.lt_map_set_norm(g_map, norms[0], norms[1], norms[2].reshape(-1), norms[3].reshape(-1))
+    K = 64
+    t_rec = time.perf_counter()
+    graph = F.TrainGraph(g_map, K, batch, {"w_bce": 1.0, "w_l2": 4.0}, dev)
+    t_rec = time.perf_counter() - t_rec
+    torch.cuda.synchronize()
+    w1 = time.perf_counter()
+    ev[2].record(stream)
+    for r0 in range(0, steps, K):
+        lo, hi = r0 * batch, (r0 + K) * batch
+        for f, v in graph.rays.items():
+            v.copy_(rays[f][lo:hi])
+        for f, v in graph.targets.items():
+            v.copy_(tgt[f][:, lo:hi].reshape(1, K, batch).permute(1, 0, 2))
+        graph.run([2e-3 * (0.5 ** (k / (steps / 4))) for k in range(r0 + 1, r0 + K + 1)], r0 + 1)
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    wall_graph = time.perf_counter() - w1
+    t_graph = ev[2].elapsed_time(ev[3]) * 1e-3
+    same = bool(torch.equal(lt.lt_map_get_params(g_map), lt.lt_map_get_params(m)))
+    # replays alone (data already in place): the steps' own device time
+    ev[2].record(stream)
+    for rep in range(4):
+        graph.run([1e-4] * K, steps + 1 + rep * K)
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    t_replay = ev[2].elapsed_time(ev[3]) * 1e-3 / (4 * K)
     fpr = map_flops_per_ray()
     valid = float(ex["mask"].float().mean())
-    del batches, rays, ex, tgt, ws
+    del batches, rays, ex, tgt, ws, graph
     torch.cuda.empty_cache()
     return {"rays": n_total, "batch": batch, "steps": steps,
             "generate_ms": t_gen * 1e3, "trace_ms": t_trace * 1e3, "train_ms": t_train * 1e3,
             "step_ms": t_train / steps * 1e3, "train_wall_s": wall,
+            "graph": {"steps_per_run": K, "record_s": t_rec, "train_ms_with_batch_copies": t_graph * 1e3,
+                      "train_wall_s": wall_graph, "step_ms": t_graph / steps * 1e3,
+                      "step_ms_replay_only": t_replay * 1e3, "params_identical_to_eager": same},
             "train_mrays_s": n_total / t_train / 1e6,
             "train_tflops_3x_forward": 3 * fpr * n_total / t_train / 1e12,
             "valid_fraction": valid,
@@ -993,6 +1030,51 @@ def measured_traffic(summary, sources):
     return d
 
 
+def train_probe(heads: int, steps: int = 50, batch: int = 65536):
+    """The short program the training-step kernel traces profile: the 5 x 128
+    tanh map with `heads` heads, eager lt_map_train_step on one fixed batch
+    of 65,536 rays (random targets, half valid), 3 warm-up steps then `steps`
+    timed ones, and the same steps as one recorded run (fit.TrainGraph)."""
+    import torch
+    import paper_2605_04017_amd as lt
+    import synth
+    dev = torch.device("cuda")
+    rays = {k: torch.from_numpy(v).to(dev) for k, v in synth.config_rays(2, batch).items()}
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(17)
+    t = {"valid": (torch.rand((heads, batch), device=dev, generator=gen) > 0.5).to(torch.uint8)}
+    for k in ("x", "y", "dx", "dy", "throughput"):
+        t[k] = torch.randn((heads, batch), device=dev, generator=gen)
+    m = lt.lt_map_create(MAP_WIDTH, MAP_DEPTH, heads, lt.LT_ACT_TANH)
+    lt.lt_map_set_params(m, torch.from_numpy(F.init_params(MAP_WIDTH, MAP_DEPTH, heads, 3)).to(dev))
+    ws = lt.workspace(m, batch)
+    loss = torch.zeros(3, dtype=torch.float32, device=dev)
+    for k in range(3):
+        lt.lt_map_train_step(m, rays, t, {"lr": 1e-4, "step": k + 1}, ws, loss)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for k in range(steps):
+        lt.lt_map_train_step(m, rays, t, {"lr": 1e-4, "step": k + 4}, ws, loss)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    eager = e0.elapsed_time(e1) / steps
+    g = F.TrainGraph(m, steps, batch, {}, dev)
+    for f, v in g.rays.items():
+        v.copy_(rays[f].repeat(steps))
+    for f, v in g.targets.items():
+        v.copy_(t[f].unsqueeze(0).expand(steps, heads, batch))
+    torch.cuda.synchronize()
+    e0.record(stream)
+    g.run([1e-4] * steps, steps + 4)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    replay = e0.elapsed_time(e1) / steps
+    print(json.dumps({"probe": "train", "heads": heads, "batch": batch, "steps": steps,
+                      "eager_step_ms": eager, "graph_step_ms": replay}), flush=True)
+
+
 def traffic_probe(args):
     """Short program for the counter runs: one plain copy of COPY_PROBE_BYTES
     (a negate kernel: reads and writes that many bytes), then three launches
@@ -1159,6 +1241,8 @@ def main():
     ap.add_argument("--traffic-probe", nargs="?", const="f32",
                     choices=("f32", "bf16", "fp8", "trace", "all_f32", "all_bf16", "all_fp8"),
                     help="only run the short program the counter runs profile")
+    ap.add_argument("--train-probe", type=int, default=0, metavar="HEADS",
+                    help="only time the training step of the 5 x 128 map with this many heads")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: every box in this setup has one MI355X; "
@@ -1166,6 +1250,9 @@ def main():
         sys.exit(2)
     if args.traffic_probe:
         traffic_probe(args)
+        return
+    if args.train_probe:
+        train_probe(args.train_probe)
         return
 
     import torch

@@ -481,6 +481,14 @@ lt_status lt_map_get_params(lt_map map, float *params, int64_t count, void *stre
 lt_status lt_map_set_norm(lt_map map, const float *in_shift, const float *in_scale,
                           const float *out_shift, const float *out_scale);
 
+/* Record that the map's master parameters changed on the device outside the
+ * library's host calls, i.e. by the replay of a HIP graph that recorded
+ * lt_map_train_step (Sec. 5.1 "MLP Training", run as a graph): the packed
+ * BF16/FP8/FP32 copies are then rebuilt by the next evaluation.  Call it
+ * after each replay, before evaluating the map.  Host only, enqueues
+ * nothing.  Error: LT_ERR_ARG (NULL map). */
+lt_status lt_map_mark_updated(lt_map map);
+
 /* Build the packed copy of the parameters that lt_map_eval uses for dtype
  * now, on the stream (Sec. 5.1 "Inference": the trained network is evaluated
  * inside the renderer at reduced cost; here the reduced-precision copies are
@@ -580,7 +588,21 @@ typedef struct {
  *   + w_cos/N sum_r valid * (1 - cos(angle between predicted and target
  *     exit directions)),
  * a direction being (dx, dy, -sqrt(max(1e-6, 1 - dx^2 - dy^2))) in lens
- * units.  Adam with bias correction; step is 1-based. */
+ * units.  Adam with bias correction; step is 1-based (Sec. 5.1 "MLP
+ * Training" trains with Adam).
+ *
+ * sched (device pointer, may be NULL): when set, the learning rate and step
+ * are read from it on the device when the step runs, and lr and step above
+ * are ignored.  A step recorded into a HIP graph can then be replayed with a
+ * new learning rate and step count written into *sched before each replay.
+ * The values must satisfy step >= 1 and lr >= 0 when the step runs; they are
+ * not validated at the call. */
+typedef struct {
+    float lr;
+    int32_t reserved;
+    int64_t step;
+} lt_train_sched;
+
 typedef struct {
     float lr;
     float beta1;
@@ -590,6 +612,7 @@ typedef struct {
     float w_bce;
     float w_l2;
     float w_cos;
+    const lt_train_sched *sched;
 } lt_train_cfg;
 
 /* Bytes of device workspace a training call on n rays needs (-1 on error):
@@ -624,9 +647,8 @@ lt_status lt_map_backward(lt_map map, const float *grad_o, void *workspace,
  * regressor, Adam): forward, loss, backward and Adam on the map's FP32 master
  * parameters and moments.  loss_out (device, 3 floats, may be NULL): total,
  * BCE part, L2 part.  Allocates nothing.
- * Training (this call, lt_map_forward_train, lt_map_backward) supports at
- * most 62 heads at width 128 (any head count at widths 32 and 64); more is
- * LT_ERR_ARG before anything is enqueued. */
+ * Training (this call, lt_map_forward_train, lt_map_backward) supports every
+ * map lt_map_create accepts. */
 lt_status lt_map_train_step(lt_map map, const lt_rays *rays, const lt_targets *targets, int64_t n,
                             const lt_train_cfg *cfg, void *workspace, int64_t workspace_bytes,
                             float *loss_out, void *stream);

@@ -36,7 +36,7 @@ __all__ = ["LtError", "Lens", "lt_lens_create", "lt_lens_query", "lt_lens_paraxi
            "lt_map_quantize", "lt_rays_generate", "lt_map_eval_ex", "LT_EVAL_MASK_ONLY",
            "lt_lens_planes", "LT_TRACE_FORWARD", "LT_TRACE_FP64", "lt_rays_generate_forward", "lt_splat",
            "LT_LAMBDA_UNIFORM", "LT_LAMBDA_CIE", "mcmc_state", "lt_mcmc_init", "lt_mcmc_run",
-           "LT_EVAL_GATED", "Server", "LT_ERR_ARG", "LT_ERR_STATE"]
+           "LT_EVAL_GATED", "Server", "LT_ERR_ARG", "LT_ERR_STATE", "train_sched", "set_train_sched", "lt_map_mark_updated"]
 
 TARGET_FIELDS = ("valid", "x", "y", "dx", "dy", "throughput")
 
@@ -751,6 +751,28 @@ def lt_map_backward(m: Map, grad_o, ws, grad_params=None, n: Optional[int] = Non
     return grad_params
 
 
+def lt_map_mark_updated(m: Map):
+    """Tell the library that the map's parameters changed on the device
+    outside its calls (a replayed training-step graph): the next evaluation
+    repacks them."""
+    N.check(N.lib().lt_map_mark_updated(m.handle))
+
+
+def train_sched(device="cuda"):
+    """A device lt_train_sched (16 bytes: float lr, int32 reserved, int64
+    step) for cfg["sched"]: the training step then reads its learning rate
+    and step count from device memory when it runs (graph replay)."""
+    torch = _torch()
+    return torch.zeros(16, dtype=torch.uint8, device=device)
+
+
+def set_train_sched(sched, lr: float, step: int):
+    """Write lr and step into a device lt_train_sched with two fill kernels
+    on the current stream (ordered before later work on it, no host sync)."""
+    sched.view(_torch().float32)[0].fill_(float(lr))
+    sched.view(_torch().int64)[1].fill_(int(step))
+
+
 def _train_args(m: Map, rays: Dict, targets: Dict, cfg: Dict, loss_out, n: Optional[int]):
     """Marshalled arguments of a fused training step."""
     torch = _torch()
@@ -762,10 +784,16 @@ def _train_args(m: Map, rays: Dict, targets: Dict, cfg: Dict, loss_out, n: Optio
     for k in TARGET_FIELDS:
         dt = torch.uint8 if k == "valid" else torch.float32
         setattr(t, k, _dev_ptr(targets[k], dt, m.n_heads * n, f"targets[{k}]"))
+    sched = cfg.get("sched")
+    sptr = None
+    if sched is not None:
+        assert sched.is_cuda and sched.dtype == torch.uint8 and sched.numel() == 16 and sched.is_contiguous(), \
+            "cfg['sched'] must be a 16-byte device tensor from train_sched()"
+        sptr = sched.data_ptr()
     c = N.lt_train_cfg(float(cfg.get("lr", 1e-3)), float(cfg.get("beta1", 0.9)),
                        float(cfg.get("beta2", 0.999)), float(cfg.get("eps", 1e-8)),
-                       int(cfg["step"]), float(cfg.get("w_bce", 1.0)), float(cfg.get("w_l2", 1.0)),
-                       float(cfg.get("w_cos", 0.0)))
+                       int(cfg.get("step", 1)), float(cfg.get("w_bce", 1.0)), float(cfg.get("w_l2", 1.0)),
+                       float(cfg.get("w_cos", 0.0)), sptr)
     lp = C.c_void_p(_dev_ptr(loss_out, torch.float32, 3, "loss_out"))
     return n, _rays_struct(rays, n), t, c, loss_out, lp
 
@@ -775,8 +803,9 @@ def lt_map_train_step(m: Map, rays: Dict, targets: Dict, cfg: Dict, ws, loss_out
     """One fused forward + loss + backward + Adam step.  ``targets``: dict of
     (n_heads, n) CUDA tensors (valid uint8, the rest float32); ``cfg``: lr,
     beta1, beta2, eps, step (1-based), w_bce, w_l2, w_cos (cosine direction
-    loss; 0 = squared error on all five outputs).  Returns loss_out
-    (device float32[3]: total, bce, l2)."""
+    loss; 0 = squared error on all five outputs), sched (optional device
+    lt_train_sched from train_sched(): lr and step are then read from it when
+    the step runs).  Returns loss_out (device float32[3]: total, bce, l2)."""
     n, r, t, c, loss_out, lp = _train_args(m, rays, targets, cfg, loss_out, n)
     N.check(N.lib().lt_map_train_step(m.handle, C.byref(r), C.byref(t), int(n), C.byref(c),
                                       C.c_void_p(ws.data_ptr()), ws.numel(), lp,

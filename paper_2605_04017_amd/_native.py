@@ -100,7 +100,12 @@ class lt_targets(C.Structure):
 
 class lt_train_cfg(C.Structure):
     _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
-                ("step", C.c_int64), ("w_bce", C.c_float), ("w_l2", C.c_float), ("w_cos", C.c_float)]
+                ("step", C.c_int64), ("w_bce", C.c_float), ("w_l2", C.c_float), ("w_cos", C.c_float),
+                ("sched", C.c_void_p)]
+
+
+class lt_train_sched(C.Structure):
+    _fields_ = [("lr", C.c_float), ("reserved", C.c_int32), ("step", C.c_int64)]
 
 
 class lt_server_cfg(C.Structure):
@@ -174,6 +179,7 @@ SIGNATURES = {
     "lt_map_num_params": (C.c_int64, [C.c_void_p]),
     "lt_map_set_params": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "lt_map_get_params": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "lt_map_mark_updated": (C.c_int, [C.c_void_p]),
     "lt_map_set_norm": (C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.POINTER(C.c_float),
                                   C.POINTER(C.c_float), C.POINTER(C.c_float)]),
     "lt_map_eval": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(lt_rays), C.POINTER(lt_map_out),

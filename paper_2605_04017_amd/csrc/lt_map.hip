@@ -1011,6 +1011,15 @@ lt_status lt_map_set_norm(lt_map map, const float *in_shift, const float *in_sca
     return st;
 }
 
+lt_status lt_map_mark_updated(lt_map map)
+{
+    Map *M = as_map(map);
+    if (!M)
+        return fail(LT_ERR_ARG, "NULL map");
+    ++M->version;
+    return LT_OK;
+}
+
 lt_status lt_map_quantize(lt_map map, int32_t dtype, void *stream)
 {
     Map *M = as_map(map);

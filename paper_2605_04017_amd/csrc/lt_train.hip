@@ -12,12 +12,12 @@
 //       kept in registers (the same K permutation as the forward makes the
 //       FP32 result of one layer the BF16 B operand of the next), W^T images
 //       staged in LDS; stores the BF16 gradients as fragments;
-//   dw_hidden_kernel / dw_kernel: weight gradients sum_r delta_r h_r^T over
-//       a slice of the batch (hidden layers of width 64 and 128 / the input
-//       and output layers and width 32), the fragments transposed into LDS
-//       rows by selector MFMAs; the bias gradient comes from an extra all-ones
-//       column; one partial per slice (deterministic; 256 slices for the
-//       input and output layers, 128 for the hidden layers);
+//   dw_hidden_kernel / dw_out_kernel / dw_kernel: weight gradients
+//       sum_r delta_r h_r^T over a slice of the batch (hidden layers of width
+//       64 and 128 / their output and input layers / every layer at width
+//       32), the bias gradient from an extra all-ones column; one partial
+//       per slice (deterministic; 256 slices for the input and output
+//       layers, 128 for the hidden layers);
 //   reduce_adam_kernel: sums the slice partials and applies Adam to the FP32
 //       master parameters.
 #include <hip/hip_runtime.h>
@@ -370,9 +370,8 @@ __global__ __launch_bounds__(256) void dw_kernel(DwArgs A)
     constexpr int RS = kDwChunk + kDwPad;  // bf16 per LDS row
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
     const MapLayout &L = A.L;
-    // with H >= 64 the hidden layers go to dw_hidden_kernel and the grid
-    // covers the input (x = 0) and output (x = 1) layers only
-    const int layer = H >= 64 ? (blockIdx.x == 0 ? 0 : L.D) : static_cast<int>(blockIdx.x);
+    // launched at width 32 only (wider maps: dw_out_kernel, dw_hidden_kernel)
+    const int layer = static_cast<int>(blockIdx.x);
     const int group = blockIdx.y;
     const int slice = blockIdx.z;
     const bool is_out = layer == L.D, is_in = layer == 0;
@@ -549,6 +548,340 @@ __global__ __launch_bounds__(256) void dw_kernel(DwArgs A)
     }
 }
 
+// Output-layer weight gradient for widths 64 and 128: dW[row][unit] =
+// sum_r d[row][r] h[unit][r] and the bias gradient sum_r d[row][r] over one
+// slice of the batch per workgroup.  Rays are the K dimension of
+// v_mfma_f32_16x16x32_bf16.  The A operand (16 output slots x 32 rays) comes
+// straight from the FP32 output gradient: lane l reads 8 consecutive rays of
+// slot l % 16 (two 16-byte loads) and splits them into BF16 hi + lo in
+// registers.  The B operand (32 rays x 16 units) is the last hidden layer's
+// activations, transposed through LDS from the forward's fragment layout;
+// the bias column is a constant all-ones fragment.  Wave w of workgroup
+// (slice, y) owns the output tiles (m, n) with m = wm + WM (i + 2 y), i < 2,
+// and n = wn + WN j (WM = min(8, TO) rounded down to a power of two,
+// WN = 8 / WM): a many-head map gives each wave every n tile of two m tiles
+// (72 accumulator registers) and splits the m tiles over blockIdx.y, which
+// rereads only the small activation operand; a one-head map spreads its n
+// tiles over the waves.  The loads of chunk k + 1 are in flight while chunk
+// k's MFMAs run (chunks of 64 rays, two K steps); two LDS buffers and one
+// barrier per chunk.  One partial per slice, as dw_kernel writes for the
+// other layers.
+constexpr int kDoWaves = 8;
+constexpr int kDoChunk = 64;            // rays per chunk
+constexpr int kDoK = kDoChunk / 32;     // MFMA K steps per chunk
+constexpr int kDoRow = kDoChunk + 8;    // bf16 per LDS row (16-byte skew)
+// Two instantiations: maps with at least eight output tiles (16 heads) give
+// each wave two m tiles against every n tile (MT = 2, NTW = n tiles); fewer
+// tiles give each wave one m tile and at most half the n tiles, which keeps
+// the registers low enough for two workgroups per CU.
+constexpr int kDoManyHeadsTO = 8;
+
+// workgroups along y: m tiles are split in groups of WM * MT
+static int dw_out_yblocks(int TO, int MT)
+{
+    const int WM = TO >= 8 ? 8 : TO >= 4 ? 4 : TO >= 2 ? 2 : 1;
+    return (TO + WM * MT - 1) / (WM * MT);
+}
+
+// Input-layer weight gradient (widths 64 and 128), the last row of
+// dw_out_kernel's grid: dW0[unit][k] = sum_r delta1[unit][r] x[k][r] over
+// one slice.  Units are the M dimension (wave w takes M tile w), rays K, and
+// the 16 N columns are the inputs split into BF16 hi (0..5) and lo (6..11)
+// plus the all-ones bias column (12); the layer's weight gradient is the hi
+// column plus the lo column.  The A operand is the first hidden layer's
+// gradient, transposed through LDS from the backward's fragment layout; the
+// B operand comes straight from the FP32 inputs, lane l reading 8
+// consecutive rays of input l % 6.
+template <int H>
+__device__ __forceinline__ void dw_in_block(const DwArgs &A, __bf16 (*dT)[H * kDoRow])
+{
+    constexpr int T = H / 16, C = H / 32;
+    constexpr int kFrags = (kDoChunk / 16) * C;
+    constexpr int kDoFill = (kFrags * 64 + kDoWaves * 64 - 1) / (kDoWaves * 64);
+    const MapLayout &L = A.L;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, col = lane & 15;
+    const int mt = wave;   // this wave's M tile (units 16 mt ..) if mt < T
+    const int64_t n_chunks = A.n_pad / kDoChunk;
+    const int64_t per = (n_chunks + gridDim.x - 1) / gridDim.x;
+    const int64_t c0 = blockIdx.x * per;
+    const int64_t c1 = c0 + per < n_chunks ? c0 + per : n_chunks;
+    const int64_t tiles16 = A.n_pad / 16;
+    const bf16x8 *df = reinterpret_cast<const bf16x8 *>(A.dfrag);
+    const int feat = col % 6;      // input of this lane's B column (col < 12)
+    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    float xraw[kDoK][8];
+    bf16x8 hv[kDoFill];
+    auto load = [&](int64_t ch) {
+        const bool full = (ch + 1) * kDoChunk <= A.n;   // uniform
+#pragma unroll
+        for (int ks = 0; ks < kDoK; ++ks) {
+            const int64_t r0 = ch * kDoChunk + 32 * ks + 8 * g;
+            const float *src = A.xhat + static_cast<int64_t>(feat) * A.n_pad + r0;
+            if (full) {
+                floatx4 v0 = {0.0f, 0.0f, 0.0f, 0.0f}, v1 = v0;
+                if (col < 12) {
+                    v0 = reinterpret_cast<const floatx4 *>(src)[0];
+                    v1 = reinterpret_cast<const floatx4 *>(src)[1];
+                }
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    xraw[ks][jj] = v0[jj];
+                    xraw[ks][4 + jj] = v1[jj];
+                }
+            } else {
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj)
+                    xraw[ks][jj] = (col < 12 && r0 + jj < A.n) ? src[jj] : 0.0f;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kDoFill; ++u) {
+            const int fi = threadIdx.x + u * kDoWaves * 64;
+            if (fi < kFrags * 64) {
+                const int f = fi >> 6, ft16 = f / C, fc = f % C;
+                hv[u] = df[((ch * (kDoChunk / 16) + ft16) * C + fc) * 64 + (fi & 63)];
+            }
+        }
+    };
+    bf16x8 bx[kDoK];
+    auto stage = [&](int64_t ch, int buf) {
+#pragma unroll
+        for (int ks = 0; ks < kDoK; ++ks)
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) {
+                const float x = xraw[ks][jj];
+                const __bf16 h = to_bf16(x);
+                const bool live = ch * kDoChunk + 32 * ks + 8 * g + jj < A.n;
+                bx[ks][jj] = col < 6 ? h : col < 12 ? to_bf16(x - static_cast<float>(h))
+                                                    : to_bf16(col == 12 && live ? 1.0f : 0.0f);
+            }
+#pragma unroll
+        for (int u = 0; u < kDoFill; ++u) {
+            const int fi = threadIdx.x + u * kDoWaves * 64;
+            if (fi < kFrags * 64) {
+                const int f = fi >> 6, ft16 = f / C, fc = f % C;
+                const int fl = fi & 63, fg = fl >> 4, fcol = fl & 15;
+                const bool live = ch * kDoChunk + 16 * ft16 + fcol < A.n;
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj)
+                    dT[buf][(32 * fc + perm32(8 * fg + jj)) * kDoRow + 16 * ft16 + fcol] =
+                        live ? hv[u][jj] : to_bf16(0.0f);
+            }
+        }
+    };
+    if (c0 < c1) {
+        load(c0);
+        stage(c0, 0);
+    }
+    __syncthreads();
+    for (int64_t ch = c0; ch < c1; ++ch) {
+        const int buf = static_cast<int>((ch - c0) & 1);
+        if (ch + 1 < c1)
+            load(ch + 1);
+        if (mt < T) {
+#pragma unroll
+            for (int ks = 0; ks < kDoK; ++ks) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&dT[buf][(16 * mt + col) * kDoRow + 32 * ks + 8 * g]);
+                acc = mfma_bf16(a, bx[ks], acc);
+            }
+        }
+        if (ch + 1 < c1)
+            stage(ch + 1, buf ^ 1);
+        __syncthreads();
+    }
+    // D[m = unit 16 mt + 4 g + e][n = col]: weight = hi column + lo column
+    float *out = A.partial + static_cast<int64_t>(blockIdx.x) * L.n_params;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const float v = acc[e];
+        const float partner = __shfl(v, (lane + 6) & 63);
+        const int unit = 16 * mt + 4 * g + e;
+        if (mt < T) {
+            if (col < 6)
+                out[L.w_off[0] + unit * 6 + col] = v + partner;
+            else if (col == 12)
+                out[L.b_off[0] + unit] = v;
+        }
+    }
+}
+
+template <int H, int MT, int NTW>
+__global__ __launch_bounds__(kDoWaves * 64) void dw_out_kernel(DwArgs A)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 hT[2][H * kDoRow];
+    if (blockIdx.y == gridDim.y - 1) {   // the input layer (uniform per block)
+        dw_in_block<H>(A, hT);
+        return;
+    }
+    constexpr int T = H / 16, C = H / 32, NTN = T + 1;
+    const MapLayout &L = A.L;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, col = lane & 15;
+    const int TO = L.TO;
+    const int WM = TO >= 8 ? 8 : TO >= 4 ? 4 : TO >= 2 ? 2 : 1;
+    const int WN = kDoWaves / WM;
+    const int wm = wave % WM, wn = wave / WM;
+    const int mt0 = wm + WM * MT * static_cast<int>(blockIdx.y);   // m tile i: mt0 + WM i
+    const int n_mt = mt0 < TO ? (TO - mt0 + WM - 1) / WM : 0;
+    const int n_nt = (NTN - wn + WN - 1) / WN;
+
+    // output rows of this lane's A fragments (-1: padding slot)
+    int arow[MT];
+#pragma unroll
+    for (int i = 0; i < MT; ++i) {
+        const int slot = 16 * (mt0 + WM * i) + col;
+        const int head = slot / kHeadSlots, q = slot % kHeadSlots;
+        arow[i] = (i < n_mt && head < L.P && q < kMapOut) ? head * kMapOut + q : -1;
+    }
+    // 16-byte loads of 8 rays need 16-byte aligned rows
+    const bool vec = A.dout_stride % 4 == 0 && reinterpret_cast<uintptr_t>(A.dout) % 16 == 0;
+    const int64_t n_chunks = A.n_pad / kDoChunk;
+    const int64_t per = (n_chunks + gridDim.x - 1) / gridDim.x;
+    const int64_t c0 = blockIdx.x * per;
+    const int64_t c1 = c0 + per < n_chunks ? c0 + per : n_chunks;
+    const int64_t tiles16 = A.n_pad / 16;
+    const bf16x8 *hf = reinterpret_cast<const bf16x8 *>(A.hfrag);
+
+    floatx4 acc[MT][NTW];
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int j = 0; j < NTW; ++j)
+            acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    bf16x8 ones = {};
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj)
+        ones[jj] = to_bf16(col == 0 ? 1.0f : 0.0f);
+
+    // the LDS transpose of a chunk: fragments f (ray tile f / C, feature
+    // chunk f % C), lane-loads fi = 64 f + lane spread over the threads
+    constexpr int kFrags = (kDoChunk / 16) * C;
+    constexpr int kDoFill = (kFrags * 64 + kDoWaves * 64 - 1) / (kDoWaves * 64);
+
+    // A operand: per m tile and K step (32 rays), lane l holds rays
+    // 32 ks + 8 g .. + 7 of slot l % 16
+    float araw[MT][kDoK][8];
+    bf16x8 hv[kDoFill];
+    auto load = [&](int64_t ch) {
+        const bool full = vec && (ch + 1) * kDoChunk <= A.n;   // uniform
+#pragma unroll
+        for (int i = 0; i < MT; ++i) {
+            const float *src_row = A.dout + static_cast<int64_t>(arow[i] < 0 ? 0 : arow[i]) * A.dout_stride;
+#pragma unroll
+            for (int ks = 0; ks < kDoK; ++ks) {
+                const int64_t r0 = ch * kDoChunk + 32 * ks + 8 * g;
+                if (full) {
+                    floatx4 v0 = {0.0f, 0.0f, 0.0f, 0.0f}, v1 = v0;
+                    if (arow[i] >= 0) {
+                        const floatx4 *src = reinterpret_cast<const floatx4 *>(src_row + r0);
+                        v0 = src[0];
+                        v1 = src[1];
+                    }
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) {
+                        araw[i][ks][jj] = v0[jj];
+                        araw[i][ks][4 + jj] = v1[jj];
+                    }
+                } else {
+#pragma unroll
+                    for (int jj = 0; jj < 8; ++jj)
+                        araw[i][ks][jj] = (arow[i] >= 0 && r0 + jj < A.n) ? src_row[r0 + jj] : 0.0f;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kDoFill; ++u) {
+            const int fi = threadIdx.x + u * kDoWaves * 64;
+            if (fi < kFrags * 64) {
+                const int f = fi >> 6, ft16 = f / C, fc = f % C;
+                hv[u] = hf[(((static_cast<int64_t>(L.D) - 1) * tiles16 + ch * (kDoChunk / 16) + ft16) * C + fc) * 64 +
+                           (fi & 63)];
+            }
+        }
+    };
+    bf16x8 ahi[MT][kDoK], alo[MT][kDoK];
+    auto stage = [&](int64_t ch, int buf) {
+#pragma unroll
+        for (int i = 0; i < MT; ++i)
+#pragma unroll
+            for (int ks = 0; ks < kDoK; ++ks)
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj) {
+                    const __bf16 h = to_bf16(araw[i][ks][jj]);
+                    ahi[i][ks][jj] = h;
+                    alo[i][ks][jj] = to_bf16(araw[i][ks][jj] - static_cast<float>(h));
+                }
+#pragma unroll
+        for (int u = 0; u < kDoFill; ++u) {
+            const int fi = threadIdx.x + u * kDoWaves * 64;
+            if (fi < kFrags * 64) {
+                const int f = fi >> 6, ft16 = f / C, fc = f % C;
+                const int fl = fi & 63, fg = fl >> 4, fcol = fl & 15;
+                const bool live = ch * kDoChunk + 16 * ft16 + fcol < A.n;
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj)
+                    hT[buf][(32 * fc + perm32(8 * fg + jj)) * kDoRow + 16 * ft16 + fcol] =
+                        live ? hv[u][jj] : to_bf16(0.0f);
+            }
+        }
+    };
+
+    if (c0 < c1) {
+        load(c0);
+        stage(c0, 0);
+    }
+    __syncthreads();
+    for (int64_t ch = c0; ch < c1; ++ch) {
+        const int buf = static_cast<int>((ch - c0) & 1);
+        if (ch + 1 < c1)
+            load(ch + 1);
+#pragma unroll
+        for (int j = 0; j < NTW; ++j) {
+            if (j < n_nt) {
+                const int nt = wn + WN * j;
+#pragma unroll
+                for (int ks = 0; ks < kDoK; ++ks) {
+                    const bf16x8 b =
+                        nt < T ? *reinterpret_cast<const bf16x8 *>(&hT[buf][(16 * nt + col) * kDoRow + 32 * ks + 8 * g])
+                               : ones;
+#pragma unroll
+                    for (int i = 0; i < MT; ++i) {
+                        if (i < n_mt) {
+                            acc[i][j] = mfma_bf16(ahi[i][ks], b, acc[i][j]);
+                            acc[i][j] = mfma_bf16(alo[i][ks], b, acc[i][j]);
+                        }
+                    }
+                }
+            }
+        }
+        if (ch + 1 < c1)
+            stage(ch + 1, buf ^ 1);
+        __syncthreads();
+    }
+    // --- partial gradients of this slice
+    float *out = A.partial + static_cast<int64_t>(blockIdx.x) * L.n_params;
+#pragma unroll
+    for (int i = 0; i < MT; ++i) {
+#pragma unroll
+        for (int j = 0; j < NTW; ++j) {
+            const int nt = wn + WN * j;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int slot = 16 * (mt0 + WM * i) + 4 * g + e;
+                const int head = slot / kHeadSlots, q = slot % kHeadSlots;
+                const int row = head * kMapOut + q;
+                if (i < n_mt && j < n_nt && head < L.P && q < kMapOut) {
+                    if (nt < T)
+                        out[L.w_off[L.D] + static_cast<int64_t>(row) * H + 16 * nt + col] = acc[i][j][e];
+                    else if (col == 0)
+                        out[L.b_off[L.D] + row] = acc[i][j][e];
+                }
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------- reduce + Adam ----
 
 struct AdamArgs {
@@ -557,7 +890,9 @@ struct AdamArgs {
     int64_t slices_h, hid_lo, hid_hi;   // parameters [hid_lo, hid_hi) have slices_h partials
     float *master, *m, *v;
     float *grad_out;          // if non-null: write the gradient, no update
-    float lr, beta1, beta2, eps, bc1, bc2;
+    float lr, beta1, beta2, eps;
+    int64_t step;
+    const lt_train_sched *sched;   // if non-null: lr and step read from it
     const float *loss_partial;
     int64_t loss_blocks;
     float *loss_out;          // [3]
@@ -578,6 +913,23 @@ static void set_hidden_range(AdamArgs &A, const MapLayout &L, int64_t slices_h)
 
 __global__ __launch_bounds__(256) void reduce_adam_kernel(AdamArgs A)
 {
+    // learning rate and bias corrections 1 - beta^step, the same arithmetic
+    // whether lr and step come from the call or from device memory; one
+    // thread per block evaluates the powers
+    __shared__ float sched_vals[3];
+    if (threadIdx.x == 0) {
+        float lr0 = A.lr;
+        int64_t step = A.step;
+        if (A.sched) {
+            lr0 = A.sched->lr;
+            step = A.sched->step;
+        }
+        sched_vals[0] = lr0;
+        sched_vals[1] = static_cast<float>(1.0 - pow(static_cast<double>(A.beta1), static_cast<double>(step)));
+        sched_vals[2] = static_cast<float>(1.0 - pow(static_cast<double>(A.beta2), static_cast<double>(step)));
+    }
+    __syncthreads();
+    const float lr = sched_vals[0], bc1 = sched_vals[1], bc2 = sched_vals[2];
     for (int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; k < A.n_params;
          k += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         // slices summed in order; sixteen loads in flight at a time
@@ -603,8 +955,8 @@ __global__ __launch_bounds__(256) void reduce_adam_kernel(AdamArgs A)
         const float v = A.beta2 * A.v[k] + (1.0f - A.beta2) * gsum * gsum;
         A.m[k] = m;
         A.v[k] = v;
-        const float mh = m / A.bc1, vh = v / A.bc2;
-        A.master[k] -= A.lr * mh / (sqrtf(vh) + A.eps);
+        const float mh = m / bc1, vh = v / bc2;
+        A.master[k] -= lr * mh / (sqrtf(vh) + A.eps);
     }
     if (A.loss_out && blockIdx.x == 0) {
         // fixed-order tree over the per-block loss partials (deterministic)
@@ -778,62 +1130,77 @@ __global__ __launch_bounds__(256) void dw_hidden_kernel(DwArgs A)
 // LDS of dw_kernel: the staged output-gradient rows of one group (two
 // 16-row fragments per output tile) or the layer's own rows, the activation
 // rows and the selector, each a padded chunk of BF16.
+// LDS of dw_kernel (width 32: every layer, the output layer staging 2 x 16
+// rows per output tile); 0 at widths 64 and 128, whose weight gradients use
+// static LDS.
 static size_t dw_lds_bytes(const MapLayout &L)
 {
+    if (L.H >= 64)
+        return 0;
     const int rows_max = 2 * 16 * L.TO > L.H ? 2 * 16 * L.TO : L.H;
     return static_cast<size_t>(rows_max + L.H + 16) * (kDwChunk + kDwPad) * 2;
 }
 
-// Checked by every training call before it enqueues anything: at width 128
-// the output-gradient staging of more than 62 heads exceeds a CU's LDS.
+// Checked by every training call before it enqueues anything (every map
+// lt_map_create accepts fits: 64 heads at width 32 stage 154 KiB).
 static lt_status check_train_shape(const MapLayout &L)
 {
     if (dw_lds_bytes(L) > static_cast<size_t>(kMaxLds))
-        return fail(LT_ERR_ARG, "too many heads to train at this width (at most 62 at width 128)");
+        return fail(LT_ERR_ARG, "too many heads to train at this width");
     return LT_OK;
 }
 
 template <int H>
 static lt_status launch_dw(const DwArgs &A, const WsLayout &w, hipStream_t s)
 {
-    auto kern = dw_kernel<H>;
-    static bool attr = false;
-    if (!attr) {
-        lt_status st = check_hip(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                     kMaxLds),
-                                 "hipFuncSetAttribute");
-        if (st != LT_OK)
-            return st;
-        attr = true;
-    }
     const MapLayout &L = A.L;
-    const int T = H / 16;
-    int max_groups = 1;
-    for (int layer = 0; layer <= L.D; ++layer) {
-        if (H >= 64 && layer != 0 && layer != L.D)
-            continue;   // hidden layers: dw_hidden_kernel
-        const int tiles = (layer == L.D ? L.TO : T) * (layer == 0 ? 1 : T + 1);
-        const int gr = (tiles + 4 * kDwTilesPerWave - 1) / (4 * kDwTilesPerWave);
-        if (gr > max_groups)
-            max_groups = gr;
-    }
-    const size_t lds = dw_lds_bytes(L);
-    if (lds > static_cast<size_t>(kMaxLds))
-        return fail(LT_ERR_ARG, "too many heads for the weight-gradient kernel");
-    const uint32_t layers = H >= 64 ? 2u : static_cast<uint32_t>(L.D + 1);
-    hipLaunchKernelGGL(kern, dim3(layers, max_groups, static_cast<uint32_t>(w.slices)), dim3(256),
-                       lds, s, A);
-    lt_status st = check_hip(hipGetLastError(), "dw_kernel launch");
     if constexpr (H >= 64) {
+        // output layer (y < yblocks) and input layer (the last y row), then
+        // the hidden layers
+        constexpr int NTN = H / 16 + 1;
+        if (L.TO >= kDoManyHeadsTO)
+            hipLaunchKernelGGL((dw_out_kernel<H, 2, NTN>),
+                               dim3(static_cast<uint32_t>(w.slices), static_cast<uint32_t>(dw_out_yblocks(L.TO, 2) + 1)),
+                               dim3(kDoWaves * 64), 0, s, A);
+        else
+            hipLaunchKernelGGL((dw_out_kernel<H, 1, (NTN + 1) / 2>),
+                               dim3(static_cast<uint32_t>(w.slices), static_cast<uint32_t>(dw_out_yblocks(L.TO, 1) + 1)),
+                               dim3(kDoWaves * 64), 0, s, A);
+        lt_status st = check_hip(hipGetLastError(), "dw_out_kernel launch");
         if (st == LT_OK && L.D > 1) {
             const size_t lds_h = static_cast<size_t>(2 * H + 16) * (kDwChunk + kDwPad) * 2;
             hipLaunchKernelGGL(dw_hidden_kernel<H>, dim3(L.D - 1, static_cast<uint32_t>(w.slices_h)), dim3(256),
                                lds_h, s, A);
             st = check_hip(hipGetLastError(), "dw_hidden_kernel launch");
         }
+        return st;
+    } else {
+        // width 32: every layer in dw_kernel
+        auto kern = dw_kernel<H>;
+        static bool attr = false;
+        if (!attr) {
+            lt_status st = check_hip(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                                         hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds),
+                                     "hipFuncSetAttribute");
+            if (st != LT_OK)
+                return st;
+            attr = true;
+        }
+        const int T = H / 16;
+        int max_groups = 1;
+        for (int layer = 0; layer <= L.D; ++layer) {
+            const int tiles = (layer == L.D ? L.TO : T) * (layer == 0 ? 1 : T + 1);
+            const int gr = (tiles + 4 * kDwTilesPerWave - 1) / (4 * kDwTilesPerWave);
+            if (gr > max_groups)
+                max_groups = gr;
+        }
+        const size_t lds = dw_lds_bytes(L);
+        if (lds > static_cast<size_t>(kMaxLds))
+            return fail(LT_ERR_ARG, "too many heads for the weight-gradient kernel");
+        hipLaunchKernelGGL(kern, dim3(static_cast<uint32_t>(L.D + 1), max_groups, static_cast<uint32_t>(w.slices)),
+                           dim3(256), lds, s, A);
+        return check_hip(hipGetLastError(), "dw_kernel launch");
     }
-    return st;
 }
 
 static lt_status ensure_packed_wt(Map &M, hipStream_t s)
@@ -933,7 +1300,7 @@ static lt_status check_train_args(const Map *M, const lt_rays *rays, const lt_ta
     if (!targets->valid || !targets->x || !targets->y || !targets->dx || !targets->dy ||
         !targets->throughput)
         return fail(LT_ERR_ARG, "NULL target field");
-    if (cfg->step < 1 || !(cfg->lr >= 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) ||
+    if ((!cfg->sched && (cfg->step < 1 || !(cfg->lr >= 0.0f))) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) ||
         !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) || !(cfg->eps > 0.0f) ||
         !(cfg->w_cos >= 0.0f && cfg->w_cos < 1e30f))
         return fail(LT_ERR_ARG, "bad optimiser settings (step must be >= 1)");
@@ -1105,7 +1472,16 @@ static lt_status train_step(Map &Mr, const lt_rays *rays, const lt_targets *targ
                             hipStream_t s)
 {
     Map *M = &Mr;
-    lt_status st = ensure_packed_bf16(*M, s);
+    // A step recorded into a HIP graph changes the master parameters on
+    // every replay, so the recording must repack them each time, whatever the
+    // host-side bookkeeping says at recording time.
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    lt_status st = check_hip(hipStreamIsCapturing(s, &cs), "hipStreamIsCapturing");
+    if (st != LT_OK)
+        return st;
+    if (cs != hipStreamCaptureStatusNone)
+        M->packed_bf16 = M->packed_wt = ~0ull;
+    st = ensure_packed_bf16(*M, s);
     if (st != LT_OK)
         return st;
     EvalArgs A{};
@@ -1155,8 +1531,8 @@ static lt_status train_step(Map &Mr, const lt_rays *rays, const lt_targets *targ
     AA.beta1 = cfg->beta1;
     AA.beta2 = cfg->beta2;
     AA.eps = cfg->eps;
-    AA.bc1 = static_cast<float>(1.0 - std::pow(static_cast<double>(cfg->beta1), static_cast<double>(cfg->step)));
-    AA.bc2 = static_cast<float>(1.0 - std::pow(static_cast<double>(cfg->beta2), static_cast<double>(cfg->step)));
+    AA.step = cfg->step;
+    AA.sched = cfg->sched;
     AA.loss_partial = reinterpret_cast<const float *>(wb + w.loss);
     AA.loss_blocks = w.loss_blocks * M->lay.P;
     AA.loss_out = loss_out;

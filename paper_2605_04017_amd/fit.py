@@ -164,26 +164,46 @@ def sampler_dataset(lens, path, n_valid: int, seed: int, n_chains: int = 1 << 20
 
 
 def fit_epochs(m, rays: Dict, targets: Dict, epochs: int, batch: int, cfg: Dict, seed: int,
-               lr=paper_lr, stream=None):
+               lr=paper_lr, stream=None, graph_steps: int = 0):
     """Adam over `epochs` shuffled passes of a fixed dataset (rays: dict of
     [n] device tensors; targets: dict of [1, n] tensors as lt_map_train_step
     takes them), `batch` rays per step, the learning rate lr(step) from step 0
-    (the paper's schedule by default).  cfg: the loss weights.  Returns
-    (steps, last loss tensor)."""
+    (the paper's schedule by default).  cfg: the loss weights.  With
+    graph_steps > 0 the steps run in recorded runs of that many steps
+    (TrainGraph; each run's shuffled batches gathered into its buffers), the
+    last steps of an epoch that do not fill a run eagerly; the result is the
+    same as the eager loop's.  Returns (steps, last loss tensor)."""
     import torch
     from . import lt_map_train_step, workspace
     n = int(rays["x"].numel())
     per_epoch = n // batch
+    dev = rays["x"].device
     ws = workspace(m, batch)
-    g = torch.Generator(device=rays["x"].device)
+    g = torch.Generator(device=dev)
     g.manual_seed(seed)
+    K = min(int(graph_steps), per_epoch)
+    G = TrainGraph(m, K, batch, cfg, dev) if K > 0 else None
+    P = m.n_heads
     step, loss = 0, None
     for _ in range(epochs):
-        perm = torch.randperm(n, device=rays["x"].device, generator=g)
+        perm = torch.randperm(n, device=dev, generator=g)
+        b = 0
+        if G is not None:
+            while b + K <= per_epoch:
+                idx = perm[b * batch:(b + K) * batch]
+                for f, v in G.rays.items():
+                    torch.index_select(rays[f], 0, idx, out=v)
+                for f, v in G.targets.items():
+                    v.copy_(targets[f].index_select(1, idx).reshape(P, K, batch).permute(1, 0, 2))
+                loss = G.run([lr(step + k) for k in range(K)], step + 1)[K - 1]
+                step += K
+                b += K
+            if b == per_epoch:
+                continue
         R = {k: v[perm] for k, v in rays.items()}
         T = {k: v[:, perm] for k, v in targets.items()}
-        for b in range(per_epoch):
-            lo = b * batch
+        for bb in range(b, per_epoch):
+            lo = bb * batch
             rb = {k: v[lo:lo + batch] for k, v in R.items()}
             tb = {k: v[:, lo:lo + batch] for k, v in T.items()}
             c = dict(cfg)
@@ -192,3 +212,61 @@ def fit_epochs(m, rays: Dict, targets: Dict, epochs: int, batch: int, cfg: Dict,
             c["step"] = step
             loss = lt_map_train_step(m, rb, tb, c, ws, stream=stream)
     return step, loss
+
+
+class TrainGraph:
+    """A run of `steps` fused training steps (lt_map_train_step: forward,
+    loss, backward, reduce + Adam, with the two repacks) recorded once into
+    one HIP graph and replayed, so a run costs one graph launch instead of
+    eight kernel launches and the wrapper's marshalling per step.
+
+    Step k of a run trains on rays [k * batch, (k + 1) * batch) of the static
+    buffers `rays` (dict of [steps * batch] tensors) and on targets[f][k]
+    (`targets`: dict of [steps, n_heads, batch] tensors); fill them before
+    run(), e.g. with a gather of the next shuffled batches.  Learning rate and
+    step count come from a device array of lt_train_sched entries that run()
+    writes with one copy, so one recording serves every run.  Replays and
+    eager calls on the same map may be mixed: each recorded step repacks the
+    parameters before its forward, and run() marks the map updated
+    (lt_map_mark_updated) so that the next eager evaluation repacks too.  The
+    map must not be trained or have its parameters set by other calls while a
+    replay is in flight."""
+
+    def __init__(self, m, steps: int, batch: int, cfg: Dict, device="cuda"):
+        import torch
+        from . import RAY_FIELDS, TARGET_FIELDS, lt_map_train_step, workspace
+        self.m, self.steps, self.batch = m, int(steps), int(batch)
+        P = m.n_heads
+        self.rays = {k: torch.zeros(steps * batch, dtype=torch.float32, device=device) for k in RAY_FIELDS}
+        self.targets = {k: torch.zeros((steps, P, batch), dtype=torch.uint8 if k == "valid" else torch.float32,
+                                       device=device) for k in TARGET_FIELDS}
+        self.ws = workspace(m, batch, device)
+        self.loss = torch.zeros((steps, 3), dtype=torch.float32, device=device)
+        self.sched = torch.zeros((steps, 16), dtype=torch.uint8, device=device)
+        c = {k: v for k, v in cfg.items() if k not in ("lr", "step")}
+        self.graph = torch.cuda.CUDAGraph()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(self.graph):
+            st = torch.cuda.current_stream()
+            for k in range(self.steps):
+                rb = {f: v[k * batch:(k + 1) * batch] for f, v in self.rays.items()}
+                tb = {f: v[k] for f, v in self.targets.items()}
+                lt_map_train_step(m, rb, tb, dict(c, sched=self.sched[k]), self.ws, self.loss[k], batch, st)
+        torch.cuda.synchronize()
+
+    def run(self, lrs, first_step: int):
+        """Replay the recorded steps with learning rates lrs[k] and step
+        counts first_step + k (1-based); returns the device losses
+        [steps, 3] (total, BCE, L2 per step)."""
+        import numpy as np
+        import torch
+        from . import lt_map_mark_updated
+        assert len(lrs) == self.steps
+        host = np.zeros(self.steps, dtype=[("lr", "<f4"), ("reserved", "<i4"), ("step", "<i8")])
+        host["lr"] = np.asarray(lrs, np.float32)
+        host["step"] = first_step + np.arange(self.steps, dtype=np.int64)
+        self.sched.copy_(torch.from_numpy(host.view(np.uint8).reshape(self.steps, 16)))
+        self.graph.replay()
+        lt_map_mark_updated(self.m)
+        return self.loss
+

@@ -74,3 +74,32 @@ def test_fit_epochs_reduces_loss(dev):
     torch.cuda.synchronize()
     assert s1 == 8 and s2 == 32
     assert float(l2[0]) < float(l1[0])
+
+
+def test_fit_epochs_graph_runs_match_eager(dev):
+    """fit_epochs with recorded runs (graph_steps = 3 of the 8 steps per
+    epoch: two replayed runs and two eager steps each epoch) leaves exactly
+    the parameters of the eager loop after two epochs."""
+    import torch
+    import paper_2605_04017_amd as lt
+    from paper_2605_04017_amd import fit as F
+    lens = synth.config_lens(2)
+    h = lt.lt_lens_create(lens.surfaces, lens.glasses)
+    rays = lt.lt_rays_generate(h, 1 << 15, 15)
+    ex = lt.lt_trace(h, (0, 0, 0), rays)
+    tg = {"valid": ex["mask"].reshape(1, -1)}
+    for k in F.REG_FIELDS:
+        tg[k] = ex[k].reshape(1, -1)
+    cfg = {"w_bce": 1.0, "w_l2": 1.0}
+    maps = []
+    for graph_steps in (0, 3):
+        m = lt.lt_map_create(32, 3, 1, lt.LT_ACT_TANH)
+        lt.lt_map_set_params(m, torch.from_numpy(F.init_params(32, 3, 1, 9)).to(dev))
+        s, loss = F.fit_epochs(m, rays, tg, 2, 4096, cfg, 21, lr=lambda k: 1e-3 * 0.9 ** k,
+                               graph_steps=graph_steps)
+        torch.cuda.synchronize()
+        assert s == 16
+        maps.append((m, loss.clone()))
+    assert torch.equal(lt.lt_map_get_params(maps[0][0]), lt.lt_map_get_params(maps[1][0]))
+    assert torch.equal(lt.lt_map_adam_state(maps[0][0]), lt.lt_map_adam_state(maps[1][0]))
+    assert torch.equal(maps[0][1], maps[1][1])
