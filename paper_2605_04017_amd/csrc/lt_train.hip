@@ -1472,16 +1472,12 @@ static lt_status train_step(Map &Mr, const lt_rays *rays, const lt_targets *targ
                             hipStream_t s)
 {
     Map *M = &Mr;
-    // A step recorded into a HIP graph changes the master parameters on
-    // every replay, so the recording must repack them each time, whatever the
-    // host-side bookkeeping says at recording time.
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    lt_status st = check_hip(hipStreamIsCapturing(s, &cs), "hipStreamIsCapturing");
-    if (st != LT_OK)
-        return st;
-    if (cs != hipStreamCaptureStatusNone)
-        M->packed_bf16 = M->packed_wt = ~0ull;
-    st = ensure_packed_bf16(*M, s);
+    // The step always repacks: in a training loop the previous step's Adam
+    // update has made the packed copies stale anyway, and a step recorded
+    // into a HIP graph must repack on every replay whatever the host-side
+    // bookkeeping says at recording time.
+    M->packed_bf16 = M->packed_wt = ~0ull;
+    lt_status st = ensure_packed_bf16(*M, s);
     if (st != LT_OK)
         return st;
     EvalArgs A{};
