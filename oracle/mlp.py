@@ -31,7 +31,10 @@ split hi/lo BF16 for the input layer and the output layer, OCP FP8 E4M3
 (bias 7, max 448, round-to-nearest-even, subnormals, saturating) with
 power-of-two per-layer scales for the hidden layers in FP8 mode -- and
 otherwise computes in FP64, so it pins the kernels up to FP32 accumulation
-order.
+order.  BF16 evaluation of a tanh map runs the folded form of the same
+network (`forward_folded_bf16`): with k = 2 log2 e, r = 1 / (1 + 2^(k z))
+and tanh z = 1 - 2 r, the scale k and the affine map move into the weights,
+and the rounded activation is r instead of tanh z.
 """
 from __future__ import annotations
 
@@ -329,13 +332,64 @@ def hidden_layer_fp8(z_prev: np.ndarray, W: np.ndarray, b: np.ndarray, sw: float
     return (hq @ Wq.T) / (sw * sh) + b
 
 
-def forward_quantized(p: MapParams, xhat: np.ndarray, mode: str):
-    """Forward pass with the kernels' rounding.  mode: "bf16" or "fp8".
+# ----------------------------------------------- folded BF16 evaluation --
+# tanh z = 1 - 2 r with r = 1 / (1 + 2^(k z)), k = 2 log2 e.  A layer
+# z' = W h + b then reads z' = -2 W r + (b + W 1), and its scaled output
+# u' = k z' feeds the next r = 1 / (1 + 2^u') directly.  The products with
+# k are taken in FP32 (the packer's arithmetic) before any rounding.
 
-    bf16: split input layer, hidden layers with BF16 weights and BF16-rounded
-    activations, split output layer.  fp8: the same input and output layers;
-    every hidden layer is hidden_layer_fp8 (one FP8 rounding of each scaled
-    activation); the last hidden activation is rounded to BF16."""
+K_TANH = float(np.float32(2.0 * math.log2(math.e)))
+
+
+def scale_f32(a: np.ndarray, s: float) -> np.ndarray:
+    """a * s as the packer computes it: FP32 operands, one FP32 rounding."""
+    return (np.asarray(a, np.float32) * np.float32(s)).astype(np.float64)
+
+
+def activation_folded_bf16(u: np.ndarray) -> np.ndarray:
+    """r = 1 / (1 + 2^u) = (1 - tanh(u / k)) / 2, rounded once to BF16."""
+    return round_bf16(1.0 / (1.0 + np.exp2(u)))
+
+
+def hidden_layer_folded_bf16(r: np.ndarray, W: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """u = Wq r + c with Wq = BF16(-2 k W) and c = k b - Wq 1 / 2, so that
+    u = k (W' h + b) for h = 1 - 2 r and W' = Wq / (-2 k), the rounded weights
+    (the sums exact; the kernels accumulate in FP32)."""
+    Wq = round_bf16(scale_f32(W, -2.0 * K_TANH))
+    c = scale_f32(b, K_TANH) - 0.5 * Wq.sum(1)
+    return r @ Wq.T + c
+
+
+def output_layer_folded(r: np.ndarray, Wo: np.ndarray, bo: np.ndarray) -> np.ndarray:
+    """o = Wo (1 - 2 r) + bo with Wo split into BF16 hi + lo: the weights
+    -2 W_hi and -2 W_lo (exact) and the bias bo + (W_hi + W_lo) 1."""
+    W_hi, W_lo = split_bf16(Wo)
+    return r @ (-2.0 * W_hi).T + r @ (-2.0 * W_lo).T + (bo + (W_hi + W_lo).sum(1))
+
+
+def forward_folded_bf16(p: MapParams, xhat: np.ndarray) -> np.ndarray:
+    """BF16 evaluation of a tanh map in the folded form: the split input layer
+    on k W0 and k b0, hidden_layer_folded_bf16 between activations
+    activation_folded_bf16, output_layer_folded."""
+    L = len(p.W)
+    u, _ = input_layer_split(xhat, scale_f32(p.W[0], K_TANH), scale_f32(p.b[0], K_TANH))
+    r = activation_folded_bf16(u)
+    for li in range(1, L - 1):
+        r = activation_folded_bf16(hidden_layer_folded_bf16(r, p.W[li], p.b[li]))
+    return output_layer_folded(r, p.W[L - 1], p.b[L - 1])
+
+
+def forward_quantized(p: MapParams, xhat: np.ndarray, mode: str):
+    """Forward pass with the kernels' rounding.  mode: "bf16" (BF16
+    evaluation: forward_folded_bf16 for tanh maps, the unfolded form below for
+    ReLU), "bf16_train" (the training forward: always unfolded) or "fp8".
+
+    Unfolded bf16: split input layer, hidden layers with BF16 weights and
+    BF16-rounded activations, split output layer.  fp8: the same input and
+    output layers; every hidden layer is hidden_layer_fp8 (one FP8 rounding of
+    each scaled activation); the last hidden activation is rounded to BF16."""
+    if mode == "bf16" and p.desc.activation == ACT_TANH:
+        return forward_folded_bf16(p, xhat)
     L = len(p.W)
     z, _ = input_layer_split(xhat, p.W[0], p.b[0])
     if mode == "fp8":

@@ -63,7 +63,8 @@ struct Map {
     MapLayout lay;
     float *master = nullptr;      // FP32 parameters (n_params)
     float *norm = nullptr;        // in_shift[6], in_scale[6], out_shift[5P], out_scale[5P]
-    uint8_t *img_bf16 = nullptr;  // packed BF16 image
+    uint8_t *img_bf16 = nullptr;  // packed BF16 evaluation image (folded network for tanh maps)
+    uint8_t *img_bf16_train = nullptr;  // packed BF16 image of the training forward (unfolded)
     uint8_t *img_fp8 = nullptr;   // packed FP8 image (hidden layers) + scales
     float *fp8_scales = nullptr;  // per hidden layer: 1 / (s_w * s_h), s_h
     uint8_t *img_wt = nullptr;    // packed BF16 W^T image for the backward pass
@@ -71,6 +72,7 @@ struct Map {
     float *adam_m = nullptr, *adam_v = nullptr;
     uint64_t version = 0;         // bumped by every parameter write
     uint64_t packed_bf16 = ~0ull, packed_fp8 = ~0ull, packed_wt = ~0ull, packed_f32 = ~0ull;
+    uint64_t packed_train = ~0ull;
     bool has_params = false;
 };
 

@@ -83,11 +83,39 @@ MapLayout make_layout(const lt_map_desc &d)
 // same BF16 input and output layers, hidden biases multiplied by s_w * s_h,
 // two extra floats per hidden layer (1 / (s_w s_h), s_h); the hidden FP8
 // fragments are written by pack_fp8_hidden_kernel.
+// With fold (BF16 evaluation image of a tanh map) the image holds the folded
+// network: with k = 2 log2 e, r = 1 / (1 + 2^(k z)) and tanh z = 1 - 2 r, the
+// input layer carries k W0 and k b0, a hidden layer BF16(-2 k W) and the bias
+// k b - (sum of that row of BF16(-2 k W)) / 2, the output layer -2 W (hi and
+// lo parts) and the bias b + (sum of that row of W_hi + W_lo), so that every
+// layer's accumulator is the next activation's exponent (or the output).
+// The products with k are FP32 products.
+__device__ __forceinline__ float fold_hidden_bias(const float *P, const MapLayout &L, int l, int m)
+{
+#pragma clang fp contract(off)
+    float sum = 0.0f;
+    for (int j = 0; j < L.H; ++j)
+        sum += static_cast<float>(to_bf16(P[L.w_off[l] + static_cast<int64_t>(m) * L.H + j] * (-2.0f * kTanhK)));
+    return P[L.b_off[l] + m] * kTanhK - 0.5f * sum;
+}
+
+__device__ __forceinline__ float fold_output_bias(const float *P, const MapLayout &L, int row)
+{
+    float sum = 0.0f;
+    for (int j = 0; j < L.H; ++j) {
+        const float w = P[L.w_off[L.D] + static_cast<int64_t>(row) * L.H + j];
+        const float hi = static_cast<float>(to_bf16(w));
+        sum += hi + static_cast<float>(to_bf16(w - hi));
+    }
+    return P[L.b_off[L.D] + row] + sum;
+}
+
 __global__ void pack_bf16_kernel(const float *__restrict__ P, const float *__restrict__ norm,
                                  MapLayout L, uint8_t *__restrict__ img,
-                                 const float *__restrict__ fp8_scales)
+                                 const float *__restrict__ fp8_scales, bool fold)
 {
     const bool fp8 = fp8_scales != nullptr;
+    fold = fold && !fp8;
     const int64_t n_w0 = static_cast<int64_t>(L.T) * 512;
     const int64_t n_hid = fp8 ? 0 : static_cast<int64_t>(L.D - 1) * L.T * L.C * 512;
     const int64_t n_out = static_cast<int64_t>(L.TO) * 2 * L.C * 512;
@@ -121,6 +149,8 @@ __global__ void pack_bf16_kernel(const float *__restrict__ P, const float *__res
                 const float w = P[L.w_off[L.D] + static_cast<int64_t>(head * kMapOut + q) * L.H + k];
                 const float hi = static_cast<float>(to_bf16(w));
                 v = cc < L.C ? hi : w - hi;
+                if (fold)
+                    v = -2.0f * static_cast<float>(to_bf16(v));
             }
             reinterpret_cast<__bf16 *>(img + img_cmp)[loc] = to_bf16(v);
         } else if (e >= n_frag + n_lg + bias_floats) {
@@ -128,7 +158,8 @@ __global__ void pack_bf16_kernel(const float *__restrict__ P, const float *__res
             int head = 0, q = 0;
             cmp_tile_row(b / 16, L.LT, b % 16, &head, &q);
             reinterpret_cast<float *>(img + img_cmp_bias)[b] =
-                head < L.P ? P[L.b_off[L.D] + head * kMapOut + q] : 0.0f;
+                head < L.P ? (fold ? fold_output_bias(P, L, head * kMapOut + q) : P[L.b_off[L.D] + head * kMapOut + q])
+                           : 0.0f;
         } else if (e < n_frag) {
             const bool is_w0 = e < n_w0, is_hid = !is_w0 && e < n_w0 + n_hid;
             const int64_t loc = is_w0 ? e : is_hid ? e - n_w0 : e - n_w0 - n_hid;
@@ -144,7 +175,7 @@ __global__ void pack_bf16_kernel(const float *__restrict__ P, const float *__res
                 const int m = static_cast<int>(f) * 16 + mrow;
                 const float *W0 = P + L.w_off[0];
                 if (kp < 18) {
-                    const float w = W0[m * 6 + (kp % 6)];
+                    const float w = fold ? W0[m * 6 + (kp % 6)] * kTanhK : W0[m * 6 + (kp % 6)];
                     const float hi = static_cast<float>(to_bf16(w));
                     v = kp < 12 ? hi : w - hi;
                 }
@@ -156,6 +187,8 @@ __global__ void pack_bf16_kernel(const float *__restrict__ P, const float *__res
                 const int m = t * 16 + mrow;
                 const int k = 32 * c + perm32(kp);
                 v = P[L.w_off[l] + static_cast<int64_t>(m) * L.H + k];
+                if (fold)
+                    v *= -2.0f * kTanhK;
             } else {
                 const int t = static_cast<int>(f / (2 * L.C));
                 const int cc = static_cast<int>(f % (2 * L.C));
@@ -168,6 +201,8 @@ __global__ void pack_bf16_kernel(const float *__restrict__ P, const float *__res
                     const float w = P[L.w_off[L.D] + static_cast<int64_t>(row) * L.H + k];
                     const float hi = static_cast<float>(to_bf16(w));
                     v = cc < L.C ? hi : w - hi;
+                    if (fold)
+                        v = -2.0f * static_cast<float>(to_bf16(v));
                 }
             }
             reinterpret_cast<__bf16 *>(img + base)[loc] = to_bf16(v);
@@ -182,11 +217,13 @@ __global__ void pack_bf16_kernel(const float *__restrict__ P, const float *__res
                 v = P[L.b_off[l] + m];
                 if (fp8 && l >= 1)
                     v *= fp8_scales[l - 1] * kFp8ActScale;
+                if (fold)
+                    v = l == 0 ? v * kTanhK : fold_hidden_bias(P, L, l, m);
             } else if (b < nb_hidden + 16LL * L.TO) {
                 const int slot = static_cast<int>(b - nb_hidden);
                 const int head = slot / kHeadSlots, q = slot % kHeadSlots;
                 if (head < L.P && q < kMapOut)
-                    v = P[L.b_off[L.D] + head * kMapOut + q];
+                    v = fold ? fold_output_bias(P, L, head * kMapOut + q) : P[L.b_off[L.D] + head * kMapOut + q];
             } else if (b < nb_norm) {
                 v = norm[b - nb_hidden - 16LL * L.TO];
             } else {
@@ -457,7 +494,11 @@ __global__ __launch_bounds__((eval_waves<H, TRAIN>() * 64)) void map_eval_bf16_k
                 for (int nt = 0; nt < NT; ++nt)
     #pragma unroll
                     for (int c = 0; c < C; ++c) {
-                        bop[nt][c] = act_pack<ACT>(acc[nt][2 * c], acc[nt][2 * c + 1]);
+                        // evaluation of a tanh map reads the folded image
+                        if constexpr (ACT == LT_ACT_TANH && !TRAIN)
+                            bop[nt][c] = act_pack_folded(acc[nt][2 * c], acc[nt][2 * c + 1]);
+                        else
+                            bop[nt][c] = act_pack<ACT>(acc[nt][2 * c], acc[nt][2 * c + 1]);
                         if constexpr (TRAIN) {
                             const int64_t fi = ((static_cast<int64_t>(l - 1) * (A.n_pad / 16) +
                                                  tile * NT + nt) * C + c) * 64 + lane;
@@ -750,7 +791,7 @@ static lt_status launch_bf16_impl(const Map &M, const lt_rays &rays, const lt_ma
                                   EvalArgs A, hipStream_t s)
 {
     const MapLayout &L = M.lay;
-    A.img = FP8 ? M.img_fp8 : M.img_bf16;
+    A.img = FP8 ? M.img_fp8 : TRAIN ? M.img_bf16_train : M.img_bf16;
     A.lds_bytes = FP8 ? L.img8_lds_bytes : L.out_in_lds_bytes;
     if (A.lds_bytes % 1024 != 0 || A.lds_bytes > kMaxLds)
         return fail(LT_ERR_STATE, "packed image not staged in whole 1 KiB rows");
@@ -812,20 +853,38 @@ lt_status launch_map_forward(const Map &M, const lt_rays &rays, const lt_map_out
 template lt_status launch_map_forward<true>(const Map &, const lt_rays &, const lt_map_out &,
                                             EvalArgs, hipStream_t);
 
-lt_status ensure_packed_bf16(Map &M, hipStream_t s)
+static lt_status pack_bf16(const Map &M, uint8_t *img, bool fold, hipStream_t s)
 {
-    if (M.packed_bf16 == M.version)
-        return LT_OK;
     const MapLayout &L = M.lay;
     const int64_t total = L.img_bytes / 2 + 16;
     int grid = static_cast<int>((total + 255) / 256);
     if (grid > 4096)
         grid = 4096;
-    hipLaunchKernelGGL(pack_bf16_kernel, dim3(grid), dim3(256), 0, s, M.master, M.norm, L,
-                       M.img_bf16, static_cast<const float *>(nullptr));
-    lt_status st = check_hip(hipGetLastError(), "pack_bf16_kernel launch");
+    hipLaunchKernelGGL(pack_bf16_kernel, dim3(grid), dim3(256), 0, s, M.master, M.norm, L, img,
+                       static_cast<const float *>(nullptr), fold);
+    return check_hip(hipGetLastError(), "pack_bf16_kernel launch");
+}
+
+// The BF16 evaluation image: the folded network for tanh maps.
+lt_status ensure_packed_bf16(Map &M, hipStream_t s)
+{
+    if (M.packed_bf16 == M.version)
+        return LT_OK;
+    lt_status st = pack_bf16(M, M.img_bf16, M.lay.act == LT_ACT_TANH, s);
     if (st == LT_OK)
         M.packed_bf16 = M.version;
+    return st;
+}
+
+// The training forward's image: the network as written (its stored
+// activations are tanh z, which the backward differentiates).
+lt_status ensure_packed_train(Map &M, hipStream_t s)
+{
+    if (M.packed_train == M.version)
+        return LT_OK;
+    lt_status st = pack_bf16(M, M.img_bf16_train, false, s);
+    if (st == LT_OK)
+        M.packed_train = M.version;
     return st;
 }
 
@@ -850,7 +909,7 @@ static lt_status ensure_packed_fp8(Map &M, hipStream_t s)
     if (grid > 4096)
         grid = 4096;
     hipLaunchKernelGGL(pack_bf16_kernel, dim3(grid), dim3(256), 0, s, M.master, M.norm, L,
-                       M.img_fp8, static_cast<const float *>(M.fp8_scales));
+                       M.img_fp8, static_cast<const float *>(M.fp8_scales), false);
     st = check_hip(hipGetLastError(), "pack_bf16_kernel (fp8 image) launch");
     if (st == LT_OK)
         M.packed_fp8 = M.version;
@@ -897,6 +956,7 @@ lt_status lt_map_create(const lt_map_desc *desc, lt_map *out)
     bool okk = hipMalloc(&M->master, np * 4) == hipSuccess &&
                hipMalloc(&M->norm, nnorm * 4) == hipSuccess &&
                hipMalloc(&M->img_bf16, static_cast<size_t>(M->lay.img_bytes)) == hipSuccess &&
+               hipMalloc(&M->img_bf16_train, static_cast<size_t>(M->lay.img_bytes)) == hipSuccess &&
                hipMalloc(&M->img_wt, static_cast<size_t>(wt_bytes(M->lay))) == hipSuccess &&
                hipMalloc(&M->img_fp8, static_cast<size_t>(M->lay.img8_bytes)) == hipSuccess &&
                hipMalloc(&M->img_f32, static_cast<size_t>(f32_image_bytes(M->lay))) == hipSuccess &&
@@ -907,6 +967,7 @@ lt_status lt_map_create(const lt_map_desc *desc, lt_map *out)
         (void)hipFree(M->master);
         (void)hipFree(M->norm);
         (void)hipFree(M->img_bf16);
+        (void)hipFree(M->img_bf16_train);
         (void)hipFree(M->img_wt);
         (void)hipFree(M->img_fp8);
         (void)hipFree(M->img_f32);
@@ -941,6 +1002,7 @@ lt_status lt_map_destroy(lt_map map)
     (void)hipFree(M->master);
     (void)hipFree(M->norm);
     (void)hipFree(M->img_bf16);
+    (void)hipFree(M->img_bf16_train);
     (void)hipFree(M->img_wt);
     (void)hipFree(M->img_fp8);
     (void)hipFree(M->img_f32);

@@ -52,12 +52,24 @@ __host__ __device__ __forceinline__ int perm32(int kp)
 
 __device__ __forceinline__ __bf16 to_bf16(float v) { return static_cast<__bf16>(v); }
 
+// 2 log2 e: tanh z = 1 - 2 / (1 + 2^(kTanhK z))
+constexpr float kTanhK = 2.8853900817779268f;
+
 __device__ __forceinline__ float act_tanh(float z)
 {
     // tanh z = 1 - 2 / (1 + 2^(2 z log2 e)); saturates correctly at +-inf
-    const float e = __builtin_amdgcn_exp2f(z * 2.8853900817779268f);
+    const float e = __builtin_amdgcn_exp2f(z * kTanhK);
     return fmaf(-2.0f, __builtin_amdgcn_rcpf(1.0f + e), 1.0f);
 }
+
+// The folded activation of BF16 evaluation: the packed weights carry k and
+// the affine map h = 1 - 2 r, so the accumulator u = k z gives
+// r = 1 / (1 + 2^u) directly (exp2, add, reciprocal).
+__device__ __forceinline__ float act_folded(float u)
+{
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(u));
+}
+
 
 template <int ACT>
 __device__ __forceinline__ float act(float z)
@@ -89,6 +101,12 @@ __device__ __forceinline__ bf16x8 pack8(float a0, float a1, float a2, float a3, 
     return bf16x8{q0[0], q0[1], q1[0], q1[1], q2[0], q2[1], q3[0], q3[1]};
 }
 
+__device__ __forceinline__ bf16x8 act_pack_folded(floatx4 lo, floatx4 hi)
+{
+    return pack8(act_folded(lo[0]), act_folded(lo[1]), act_folded(lo[2]), act_folded(lo[3]),
+                 act_folded(hi[0]), act_folded(hi[1]), act_folded(hi[2]), act_folded(hi[3]));
+}
+
 template <int ACT>
 __device__ __forceinline__ bf16x8 act_pack(floatx4 lo, floatx4 hi)
 {
@@ -100,7 +118,7 @@ __device__ __forceinline__ bf16x8 act_pack(floatx4 lo, floatx4 hi)
 // multiplier and the output scale s into the final FMA
 __device__ __forceinline__ float tanh_scaled(float z, float zs, float s)
 {
-    const float e = __builtin_amdgcn_exp2f(z * (zs * 2.8853900817779268f));
+    const float e = __builtin_amdgcn_exp2f(z * (zs * kTanhK));
     return fmaf(-2.0f * s, __builtin_amdgcn_rcpf(1.0f + e), s);
 }
 
@@ -446,6 +464,7 @@ __device__ __forceinline__ void stage_barrier()
 }
 
 lt_status ensure_packed_bf16(Map &M, hipStream_t s);
+lt_status ensure_packed_train(Map &M, hipStream_t s);
 template <bool TRAIN>
 lt_status launch_map_forward(const Map &M, const lt_rays &rays, const lt_map_out &out, EvalArgs A,
                              hipStream_t s);

@@ -60,8 +60,7 @@ F32Layout f32_layout(const MapLayout &L)
 //   hidden layers l:    W' = -2 k W,   b' = k (b + sum_j W[i][j])   (input h = 1 - 2 r)
 //   output layer:       W' = -2 W,     b' = b + sum_j W[i][j]
 // so every layer computes the same pre-activation (times k) from r.  Row
-// sums are taken in FP64 when the image is built.
-constexpr float kTanhK = 2.8853900817779268f;
+// sums are taken in FP64 when the image is built.  (kTanhK: lt_map_dev.h.)
 
 __device__ float row_sum(const float *__restrict__ W, int n)
 {

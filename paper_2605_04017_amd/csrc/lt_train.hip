@@ -606,7 +606,6 @@ __device__ __forceinline__ void dw_in_block(const DwArgs &A, __bf16 (*dT)[H * kD
     const int64_t per = (n_chunks + gridDim.x - 1) / gridDim.x;
     const int64_t c0 = blockIdx.x * per;
     const int64_t c1 = c0 + per < n_chunks ? c0 + per : n_chunks;
-    const int64_t tiles16 = A.n_pad / 16;
     const bf16x8 *df = reinterpret_cast<const bf16x8 *>(A.dfrag);
     const int feat = col % 6;      // input of this lane's B column (col < 12)
     floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -1380,7 +1379,7 @@ lt_status lt_map_forward_train(lt_map map, const lt_rays *rays, float *o_raw, vo
     if (st != LT_OK)
         return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    st = ensure_packed_bf16(*M, s);
+    st = ensure_packed_train(*M, s);
     if (st != LT_OK)
         return st;
     uint8_t *wb = static_cast<uint8_t *>(ws);
@@ -1476,8 +1475,8 @@ static lt_status train_step(Map &Mr, const lt_rays *rays, const lt_targets *targ
     // update has made the packed copies stale anyway, and a step recorded
     // into a HIP graph must repack on every replay whatever the host-side
     // bookkeeping says at recording time.
-    M->packed_bf16 = M->packed_wt = ~0ull;
-    lt_status st = ensure_packed_bf16(*M, s);
+    M->packed_train = M->packed_wt = ~0ull;
+    lt_status st = ensure_packed_train(*M, s);
     if (st != LT_OK)
         return st;
     EvalArgs A{};

@@ -21,6 +21,10 @@ from oracle import mlp
 pytestmark = pytest.mark.gpu
 
 MED_TOL, P99_TOL, MAX_TOL = 1e-5, 2e-3, 2e-2
+# BF16 evaluation of a tanh map rounds r = (1 - h) / 2 rather than h: a
+# rounding flip moves h = 1 - 2 r by twice r's BF16 ulp, so the 99th
+# percentile and maximum bounds double (the median stays at FP32 level)
+FOLDED_SCALE = 2.0
 # FP8 hidden layers: 3 mantissa bits, so a flip is 16 times a BF16 one
 FP8_TOLS = (1e-4, 3e-2, 3e-1)
 
@@ -69,11 +73,11 @@ def run_eval(m, rays, dev, dtype):
     return {k: v.cpu().numpy() for k, v in out.items()}
 
 
-def _check_stats(err, what):
+def _check_stats(err, what, scale=1.0):
     med, p99, mx = np.median(err), np.quantile(err, 0.99), err.max()
     assert med <= MED_TOL, f"{what}: median error {med:.3e}"
-    assert p99 <= P99_TOL, f"{what}: 99th percentile error {p99:.3e}"
-    assert mx <= MAX_TOL, f"{what}: max error {mx:.3e}"
+    assert p99 <= scale * P99_TOL, f"{what}: 99th percentile error {p99:.3e}"
+    assert mx <= scale * MAX_TOL, f"{what}: max error {mx:.3e}"
     return med, p99, mx
 
 
@@ -84,9 +88,10 @@ def compare(g, p, rays, mode, sel=None):
     xhat = mlp.features(sub, p)
     o = mlp.forward(p, xhat)[0] if mode == "f32" else mlp.forward_quantized(p, xhat, mode)
     ref = mlp.decode(o, p, sub)
+    scale = FOLDED_SCALE if (mode == "bf16" and p.desc.activation == mlp.ACT_TANH) else 1.0
     dl = np.abs(g["logit"] - ref["logit"]).reshape(-1)
-    stl = _check_stats(dl, "logit")
-    sure = np.abs(ref["logit"]) > MAX_TOL
+    stl = _check_stats(dl, "logit", scale)
+    sure = np.abs(ref["logit"]) > scale * MAX_TOL
     assert np.array_equal(g["mask"][sure], ref["mask"][sure])
     both = (g["mask"] == 1) & (ref["mask"] == 1)
     errs = []
@@ -94,7 +99,7 @@ def compare(g, p, rays, mode, sel=None):
         for k, idx in (("x", 0), ("y", 1), ("dx", 2), ("dy", 3), ("throughput", 4)):
             errs.append(np.abs(g[k][h][both[h]] - ref[k][h][both[h]]) / p.out_scale[h, idx])
     err = np.concatenate(errs)
-    sto = _check_stats(err, "outputs") if err.size else (0, 0, 0)
+    sto = _check_stats(err, "outputs", scale) if err.size else (0, 0, 0)
     # empty-set semantics
     off = g["mask"] == 0
     assert np.all(np.isnan(g["x"][off])) and np.all(g["throughput"][off] == 0)

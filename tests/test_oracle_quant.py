@@ -1,5 +1,6 @@
 """Pins for the oracle's reduced-precision network (oracle/mlp.py:
-forward_quantized, forward_quantized_cache, backward_quantized), which every
+forward_quantized in its BF16 evaluation (folded for tanh), BF16 training
+and FP8 forms, forward_quantized_cache, backward_quantized), which every
 BF16 / FP8 parity test of the GPU kernels is measured against.
 
 Three kinds of pin, none of which reuses the oracle's rounding code:
@@ -11,7 +12,10 @@ Three kinds of pin, none of which reuses the oracle's rounding code:
     summation order;
   * special cases with a plain definition: with BF16-exact (and FP8-exact)
     parameters and inputs the split terms vanish and the network is the FP64
-    network with every activation rounded exactly once;
+    network with every activation rounded exactly once; for the folded BF16
+    evaluation of a tanh map, with weights whose folded copies are BF16-exact,
+    it is the FP64 tanh network in which every hidden value passes through
+    r = (1 - tanh z) / 2 rounded exactly once;
   * the accuracy the split layers promise: hi + lo BF16 inputs and weights
     reproduce the exact layer to 3.1 * 2^-16 of the sum of |x_i W_ji|, split
     weights on BF16 activations to 2.1 * 2^-16 of it (the dropped terms
@@ -76,9 +80,63 @@ def act(z, kind):
 
 # --------------------------------------------- scalar-loop references ----
 
+K2 = float(np.float32(2.0 / math.log(2.0)))   # 2 log2 e as an FP32 number
+
+
+def f32mul(a, b):
+    """a * b with FP32 operands and one FP32 rounding."""
+    return float(np.float32(np.float32(a) * np.float32(b)))
+
+
+def loop_forward_folded(p, x):
+    """One ray through the BF16 evaluation of a tanh map, neuron by neuron:
+    every hidden value is r = (1 - tanh z) / 2, rounded once; the layers
+    carry k = 2 log2 e and the map h = 1 - 2 r (u = k z, r = 1 / (1 + 2^u)),
+    with each folded weight, k W0 (split hi + lo) and BF16(-2 k W), and each
+    k b formed in FP32 as the packer forms them."""
+    L = len(p.W)
+    x_hi = bf(x)
+    x_lo = bf(x - x_hi)
+    kW0 = np.vectorize(lambda w: f32mul(w, K2))(p.W[0])
+    W0_hi = bf(kW0)
+    W0_lo = bf(kW0 - W0_hi)
+    u = []
+    for j in range(p.W[0].shape[0]):
+        s = f32mul(p.b[0][j], K2)
+        for i in range(6):
+            s += x_hi[i] * W0_hi[j, i] + x_lo[i] * W0_hi[j, i] + x_hi[i] * W0_lo[j, i]
+        u.append(s)
+    r = bf(np.array([(1.0 - math.tanh(v / K2)) / 2.0 for v in u]))
+    for li in range(1, L - 1):
+        W = p.W[li]
+        un = []
+        for j in range(W.shape[0]):
+            # k (sum_i W'_ji (1 - 2 r_i) + b_j) with W'_ji = BF16(-2 k W_ji) / (-2 k)
+            s = f32mul(p.b[li][j], K2)
+            for i in range(W.shape[1]):
+                wq = bf(f32mul(W[j, i], -2.0 * K2))
+                s += wq * r[i] - 0.5 * wq
+            un.append(s)
+        r = bf(np.array([(1.0 - math.tanh(v / K2)) / 2.0 for v in un]))
+    Wo = p.W[L - 1]
+    Wo_hi = bf(Wo)
+    Wo_lo = bf(Wo - Wo_hi)
+    o = []
+    for k in range(Wo.shape[0]):
+        s = p.b[L - 1][k]
+        for j in range(Wo.shape[1]):
+            s += (1.0 - 2.0 * r[j]) * (Wo_hi[k, j] + Wo_lo[k, j])
+        o.append(s)
+    return np.array(o)
+
+
 def loop_forward(p, x, mode):
-    """One ray through the quantised network, neuron by neuron."""
+    """One ray through the quantised network, neuron by neuron.  mode "bf16"
+    is the BF16 evaluation (folded for tanh maps), "bf16_train" the training
+    forward, "fp8" the FP8 evaluation."""
     kind = p.desc.activation
+    if mode == "bf16" and kind == mlp.ACT_TANH:
+        return loop_forward_folded(p, x)
     L = len(p.W)
     x_hi = bf(x)
     x_lo = bf(x - x_hi)
@@ -199,7 +257,7 @@ def inputs(n, seed):
 
 # --------------------------------------------------------------- pins ----
 
-def pin_forward_loops(modes=("bf16", "fp8")):
+def pin_forward_loops(modes=("bf16", "bf16_train", "fp8")):
     for mode in modes:
         for kind in (mlp.ACT_TANH, mlp.ACT_RELU):
             p = net(act_kind=kind, seed=3 + kind)
@@ -222,7 +280,7 @@ def pin_exact_parameters_round_once():
             p.W[li] = bf(p.W[li])
             p.b[li] = bf(p.b[li])
         X = bf(inputs(20, 12))
-        o = mlp.forward_quantized(p, X, "bf16")
+        o = mlp.forward_quantized(p, X, "bf16_train")
         for r in range(X.shape[0]):
             h = X[r]
             for li in range(len(p.W)):
@@ -244,6 +302,71 @@ def pin_exact_parameters_round_once():
             h = bf(np.array([act(v, kind) for v in z]))
             ref = q.W[-1] @ h + q.b[-1]   # BF16-exact output weights: no lo part
             assert np.allclose(o8[r], ref, rtol=0, atol=1e-12), ("fp8", kind, r)
+
+
+def pin_folded_round_once():
+    """BF16 evaluation of a tanh map with weights and inputs chosen so that
+    every folded copy is exact (k W0, k b and BF16(-2 k W) equal their FP64
+    products, split parts vanish): the network is the FP64 tanh network in
+    which every hidden value h = tanh z is replaced by 1 - 2 BF16((1 - h) / 2),
+    the output layer taking h in that form."""
+    p = net(seed=61)
+    # weights w = q / (-2 k) for q on a coarse binary grid, so that
+    # FP32(w * (-2 k)) == q exactly (the grid is checked, not assumed)
+    rng = np.random.default_rng(62)
+    for li in range(len(p.W)):
+        q = rng.integers(-8, 9, p.W[li].shape) / 8.0
+        W = np.float32(q) / np.float32(-2.0 * K2)
+        W = W.astype(np.float64)
+        back = np.vectorize(lambda w: f32mul(w, -2.0 * K2))(W)
+        keep = (back == q) & (np.vectorize(lambda w: f32mul(w, K2))(W) == -q / 2)
+        p.W[li] = np.where(keep, W, 0.0)
+        qb = rng.integers(-8, 9, p.b[li].shape) / 8.0
+        b = (np.float32(qb) / np.float32(K2)).astype(np.float64)
+        okb = np.vectorize(lambda v: f32mul(v, K2))(b) == qb
+        p.b[li] = np.where(okb, b, 0.0)
+    # the output layer splits its weights: make them BF16-exact
+    p.W[-1] = bf(p.W[-1])
+    p.W[-1] = np.where(bf(p.W[-1] - bf(p.W[-1])) == 0, p.W[-1], 0.0)
+    X = bf(inputs(20, 63))
+    o = mlp.forward_quantized(p, X, "bf16")
+    for r_i in range(X.shape[0]):
+        h = X[r_i]
+        for li in range(len(p.W)):
+            z = p.W[li] @ h + p.b[li]
+            if li < len(p.W) - 1:
+                rq = bf(np.array([(1.0 - math.tanh(v)) / 2.0 for v in z]))
+                h = 1.0 - 2.0 * rq
+            else:
+                h = z
+        assert np.allclose(o[r_i], h, rtol=0, atol=1e-12), ("folded", r_i, np.abs(o[r_i] - h).max())
+
+
+def pin_scale_is_an_fp32_product():
+    """The folded weights are FP32 products (the packer multiplies FP32 values
+    in FP32): the oracle's products equal torch's FP32 multiplication, which
+    differs from the FP64 product on most of these values."""
+    rng = np.random.default_rng(81)
+    a = rng.normal(0, 3, 5000)
+    for sc in (mlp.K_TANH, -2.0 * mlp.K_TANH):
+        ref = (torch.from_numpy(a.astype(np.float32)) * torch.tensor(sc, dtype=torch.float32)).double().numpy()
+        assert np.array_equal(mlp.scale_f32(a, sc), ref)
+        assert np.mean(ref != a.astype(np.float32).astype(np.float64) * sc) > 0.5
+
+
+def pin_folded_close_to_unfolded():
+    """The folded and unfolded BF16 evaluations of one tanh network differ
+    only by where BF16 rounds (r instead of tanh z, BF16(-2 k W) instead of
+    BF16(W)): both stay within BF16 accuracy of the FP64 network and of each
+    other, while a dropped bias correction or a missing factor would not."""
+    p = net(seed=71, width=32, depth=4, heads=2)
+    X = inputs(400, 72)
+    o64, _ = mlp.forward(p, X)
+    of = mlp.forward_quantized(p, X, "bf16")
+    ou = mlp.forward_quantized(p, X, "bf16_train")
+    scale = np.abs(o64).max()
+    assert np.abs(of - o64).max() < 0.05 * scale and np.abs(ou - o64).max() < 0.05 * scale
+    assert np.abs(of - ou).max() < 0.05 * scale
 
 
 def pin_split_layer_accuracy():
@@ -268,7 +391,7 @@ def pin_training_forward():
     p = net(seed=31)
     X = inputs(50, 32)
     o, (x_hi, x_lo, hs) = mlp.forward_quantized_cache(p, X)
-    assert np.array_equal(o, mlp.forward_quantized(p, X, "bf16"))
+    assert np.array_equal(o, mlp.forward_quantized(p, X, "bf16_train"))
     assert len(hs) == p.desc.depth and all(np.array_equal(h, bf(h)) for h in hs)
 
 
@@ -285,7 +408,8 @@ def pin_backward_loops():
             assert np.allclose(gb, rb, rtol=0, atol=1e-12 * max(1.0, np.abs(rb).max())), (kind, li, "b")
 
 
-ALL_PINS = (pin_forward_loops, pin_exact_parameters_round_once, pin_split_layer_accuracy,
+ALL_PINS = (pin_forward_loops, pin_exact_parameters_round_once, pin_folded_round_once,
+            pin_scale_is_an_fp32_product, pin_folded_close_to_unfolded, pin_split_layer_accuracy,
             pin_training_forward, pin_backward_loops)
 
 
@@ -368,13 +492,45 @@ def _transpose_unrounded(W):
     return W
 
 
+def _folded_act_unrounded(u):
+    return 1.0 / (1.0 + np.exp2(u))
+
+
+def _folded_act_natural_exp(u):
+    return mlp.round_bf16(1.0 / (1.0 + np.exp(u)))
+
+
+def _folded_hidden_no_bias_correction(r, W, b):
+    Wq = mlp.round_bf16(mlp.scale_f32(W, -2.0 * mlp.K_TANH))
+    return r @ Wq.T + mlp.scale_f32(b, mlp.K_TANH)
+
+
+def _folded_hidden_unrounded_weights(r, W, b):
+    Wq = mlp.scale_f32(W, -2.0 * mlp.K_TANH)
+    return r @ Wq.T + mlp.scale_f32(b, mlp.K_TANH) - 0.5 * Wq.sum(1)
+
+
+def _folded_output_no_bias_correction(r, Wo, bo):
+    W_hi, W_lo = mlp.split_bf16(Wo)
+    return r @ (-2.0 * W_hi).T + r @ (-2.0 * W_lo).T + bo
+
+
+def _scale_f64(a, s):
+    return np.asarray(a, np.float64) * s
+
+
 MUTANTS = [("input_layer_split", _input_drop_xlo), ("input_layer_split", _input_drop_wlo),
            ("input_layer_split", _input_no_split), ("output_layer_split", _output_drop_wlo),
            ("activation_bf16", _activation_round_z_too), ("activation_bf16", _activation_unrounded),
            ("hidden_layer_bf16", _hidden_unrounded_weights), ("hidden_layer_fp8", _fp8_double_rounding),
            ("hidden_layer_fp8", _fp8_unscaled_weights), ("output_grad_split", _grad_no_split),
            ("hidden_grad_bf16", _grad_unrounded), ("hidden_grad_bf16", _grad_wrong_derivative),
-           ("transpose_weights_bf16", _transpose_unrounded)]
+           ("transpose_weights_bf16", _transpose_unrounded),
+           ("activation_folded_bf16", _folded_act_unrounded),
+           ("activation_folded_bf16", _folded_act_natural_exp),
+           ("hidden_layer_folded_bf16", _folded_hidden_no_bias_correction),
+           ("hidden_layer_folded_bf16", _folded_hidden_unrounded_weights),
+           ("output_layer_folded", _folded_output_no_bias_correction), ("scale_f32", _scale_f64)]
 
 
 @pytest.mark.skipif(not hasattr(torch, "float8_e4m3fn"), reason="torch without float8_e4m3fn")
