@@ -182,11 +182,19 @@ __host__ __device__ __forceinline__ RayOut trace_one_ff(const TraceTable &T, flo
                 qz = dw_add_f(qz, dt * dz.h);
             }
         }
-        // clear aperture (closed disk), decided in double-word
+        // clear aperture (closed disk): an FP32 test decides every ray whose
+        // squared height is further than 1e-5 (relative) from the edge (its
+        // error is a few ulps); the rest, and NaN, are decided in double-word
         {
-            const ff m = dw_sub(dw_add(dw_sqr(qx), dw_sqr(qy)), ff{G.sd2_h, G.sd2_l});
-            if (!(ff_to_f(m) <= 0.0f))  // also rejects NaN
-                return o;
+            const float mf = fmaf(qx.h, qx.h, fmaf(qy.h, qy.h, -G.sd2_h));
+            if (fabsf(mf) > 1.0e-5f * G.sd2_h) {
+                if (mf > 0.0f)
+                    return o;
+            } else {
+                const ff m = dw_sub(dw_add(dw_sqr(qx), dw_sqr(qy)), ff{G.sd2_h, G.sd2_l});
+                if (!(ff_to_f(m) <= 0.0f))  // also rejects NaN
+                    return o;
+            }
         }
         px = dw_norm(qx);
         py = dw_norm(qy);
@@ -206,7 +214,7 @@ __host__ __device__ __forceinline__ RayOut trace_one_ff(const TraceTable &T, flo
         const ff ci = ff_neg(dn);
         const ff n2 = g2 == kAirCode ? ff_make(1.0f) : glass_n_ff(T.glass[g2], l2, il2);
         const ff n1 = ncur;
-        const ff eta = dw_div(n1, n2);
+        const ff eta = g2 == kAirCode ? n1 : dw_div(n1, n2);   // into air: n1 / 1
         const ff sin2 = dw_sub(ff_make(1.0f), dw_sqr(ci));
         const ff k = dw_sub(ff_make(1.0f), dw_mul(dw_sqr(eta), sin2));
         const bool tir = ff_to_f(k) < 0.0f;
