@@ -339,9 +339,10 @@ lt_status lt_mcmc_run(lt_lens lens, const lt_path *path, const lt_mcmc_cfg *cfg,
  * that contains the vertex, clear-aperture clipping (closed disk), vector
  * Snell refraction or mirror reflection, and the unpolarised Fresnel factor;
  * TIR on a transmit step kills the ray, on a reflect step reflects all of it.
- * All arithmetic is FP32 instructions: geometry is carried as compensated
- * float pairs (about 44 significant bits) so exit positions stay within
- * 1e-5 mm of the exact trace; Fresnel factors are plain FP32.
+ * All arithmetic is FP32 instructions: geometry is carried as double-words
+ * (pairs of floats, unnormalised between interactions, well over 40
+ * significant bits in absolute terms) so exit positions stay within 1e-5 mm
+ * of the exact trace; Fresnel factors are plain FP32.
  * Errors: LT_ERR_ARG (NULL handle/pointers with n > 0, n < 0),
  * LT_ERR_PATH, LT_ERR_DEVICE (launch failure). */
 lt_status lt_trace(lt_lens lens, const lt_path *path, const lt_rays *rays,

@@ -22,10 +22,9 @@
 //                     near-flat surfaces and the transmitted cosine near
 //                     grazing incidence.
 //   trace_one_f64  -- the same operators in FP64, an option outside the
-//                     FP32 form of the tracer: gfx950 runs FP64 vector
-//                     arithmetic at half its FP32 rate, so this takes about
-//                     half the float-pair variant's time and returns the
-//                     FP32 roundings of FP64 results.
+//                     FP32 form of the tracer (gfx950 runs FP64 vector
+//                     arithmetic at half its FP32 rate); it returns the FP32
+//                     roundings of FP64 results.
 #pragma once
 
 #include <hip/hip_runtime.h>
