@@ -536,8 +536,9 @@ __global__ __launch_bounds__((eval_waves<H, TRAIN>() * 64)) void map_eval_bf16_k
             // per workgroup pass (cmp_copy).  The logit tiles give lane k head
             // k's mask bits for the wave's rays; the reservation runs on the
             // first two field tiles' barriers; a head block's entries are
-            // stored after the next tile's barrier, so that barrier waits for
-            // no store.
+            // stored after the next tile's barrier, before its MFMAs, and the
+            // barrier after that waits for them (vector memory operations
+            // complete in order, so its wait for the tile copy includes them).
             const float *cb = cmp_consts;
             uint8_t *agg = lds + A.cmp.agg;
             const bool more = tbase + static_cast<int64_t>(gridDim.x) * kWaves < n_tiles;

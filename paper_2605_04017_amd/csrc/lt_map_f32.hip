@@ -204,8 +204,8 @@ constexpr int kF32NT = 2;
 // whose signs give lane k head k's mask bits for the wave's rays, then one
 // stage per 16-head block with its five field tiles; the reservation runs on
 // the first two block stages' barriers, and a block's entries are stored
-// after the next stage's barrier, so that the barrier does not wait for the
-// stores.
+// after the next stage's barrier, before that stage's MFMAs, which cover the
+// stores' completion before the following barrier waits for them.
 template <int H, int ACT, bool CMP>
 __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args A, lt_rays rays,
                                                                       lt_map_out out)
