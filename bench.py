@@ -265,8 +265,8 @@ def paper_pair(lt, synth, lens, dev, steps, rays, batch=65536, seed=3003,
 
 def paper_recipe(lt, synth, dev, path=(1, 2, 10), n_valid=81_000_000, epochs=40, batch=8192,
                  uniform_steps=3000, n_eval=1 << 20, seed=3301, w_cos=200.0):
-    """The paper's training recipe (Sec. 5.1) against this build's default
-    for one ghost path of the 11-surface lens, at the paper's network size
+    """The paper's training recipe (Sec. 5.1) against the library's default
+    short fit for one ghost path of the 11-surface lens, at the paper's network size
     (classifier 2 x 32, BCE; regressor 5 x 32, MSE + cosine direction loss):
     - paper: the regressor on n_valid rays (81 M by default, the paper's
       count per path) uniform over the path's valid region from the
