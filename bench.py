@@ -1285,8 +1285,10 @@ def main():
                    "rays": n, "paths": P,
                    "map": "6-D canonical input, 5 x 128 tanh, 56 heads (mask logit + x, y, dx, dy, "
                           f"throughput each), fitted for {args.fit_steps} steps of 65,536 GPU-traced rays"},
-        "value_note": "map ray-path evaluations per second (rays x paths); map_over_trace compares with "
-                      "each tracer variant that holds 1e-5 mm / 1e-6 rad against the FP64 oracle",
+        "value_note": "map ray-path evaluations per second (rays x paths), FP32 map; map_over_trace compares "
+                      "with each tracer variant that holds 1e-5 mm / 1e-6 rad against the FP64 oracle; the "
+                      "BF16 and FP8 maps of the same workload: all_paths_16M (map_over_trace, "
+                      "map_error_vs_gpu_tracer and roofline_by_dtype per dtype)",
         "map_over_trace": A["map_over_trace"]["f32"],
         "roofline": {"bound": "mfma", "achieved": rl["achieved"], "peak": rl["peak"], "unit": "TFLOP/s",
                      "frac": rl["frac"], "traffic": traffic,
