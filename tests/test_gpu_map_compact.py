@@ -93,6 +93,12 @@ def check_against_full(full, c, n, P, block, cap=None, with_dz=True):
     (64, 4, 2, 0, 0, 0, 7777),
     (32, 2, 3, 1, 1, 1, 20001),
     (32, 5, 17, 0, 0, 1, 5003),
+    # the most heads a map takes: four full head blocks, every lane of the
+    # reservation arrays in use
+    (128, 5, 64, 1, 1, 0, 20011),
+    (128, 5, 64, 2, 0, 0, 9001),
+    (128, 5, 64, 0, 1, 0, 6007),
+    (64, 3, 64, 1, 0, 0, 5003),
 ])
 def test_compact_matches_eval(dev, width, depth, heads, dtype, canonical, forward, n):
     import torch
