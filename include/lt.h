@@ -529,6 +529,35 @@ lt_status lt_map_eval(lt_map map, int32_t dtype, const lt_rays *rays, const lt_m
 lt_status lt_map_eval_ex(lt_map map, int32_t dtype, const lt_rays *rays, const lt_map_out *out,
                          int64_t n, uint32_t flags, const uint8_t *mask_in, void *stream);
 
+/* The paper's factorised form evaluated where the classifier says valid
+ * (Sec. 4.2, "Neural Ray Masking": the regressor's output is needed only
+ * where g(x) = 1), in two calls:
+ *
+ * lt_mask_index: the dense list of the set entries of mask[0, n) (device
+ * uint8, e.g. a classifier's out->mask from LT_EVAL_MASK_ONLY): entry k of
+ * idx (device int32, k < min(*count, capacity)) is the index of a set entry;
+ * entries from one block of 256 keep their order, blocks land in any order.
+ * *count (device int64) is the number of set entries, cleared by a kernel on
+ * the stream and counted even beyond capacity.  n = 0 writes a zero count.
+ * Errors: LT_ERR_ARG (NULL count; NULL mask with n > 0; NULL idx with
+ * capacity > 0; n outside 0 .. 2^31 - 1; negative capacity), LT_ERR_DEVICE. */
+lt_status lt_mask_index(const uint8_t *mask, int64_t n, int32_t *idx, int64_t capacity, int64_t *count,
+                        void *stream);
+
+/* lt_map_eval_indexed: a one-head map (the regressor) on the rays listed in
+ * idx: entry k < min(*count, max_n) evaluates ray idx[k] of `rays` and writes
+ * its exit fields x, y, dx, dy, dz and throughput at index k of out (arrays
+ * of max_n), exactly the values lt_map_eval writes for that ray; out->logit
+ * and out->mask are not touched (may be NULL).  count (device int64, e.g.
+ * lt_mask_index's) may be NULL: then max_n entries.  The caller guarantees
+ * that every listed index addresses a ray of `rays`.  The work scales with
+ * the listed rays, not with the batch.  Errors: LT_ERR_ARG (NULL map, rays,
+ * out field, or idx with max_n > 0; a map with more than one head; max_n
+ * outside 0 .. 2^31 - 1), LT_ERR_DTYPE, LT_ERR_STATE (parameters never
+ * set), LT_ERR_DEVICE. */
+lt_status lt_map_eval_indexed(lt_map map, int32_t dtype, const lt_rays *rays, const int32_t *idx,
+                              const int64_t *count, int64_t max_n, const lt_map_out *out, void *stream);
+
 /* Compacted outputs of lt_map_eval_compact, per head p = 0 .. n_heads - 1
  * (device buffers owned by the caller): */
 typedef struct {

@@ -36,7 +36,8 @@ __all__ = ["LtError", "Lens", "lt_lens_create", "lt_lens_query", "lt_lens_paraxi
            "lt_map_quantize", "lt_rays_generate", "lt_map_eval_ex", "LT_EVAL_MASK_ONLY",
            "lt_lens_planes", "LT_TRACE_FORWARD", "LT_TRACE_FP64", "lt_rays_generate_forward", "lt_splat",
            "LT_LAMBDA_UNIFORM", "LT_LAMBDA_CIE", "mcmc_state", "lt_mcmc_init", "lt_mcmc_run",
-           "LT_EVAL_GATED", "Server", "LT_ERR_ARG", "LT_ERR_STATE", "train_sched", "set_train_sched", "lt_map_mark_updated"]
+           "LT_EVAL_GATED", "Server", "LT_ERR_ARG", "LT_ERR_STATE", "train_sched", "set_train_sched", "lt_map_mark_updated",
+           "lt_mask_index", "lt_map_eval_indexed"]
 
 TARGET_FIELDS = ("valid", "x", "y", "dx", "dy", "throughput")
 
@@ -659,6 +660,52 @@ def lt_map_eval_ex(m: Map, dtype: int, rays: Dict, out: Optional[Dict] = None,
     N.check(N.lib().lt_map_eval_ex(m.handle, int(dtype), C.byref(_rays_struct(rays, n)), C.byref(o),
                                    int(n), int(flags), C.c_void_p(mp),
                                    C.c_void_p(_stream_ptr(stream) if n else 0)))
+    return out
+
+
+def lt_mask_index(mask, n: Optional[int] = None, capacity: Optional[int] = None, idx=None, count=None,
+                  stream=None):
+    """Dense list of the set entries of a uint8 mask (lt_mask_index), e.g. a
+    classifier's mask: returns (idx int32 [capacity], count int64 [1]);
+    entries past min(count, capacity) are not written."""
+    torch = _torch()
+    flat = mask.reshape(-1)
+    if n is None:
+        n = int(flat.numel())
+    if capacity is None:
+        capacity = n
+    if idx is None:
+        idx = torch.empty(max(capacity, 1), dtype=torch.int32, device=flat.device)
+    if count is None:
+        count = torch.empty(1, dtype=torch.int64, device=flat.device)
+    mp = _dev_ptr(flat, torch.uint8, n, "mask") if n else None
+    ip = _dev_ptr(idx, torch.int32, capacity, "idx") if capacity else None
+    cp = _dev_ptr(count, torch.int64, 1, "count")
+    N.check(N.lib().lt_mask_index(C.c_void_p(mp), int(n), C.c_void_p(ip), int(capacity), C.c_void_p(cp),
+                                  C.c_void_p(_stream_ptr(stream))))
+    return idx, count
+
+
+def lt_map_eval_indexed(m: Map, dtype: int, rays: Dict, idx, count=None, max_n: Optional[int] = None,
+                        out: Optional[Dict] = None, stream=None) -> Dict:
+    """A one-head map on the listed rays (lt_map_eval_indexed): entry k below
+    min(count, max_n) evaluates ray idx[k] and its exit fields land at k of
+    the (1, max_n) outputs; ``count`` (int64 [1] on the device) may be None."""
+    torch = _torch()
+    if max_n is None:
+        max_n = int(idx.numel())
+    wanted = MAP_FIELDS[2:]
+    if out is None:
+        out = {k: torch.empty((1, max(max_n, 1)), dtype=torch.float32, device=rays["x"].device) for k in wanted}
+    o = N.lt_map_out()
+    for k in MAP_FIELDS:
+        setattr(o, k, _dev_ptr(out[k], torch.float32, max_n, f"out[{k}]") if (k in wanted and max_n) else None)
+    n_rays = int(rays["x"].numel())
+    ip = _dev_ptr(idx, torch.int32, max_n, "idx") if max_n else None
+    cp = _dev_ptr(count, torch.int64, 1, "count") if count is not None else None
+    N.check(N.lib().lt_map_eval_indexed(m.handle, int(dtype), C.byref(_rays_struct(rays, n_rays)), C.c_void_p(ip),
+                                        C.c_void_p(cp), int(max_n), C.byref(o),
+                                        C.c_void_p(_stream_ptr(stream) if max_n else 0)))
     return out
 
 

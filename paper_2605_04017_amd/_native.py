@@ -149,6 +149,9 @@ SIGNATURES = {
                                  C.c_int64, C.c_uint32, C.c_void_p, C.c_void_p]),
     "lt_map_eval_compact": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(lt_rays),
                                       C.POINTER(lt_map_compact), C.c_int64, C.c_void_p]),
+    "lt_mask_index": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "lt_map_eval_indexed": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(lt_rays), C.c_void_p, C.c_void_p,
+                                      C.c_int64, C.POINTER(lt_map_out), C.c_void_p]),
     "lt_rays_generate": (C.c_int, [C.c_void_p, C.POINTER(lt_raygen), C.POINTER(lt_ray_buffers),
                                    C.c_int64, C.c_void_p]),
     "lt_rays_generate_forward": (C.c_int, [C.c_void_p, C.POINTER(lt_raygen_forward),

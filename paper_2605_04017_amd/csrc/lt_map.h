@@ -80,8 +80,15 @@ Map *as_map(lt_map h);
 MapLayout make_layout(const lt_map_desc &d);
 int64_t wt_bytes(const MapLayout &L);
 int64_t f32_image_bytes(const MapLayout &L);
+// Indexed evaluation (lt_map_eval_indexed): entry k evaluates ray in_idx[k],
+// for k below min(*n_dev, n); n_dev may be null.
+struct EvalIndex {
+    const int32_t *in_idx;
+    const int64_t *n_dev;
+};
+
 lt_status eval_f32(Map &M, const lt_rays &rays, const lt_map_out &out, int64_t n, uint32_t flags,
-                   const uint8_t *mask_in, hipStream_t s);
+                   const uint8_t *mask_in, hipStream_t s, const EvalIndex *ix = nullptr);
 lt_status ensure_packed_f32(Map &M, hipStream_t s);
 struct MapCompact;
 lt_status eval_f32_compact(Map &M, const lt_rays &rays, const MapCompact &C, int64_t n, hipStream_t s);

@@ -338,7 +338,9 @@ __global__ __launch_bounds__((eval_waves<H, TRAIN>() * 64)) void map_eval_bf16_k
     // compacted evaluation, which stages only the input and hidden layers
     const float *nrm = (CMP ? reinterpret_cast<const float *>(A.img + A.img_bias) : bias) + A.D * H + 16 * A.TO;
     const uint8_t *out_frag = A.out_from_lds ? lds + A.img_out : A.img + A.img_out;
-    const int64_t n = A.n;
+    // indexed evaluation: plain (uncompacted) evaluation only
+    constexpr bool kIdx = !CMP && !TRAIN;
+    const int64_t n = kIdx ? eval_count(A.n, A.n_dev) : A.n;
     const int64_t n_tiles = TRAIN ? A.n_pad / RPW : (n + RPW - 1) / RPW;
     // Phase offset (BF16 evaluation at width 128 with the output layer resident in LDS):
     // the two waves of a SIMD alternate between a layer's MFMAs and the other
@@ -389,12 +391,13 @@ __global__ __launch_bounds__((eval_waves<H, TRAIN>() * 64)) void map_eval_bf16_k
             const int64_t r = ray0 + nt * 16 + col;
             float f[6] = {0, 0, 0, 0, 0, 0};
             if (r < n) {
-                f[0] = rays.x[r];
-                f[1] = rays.y[r];
-                f[2] = rays.dx[r];
-                f[3] = rays.dy[r];
-                f[4] = rays.dz[r];
-                f[5] = rays.lambda_nm[r];
+                const int64_t ri = kIdx ? eval_ray(A.in_idx, r) : r;
+                f[0] = rays.x[ri];
+                f[1] = rays.y[ri];
+                f[2] = rays.dx[ri];
+                f[3] = rays.dy[ri];
+                f[4] = rays.dz[ri];
+                f[5] = rays.lambda_nm[ri];
             }
             fr[nt] = CanonFrame{1.0f, 0.0f, 1.0f};
             if (A.canonical) {
@@ -677,7 +680,7 @@ __global__ __launch_bounds__((eval_waves<H, TRAIN>() * 64)) void map_eval_bf16_k
                     const int64_t idx = static_cast<int64_t>(head) * n + r;
                     const float logit = w[0];
                     const bool gated = (A.flags & LT_EVAL_GATED) != 0;
-                    const bool m = gated ? A.mask_in[idx] != 0 : logit > 0.0f;
+                    const bool m = gated ? (!A.mask_in || A.mask_in[idx] != 0) : logit > 0.0f;
                     if (!gated) {
                         out.logit[idx] = logit;
                         out.mask[idx] = m ? 1 : 0;
@@ -746,6 +749,41 @@ __global__ void zero_counts_kernel(unsigned long long *count, int P)
 {
     if (static_cast<int>(threadIdx.x) < P)
         count[threadIdx.x] = 0ull;
+}
+
+// Dense list of the set entries of mask[0, n) (a classifier's mask, Sec. 4.2):
+// per block of 256 entries a wave ballot counts the set ones, one atomic add
+// on *count reserves the block's range, and each set entry writes its index
+// there.  Entries of one block keep their order; blocks land in any order.
+__global__ __launch_bounds__(256) void mask_index_kernel(const uint8_t *__restrict__ mask, int64_t n,
+                                                         int32_t *__restrict__ idx, int64_t cap,
+                                                         unsigned long long *count)
+{
+    __shared__ unsigned wave_cnt[4];
+    __shared__ unsigned long long blk_base;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int64_t b0 = static_cast<int64_t>(blockIdx.x) * 256; b0 < n; b0 += static_cast<int64_t>(gridDim.x) * 256) {
+        const int64_t r = b0 + threadIdx.x;
+        const bool v = r < n && mask[r] != 0;
+        const uint64_t bal = __ballot(v);
+        if (lane == 0)
+            wave_cnt[wave] = static_cast<unsigned>(__popcll(bal));
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned tot = wave_cnt[0] + wave_cnt[1] + wave_cnt[2] + wave_cnt[3];
+            blk_base = tot ? atomicAdd(count, static_cast<unsigned long long>(tot)) : 0ull;
+        }
+        __syncthreads();
+        unsigned pre = 0;
+        for (int w = 0; w < wave; ++w)
+            pre += wave_cnt[w];
+        if (v) {
+            const int64_t pos = static_cast<int64_t>(blk_base) + pre + __popcll(bal & ((1ull << lane) - 1ull));
+            if (pos < cap)
+                idx[pos] = static_cast<int32_t>(r);
+        }
+        __syncthreads();  // wave_cnt and blk_base are rewritten by the next block
+    }
 }
 
 static int g_num_cus = 0;
@@ -1151,6 +1189,72 @@ lt_status lt_map_eval(lt_map map, int32_t dtype, const lt_rays *rays, const lt_m
                       int64_t n, void *stream)
 {
     return lt_map_eval_ex(map, dtype, rays, out, n, 0u, nullptr, stream);
+}
+
+lt_status lt_mask_index(const uint8_t *mask, int64_t n, int32_t *idx, int64_t capacity, int64_t *count,
+                        void *stream)
+{
+    if (!count || (n > 0 && !mask) || (capacity > 0 && !idx))
+        return fail(LT_ERR_ARG, "NULL mask, idx or count");
+    if (n < 0 || n > 0x7fffffffLL)
+        return fail(LT_ERR_ARG, "entry count must be in 0 .. 2^31 - 1 (32-bit indices)");
+    if (capacity < 0)
+        return fail(LT_ERR_ARG, "negative capacity");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    unsigned long long *cnt = reinterpret_cast<unsigned long long *>(count);
+    hipLaunchKernelGGL(zero_counts_kernel, dim3(1), dim3(64), 0, s, cnt, 1);
+    lt_status st = check_hip(hipGetLastError(), "zero_counts_kernel launch");
+    if (st != LT_OK || n == 0)
+        return st;
+    const int64_t blocks = (n + 255) / 256;
+    const int grid = static_cast<int>(blocks < 4 * num_cus() ? blocks : 4 * num_cus());
+    hipLaunchKernelGGL(mask_index_kernel, dim3(grid), dim3(256), 0, s, mask, n, idx, capacity, cnt);
+    return check_hip(hipGetLastError(), "mask_index_kernel launch");
+}
+
+lt_status lt_map_eval_indexed(lt_map map, int32_t dtype, const lt_rays *rays, const int32_t *idx,
+                              const int64_t *count, int64_t max_n, const lt_map_out *out, void *stream)
+{
+    Map *M = as_map(map);
+    if (!M || !rays || !out || (max_n > 0 && !idx))
+        return fail(LT_ERR_ARG, "NULL map, rays, idx or out");
+    if (max_n < 0 || max_n > 0x7fffffffLL)
+        return fail(LT_ERR_ARG, "max_n must be in 0 .. 2^31 - 1");
+    if (M->lay.P != 1)
+        return fail(LT_ERR_ARG, "indexed evaluation takes one-head maps");
+    if (dtype != LT_BF16 && dtype != LT_FP8 && dtype != LT_F32)
+        return fail(LT_ERR_DTYPE, "precision not available (LT_F32, LT_BF16, LT_FP8)");
+    if (dtype == LT_FP8 && !M->lay.fp8_ok)
+        return fail(LT_ERR_DTYPE, "LT_FP8 needs width 128 and tanh");
+    if (max_n == 0)
+        return LT_OK;
+    if (!M->has_params)
+        return fail(LT_ERR_STATE, "parameters were never set");
+    if (!rays->x || !rays->y || !rays->dx || !rays->dy || !rays->dz || !rays->lambda_nm)
+        return fail(LT_ERR_ARG, "NULL ray field");
+    if (!out->x || !out->y || !out->dx || !out->dy || !out->dz || !out->throughput)
+        return fail(LT_ERR_ARG, "NULL output field");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // the regressor half of LT_EVAL_GATED with every listed ray valid
+    const EvalIndex ix{idx, count};
+    EvalArgs A{};
+    A.n = max_n;
+    A.flags = LT_EVAL_GATED;
+    A.mask_in = nullptr;
+    A.in_idx = idx;
+    A.n_dev = count;
+    if (dtype == LT_F32)
+        return eval_f32(*M, *rays, *out, max_n, LT_EVAL_GATED, nullptr, s, &ix);
+    if (dtype == LT_FP8) {
+        lt_status st = ensure_packed_fp8(*M, s);
+        if (st != LT_OK)
+            return st;
+        return launch_bf16_impl<128, LT_ACT_TANH, false, true>(*M, *rays, *out, A, s);
+    }
+    lt_status st = ensure_packed_bf16(*M, s);
+    if (st != LT_OK)
+        return st;
+    return launch_map_forward<false>(*M, *rays, *out, A, s);
 }
 
 lt_status lt_map_eval_compact(lt_map map, int32_t dtype, const lt_rays *rays,

@@ -189,8 +189,12 @@ struct EvalArgs {
     float dz_sign;        // sign of the decoded exit dz: -1 sensor-side map, +1 forward map
     float *canon_out;     // training forward: [3][n_pad] frame (c, s, sg) per ray, or null
     uint32_t flags;       // LT_EVAL_MASK_ONLY / LT_EVAL_GATED
-    const uint8_t *mask_in;  // LT_EVAL_GATED: [P][n] validity from a classifier
+    const uint8_t *mask_in;  // LT_EVAL_GATED: [P][n] validity from a classifier (null: all valid)
     int64_t n;
+    // indexed evaluation (one head): entry k evaluates ray in_idx[k], for k
+    // below min(*n_dev, n) (n_dev may be null); null in_idx: entry k is ray k
+    const int32_t *in_idx;
+    const int64_t *n_dev;
     // training forward only
     float *xhat_out;      // [6][n_pad]
     uint8_t *hfrag_out;   // [D][n_pad/16][C][64 lanes][16 B] BF16 activation fragments
@@ -304,7 +308,7 @@ __device__ __forceinline__ void decode_store(floatx4 v, int to, int g, int64_t r
     const bool gated = (flags & LT_EVAL_GATED) != 0, fields = (flags & LT_EVAL_MASK_ONLY) == 0;
     if (even) {
         const float logit = v[0];
-        const bool m = gated ? mask_in[idx] != 0 : logit > 0.0f;
+        const bool m = gated ? (!mask_in || mask_in[idx] != 0) : logit > 0.0f;
         if (!gated) {
             out.logit[idx] = logit;
             out.mask[idx] = m ? 1 : 0;
@@ -319,10 +323,25 @@ __device__ __forceinline__ void decode_store(floatx4 v, int to, int g, int64_t r
             out.dz[idx] = m ? f.dz : nan;
         }
     } else if (fields) {
-        const bool m = gated ? mask_in[idx] != 0 : recv > 0.0f;
+        const bool m = gated ? (!mask_in || mask_in[idx] != 0) : recv > 0.0f;
         const float thr = fmaf(out_scale[5 * hs + 4], v[1], out_shift[5 * hs + 4]);
         out.throughput[idx] = m ? thr : 0.0f;
     }
+}
+
+// Indexed evaluation: the number of entries (min(*n_dev, n), n when n_dev is
+// null) and the input ray of entry r.
+__device__ __forceinline__ int64_t eval_count(int64_t n, const int64_t *n_dev)
+{
+    if (!n_dev)
+        return n;
+    const int64_t c = *n_dev;
+    return c < 0 ? 0 : (c < n ? c : n);
+}
+
+__device__ __forceinline__ int64_t eval_ray(const int32_t *in_idx, int64_t r)
+{
+    return in_idx ? static_cast<int64_t>(in_idx[r]) : r;
 }
 
 // ---- compacted evaluation

@@ -167,6 +167,8 @@ struct F32Args {
     uint32_t flags;
     const uint8_t *mask_in;
     int64_t n;
+    const int32_t *in_idx;  // indexed evaluation: entry k is ray in_idx[k] (null: ray k)
+    const int64_t *n_dev;   // indexed evaluation: entries min(*n_dev, n) (may be null)
     MapCompact cmp;       // CMP: compacted outputs
     int64_t cmp_consts;   // CMP: LDS offset of the compacted-evaluation tiles' biases
     int64_t cmp_bits;     // CMP: LDS offset of the per-wave mask bits and positions (1 KiB per wave)
@@ -231,7 +233,7 @@ __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args
     const float *bias = reinterpret_cast<const float *>(lds);
     const float *nrm = bias + A.D * H + 16 * A.TO;
     const float *w0 = reinterpret_cast<const float *>(lds + A.F.w0);
-    const int64_t n = A.n;
+    const int64_t n = CMP ? A.n : eval_count(A.n, A.n_dev);  // indexed: uncompacted only
     const int64_t wg_tiles = (n + 16 * kF32NT * kF32Waves - 1) / (16 * kF32NT * kF32Waves);
     const int64_t tile_bytes = static_cast<int64_t>(K4) * kF32Frag;
     const int per_group = static_cast<int>(kF32Stage / tile_bytes);
@@ -288,15 +290,16 @@ __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args
 #pragma unroll
         for (int nt = 0; nt < kF32NT; ++nt) {
             const int64_t r = ray0 + nt * 16 + col;
+            const int64_t ri = CMP ? r : r < n ? eval_ray(A.in_idx, r) : 0;  // the input ray of entry r
             fr[nt] = CanonFrame{1.0f, 0.0f, 1.0f};
             if (A.canonical) {
                 // every lane needs its ray's x, y, dx, dy for the frame
                 float f[4] = {0.0f, 0.0f, 0.0f, 0.0f};
                 if (r < n) {
-                    f[0] = rays.x[r];
-                    f[1] = rays.y[r];
-                    f[2] = rays.dx[r];
-                    f[3] = rays.dy[r];
+                    f[0] = rays.x[ri];
+                    f[1] = rays.y[ri];
+                    f[2] = rays.dx[ri];
+                    f[3] = rays.dy[ri];
                 }
                 fr[nt] = canon_in(f);
                 if (CMP && g == 0) {
@@ -306,7 +309,7 @@ __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args
                     fw[1] = fr[nt].s;
                     fw[2] = fr[nt].sg;
                 }
-                const float fz = r < n ? rays.dz[r] : 0.0f, fl = r < n ? rays.lambda_nm[r] : 0.0f;
+                const float fz = r < n ? rays.dz[ri] : 0.0f, fl = r < n ? rays.lambda_nm[ri] : 0.0f;
                 // k = g (0..3) and 4 + g (dz, lambda, pad, pad)
                 const float f0 = g == 0 ? f[0] : g == 1 ? f[1] : g == 2 ? f[2] : f[3];
                 xin[nt][0] = r < n ? (f0 - nrm[g]) * nrm[6 + g] : 0.0f;
@@ -320,7 +323,7 @@ __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args
                 if (r < n && k < 6) {
                     const float *src = k == 0 ? rays.x : k == 1 ? rays.y : k == 2 ? rays.dx
                                      : k == 3 ? rays.dy : k == 4 ? rays.dz : rays.lambda_nm;
-                    f = (src[r] - nrm[k]) * nrm[6 + k];
+                    f = (src[ri] - nrm[k]) * nrm[6 + k];
                 }
                 xin[nt][c] = f;
             }
@@ -504,11 +507,15 @@ __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args
 template <int H, int ACT, bool CMP = false>
 static lt_status launch_f32(const Map &M, const lt_rays &rays, const lt_map_out &out, int64_t n,
                             uint32_t flags, const uint8_t *mask_in, hipStream_t s,
-                            const MapCompact *cmp = nullptr)
+                            const MapCompact *cmp = nullptr, const EvalIndex *ix = nullptr)
 {
     F32Args A{};
     A.flags = flags;
     A.mask_in = mask_in;
+    if (ix) {
+        A.in_idx = ix->in_idx;
+        A.n_dev = ix->n_dev;
+    }
     A.img = M.img_f32;
     A.F = f32_layout(M.lay);
     A.D = M.lay.D;
@@ -569,7 +576,7 @@ lt_status ensure_packed_f32(Map &M, hipStream_t s)
 }
 
 lt_status eval_f32(Map &M, const lt_rays &rays, const lt_map_out &out, int64_t n, uint32_t flags,
-                   const uint8_t *mask_in, hipStream_t s)
+                   const uint8_t *mask_in, hipStream_t s, const EvalIndex *ix)
 {
     lt_status st = ensure_packed_f32(M, s);
     if (st != LT_OK)
@@ -577,13 +584,13 @@ lt_status eval_f32(Map &M, const lt_rays &rays, const lt_map_out &out, int64_t n
     const int H = M.lay.H;
     const bool relu = M.lay.act == LT_ACT_RELU;
     if (H == 128)
-        return relu ? launch_f32<128, LT_ACT_RELU>(M, rays, out, n, flags, mask_in, s)
-                    : launch_f32<128, LT_ACT_TANH>(M, rays, out, n, flags, mask_in, s);
+        return relu ? launch_f32<128, LT_ACT_RELU>(M, rays, out, n, flags, mask_in, s, nullptr, ix)
+                    : launch_f32<128, LT_ACT_TANH>(M, rays, out, n, flags, mask_in, s, nullptr, ix);
     if (H == 64)
-        return relu ? launch_f32<64, LT_ACT_RELU>(M, rays, out, n, flags, mask_in, s)
-                    : launch_f32<64, LT_ACT_TANH>(M, rays, out, n, flags, mask_in, s);
-    return relu ? launch_f32<32, LT_ACT_RELU>(M, rays, out, n, flags, mask_in, s)
-                : launch_f32<32, LT_ACT_TANH>(M, rays, out, n, flags, mask_in, s);
+        return relu ? launch_f32<64, LT_ACT_RELU>(M, rays, out, n, flags, mask_in, s, nullptr, ix)
+                    : launch_f32<64, LT_ACT_TANH>(M, rays, out, n, flags, mask_in, s, nullptr, ix);
+    return relu ? launch_f32<32, LT_ACT_RELU>(M, rays, out, n, flags, mask_in, s, nullptr, ix)
+                : launch_f32<32, LT_ACT_TANH>(M, rays, out, n, flags, mask_in, s, nullptr, ix);
 }
 
 lt_status eval_f32_compact(Map &M, const lt_rays &rays, const MapCompact &C, int64_t n, hipStream_t s)
