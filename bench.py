@@ -252,14 +252,36 @@ def paper_pair(lt, synth, lens, dev, steps, rays, batch=65536, seed=3003,
     res = {"classifier": "2 x 32 tanh, BCE", "regressor": f"5 x 32 tanh, MSE(x, y, I) + {w_cos:g} x (1 - cos)",
            "fit_steps": steps, "fit_seconds": t_fit,
            "flops_per_ray": map_flops_per_ray(32, 2, 1) + map_flops_per_ray(32, 5, 1)}
+    # the regressor on the classifier's valid rays only (lt_mask_index +
+    # lt_map_eval_indexed): the same values as the gated regressor on those
+    # rays (tests/test_gpu_map_indexed.py), work in proportion to them
+    cls_out = {"logit": torch.empty((1, n), dtype=torch.float32, device=dev),
+               "mask": torch.empty((1, n), dtype=torch.uint8, device=dev)}
+    idx = torch.empty(n, dtype=torch.int32, device=dev)
+    cnt = torch.empty(1, dtype=torch.int64, device=dev)
+    reg_out = {f: torch.empty((1, n), dtype=torch.float32, device=dev)
+               for f in ("x", "y", "dx", "dy", "dz", "throughput")}
+
+    def pair_indexed(dt):
+        lt.lt_map_eval_ex(cls, dt, rays, cls_out, n, lt.LT_EVAL_MASK_ONLY, None, stream)
+        lt.lt_mask_index(cls_out["mask"], n=n, capacity=n, idx=idx, count=cnt, stream=stream)
+        lt.lt_map_eval_indexed(reg, dt, rays, idx, cnt, n, reg_out, stream)
+
     for name, dt in (("f32", lt.LT_F32), ("bf16", lt.LT_BF16)):
         t = time_kernel(lambda: pair(dt), stream, 5)
         res[f"{name}_ms"] = t * 1e3
         res[f"{name}_mrays_s"] = n / t / 1e6
+        t_ix = time_kernel(lambda: pair_indexed(dt), stream, 5)
+        res[f"{name}_indexed_ms"] = t_ix * 1e3
+        res[f"{name}_indexed_mrays_s"] = n / t_ix / 1e6
         k = 65536
         g = eval_host(pair(dt, k))
         o = {f: v.cpu().numpy() for f, v in lt.lt_trace(h, (0, 0, 0), {f: v[:k] for f, v in rays.items()}).items()}
         res[f"{name}_error_vs_gpu_tracer"] = exit_error(g, o, k)
+    torch.cuda.synchronize()
+    res["indexed_valid_fraction"] = int(cnt.item()) / n
+    res["indexed"] = ("classifier (LT_EVAL_MASK_ONLY), lt_mask_index, regressor on the listed rays "
+                      "(lt_map_eval_indexed); its values equal the gated pair's on the valid rays")
     return res
 
 

@@ -536,7 +536,8 @@ lt_status lt_map_eval_ex(lt_map map, int32_t dtype, const lt_rays *rays, const l
  * lt_mask_index: the dense list of the set entries of mask[0, n) (device
  * uint8, e.g. a classifier's out->mask from LT_EVAL_MASK_ONLY): entry k of
  * idx (device int32, k < min(*count, capacity)) is the index of a set entry;
- * entries from one block of 256 keep their order, blocks land in any order.
+ * entries from one aligned tile of 16,384 keep their order and stay
+ * together, tiles land in any order (one atomic add per tile).
  * *count (device int64) is the number of set entries, cleared by a kernel on
  * the stream and counted even beyond capacity.  n = 0 writes a zero count.
  * Errors: LT_ERR_ARG (NULL count; NULL mask with n > 0; NULL idx with

@@ -751,38 +751,87 @@ __global__ void zero_counts_kernel(unsigned long long *count, int P)
         count[threadIdx.x] = 0ull;
 }
 
-// Dense list of the set entries of mask[0, n) (a classifier's mask, Sec. 4.2):
-// per block of 256 entries a wave ballot counts the set ones, one atomic add
-// on *count reserves the block's range, and each set entry writes its index
-// there.  Entries of one block keep their order; blocks land in any order.
+// Dense list of the set entries of mask[0, n) (a classifier's mask, Sec. 4.2).
+// A workgroup takes a tile of kIdxTile entries: each thread reads four 16-byte
+// groups (group j of thread t at j * 4096 + 16 t, so a wave's loads are
+// contiguous), counts their non-zero bytes, and one block scan of the four
+// counts packed in 16-bit fields of a 64-bit word (each total is at most 4096)
+// gives every group its place.  One atomic add on *count per tile reserves the
+// tile's range: all atomics hit one address and the L2 serialises them, so the
+// tile is large enough that they cost less than reading the mask.  Entries of
+// one tile keep their order; tiles land in any order.
+constexpr int kIdxTile = 256 * 64;
+
+__device__ __forceinline__ unsigned nonzero_bytes4(uint32_t w)
+{
+    // bit 7 of each byte set iff the byte is non-zero, then bits 7, 15, 23, 31 -> 0..3
+    const uint32_t h = (((w & 0x7f7f7f7fu) + 0x7f7f7f7fu) | w) & 0x80808080u;
+    return ((h >> 7) & 1u) | ((h >> 14) & 2u) | ((h >> 21) & 4u) | ((h >> 28) & 8u);
+}
+
 __global__ __launch_bounds__(256) void mask_index_kernel(const uint8_t *__restrict__ mask, int64_t n,
                                                          int32_t *__restrict__ idx, int64_t cap,
-                                                         unsigned long long *count)
+                                                         unsigned long long *count, int aligned16)
 {
-    __shared__ unsigned wave_cnt[4];
+    __shared__ unsigned long long wave_tot[4];
     __shared__ unsigned long long blk_base;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int64_t b0 = static_cast<int64_t>(blockIdx.x) * 256; b0 < n; b0 += static_cast<int64_t>(gridDim.x) * 256) {
-        const int64_t r = b0 + threadIdx.x;
-        const bool v = r < n && mask[r] != 0;
-        const uint64_t bal = __ballot(v);
-        if (lane == 0)
-            wave_cnt[wave] = static_cast<unsigned>(__popcll(bal));
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const unsigned tot = wave_cnt[0] + wave_cnt[1] + wave_cnt[2] + wave_cnt[3];
-            blk_base = tot ? atomicAdd(count, static_cast<unsigned long long>(tot)) : 0ull;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t tile0 = static_cast<int64_t>(blockIdx.x) * kIdxTile;
+    unsigned nz[4];
+    unsigned long long packed = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int64_t r0 = tile0 + j * 4096 + t * 16;
+        unsigned m = 0;
+        if (aligned16 && r0 + 16 <= n) {
+            const uint4 w = *reinterpret_cast<const uint4 *>(mask + r0);
+            m = nonzero_bytes4(w.x) | (nonzero_bytes4(w.y) << 4) | (nonzero_bytes4(w.z) << 8) |
+                (nonzero_bytes4(w.w) << 12);
+        } else {
+            for (int i = 0; i < 16; ++i)
+                if (r0 + i < n && mask[r0 + i] != 0)
+                    m |= 1u << i;
         }
-        __syncthreads();
-        unsigned pre = 0;
-        for (int w = 0; w < wave; ++w)
-            pre += wave_cnt[w];
-        if (v) {
-            const int64_t pos = static_cast<int64_t>(blk_base) + pre + __popcll(bal & ((1ull << lane) - 1ull));
+        nz[j] = m;
+        packed |= static_cast<unsigned long long>(__popc(m)) << (16 * j);
+    }
+    // inclusive scan of the packed counts across the wave, then across the four waves
+    unsigned long long inc = packed;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const unsigned long long o = __shfl_up(inc, d, 64);
+        if (lane >= d)
+            inc += o;
+    }
+    if (lane == 63)
+        wave_tot[wave] = inc;
+    __syncthreads();
+    unsigned long long before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const unsigned long long v = wave_tot[w];
+        before += w < wave ? v : 0ull;
+        tot += v;
+    }
+    unsigned gtot[4], gbase[4], sum = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        gtot[j] = static_cast<unsigned>((tot >> (16 * j)) & 0xffffu);
+        gbase[j] = sum;
+        sum += gtot[j];
+    }
+    if (t == 0)
+        blk_base = sum ? atomicAdd(count, static_cast<unsigned long long>(sum)) : 0ull;
+    __syncthreads();
+    const unsigned long long excl = before + inc - packed;
+    const int64_t base = static_cast<int64_t>(blk_base);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        int64_t pos = base + gbase[j] + static_cast<int64_t>((excl >> (16 * j)) & 0xffffu);
+        const int64_t r0 = tile0 + j * 4096 + t * 16;
+        for (unsigned m = nz[j]; m; m &= m - 1u, ++pos)
             if (pos < cap)
-                idx[pos] = static_cast<int32_t>(r);
-        }
-        __syncthreads();  // wave_cnt and blk_base are rewritten by the next block
+                idx[pos] = static_cast<int32_t>(r0 + __builtin_ctz(m));
     }
 }
 
@@ -1206,9 +1255,10 @@ lt_status lt_mask_index(const uint8_t *mask, int64_t n, int32_t *idx, int64_t ca
     lt_status st = check_hip(hipGetLastError(), "zero_counts_kernel launch");
     if (st != LT_OK || n == 0)
         return st;
-    const int64_t blocks = (n + 255) / 256;
-    const int grid = static_cast<int>(blocks < 4 * num_cus() ? blocks : 4 * num_cus());
-    hipLaunchKernelGGL(mask_index_kernel, dim3(grid), dim3(256), 0, s, mask, n, idx, capacity, cnt);
+    // n < 2^31 keeps the grid under 2^17 tiles
+    const int grid = static_cast<int>((n + kIdxTile - 1) / kIdxTile);
+    const int aligned16 = (reinterpret_cast<uintptr_t>(mask) & 15u) == 0;
+    hipLaunchKernelGGL(mask_index_kernel, dim3(grid), dim3(256), 0, s, mask, n, idx, capacity, cnt, aligned16);
     return check_hip(hipGetLastError(), "mask_index_kernel launch");
 }
 

@@ -35,34 +35,37 @@ def _dev_rays(rays, dev):
     return {k: torch.from_numpy(np.ascontiguousarray(v)).to(dev) for k, v in rays.items()}
 
 
-@pytest.mark.parametrize("n,density,cap_frac", [(0, 0.5, 1.0), (1, 1.0, 1.0), (255, 0.3, 1.0), (256, 0.9, 1.0),
-                                                 (257, 0.5, 1.0), (100003, 0.17, 1.0), (100003, 0.5, 0.25),
-                                                 (1 << 20, 0.02, 1.0)])
-def test_mask_index(dev, n, density, cap_frac):
+@pytest.mark.parametrize("n,density,cap_frac,offset", [
+    (0, 0.5, 1.0, 0), (1, 1.0, 1.0, 0), (255, 0.3, 1.0, 0), (256, 0.9, 1.0, 0), (257, 0.5, 1.0, 0),
+    (16384, 1.0, 1.0, 0), (16400, 0.6, 1.0, 0), (100003, 0.17, 1.0, 0), (100003, 0.5, 0.25, 0),
+    (100003, 0.3, 1.0, 5), (1 << 20, 0.02, 1.0, 0), (1 << 22, 0.166, 1.0, 3)])
+def test_mask_index(dev, n, density, cap_frac, offset):
     import torch
     import paper_2605_04017_amd as lt
     rng = np.random.default_rng(n + int(100 * density))
-    mask_np = (rng.random(n) < density).astype(np.uint8)
-    mask = torch.from_numpy(mask_np).to(dev)
+    # set entries hold any non-zero byte; an offset start takes the unaligned path
+    mask_np = np.where(rng.random(n) < density, rng.integers(1, 256, n), 0).astype(np.uint8)
+    mask = torch.zeros(n + offset, dtype=torch.uint8, device=dev)[offset:]
+    mask.copy_(torch.from_numpy(mask_np))
     cap = int(n * cap_frac)
     idx, cnt = lt.lt_mask_index(mask, n=n, capacity=cap)
     torch.cuda.synchronize()
-    total = int(mask_np.sum())
+    total = int(np.count_nonzero(mask_np))
     assert int(cnt.item()) == total
     k = min(total, cap)
     got = idx[:k].cpu().numpy().astype(np.int64)
     set_rays = np.nonzero(mask_np)[0]
     assert len(np.unique(got)) == k, "an index listed twice"
-    assert np.all(mask_np[got] == 1), "an unset entry listed"
+    assert np.all(mask_np[got] != 0), "an unset entry listed"
     if cap >= total:
         assert np.array_equal(np.sort(got), set_rays)
-    # entries of one block of 256 keep their order and stay together
-    blk = got // 256
+    # entries of one tile of 16,384 keep their order and stay together
+    blk = got // 16384
     same = blk[1:] == blk[:-1]
     assert np.all(got[1:][same] > got[:-1][same])
     if cap >= total and k > 1:
         assert 1 + int((~same).sum()) == len(np.unique(blk)), "a block split into several runs"
-    print(f"[mask_index] n={n} set={total} cap={cap}: list matches the mask", flush=True)
+    print(f"[mask_index] n={n} set={total} cap={cap} offset={offset}: list matches the mask", flush=True)
 
 
 @pytest.mark.parametrize("width,depth,dtype,canonical,n_rays,k", [
