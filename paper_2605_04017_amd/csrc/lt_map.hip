@@ -850,6 +850,22 @@ int num_cus()
     return g_num_cus;
 }
 
+int resident_blocks(const void *kern, int block, size_t lds, std::atomic<uint64_t> &memo)
+{
+    const uint64_t key = static_cast<uint64_t>(lds) << 8;
+    const uint64_t m = memo.load(std::memory_order_relaxed);
+    if (m != 0 && (m & ~0xffull) == key)
+        return static_cast<int>(m & 0xffu);
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, block, lds) != hipSuccess) {
+        (void)hipGetLastError();  // a failed query must not surface as a launch error
+        occ = 1;
+    }
+    occ = occ < 1 ? 1 : occ > 255 ? 255 : occ;
+    memo.store(key | static_cast<uint64_t>(occ), std::memory_order_relaxed);
+    return occ;
+}
+
 template <int H, int ACT, bool TRAIN, bool FP8, bool BIG, bool CMP = false>
 static lt_status launch_kernel(EvalArgs A, int64_t dyn_lds, const lt_rays &rays,
                                const lt_map_out &out, hipStream_t s)
@@ -868,7 +884,12 @@ static lt_status launch_kernel(EvalArgs A, int64_t dyn_lds, const lt_rays &rays,
     constexpr int kWaves = eval_waves<H, TRAIN>();
     constexpr int kRays = 16 * eval_subtiles<H, TRAIN>() * kWaves;  // rays per workgroup pass
     const int64_t tiles = (A.n + kRays - 1) / kRays;
-    const int grid = static_cast<int>(tiles < num_cus() ? tiles : num_cus());
+    // the compacted schedule keeps one workgroup per CU
+    static std::atomic<uint64_t> memo{0};
+    const int64_t cap = static_cast<int64_t>(num_cus()) *
+                        (CMP ? 1 : resident_blocks(reinterpret_cast<const void *>(kern), kWaves * 64,
+                                                   static_cast<size_t>(dyn_lds), memo));
+    const int grid = static_cast<int>(tiles < cap ? tiles : cap);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kWaves * 64), static_cast<size_t>(dyn_lds), s, A,
                        rays, out);
     return check_hip(hipGetLastError(), "map_eval_bf16_kernel launch");

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <atomic>
 
 #include "lt.h"
 #include "lt_map.h"
@@ -162,6 +163,13 @@ constexpr float kFp8Max = 448.0f;
 constexpr float kFp8ActScale = 256.0f;  // tanh activations (|h| <= 1) scaled by 2^8
 
 int num_cus();
+
+// Workgroups of `kern` (block threads, lds bytes of dynamic LDS) that one CU
+// holds at once, at least 1; memoised per kernel for the last LDS size.  A
+// persistent evaluation grid of num_cus() x this many workgroups keeps every
+// slot busy: narrow maps (few registers, little LDS) fit two per CU and hide
+// their ray loads behind each other.
+int resident_blocks(const void *kern, int block, size_t lds, std::atomic<uint64_t> &memo);
 
 // Compacted evaluation (Sec. 4.2: where g(x) = 0 the map outputs nothing).
 // Per head p: bit r % 32 of bits[p * n_words + r / 32] is ray r's mask, and

@@ -173,6 +173,8 @@ struct F32Args {
     int64_t cmp_consts;   // CMP: LDS offset of the compacted-evaluation tiles' biases
     int64_t cmp_bits;     // CMP: LDS offset of the per-wave mask bits and positions (1 KiB per wave)
     int64_t cmp_frames;   // CMP: LDS offset of the per-wave canonical frames (32 rays x 3 floats)
+    int64_t stage;        // width < 128: bytes of each staging buffer (<= kF32Stage)
+    int all_stages;       // width < 128, uncompacted: every stage resident in LDS (stage j in buffer j)
 };
 
 __device__ __forceinline__ floatx4 mfma_f32(float a, float b, floatx4 c)
@@ -236,9 +238,15 @@ __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args
     const int64_t n = CMP ? A.n : eval_count(A.n, A.n_dev);  // indexed: uncompacted only
     const int64_t wg_tiles = (n + 16 * kF32NT * kF32Waves - 1) / (16 * kF32NT * kF32Waves);
     const int64_t tile_bytes = static_cast<int64_t>(K4) * kF32Frag;
-    const int per_group = static_cast<int>(kF32Stage / tile_bytes);
+    // narrow maps size the two staging buffers to their largest stage, so
+    // that the LDS leaves room for a second workgroup on the CU
+    const int64_t stage_bytes = (CMP || H >= 128) ? static_cast<int64_t>(kF32Stage) : A.stage;
+    const int per_group = static_cast<int>(stage_bytes / tile_bytes);
     const int n_groups = (A.TO + per_group - 1) / per_group;
     const int stages = CMP ? A.D + A.LT : (A.D - 1) + n_groups;  // weight stages of one tile
+    // narrow maps whose stages all fit in LDS copy them once and run without
+    // a workgroup barrier per stage (the waves run free)
+    const bool all_res = (!CMP && H < 128) ? A.all_stages != 0 : false;
 
     // Stage j of a tile: hidden layer j + 1 (j < D - 1), else output group
     // j - (D - 1).  Stages stream through two LDS buffers: while the waves
@@ -263,7 +271,7 @@ __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args
     auto prefetch = [&](int j, int b) {
         int64_t bytes = 0;
         const uint8_t *src = stage_src(j, &bytes);
-        uint8_t *dst = stage0 + b * kF32Stage;
+        uint8_t *dst = stage0 + b * stage_bytes;
         for (int64_t row = wave; row * 1024 < bytes; row += kF32Waves)
             __builtin_amdgcn_global_load_lds(src + row * 1024 + lane * 16, dst + row * 1024, 16, 0, 0);
     };
@@ -273,8 +281,13 @@ __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args
         __syncthreads();
     };
     int buf = 0;
-    if (static_cast<int64_t>(blockIdx.x) < wg_tiles)
+    if (all_res) {
+        for (int j = 0; j < stages; ++j)
+            prefetch(j, j);
+        stage_ready();
+    } else if (static_cast<int64_t>(blockIdx.x) < wg_tiles) {
         prefetch(0, 0);
+    }
     // CMP: this wave's mask bits [64] and first output positions [64] per
     // head, in LDS rather than registers (the kernel is at its register limit)
     uint64_t *wave_bits = reinterpret_cast<uint64_t *>(lds + A.cmp_bits) + wave * 128;
@@ -345,12 +358,14 @@ __global__ __launch_bounds__(kF32Waves * 64, 2) void map_eval_f32_kernel(F32Args
         float h[kF32NT][T][4];
         // stage j's copies are complete; the next stage's start; its buffer
         auto begin_stage = [&](int j) -> const float * {
+            if (all_res)
+                return reinterpret_cast<const float *>(stage0 + j * stage_bytes);
             stage_ready();
             if (j + 1 < stages)
                 prefetch(j + 1, buf ^ 1);
             else if (more)
                 prefetch(0, buf ^ 1);
-            const float *wl = reinterpret_cast<const float *>(stage0 + buf * kF32Stage);
+            const float *wl = reinterpret_cast<const float *>(stage0 + buf * stage_bytes);
             buf ^= 1;
             return wl;
         };
@@ -527,7 +542,25 @@ static lt_status launch_f32(const Map &M, const lt_rays &rays, const lt_map_out 
     A.n = n;
     auto kern = map_eval_f32_kernel<H, ACT, CMP>;
     static bool attr = false;
-    size_t lds = static_cast<size_t>(A.F.resident + 2 * kF32Stage);
+    A.stage = kF32Stage;
+    if (!CMP && H < 128) {
+        // the largest stage: a hidden layer, or every output tile in one group
+        const int64_t outs = static_cast<int64_t>(A.TO) * (H / 4) * kF32Frag;
+        const int64_t need = A.F.layer_bytes > outs ? A.F.layer_bytes : outs;
+        if (need < kF32Stage)
+            A.stage = (need + 1023) / 1024 * 1024;
+    }
+    size_t lds = static_cast<size_t>(A.F.resident + 2 * A.stage);
+    if (!CMP && H < 128) {
+        const int64_t tile_bytes = static_cast<int64_t>(H / 4) * kF32Frag;
+        const int64_t per_group = A.stage / tile_bytes;
+        const int64_t stages = (A.D - 1) + (A.TO + per_group - 1) / per_group;
+        const int64_t all = A.F.resident + stages * A.stage;
+        if (all <= kMaxLds) {
+            A.all_stages = 1;
+            lds = static_cast<size_t>(all);
+        }
+    }
     if constexpr (CMP) {
         A.cmp = *cmp;
         A.cmp.agg = static_cast<int64_t>(lds);
@@ -550,7 +583,10 @@ static lt_status launch_f32(const Map &M, const lt_rays &rays, const lt_map_out 
         attr = true;
     }
     const int64_t tiles = (n + 16 * kF32NT * kF32Waves - 1) / (16 * kF32NT * kF32Waves);
-    const int64_t cap = num_cus();
+    // the compacted schedule keeps one workgroup per CU
+    static std::atomic<uint64_t> memo{0};
+    const int64_t cap = static_cast<int64_t>(num_cus()) *
+                        (CMP ? 1 : resident_blocks(reinterpret_cast<const void *>(kern), kF32Waves * 64, lds, memo));
     const int grid = static_cast<int>(tiles < cap ? tiles : cap);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kF32Waves * 64), lds, s, A, rays, out);
     return check_hip(hipGetLastError(), "map_eval_f32_kernel launch");
