@@ -200,7 +200,9 @@ __device__ __forceinline__ float act_f32(float u)
 // one buffer shared by two four-wave workgroups, the copies overlap the
 // MFMAs and each staged byte serves twice as many rays (measured: 4.85 ->
 // 4.78 ms on 4,194,304 rays; with the copies left out entirely, 4.40 ms,
-// the remaining gap being the per-stage barrier).
+// the remaining gap being the per-stage barrier).  Narrower maps size the
+// buffers to their largest stage and, when every stage fits, keep all of
+// them resident with no barrier per stage; two such workgroups share a CU.
 constexpr int kF32NT = 2;
 
 // CMP: compacted evaluation.  After the hidden layers, the output layer runs
